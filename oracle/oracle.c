@@ -1,0 +1,261 @@
+/*
+ * CPU ORACLE -- test infrastructure only.
+ *
+ * Plain, slow, obviously correct reference for the batched sorted search.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load this file's library; the product path never does.  It
+ * shares no code, header or table with the device library.
+ *
+ * The search result (Sec. 1 of the paper: the index of the largest table
+ * element that is less than a given target), read with a strict "<" and -1
+ * when no element qualifies, has a plain definition:
+ *
+ *     idx(x) = #{ i in [0, n) : a[i] < x } - 1.
+ *
+ * Every method in the library (bisection, Sec. 3.2; the exponent hash with
+ * an in-bin linear scan, Sec. 3.4-3.5; the learned index) must reach exactly
+ * this number, so the oracle is the definition written out: one full pass
+ * over the table per target, IEEE ordered compares, no early exit.  Special
+ * targets need no special code: a NaN target compares false with every entry
+ * (-> -1), -0.0 equals +0.0, denormals compare exactly, -inf -> -1 and
+ * +inf -> (number of finite entries) - 1.
+ *
+ * Build: gcc -O2 -shared -fPIC -pthread, never with -ffast-math, -ffinite-math
+ * or flush-to-zero flags (they would change the meaning of the compares).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <unistd.h>
+
+/* ---- host threading: static chunks over the targets ----------------------- */
+
+typedef void (*chunk_fn)(void *ctx, int64_t begin, int64_t end, int tid);
+
+typedef struct {
+    chunk_fn fn;
+    void *ctx;
+    int64_t begin, end;
+    int tid;
+} chunk_job;
+
+static void *chunk_main(void *p) {
+    chunk_job *j = (chunk_job *)p;
+    j->fn(j->ctx, j->begin, j->end, j->tid);
+    return NULL;
+}
+
+int oracle_default_threads(void) {
+    long c = sysconf(_SC_NPROCESSORS_ONLN);
+    if (c < 1) c = 1;
+    const char *env = getenv("OMP_NUM_THREADS");
+    if (env) {
+        long e = strtol(env, NULL, 10);
+        if (e > 0 && e < c) c = e;
+    }
+    return c > 256 ? 256 : (int)c;
+}
+
+/* Runs fn over [0, count) split into `threads` contiguous chunks; returns the
+ * number of threads that actually ran. */
+static int run_chunks(int threads, int64_t count, chunk_fn fn, void *ctx) {
+    if (threads <= 0) threads = oracle_default_threads();
+    if (threads > 256) threads = 256;
+    if (count < threads) threads = count > 0 ? (int)count : 1;
+    if (threads == 1) {
+        fn(ctx, 0, count, 0);
+        return 1;
+    }
+    pthread_t th[256];
+    chunk_job job[256];
+    int ran = 0;
+    for (int t = 0; t < threads; ++t) {
+        job[t].fn = fn;
+        job[t].ctx = ctx;
+        job[t].begin = count * t / threads;
+        job[t].end = count * (t + 1) / threads;
+        job[t].tid = t;
+        if (pthread_create(&th[t], NULL, chunk_main, &job[t]) != 0) {
+            fn(ctx, job[t].begin, job[t].end, t);
+            job[t].fn = NULL;
+        } else {
+            ++ran;
+        }
+    }
+    for (int t = 0; t < threads; ++t)
+        if (job[t].fn) pthread_join(th[t], NULL);
+    return ran > 0 ? ran : 1;
+}
+
+/* ---- the definition: idx(x) = #{a[i] < x} - 1 ----------------------------- */
+
+typedef struct {
+    const double *a;
+    int64_t n;
+    const double *x;
+    int32_t *out;
+} count_ctx;
+
+static void count_chunk(void *p, int64_t b, int64_t e, int tid) {
+    (void)tid;
+    count_ctx *c = (count_ctx *)p;
+    for (int64_t k = b; k < e; ++k) {
+        const double xk = c->x[k];
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < c->n; ++i) cnt += (c->a[i] < xk);
+        c->out[k] = (int32_t)(cnt - 1);
+    }
+}
+
+/* out[k] = #{i : a[i] < x[k]} - 1 for k in [0, m).  Returns threads used. */
+int oracle_search_lt(const double *a, int64_t n, const double *x, int64_t m, int32_t *out,
+                     int threads) {
+    count_ctx c = {a, n, x, out};
+    return run_chunks(threads, m, count_chunk, &c);
+}
+
+/* Same definition at selected positions only: out[j] = idx(x[pos[j]]). */
+typedef struct {
+    const double *a;
+    int64_t n;
+    const double *x;
+    const int64_t *pos;
+    int32_t *out;
+} count_at_ctx;
+
+static void count_at_chunk(void *p, int64_t b, int64_t e, int tid) {
+    (void)tid;
+    count_at_ctx *c = (count_at_ctx *)p;
+    for (int64_t j = b; j < e; ++j) {
+        const double xk = c->x[c->pos[j]];
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < c->n; ++i) cnt += (c->a[i] < xk);
+        c->out[j] = (int32_t)(cnt - 1);
+    }
+}
+
+int oracle_search_lt_at(const double *a, int64_t n, const double *x, const int64_t *pos,
+                        int64_t count, int32_t *out, int threads) {
+    count_at_ctx c = {a, n, x, pos, out};
+    return run_chunks(threads, count, count_at_chunk, &c);
+}
+
+/* Segmented form for batched workloads: segment s searches table
+ * tables[toff[s] .. toff[s+1]) with targets x[qoff[s] .. qoff[s+1]). */
+int oracle_search_lt_segments(const double *tables, const int64_t *toff, const double *x,
+                              const int64_t *qoff, int32_t nseg, int32_t *out, int threads) {
+    int used = 1;
+    for (int32_t s = 0; s < nseg; ++s) {
+        int64_t m = qoff[s + 1] - qoff[s];
+        if (m <= 0) continue;
+        int u = oracle_search_lt(tables + toff[s], toff[s + 1] - toff[s], x + qoff[s], m,
+                                 out + qoff[s], threads);
+        if (u > used) used = u;
+    }
+    return used;
+}
+
+/* ---- bracket check: a[i] < x <= a[i+1], with a[-1] = -inf, a[n] = +inf ----
+ * For a table sorted non-decreasing this property holds for exactly one i
+ * in [-1, n-1], which makes it an exact per-target check at any size.  A NaN
+ * target must give -1.  Returns the number of violations; *first_bad gets the
+ * smallest violating position (or -1). */
+typedef struct {
+    const double *a;
+    int64_t n;
+    const double *x;
+    const int32_t *idx;
+    int64_t bad[256];
+    int64_t first[256];
+} bracket_ctx;
+
+static void bracket_chunk(void *p, int64_t b, int64_t e, int tid) {
+    bracket_ctx *c = (bracket_ctx *)p;
+    int64_t bad = 0, first = -1;
+    for (int64_t k = b; k < e; ++k) {
+        const double xk = c->x[k];
+        const int64_t i = c->idx[k];
+        int ok;
+        if (xk != xk) {
+            ok = (i == -1);
+        } else if (i < -1 || i > c->n - 1) {
+            ok = 0;
+        } else {
+            int lower_ok = (i == -1) || (c->a[i] < xk);
+            int upper_ok = (i == c->n - 1) || (xk <= c->a[i + 1]);
+            ok = lower_ok && upper_ok;
+        }
+        if (!ok) {
+            if (first < 0) first = k;
+            ++bad;
+        }
+    }
+    c->bad[tid] = bad;
+    c->first[tid] = first;
+}
+
+int64_t oracle_check_bracket(const double *a, int64_t n, const double *x, int64_t m,
+                             const int32_t *idx, int64_t *first_bad, int threads) {
+    bracket_ctx *c = (bracket_ctx *)calloc(1, sizeof(bracket_ctx));
+    if (!c) return -1;
+    c->a = a;
+    c->n = n;
+    c->x = x;
+    c->idx = idx;
+    for (int t = 0; t < 256; ++t) c->first[t] = -1;
+    run_chunks(threads, m, bracket_chunk, c);
+    int64_t bad = 0, first = -1;
+    for (int t = 0; t < 256; ++t) {
+        bad += c->bad[t];
+        if (c->first[t] >= 0 && (first < 0 || c->first[t] < first)) first = c->first[t];
+    }
+    free(c);
+    if (first_bad) *first_bad = first;
+    return bad;
+}
+
+/* ---- exponent-hash bins (Sec. 3.5 with Eq. 3) ------------------------------
+ * The paper's exponent hash bins a value by the base-2 exponent stored in its
+ * IEEE 754 binary64 encoding.  With s extra leading fraction bits each binade
+ * is split into 2^s equal sub-bins; s = 0 is the paper's hash.  Written out
+ * from the encoding's definition (biased exponent E, 52-bit fraction F):
+ *   normal v = 2^e (1 + f), f in [0,1):  E = e + 1023,  key = E 2^s + floor(f 2^s)
+ *   subnormal v = F 2^-1074:             E = 0,         key = floor(F 2^(s-52))
+ *   v = +0: key = 0;   v = +inf: key = 2047 2^s.
+ * Defined for v >= +0 (sign bit clear) and s in [0, 20]. */
+int64_t oracle_exponent_key(double v, int s) {
+    if (v == 0.0) return 0;
+    if (isinf(v)) return (int64_t)2047 << s;
+    if (v < 0x1p-1022) {
+        double F = ldexp(v, 1074); /* exact: the integer fraction field */
+        return (int64_t)floor(ldexp(F, s - 52));
+    }
+    int E2;
+    double mant = frexp(v, &E2); /* v = mant 2^E2, mant in [0.5, 1) */
+    int e = E2 - 1;
+    double f = 2.0 * mant - 1.0; /* exact */
+    return ((int64_t)(e + 1023) << s) + (int64_t)floor(ldexp(f, s));
+}
+
+/* Prefix-count bin table of a sorted non-negative table:
+ *   kmin = key(a[0]), nb = key(a[n-1]) - kmin + 1,
+ *   C[b] = #{ i : key(a[i]) - kmin < b },  b = 0 .. nb.
+ * Bin b holds entries C[b] .. C[b+1]-1 (the set Eq. 3 indexes by its
+ * smallest member).  Returns nb, or -1 if C would need more than cap
+ * entries, or -2 for an empty table. */
+int64_t oracle_exponent_bins(const double *a, int64_t n, int s, int64_t *C, int64_t cap,
+                             int64_t *kmin_out) {
+    if (n <= 0) return -2;
+    int64_t kmin = oracle_exponent_key(a[0], s);
+    int64_t kmax = oracle_exponent_key(a[n - 1], s);
+    int64_t nb = kmax - kmin + 1;
+    if (kmin_out) *kmin_out = kmin;
+    if (nb < 1 || nb + 1 > cap) return -1;
+    for (int64_t b = 0; b <= nb; ++b) {
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < n; ++i) cnt += (oracle_exponent_key(a[i], s) - kmin < b);
+        C[b] = cnt;
+    }
+    return nb;
+}
