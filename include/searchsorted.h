@@ -1,0 +1,166 @@
+/*
+ * libsearchsorted -- batched search over small sorted float64 tables on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * THE OPERATION (paper Sec. 1 and Sec. 3): for a small sorted table a[0..n)
+ * and many targets x, find the index of the largest table entry that is less
+ * than the target.  This library fixes the comparison as strict and returns
+ * -1 when no entry qualifies:
+ *
+ *     idx(x) = #{ i in [0, n) : a[i] < x } - 1        (int32, in [-1, n-1])
+ *
+ * Equivalently a[idx] < x <= a[idx+1] with a[-1] = -inf and a[n] = +inf.
+ * (Sec. 3 states a "<=" variant clamped to [0, n-1]; the strict form above is
+ * the one implemented.)  Consequences, all exact:
+ *   - a target below the first entry gives -1, above the last gives n-1;
+ *   - a target equal to a[i] gives the index of the last entry below it;
+ *   - NaN targets give -1; -0.0 and +0.0 compare equal; denormals are
+ *     compared exactly (no flush-to-zero anywhere);
+ *   - -inf gives -1, +inf gives (number of entries below +inf) - 1.
+ *
+ * TABLE PRECONDITION: sorted non-decreasing (duplicates allowed), no NaN.
+ * The search entry points do not check it (ss_validate_table does, on
+ * request).  A table that violates it yields unspecified indices in
+ * [-1, n-1] but never an out-of-bounds access.
+ *
+ * CONVENTIONS
+ *   - Unless stated otherwise every pointer argument is a DEVICE pointer
+ *     (hipMalloc'd or equivalent) owned by the caller; the library never
+ *     frees caller memory and keeps no reference to it after a call returns,
+ *     except where a plan or handle documents otherwise.
+ *   - Calls are asynchronous on the calling thread's current library stream
+ *     (ss_set_stream; default: the null stream) unless documented as
+ *     synchronous.  Output buffers are valid once that stream reaches the
+ *     call's work.
+ *   - Every entry point returns SS_OK (0) or a negative ss_status.  No C++
+ *     exception or abort crosses this interface.  On error, ss_last_error()
+ *     returns a message for the calling thread, and no device work has been
+ *     queued for argument errors.
+ *   - Sizes are int64_t; a table holds at most INT32_MAX entries.
+ *   - Outputs must not overlap inputs.
+ */
+#ifndef SEARCHSORTED_H
+#define SEARCHSORTED_H
+
+#include <stdint.h>
+
+#ifndef SS_API
+#define SS_API __attribute__((visibility("default")))
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SS_OK = 0,
+    SS_ERR_INVALID_ARG = -1,    /* null pointer with a nonzero count, negative
+                                   size, n > INT32_MAX, misaligned or
+                                   overlapping buffers, bad option value */
+    SS_ERR_NOT_DEVICE_PTR = -2, /* a buffer is not device-accessible memory */
+    SS_ERR_NO_DEVICE = -3,      /* no usable GPU */
+    SS_ERR_HIP = -4,            /* a HIP runtime call failed */
+    SS_ERR_OOM = -5,            /* device or host allocation failed */
+    SS_ERR_UNSUPPORTED = -6     /* valid request this build cannot serve */
+} ss_status;
+
+/* Search kernels (values of SS_OPT_FORCE_ALGO and of plan choices). */
+typedef enum {
+    SS_ALGO_AUTO = 0,
+    SS_ALGO_BINARY = 1,      /* branchless bisection (Sec. 3.2) over the table
+                                staged in LDS, fixed trip count */
+    SS_ALGO_BALLOT = 2,      /* linear scan (Sec. 2.1) limited to the bracket
+                                of the wavefront's smallest and largest
+                                target, found with wavefront ballots */
+    SS_ALGO_EXPHASH = 3,     /* exponent hash (Sec. 3.5): bin by the float64
+                                exponent bits (plus optional leading fraction
+                                bits), then a linear scan inside the bin */
+    SS_ALGO_BINARY_GLOBAL = 4 /* bisection reading the table from global
+                                memory (tables too large for LDS) */
+} ss_algo;
+
+/* Process-wide tuning options (ss_set_option / ss_get_option). */
+typedef enum {
+    SS_OPT_FORCE_ALGO = 1,       /* ss_algo; default SS_ALGO_AUTO */
+    SS_OPT_BUCKET_BITS = 2,      /* leading fraction bits s of the exponent
+                                    hash, 0..20; -1 (default) = choose per
+                                    table so the bin count fits the cap */
+    SS_OPT_BUCKET_CAP = 3,       /* max bins of the exponent hash in the
+                                    single-table path; 0 (default) = auto */
+    SS_OPT_BLOCK_SIZE = 4,       /* threads per workgroup: 256, 512 or 1024;
+                                    0 (default) = auto */
+    SS_OPT_GRID_BLOCKS = 5,      /* workgroups per launch; 0 (default) = fill
+                                    the device (persistent grid) */
+    SS_OPT_CHECK_POINTERS = 6    /* 1 (default): verify that buffers are
+                                    device memory before launching; 0: skip */
+} ss_option;
+
+/* Human-readable message for the calling thread's most recent error
+ * (empty string if none).  The pointer stays valid until the next library
+ * call on the same thread. */
+SS_API const char *ss_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+SS_API int ss_version(void);
+
+/* Selects the HIP stream (a hipStream_t, passed as void*) that subsequent
+ * calls from the calling thread enqueue on.  NULL selects the null stream.
+ * The stream is not retained: the caller keeps it alive while in use. */
+SS_API int ss_set_stream(void *hip_stream);
+
+/* Sets / reads a process-wide option (see ss_option).  Invalid option ids or
+ * values return SS_ERR_INVALID_ARG and change nothing. */
+SS_API int ss_set_option(int option, int64_t value);
+SS_API int ss_get_option(int option, int64_t *value_out /* host */);
+
+/* ---------------------------------------------------------------------------
+ * Single table.
+ * ------------------------------------------------------------------------- */
+
+/* out_idx[k] = idx(targets[k]) for k in [0, m) (the operation defined at the
+ * top of this header; paper Sec. 1, Sec. 3.2 and Sec. 3.5).
+ *   table   : n float64 entries, device, sorted non-decreasing, 8-byte aligned
+ *   n       : 0 <= n <= INT32_MAX; n == 0 makes every index -1
+ *   targets : m float64 values, device, 8-byte aligned, any values
+ *   m       : m >= 0; m == 0 is a no-op
+ *   out_idx : m int32, device, 4-byte aligned, must not overlap the inputs
+ * The kernel is chosen from n (and SS_OPT_FORCE_ALGO): the exponent hash
+ * for non-negative tables that fit in LDS (bin parameters are derived on the
+ * device from the table itself), bisection otherwise.  Allocates nothing;
+ * asynchronous; safe to capture in a HIP graph. */
+SS_API int search_sorted_batch(const double *table, int64_t n, const double *targets, int64_t m,
+                        int32_t *out_idx);
+
+/* Same as search_sorted_batch with an explicit kernel and bin bits (ignores
+ * SS_OPT_FORCE_ALGO / SS_OPT_BUCKET_BITS).  algo = SS_ALGO_AUTO behaves like
+ * search_sorted_batch; bucket_bits = -1 chooses automatically.  Used to
+ * compare the kernels on one workload. */
+SS_API int ss_search_with(const double *table, int64_t n, const double *targets, int64_t m,
+                   int32_t *out_idx, int algo, int bucket_bits);
+
+/* Checks the table precondition on the device and waits for the answer
+ * (SYNCHRONOUS on the current stream).  *bad_index_out (host) receives -1 if
+ * the table is sorted non-decreasing without NaN, else the smallest i with
+ * a[i] NaN or a[i] > a[i+1]. */
+SS_API int ss_validate_table(const double *table, int64_t n, int64_t *bad_index_out /* host */);
+
+/* Exponent-hash bin table of a table, as the search builds it in LDS, written
+ * to device memory for inspection (paper Sec. 3.5 with Eq. 3, prefix-count
+ * form).  With key_s(v) = (IEEE-754 biased exponent of v) * 2^s + (leading
+ * s fraction bits of v), kmin = key_s(a[0]) and nb = key_s(a[n-1]) - kmin + 1:
+ *     counts[b] = #{ i : key_s(a[i]) - kmin < b },   b = 0 .. nb,
+ * so bin b holds entries counts[b] .. counts[b+1]-1.
+ *   bucket_bits : s in 0..20, or -1 to use the single-table path's automatic
+ *                 choice for bin cap `cap`
+ *   counts      : device, int32, room for `cap` entries
+ *   info_out    : host, 4 int64: {s, kmin, nb, max entries in one bin}
+ * Requires 1 <= n <= 65535 and a[0] with a clear sign bit.  If nb + 1 > cap
+ * returns SS_ERR_INVALID_ARG.  SYNCHRONOUS. */
+SS_API int ss_exphash_bins(const double *table, int64_t n, int bucket_bits, int32_t *counts,
+                    int64_t cap, int64_t *info_out /* host, 4 entries */);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEARCHSORTED_H */

@@ -1,0 +1,184 @@
+"""Thin ctypes binding over ``libsearchsorted.so`` (see include/searchsorted.h).
+
+Argument marshalling only: tensors supply device pointers and sizes, torch's
+current stream is handed to the library before each call, and every step of
+the search runs in the library's HIP kernels.  There is no fallback: if the
+library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libsearchsorted.so")
+
+SS_OK = 0
+STATUS_NAMES = {
+    -1: "SS_ERR_INVALID_ARG", -2: "SS_ERR_NOT_DEVICE_PTR", -3: "SS_ERR_NO_DEVICE",
+    -4: "SS_ERR_HIP", -5: "SS_ERR_OOM", -6: "SS_ERR_UNSUPPORTED",
+}
+
+ALGO_AUTO, ALGO_BINARY, ALGO_BALLOT, ALGO_EXPHASH, ALGO_BINARY_GLOBAL = 0, 1, 2, 3, 4
+ALGO_NAMES = {ALGO_AUTO: "auto", ALGO_BINARY: "binary", ALGO_BALLOT: "ballot",
+              ALGO_EXPHASH: "exphash", ALGO_BINARY_GLOBAL: "binary_global"}
+ALGO_IDS = {v: k for k, v in ALGO_NAMES.items()}
+
+OPT_FORCE_ALGO, OPT_BUCKET_BITS, OPT_BUCKET_CAP = 1, 2, 3
+OPT_BLOCK_SIZE, OPT_GRID_BLOCKS, OPT_CHECK_POINTERS = 4, 5, 6
+
+
+class SearchSortedError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2112_03229_amd._build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    L.ss_last_error.restype = ctypes.c_char_p
+    L.ss_version.restype = I
+    L.ss_set_stream.argtypes = [P]
+    L.ss_set_option.argtypes = [I, I64]
+    L.ss_get_option.argtypes = [I, ctypes.POINTER(I64)]
+    L.search_sorted_batch.argtypes = [P, I64, P, I64, P]
+    L.ss_search_with.argtypes = [P, I64, P, I64, P, I, I]
+    L.ss_validate_table.argtypes = [P, I64, ctypes.POINTER(I64)]
+    L.ss_exphash_bins.argtypes = [P, I64, I, P, I64, ctypes.POINTER(I64)]
+    for name in ("ss_set_stream", "ss_set_option", "ss_get_option", "search_sorted_batch",
+                 "ss_search_with", "ss_validate_table", "ss_exphash_bins"):
+        getattr(L, name).restype = I
+    _register_extra(L)
+    _lib = L
+    return L
+
+
+def _register_extra(L) -> None:
+    """Signatures of the plan, paired and learned entry points (if present)."""
+    P, I64, I32, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    sigs = {
+        "ss_multi_plan_create": [P, P, I32, P, ctypes.POINTER(P)],
+        "ss_multi_search": [P, P, P],
+        "ss_plan_destroy": [P],
+        "ss_plan_info": [P, I, P, I64],
+        "ss_pair_plan_create": [P, P, P, P, I32, P, ctypes.POINTER(P)],
+        "ss_pair_search": [P, P, P, P, P],
+        "ss_learned_build": [P, I64, P, ctypes.POINTER(P)],
+        "ss_learned_search": [P, P, I64, P],
+        "ss_learned_info": [P, P],
+        "ss_learned_fallbacks": [P, ctypes.POINTER(I64)],
+        "ss_learned_predict": [P, P, I64, P],
+        "ss_learned_weights": [P, P, I64],
+        "ss_learned_destroy": [P],
+    }
+    for name, argtypes in sigs.items():
+        fn = getattr(L, name, None)
+        if fn is not None:
+            fn.argtypes = argtypes
+            fn.restype = I
+
+
+def check(rc: int) -> None:
+    if rc != SS_OK:
+        raise SearchSortedError(rc, lib().ss_last_error().decode(errors="replace"))
+
+
+def use_current_stream() -> None:
+    """Routes subsequent library calls to torch's current stream."""
+    lib().ss_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+
+
+def _need(t: torch.Tensor, dtype: torch.dtype, name: str) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.numel() and not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def set_option(opt: int, value: int) -> None:
+    check(lib().ss_set_option(opt, value))
+
+
+def get_option(opt: int) -> int:
+    v = ctypes.c_int64()
+    check(lib().ss_get_option(opt, ctypes.byref(v)))
+    return v.value
+
+
+def search_sorted_batch(table: torch.Tensor, targets: torch.Tensor,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+    """idx[k] = #{i : table[i] < targets[k]} - 1 (int32), on the GPU."""
+    _need(table, torch.float64, "table")
+    _need(targets, torch.float64, "targets")
+    if out is None:
+        out = torch.empty(targets.numel(), dtype=torch.int32, device=targets.device)
+    _need(out, torch.int32, "out")
+    if out.numel() != targets.numel():
+        raise ValueError("out must have one entry per target")
+    use_current_stream()
+    check(lib().search_sorted_batch(_ptr(table), table.numel(), _ptr(targets), targets.numel(),
+                                    _ptr(out)))
+    return out
+
+
+searchsorted_lt = search_sorted_batch
+
+
+def search_with(table: torch.Tensor, targets: torch.Tensor, algo, bucket_bits: int = -1,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """search_sorted_batch with an explicit kernel ("binary", "ballot", "exphash", ...)."""
+    if isinstance(algo, str):
+        algo = ALGO_IDS[algo]
+    _need(table, torch.float64, "table")
+    _need(targets, torch.float64, "targets")
+    if out is None:
+        out = torch.empty(targets.numel(), dtype=torch.int32, device=targets.device)
+    _need(out, torch.int32, "out")
+    if out.numel() != targets.numel():
+        raise ValueError("out must have one entry per target")
+    use_current_stream()
+    check(lib().ss_search_with(_ptr(table), table.numel(), _ptr(targets), targets.numel(),
+                               _ptr(out), int(algo), int(bucket_bits)))
+    return out
+
+
+def validate_table(table: torch.Tensor) -> int:
+    """-1 if sorted without NaN, else the first offending index (synchronous)."""
+    _need(table, torch.float64, "table")
+    bad = ctypes.c_int64()
+    use_current_stream()
+    check(lib().ss_validate_table(_ptr(table), table.numel(), ctypes.byref(bad)))
+    return bad.value
+
+
+def exphash_bins(table: torch.Tensor, bucket_bits: int = -1, cap: int = 1 << 16):
+    """Exponent-hash bin table as built on the device: (info dict, counts)."""
+    _need(table, torch.float64, "table")
+    counts = torch.full((cap,), -7, dtype=torch.int32, device=table.device)
+    info = (ctypes.c_int64 * 4)()
+    use_current_stream()
+    check(lib().ss_exphash_bins(_ptr(table), table.numel(), int(bucket_bits), _ptr(counts), cap,
+                                info))
+    s, kmin, nb, kmax_occ = (int(v) for v in info)
+    return {"bits": s, "kmin": kmin, "nb": nb, "max_occupancy": kmax_occ}, counts[:nb + 1]

@@ -1,0 +1,255 @@
+// Device building blocks of the sorted search (gfx950 / CDNA4, wave64).
+//
+// Every search routine here returns idx(x) = #{i : a[i] < x} - 1 for a table
+// a[0..n) that has been staged in LDS as `sa`, followed by SS_PAD copies of
+// +inf (so a read up to SS_PAD entries past the end is defined and never
+// counts).  Queries are processed Q at a time per lane (one query per lane
+// per slot, Q independent slots) so that LDS latency is hidden by ILP.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SS_PAD 8            // +inf sentinels after the staged table
+#define SS_SCAN_MAX SS_PAD  // longest fixed in-bin scan; longer bins bisect
+#define SS_MAX_BITS 20      // bin bits that fit in the high word of a double
+
+namespace ss {
+
+// High 32 bits of the IEEE-754 encoding, as a signed integer: sign bit,
+// 11-bit biased exponent, 20 leading fraction bits.
+__device__ __forceinline__ int hi_word(double v) { return __double2hiint(v); }
+
+// Exponent-hash key with s leading fraction bits (paper Sec. 3.5 for s = 0).
+// For v with a clear sign bit the key is non-decreasing in v; v with the
+// sign bit set (negative values, -0.0, -NaN) maps below every such key.
+__device__ __forceinline__ int hash_key(double v, int shift /* 20 - s */) {
+  return hi_word(v) >> shift;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// ---------------------------------------------------------------------------
+// Staging (a1): coalesced copy of the table into LDS plus +inf padding.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void stage_table(double* __restrict__ sa,
+                                            const double* __restrict__ table, int n) {
+  const int nt = blockDim.x;
+  for (int i = threadIdx.x; i < n + SS_PAD; i += nt)
+    sa[i] = i < n ? table[i] : __builtin_inf();
+}
+
+// ---------------------------------------------------------------------------
+// Exponent-hash bins (a2): parameters and the prefix-count table in LDS.
+//   key(v) = hi_word(v) >> (20 - s),  kmin = key(a[0]),  nb = key(a[n-1]) - kmin + 1
+//   C[b]   = #{ i : key(a[i]) - kmin < b },  b = 0..nb        (Eq. 3, prefix form)
+// ---------------------------------------------------------------------------
+struct HashParams {
+  int ok;      // 1 if the exponent hash applies to this table
+  int shift;   // 20 - s
+  int kmin;    // key of a[0]
+  int kmaxc;   // kmin + nb - 1 (upper clamp of target keys)
+  int nb;      // number of bins
+  int K;       // most entries in one bin (set by build_bins)
+};
+
+// Chooses s: the forced value if bits >= 0, else the largest s in [0, 20]
+// whose bin count fits `cap`.  Uniform across the workgroup (depends only on
+// a[0], a[n-1], bits and cap).  Not applicable when n == 0, when a[0] has its
+// sign bit set, when the keys are not ordered, or when no s fits.  `a` may
+// point to LDS or global memory.
+__device__ __forceinline__ HashParams choose_hash(const double* a, int n, int bits, int cap) {
+  HashParams hp{0, SS_MAX_BITS, 0, 0, 0, 0};
+  if (n < 1 || n > 65535) return hp;
+  const int h0 = __builtin_amdgcn_readfirstlane(hi_word(a[0]));
+  const int h1 = __builtin_amdgcn_readfirstlane(hi_word(a[n - 1]));
+  if (h0 < 0 || h1 < h0) return hp;
+  int s = bits >= 0 ? min(bits, SS_MAX_BITS) : SS_MAX_BITS;
+  for (;;) {
+    const int sh = SS_MAX_BITS - s;
+    const int nb = (h1 >> sh) - (h0 >> sh) + 1;
+    if (nb <= cap) {
+      hp.ok = 1;
+      hp.shift = __builtin_amdgcn_readfirstlane(sh);
+      hp.kmin = __builtin_amdgcn_readfirstlane(h0 >> sh);
+      hp.kmaxc = __builtin_amdgcn_readfirstlane(h1 >> sh);
+      hp.nb = __builtin_amdgcn_readfirstlane(nb);
+      return hp;
+    }
+    if (bits >= 0 || s == 0) return hp;
+    --s;
+  }
+}
+
+// Builds C[0..nb] in LDS by gap filling (each bin written by the table entry
+// that opens it; no atomics), then the largest bin occupancy K.  `scratch`
+// is one int of LDS.  Must be called by the whole workgroup.  For a table
+// that violates the sort precondition C stays within [0, n].
+template <typename CT>
+__device__ __forceinline__ void build_bins(const double* __restrict__ sa, int n, HashParams& hp,
+                                           CT* __restrict__ C, int* scratch) {
+  const int nt = blockDim.x, tid = threadIdx.x;
+  for (int b = tid; b <= hp.nb; b += nt) C[b] = 0;
+  if (tid == 0) *scratch = 0;
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) {
+    const int kb = clampi(hash_key(sa[i], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
+    const int kp =
+        i == 0 ? -1 : clampi(hash_key(sa[i - 1], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
+    for (int b = kp + 1; b <= kb; ++b) C[b] = (CT)i;
+  }
+  if (tid == 0) C[hp.nb] = (CT)n;
+  __syncthreads();
+  int mx = 0;
+  for (int b = tid; b < hp.nb; b += nt) mx = max(mx, (int)C[b + 1] - (int)C[b]);
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+  if ((tid & 63) == 0) atomicMax(scratch, mx);
+  __syncthreads();
+  hp.K = __builtin_amdgcn_readfirstlane(*scratch);
+}
+
+// ---------------------------------------------------------------------------
+// K1: branchless bisection (Sec. 3.2).  Fixed trip count ceil(log2 n) that
+// depends only on n, so the loop is wavefront-uniform; each step is one LDS
+// read, one compare and one select.  count = #{a < x}; NaN counts 0.
+// ---------------------------------------------------------------------------
+template <int Q>
+__device__ __forceinline__ void search_binary(const double* __restrict__ sa, int n,
+                                              const double (&x)[Q], int (&r)[Q]) {
+  int base[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) base[q] = 0;
+  int len = n;
+  while (len > 1) {
+    const int half = len >> 1;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) base[q] = (sa[base[q] + half] < x[q]) ? base[q] + half : base[q];
+    len -= half;
+  }
+  // n == 0: sa[0] is the +inf sentinel, so the count is 0.
+#pragma unroll
+  for (int q = 0; q < Q; ++q) r[q] = base[q] + (sa[base[q]] < x[q] ? 1 : 0) - 1;
+}
+
+// Global-memory variant for tables too large to stage (same arithmetic).
+template <int Q>
+__device__ __forceinline__ void search_binary_global(const double* __restrict__ a, int n,
+                                                     const double (&x)[Q], int (&r)[Q]) {
+  int base[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) base[q] = 0;
+  int len = n;
+  while (len > 1) {
+    const int half = len >> 1;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) base[q] = (a[base[q] + half] < x[q]) ? base[q] + half : base[q];
+    len -= half;
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+    r[q] = (n > 0 ? base[q] + (a[base[q]] < x[q] ? 1 : 0) : 0) - 1;
+}
+
+// ---------------------------------------------------------------------------
+// K3: exponent hash (Sec. 3.5).  Integer key from the high word, clamp to the
+// table's key range, C[b] gives the number of entries in earlier bins, then a
+// linear scan (Sec. 3.4's interior search) of the bin.  Entries after the bin
+// have larger keys, hence larger values, so a fixed-length scan of K entries
+// (K = largest bin) counts exactly the bin's entries below x.  Bins longer
+// than SS_SCAN_MAX are searched by bisection inside [C[b], C[b+1]).
+// NaN targets need the one select: their key lands in the last bin.
+// ---------------------------------------------------------------------------
+template <int Q>
+__device__ __forceinline__ void search_exphash(const double* __restrict__ sa,
+                                               const uint16_t* __restrict__ C,
+                                               const HashParams& hp, const double (&x)[Q],
+                                               int (&r)[Q]) {
+  int j0[Q], cnt[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int b = clampi(hash_key(x[q], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
+    j0[q] = C[b];
+    cnt[q] = 0;
+  }
+  if (hp.K <= SS_SCAN_MAX) {
+    for (int k = 0; k < hp.K; ++k) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cnt[q] += (sa[j0[q] + k] < x[q]) ? 1 : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) r[q] = (x[q] != x[q]) ? -1 : j0[q] + cnt[q] - 1;
+  } else {
+    // bisection inside the bin: largest pos in [lo, hi] with a[pos-1] < x
+    int hi[Q], pos[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int b = clampi(hash_key(x[q], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
+      hi[q] = C[b + 1];
+      pos[q] = j0[q];
+    }
+    int step = 1;
+    while (step * 2 <= hp.K) step *= 2;
+    for (; step >= 1; step >>= 1) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int cand = pos[q] + step;
+        const int ridx = max(min(cand, hi[q]) - 1, 0);
+        const bool take = (cand <= hi[q]) && (sa[ridx] < x[q]);
+        pos[q] = take ? cand : pos[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) r[q] = (x[q] != x[q]) ? -1 : pos[q] - 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K2: linear scan (Sec. 2.1) restricted to the wavefront's bracket.  The
+// smallest and largest target of the wavefront (NaN ignored) bound every
+// lane's answer; their counts come from ballots over the table held 64
+// entries per step, one per lane.  Each lane then scans only [lo, hi).
+// Cheap when a wavefront's targets are close together (sorted streams),
+// a full scan when they are spread over the table.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+template <int Q>
+__device__ __forceinline__ void search_ballot(const double* __restrict__ sa, int n,
+                                              const double (&x)[Q], int (&r)[Q]) {
+  const int lane = threadIdx.x & 63;
+  double lmin = x[0], lmax = x[0];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) {
+    lmin = fmin(lmin, x[q]);
+    lmax = fmax(lmax, x[q]);
+  }
+  const double wmin = wave_min(lmin);
+  const double wmax = wave_max(lmax);
+  int lo = 0, hi = 0;
+  for (int c = 0; c < n; c += 64) {
+    const double e = sa[min(c + lane, n)];  // index n is the +inf sentinel
+    lo += __popcll(__ballot(e < wmin));
+    hi += __popcll(__ballot(e < wmax));
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  hi = __builtin_amdgcn_readfirstlane(hi);
+  int cnt[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) cnt[q] = 0;
+  for (int j = lo; j < hi; ++j) {
+    const double aj = sa[j];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) cnt[q] += (aj < x[q]) ? 1 : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) r[q] = (x[q] != x[q]) ? -1 : lo + cnt[q] - 1;
+}
+
+}  // namespace ss

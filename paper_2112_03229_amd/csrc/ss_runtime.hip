@@ -1,0 +1,200 @@
+// Library runtime: error state, stream selection, options, device queries
+// and argument checks behind the C ABI.
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "ss_host.h"
+
+namespace ss {
+
+namespace {
+thread_local std::string t_last_error;
+thread_local hipStream_t t_stream = nullptr;
+
+std::atomic<int64_t> g_force_algo{SS_ALGO_AUTO};
+std::atomic<int64_t> g_bucket_bits{-1};
+std::atomic<int64_t> g_bucket_cap{0};
+std::atomic<int64_t> g_block_size{0};
+std::atomic<int64_t> g_grid_blocks{0};
+std::atomic<int64_t> g_check_pointers{1};
+
+std::mutex g_dev_mu;
+std::map<int, DeviceInfo> g_dev_cache;
+std::map<std::tuple<const void*, int, size_t, int>, int> g_occ_cache;
+}  // namespace
+
+int fail(int code, const std::string& msg) {
+  t_last_error = msg;
+  return code;
+}
+
+void clear_error() { t_last_error.clear(); }
+
+int hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();  // do not leave the error for an unrelated call
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(SS_ERR_OOM, msg);
+  if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return fail(SS_ERR_NO_DEVICE, msg);
+  return fail(SS_ERR_HIP, msg);
+}
+
+hipStream_t current_stream() { return t_stream; }
+
+int64_t option(int opt) {
+  switch (opt) {
+    case SS_OPT_FORCE_ALGO: return g_force_algo.load();
+    case SS_OPT_BUCKET_BITS: return g_bucket_bits.load();
+    case SS_OPT_BUCKET_CAP: return g_bucket_cap.load();
+    case SS_OPT_BLOCK_SIZE: return g_block_size.load();
+    case SS_OPT_GRID_BLOCKS: return g_grid_blocks.load();
+    case SS_OPT_CHECK_POINTERS: return g_check_pointers.load();
+    default: return 0;
+  }
+}
+
+int device_info(DeviceInfo* out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev_cache.find(dev);
+    if (it != g_dev_cache.end()) {
+      *out = it->second;
+      return SS_OK;
+    }
+  }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  DeviceInfo d;
+  d.device = dev;
+  d.num_cus = prop.multiProcessorCount;
+  d.lds_per_block = prop.sharedMemPerBlock;
+  snprintf(d.arch, sizeof(d.arch), "%s", prop.gcnArchName);
+  d.arch_ok = std::string(prop.gcnArchName).rfind("gfx950", 0) == 0;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  g_dev_cache[dev] = d;
+  *out = d;
+  return SS_OK;
+}
+
+int check_span(const void* p, int64_t count, size_t elem, size_t align, const char* name) {
+  if (count < 0) return fail(SS_ERR_INVALID_ARG, std::string(name) + ": negative size");
+  if (count == 0) return SS_OK;
+  if (p == nullptr) return fail(SS_ERR_INVALID_ARG, std::string(name) + ": null pointer");
+  if (reinterpret_cast<uintptr_t>(p) % align != 0)
+    return fail(SS_ERR_INVALID_ARG, std::string(name) + ": misaligned pointer");
+  if ((uint64_t)count > (uint64_t)INT64_MAX / elem)
+    return fail(SS_ERR_INVALID_ARG, std::string(name) + ": size overflow");
+  return SS_OK;
+}
+
+int check_device_ptr(const void* p, const char* name) {
+  if (p == nullptr || !g_check_pointers.load()) return SS_OK;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SS_ERR_NOT_DEVICE_PTR, std::string(name) + ": not a device pointer");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(SS_ERR_NOT_DEVICE_PTR, std::string(name) + ": not device memory");
+  return SS_OK;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  if (!a || !b || abytes == 0 || bbytes == 0) return false;
+  uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+int blocks_per_cu(const void* kernel, int threads, size_t lds) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto key = std::make_tuple(kernel, threads, lds, dev);
+  {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_occ_cache.find(key);
+    if (it != g_occ_cache.end()) return it->second;
+  }
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, threads, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    blocks = 1;
+  }
+  if (blocks < 1) blocks = 1;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  g_occ_cache[key] = blocks;
+  return blocks;
+}
+
+}  // namespace ss
+
+extern "C" {
+
+const char* ss_last_error(void) { return ss::t_last_error.c_str(); }
+
+int ss_version(void) { return 100; }
+
+int ss_set_stream(void* hip_stream) {
+  ss::t_stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return SS_OK;
+}
+
+int ss_set_option(int opt, int64_t v) {
+  switch (opt) {
+    case SS_OPT_FORCE_ALGO:
+      if (v < SS_ALGO_AUTO || v > SS_ALGO_BINARY_GLOBAL)
+        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_FORCE_ALGO: unknown algorithm");
+      ss::g_force_algo = v;
+      return SS_OK;
+    case SS_OPT_BUCKET_BITS:
+      if (v < -1 || v > 20)
+        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_BUCKET_BITS: expected -1..20");
+      ss::g_bucket_bits = v;
+      return SS_OK;
+    case SS_OPT_BUCKET_CAP:
+      if (v < 0 || v > 65535)
+        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_BUCKET_CAP: expected 0..65535");
+      ss::g_bucket_cap = v;
+      return SS_OK;
+    case SS_OPT_BLOCK_SIZE:
+      if (v != 0 && v != 256 && v != 512 && v != 1024)
+        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_BLOCK_SIZE: expected 0, 256, 512 or 1024");
+      ss::g_block_size = v;
+      return SS_OK;
+    case SS_OPT_GRID_BLOCKS:
+      if (v < 0 || v > (1 << 20))
+        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_GRID_BLOCKS: expected 0..2^20");
+      ss::g_grid_blocks = v;
+      return SS_OK;
+    case SS_OPT_CHECK_POINTERS:
+      if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_CHECK_POINTERS: 0 or 1");
+      ss::g_check_pointers = v;
+      return SS_OK;
+    default:
+      return ss::fail(SS_ERR_INVALID_ARG, "unknown option");
+  }
+}
+
+int ss_get_option(int opt, int64_t* value_out) {
+  if (!value_out) return ss::fail(SS_ERR_INVALID_ARG, "value_out is null");
+  switch (opt) {
+    case SS_OPT_FORCE_ALGO:
+    case SS_OPT_BUCKET_BITS:
+    case SS_OPT_BUCKET_CAP:
+    case SS_OPT_BLOCK_SIZE:
+    case SS_OPT_GRID_BLOCKS:
+    case SS_OPT_CHECK_POINTERS:
+      *value_out = ss::option(opt);
+      return SS_OK;
+    default:
+      return ss::fail(SS_ERR_INVALID_ARG, "unknown option");
+  }
+}
+
+}  // extern "C"

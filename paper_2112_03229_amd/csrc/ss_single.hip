@@ -1,0 +1,336 @@
+// Single-table search: kernels K1 (bisection), K2 (ballot-bracketed linear
+// scan), K3 (exponent hash) and the global-memory bisection, plus the C ABI
+// entry points search_sorted_batch, ss_search_with, ss_validate_table and
+// ss_exphash_bins.
+//
+// Launch shape: a persistent grid (enough workgroups to fill every CU at the
+// occupancy the LDS footprint allows).  Each workgroup stages the table once
+// (K3 also builds its bin table in LDS) and then streams tiles of
+// blockDim.x * Q targets: slot q of lane t reads target base + q*blockDim.x + t,
+// so every load and store instruction of a wavefront covers one contiguous
+// run (512 B of targets, 256 B of indices).  Targets are read and indices
+// written with non-temporal hints: each byte is touched once.
+#include <algorithm>
+#include <string>
+
+#include "ss_device.h"
+#include "ss_host.h"
+
+namespace ss {
+
+constexpr int kQ = 8;                 // targets per lane per tile
+constexpr int kDefaultBlock = 256;    // threads per workgroup
+constexpr size_t kStageLimit = 65536; // LDS bytes a single-table launch may use
+
+struct SingleArgs {
+  const double* table;
+  const double* x;
+  int32_t* out;
+  int64_t m;
+  int n;
+  int bits;     // exponent-hash bits, -1 = automatic
+  int cap;      // exponent-hash bin cap
+  int c_off;    // byte offset of the bin table in LDS
+  int scr_off;  // byte offset of one int of LDS scratch
+};
+
+// Streams the tiles assigned to this workgroup through `search`.
+template <int Q, typename Search>
+__device__ __forceinline__ void stream_tiles(const double* __restrict__ x, int64_t m,
+                                             int32_t* __restrict__ out, Search&& search) {
+  const int nt = blockDim.x;
+  const int64_t per_tile = (int64_t)nt * Q;
+  const int64_t ntiles = (m + per_tile - 1) / per_tile;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t base = t * per_tile + threadIdx.x;
+    double xv[Q];
+    int r[Q];
+    if ((t + 1) * per_tile <= m) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) xv[q] = __builtin_nontemporal_load(x + base + (int64_t)q * nt);
+      search(xv, r);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(r[q], out + base + (int64_t)q * nt);
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int64_t k = base + (int64_t)q * nt;
+        xv[q] = k < m ? x[k] : __builtin_nan("");
+      }
+      search(xv, r);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int64_t k = base + (int64_t)q * nt;
+        if (k < m) out[k] = r[q];
+      }
+    }
+  }
+}
+
+template <int ALGO, int Q>
+__global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  if constexpr (ALGO == SS_ALGO_BINARY_GLOBAL) {
+    const double* __restrict__ tab = a.table;
+    const int n = a.n;
+    stream_tiles<Q>(a.x, a.m, a.out, [&](const double(&xv)[Q], int(&r)[Q]) {
+      search_binary_global<Q>(tab, n, xv, r);
+    });
+    return;
+  } else {
+    double* sa = reinterpret_cast<double*>(lds);
+    const int n = a.n;
+    stage_table(sa, a.table, n);
+    __syncthreads();
+    if constexpr (ALGO == SS_ALGO_EXPHASH) {
+      uint16_t* C = reinterpret_cast<uint16_t*>(lds + a.c_off);
+      int* scratch = reinterpret_cast<int*>(lds + a.scr_off);
+      HashParams hp = choose_hash(sa, n, a.bits, a.cap);
+      if (hp.ok) {
+        build_bins(sa, n, hp, C, scratch);
+        stream_tiles<Q>(a.x, a.m, a.out, [&](const double(&xv)[Q], int(&r)[Q]) {
+          search_exphash<Q>(sa, C, hp, xv, r);
+        });
+        return;
+      }
+      // not applicable (negative entries, unordered keys): bisection below
+    }
+    if constexpr (ALGO == SS_ALGO_BALLOT) {
+      stream_tiles<Q>(a.x, a.m, a.out, [&](const double(&xv)[Q], int(&r)[Q]) {
+        search_ballot<Q>(sa, n, xv, r);
+      });
+      return;
+    }
+    stream_tiles<Q>(a.x, a.m, a.out, [&](const double(&xv)[Q], int(&r)[Q]) {
+      search_binary<Q>(sa, n, xv, r);
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+static int auto_cap(int64_t n) {
+  int64_t c = 64;
+  while (c < 4 * n && c < 16384) c <<= 1;
+  return (int)c;
+}
+
+struct SinglePlan {
+  int algo;
+  int cap;
+  size_t lds;
+  int c_off, scr_off;
+};
+
+// Chooses the kernel and its LDS layout.  Returns SS_OK or an error for a
+// forced kernel that cannot run on this table size.
+static int plan_single(int64_t n, int algo, int cap_opt, SinglePlan* p) {
+  const size_t tab_bytes = align_up((size_t)(n + SS_PAD) * sizeof(double), 16);
+  const bool stageable = tab_bytes <= kStageLimit;
+  if (algo == SS_ALGO_AUTO) {
+    if (n >= 1 && n <= 65535 && stageable) algo = SS_ALGO_EXPHASH;
+    else algo = stageable ? SS_ALGO_BINARY : SS_ALGO_BINARY_GLOBAL;
+  }
+  // an empty table is answered by the staged bisection (its +inf sentinel
+  // makes every count 0) so that no kernel reads a zero-length table
+  if (n == 0) algo = SS_ALGO_BINARY;
+  p->algo = algo;
+  p->cap = 0;
+  p->c_off = p->scr_off = 0;
+  if (algo == SS_ALGO_BINARY_GLOBAL) {
+    p->lds = 0;
+    return SS_OK;
+  }
+  if (!stageable)
+    return fail(SS_ERR_UNSUPPORTED, "table too large to stage in LDS for the forced kernel");
+  p->lds = tab_bytes;
+  if (algo == SS_ALGO_EXPHASH) {
+    int cap = cap_opt > 0 ? cap_opt : auto_cap(n);
+    // shrink the bin cap until table + bins + scratch fit
+    while (cap > 16 && tab_bytes + align_up((size_t)(cap + 1) * 2, 16) + 16 > kStageLimit) cap >>= 1;
+    p->cap = cap;
+    p->c_off = (int)tab_bytes;
+    p->scr_off = (int)(tab_bytes + align_up((size_t)(cap + 1) * 2, 16));
+    p->lds = (size_t)p->scr_off + 16;
+    if (p->lds > kStageLimit) {
+      p->algo = SS_ALGO_BINARY;
+      p->lds = tab_bytes;
+    }
+  }
+  return SS_OK;
+}
+
+template <int Q>
+static const void* single_kernel_ptr(int algo) {
+  switch (algo) {
+    case SS_ALGO_BINARY: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BINARY, Q>);
+    case SS_ALGO_BALLOT: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BALLOT, Q>);
+    case SS_ALGO_EXPHASH: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_EXPHASH, Q>);
+    case SS_ALGO_BINARY_GLOBAL:
+      return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BINARY_GLOBAL, Q>);
+    default: return nullptr;
+  }
+}
+
+static int check_single_args(const double* table, int64_t n, const double* x, int64_t m,
+                             const int32_t* out) {
+  if (n < 0 || m < 0) return fail(SS_ERR_INVALID_ARG, "negative size");
+  if (n > INT32_MAX) return fail(SS_ERR_INVALID_ARG, "n exceeds INT32_MAX");
+  if (m == 0) return SS_OK;
+  int rc;
+  if ((rc = check_span(table, n, sizeof(double), alignof(double), "table")) != SS_OK) return rc;
+  if ((rc = check_span(x, m, sizeof(double), alignof(double), "targets")) != SS_OK) return rc;
+  if ((rc = check_span(out, m, sizeof(int32_t), alignof(int32_t), "out_idx")) != SS_OK) return rc;
+  if (overlaps(out, (size_t)m * 4, x, (size_t)m * 8) ||
+      overlaps(out, (size_t)m * 4, table, (size_t)n * 8))
+    return fail(SS_ERR_INVALID_ARG, "out_idx overlaps an input");
+  if (n > 0 && (rc = check_device_ptr(table, "table")) != SS_OK) return rc;
+  if ((rc = check_device_ptr(x, "targets")) != SS_OK) return rc;
+  if ((rc = check_device_ptr(out, "out_idx")) != SS_OK) return rc;
+  return SS_OK;
+}
+
+int launch_single(const double* table, int64_t n, const double* x, int64_t m, int32_t* out,
+                  int algo, int bits) {
+  if (algo < SS_ALGO_AUTO || algo > SS_ALGO_BINARY_GLOBAL)
+    return fail(SS_ERR_INVALID_ARG, "unknown algorithm");
+  if (bits < -1 || bits > SS_MAX_BITS) return fail(SS_ERR_INVALID_ARG, "bucket_bits: -1..20");
+  int rc = check_single_args(table, n, x, m, out);
+  if (rc != SS_OK || m == 0) return rc;
+  DeviceInfo di;
+  if ((rc = device_info(&di)) != SS_OK) return rc;
+  SinglePlan p;
+  if ((rc = plan_single(n, algo, (int)option(SS_OPT_BUCKET_CAP), &p)) != SS_OK) return rc;
+  int nt = (int)option(SS_OPT_BLOCK_SIZE);
+  if (nt == 0) nt = kDefaultBlock;
+  const void* kern = single_kernel_ptr<kQ>(p.algo);
+  const int64_t per_tile = (int64_t)nt * kQ;
+  const int64_t ntiles = (m + per_tile - 1) / per_tile;
+  int64_t grid = option(SS_OPT_GRID_BLOCKS);
+  if (grid <= 0) grid = (int64_t)blocks_per_cu(kern, nt, p.lds) * di.num_cus;
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
+  SingleArgs a{table, x, out, m, (int)n, bits, p.cap, p.c_off, p.scr_off};
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel(kern, dim3((unsigned)grid), dim3(nt), args, p.lds,
+                                 current_stream());
+  if (e != hipSuccess) return hip_fail(e, "hipLaunchKernel(single)");
+  return SS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Table validation: smallest i with a[i] NaN or a[i] > a[i+1].
+
+__global__ void validate_kernel(const double* __restrict__ a, int64_t n,
+                                unsigned long long* __restrict__ bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = a[i];
+    const bool broken = (v != v) || (i + 1 < n && v > a[i + 1]);
+    if (broken) atomicMin(bad, (unsigned long long)i);
+  }
+}
+
+// Bin table of one table into global memory (one workgroup).  info receives
+// {s, kmin, nb, K} or s = -1 if the exponent hash does not apply.
+__global__ __launch_bounds__(1024) void bins_kernel(const double* __restrict__ a, int n, int bits,
+                                                    int cap, int32_t* __restrict__ counts,
+                                                    int64_t* __restrict__ info) {
+  __shared__ int scratch;
+  HashParams hp = choose_hash(a, n, bits, cap);
+  if (!hp.ok) {
+    if (threadIdx.x == 0) info[0] = -1;
+    return;
+  }
+  build_bins(a, n, hp, counts, &scratch);
+  if (threadIdx.x == 0) {
+    info[0] = SS_MAX_BITS - hp.shift;
+    info[1] = hp.kmin;
+    info[2] = hp.nb;
+    info[3] = hp.K;
+  }
+}
+
+}  // namespace ss
+
+extern "C" {
+
+int search_sorted_batch(const double* table, int64_t n, const double* targets, int64_t m,
+                        int32_t* out_idx) {
+  ss::clear_error();
+  return ss::launch_single(table, n, targets, m, out_idx,
+                           (int)ss::option(SS_OPT_FORCE_ALGO),
+                           (int)ss::option(SS_OPT_BUCKET_BITS));
+}
+
+int ss_search_with(const double* table, int64_t n, const double* targets, int64_t m,
+                   int32_t* out_idx, int algo, int bucket_bits) {
+  ss::clear_error();
+  return ss::launch_single(table, n, targets, m, out_idx, algo, bucket_bits);
+}
+
+int ss_validate_table(const double* table, int64_t n, int64_t* bad_index_out) {
+  ss::clear_error();
+  if (!bad_index_out) return ss::fail(SS_ERR_INVALID_ARG, "bad_index_out is null");
+  if (n < 0 || n > INT32_MAX) return ss::fail(SS_ERR_INVALID_ARG, "n out of range");
+  int rc = ss::check_span(table, n, sizeof(double), alignof(double), "table");
+  if (rc != SS_OK) return rc;
+  *bad_index_out = -1;
+  if (n == 0) return SS_OK;
+  if ((rc = ss::check_device_ptr(table, "table")) != SS_OK) return rc;
+  unsigned long long* d_bad = nullptr;
+  SS_TRY_HIP(hipMalloc(&d_bad, sizeof(unsigned long long)));
+  const unsigned long long init = ~0ULL;
+  hipStream_t st = ss::current_stream();
+  unsigned long long host_bad = init;
+  hipError_t e = hipMemcpyAsync(d_bad, &init, sizeof(init), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(ss::validate_kernel, dim3((unsigned)blocks), dim3(256), 0, st, table, n,
+                       d_bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&host_bad, d_bad, sizeof(host_bad), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_bad);
+  if (e != hipSuccess) return ss::hip_fail(e, "ss_validate_table");
+  *bad_index_out = host_bad == init ? -1 : (int64_t)host_bad;
+  return SS_OK;
+}
+
+int ss_exphash_bins(const double* table, int64_t n, int bucket_bits, int32_t* counts,
+                    int64_t cap, int64_t* info_out) {
+  ss::clear_error();
+  if (!info_out) return ss::fail(SS_ERR_INVALID_ARG, "info_out is null");
+  if (n < 1 || n > 65535) return ss::fail(SS_ERR_INVALID_ARG, "n must be in 1..65535");
+  if (bucket_bits < -1 || bucket_bits > SS_MAX_BITS)
+    return ss::fail(SS_ERR_INVALID_ARG, "bucket_bits: -1..20");
+  if (cap < 2 || cap > (1 << 24)) return ss::fail(SS_ERR_INVALID_ARG, "cap must be in 2..2^24");
+  int rc = ss::check_span(table, n, sizeof(double), alignof(double), "table");
+  if (rc == SS_OK) rc = ss::check_span(counts, cap, sizeof(int32_t), alignof(int32_t), "counts");
+  if (rc != SS_OK) return rc;
+  if ((rc = ss::check_device_ptr(table, "table")) != SS_OK) return rc;
+  if ((rc = ss::check_device_ptr(counts, "counts")) != SS_OK) return rc;
+  int64_t* d_info = nullptr;
+  SS_TRY_HIP(hipMalloc(&d_info, 4 * sizeof(int64_t)));
+  hipStream_t st = ss::current_stream();
+  int64_t h_info[4] = {-1, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(d_info, h_info, sizeof(h_info), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(ss::bins_kernel, dim3(1), dim3(1024), 0, st, table, (int)n, bucket_bits,
+                       (int)(cap - 1), counts, d_info);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h_info, d_info, sizeof(h_info), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_info);
+  if (e != hipSuccess) return ss::hip_fail(e, "ss_exphash_bins");
+  if (h_info[0] < 0)
+    return ss::fail(SS_ERR_INVALID_ARG,
+                    "exponent hash not applicable (sign bit of a[0], unordered keys or cap)");
+  for (int i = 0; i < 4; ++i) info_out[i] = h_info[i];
+  return SS_OK;
+}
+
+}  // extern "C"

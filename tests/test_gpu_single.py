@@ -1,0 +1,272 @@
+"""GPU parity of the single-table kernels against the CPU oracle (bit-exact).
+
+Every case compares int32 indices element by element with
+``oracle.search_lt`` on the same host bytes, or, at full workload sizes,
+checks every index with the bracket property and a seeded sample with the
+oracle's definition.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+ALGOS = ["auto", "binary", "ballot", "exphash", "binary_global"]
+TILE = 256 * 8           # targets per workgroup tile at the default launch shape
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run(binding, dev, table, x, algo="auto", bits=-1):
+    t = torch.from_numpy(np.ascontiguousarray(table)).to(dev)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    out = binding.search_with(t, xt, algo, bits)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def mixed_targets(inputs_mod, table, m, seed):
+    """Random log-uniform targets with exact hits, neighbours and specials."""
+    x = inputs_mod.table_targets(table, m, seed=seed)
+    n = table.shape[0]
+    if n:
+        k = np.arange(0, m, 7)
+        x[k] = table[k % n]
+        k = np.arange(3, m, 11)
+        x[k] = np.nextafter(table[k % n], np.inf)
+        k = np.arange(5, m, 13)
+        x[k] = np.nextafter(table[k % n], -np.inf)
+    sp = inputs_mod.special_values()
+    x[1:1 + sp.shape[0]] = sp
+    return x
+
+
+@pytest.fixture(scope="module")
+def binding(gpu):
+    from paper_2112_03229_amd import binding as b
+    return b
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 63, 64, 65, 100, 110, 300, 1000, 2000, 4000])
+def test_parity_across_sizes(binding, gpu, oracle_mod, inputs_mod, n):
+    table = inputs_mod.single_table(n) if n >= 2 else np.array([1.0])
+    m = 20 * TILE + 77
+    x = mixed_targets(inputs_mod, table, m, seed=n)
+    want = oracle_mod.search_lt(table, x)
+    for algo in ALGOS:
+        say(f"case n={n} m={m} algo={algo}")
+        got = run(binding, gpu, table, x, algo)
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, (algo, n, bad[:5], got[bad[:5]], want[bad[:5]], x[bad[:5]])
+
+
+@pytest.mark.parametrize("kind", ["random", "smooth"])
+def test_parity_smooth_and_random(binding, gpu, oracle_mod, inputs_mod, kind):
+    table = inputs_mod.single_table(300)
+    m = 64 * TILE + 5
+    x = inputs_mod.table_targets(table, m, seed=2, kind=kind)
+    want = oracle_mod.search_lt(table, x)
+    for algo in ALGOS:
+        say(f"case kind={kind} algo={algo}")
+        assert np.array_equal(run(binding, gpu, table, x, algo), want), algo
+
+
+def edge_tables():
+    return {
+        "zeros_denormals": np.array([0.0, 0.0, 5e-324, 1e-320, 1e-310, 2.2250738585072014e-308,
+                                     1e-300, 1.0, 1.0, 1.0, 2.0, 1e300]),
+        "duplicates": np.repeat(np.array([1e-3, 1.0, 7.0, 1e5]), [5, 17, 1, 30]),
+        "all_equal": np.full(50, 3.25),
+        "with_negatives": np.array([-1e10, -5.0, -1.0, -0.0, 0.0, 1e-5, 3.0, 1e20]),
+        "negative_zero_first": np.array([-0.0, 0.0, 1.0, 2.0]),
+        "with_inf": np.array([1e-3, 1.0, 10.0, np.inf]),
+        "single_zero": np.array([0.0]),
+        "huge_range": np.array([5e-324, 1e-200, 1e-100, 1.0, 1e100, 1e200, 1.7976931348623157e308]),
+        "narrow": 1.0 + np.arange(200) * 2.0 ** -40,
+    }
+
+
+@pytest.mark.parametrize("name", list(edge_tables().keys()))
+def test_edge_tables(binding, gpu, oracle_mod, inputs_mod, name):
+    table = edge_tables()[name].astype(np.float64)
+    assert np.all(table[:-1] <= table[1:])
+    m = 3 * TILE + 19
+    x = inputs_mod.log_uniform(17, 4, 1e-320, 1e305, m)
+    x[::3] *= -1.0
+    x[:table.shape[0]] = table
+    x[table.shape[0]:2 * table.shape[0]] = np.nextafter(table, np.inf)
+    sp = inputs_mod.special_values()
+    x[-sp.shape[0]:] = sp
+    want = oracle_mod.search_lt(table, x)
+    for algo in ALGOS:
+        say(f"case table={name} algo={algo}")
+        got = run(binding, gpu, table, x, algo)
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, (algo, name, bad[:5], got[bad[:5]], want[bad[:5]], x[bad[:5]])
+
+
+def test_empty_table_and_tiny_m(binding, gpu, oracle_mod, inputs_mod):
+    empty = np.zeros(0)
+    x = inputs_mod.log_uniform(1, 1, 1e-3, 1e3, 1000)
+    for algo in ALGOS:
+        say(f"case n=0 algo={algo}")
+        assert np.all(run(binding, gpu, empty, x, algo) == -1)
+    table = inputs_mod.single_table(100)
+    for m in (1, 2, 63, 64, 65, 255, 256, 257, TILE - 1, TILE, TILE + 1):
+        xm = inputs_mod.table_targets(table, m, seed=m)
+        want = oracle_mod.search_lt(table, xm)
+        for algo in ALGOS:
+            assert np.array_equal(run(binding, gpu, table, xm, algo), want), (m, algo)
+    # m == 0 is a no-op
+    t = torch.from_numpy(table).to(gpu)
+    out = binding.search_sorted_batch(t, torch.zeros(0, dtype=torch.float64, device=gpu))
+    assert out.numel() == 0
+
+
+def test_unaligned_views(binding, gpu, oracle_mod, inputs_mod):
+    table = inputs_mod.single_table(1000)
+    x = inputs_mod.table_targets(table, 5 * TILE + 3, seed=4)
+    t = torch.from_numpy(table).to(gpu)
+    xt = torch.from_numpy(x).to(gpu)
+    for off in (1, 3):
+        out = torch.full((xt.numel() - off + 1,), -9, dtype=torch.int32, device=gpu)
+        binding.search_sorted_batch(t[1:], xt[off:], out[1:])
+        torch.cuda.synchronize()
+        want = oracle_mod.search_lt(table[1:], x[off:])
+        got = out.cpu().numpy()
+        assert got[0] == -9 and np.array_equal(got[1:], want)
+
+
+@pytest.mark.parametrize("bits", list(range(0, 9)) + [12, 20])
+def test_exphash_bucket_bits(binding, gpu, oracle_mod, inputs_mod, bits):
+    table = inputs_mod.single_table(1000)
+    x = mixed_targets(inputs_mod, table, 9 * TILE + 1, seed=bits)
+    want = oracle_mod.search_lt(table, x)
+    say(f"case bits={bits}")
+    assert np.array_equal(run(binding, gpu, table, x, "exphash", bits), want)
+
+
+def test_exphash_small_caps_force_bin_bisection(binding, gpu, oracle_mod, inputs_mod):
+    table = inputs_mod.single_table(2000)
+    x = mixed_targets(inputs_mod, table, 9 * TILE + 1, seed=3)
+    want = oracle_mod.search_lt(table, x)
+    try:
+        for cap in (16, 64, 256):
+            say(f"case cap={cap}")
+            binding.set_option(binding.OPT_BUCKET_CAP, cap)
+            assert np.array_equal(run(binding, gpu, table, x, "exphash"), want), cap
+    finally:
+        binding.set_option(binding.OPT_BUCKET_CAP, 0)
+
+
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_launch_shapes(binding, gpu, oracle_mod, inputs_mod, block):
+    table = inputs_mod.single_table(300)
+    x = mixed_targets(inputs_mod, table, 40 * 1024 + 9, seed=block)
+    want = oracle_mod.search_lt(table, x)
+    try:
+        binding.set_option(binding.OPT_BLOCK_SIZE, block)
+        for grid in (0, 1, 7):
+            binding.set_option(binding.OPT_GRID_BLOCKS, grid)
+            for algo in ALGOS:
+                say(f"case block={block} grid={grid} algo={algo}")
+                assert np.array_equal(run(binding, gpu, table, x, algo), want)
+    finally:
+        binding.set_option(binding.OPT_BLOCK_SIZE, 0)
+        binding.set_option(binding.OPT_GRID_BLOCKS, 0)
+
+
+@pytest.mark.parametrize("s", [0, 3, 5, 8])
+@pytest.mark.parametrize("n", [64, 110, 1000, 4000])
+def test_exphash_bins_match_oracle(binding, gpu, oracle_mod, inputs_mod, n, s):
+    table = inputs_mod.paper_shape_table() if n == 110 else inputs_mod.single_table(n)
+    kmin, C = oracle_mod.exponent_bins(table, s)
+    info, counts = binding.exphash_bins(torch.from_numpy(table).to(gpu), s, cap=1 << 16)
+    assert info["bits"] == s and info["kmin"] == kmin and info["nb"] == C.shape[0] - 1
+    assert np.array_equal(counts.cpu().numpy().astype(np.int64), C)
+    assert info["max_occupancy"] == int(np.diff(C).max())
+
+
+def test_validate_table(binding, gpu, inputs_mod):
+    table = inputs_mod.single_table(1000)
+    t = torch.from_numpy(table).to(gpu)
+    assert binding.validate_table(t) == -1
+    bad = table.copy()
+    bad[700], bad[701] = bad[701], bad[700]
+    assert binding.validate_table(torch.from_numpy(bad).to(gpu)) == 700
+    nan = table.copy()
+    nan[33] = np.nan
+    assert binding.validate_table(torch.from_numpy(nan).to(gpu)) in (32, 33)
+
+
+def test_unsorted_table_stays_in_bounds(binding, gpu, inputs_mod):
+    # precondition violated: results are unspecified but must lie in [-1, n-1]
+    rng_tab = inputs_mod.log_uniform(5, 1, 1e-8, 1e6, 500)
+    x = inputs_mod.log_uniform(6, 1, 1e-9, 1e7, 4 * TILE + 3)
+    for algo in ALGOS:
+        got = run(binding, gpu, rng_tab, x, algo)
+        assert got.min() >= -1 and got.max() <= 499, algo
+
+
+def test_non_default_stream_and_graph_replay(binding, gpu, oracle_mod, inputs_mod):
+    table = inputs_mod.single_table(1000)
+    x = inputs_mod.table_targets(table, 50 * TILE + 11, seed=8)
+    want = oracle_mod.search_lt(table, x)
+    t = torch.from_numpy(table).to(gpu)
+    xt = torch.from_numpy(x).to(gpu)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = binding.search_sorted_batch(t, xt)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    # capture one call in a graph and replay it, with eager work in between
+    out2 = torch.full_like(out, -5)
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    with torch.cuda.stream(cs):
+        binding.search_sorted_batch(t, xt, out2)  # warm-up outside capture
+    cs.synchronize()
+    out2.fill_(-5)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=cs):
+        binding.search_sorted_batch(t, xt, out2)
+    for r in range(3):
+        out2.fill_(-5)
+        _ = (xt * 2.0).sum()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out2.cpu().numpy(), want), r
+
+
+@pytest.mark.parametrize("n", [100, 300, 1000])
+def test_full_size_single_tables(binding, gpu, oracle_mod, inputs_mod, n):
+    """1e8 targets per table and order, in the benchmark's launch shape:
+    every index passes the bracket check; a seeded sample equals the
+    oracle's definition."""
+    table = inputs_mod.single_table(n)
+    m = 10**8
+    t = torch.from_numpy(table).to(gpu)
+    host = torch.empty(m, dtype=torch.float64).pin_memory()
+    for kind in ("random", "smooth"):
+        say(f"case full n={n} kind={kind}")
+        inputs_mod.table_targets(table, m, seed=7, kind=kind, out=host.numpy())
+        xt = host.to(gpu, non_blocking=True)
+        out = binding.search_sorted_batch(t, xt)
+        got = out.cpu().numpy()
+        x = host.numpy()
+        bad, first = oracle_mod.check_bracket(table, x, got)
+        assert bad == 0, (kind, first)
+        pos = (inputs_mod.uniform(n, 99, 200000) * m).astype(np.int64)
+        assert np.array_equal(got[pos], oracle_mod.search_lt_at(table, x, pos))
+        del xt, out
+
+
+def test_full_size_single64(binding, gpu, oracle_mod, inputs_mod):
+    table = inputs_mod.single64_table()
+    x = inputs_mod.table_targets(table, 10**6, seed=64)
+    want = oracle_mod.search_lt(table, x)
+    for algo in ALGOS:
+        say(f"case single64 algo={algo}")
+        assert np.array_equal(run(binding, gpu, table, x, algo), want), algo
