@@ -1,0 +1,275 @@
+"""Benchmark of the batched sorted search on one MI355X.
+
+Workload (one "step"): three single tables of 100, 300 and 1000 float64
+entries (sorted log-uniform draws on [1e-8, 1e6]), each searched with 1e8
+float64 targets in two orders -- i.i.d. log-uniform on [0.5e-8, 2e6] and a
+smooth sorted random walk in log space -- i.e. six launches of the library's
+automatically chosen kernel, 6e8 queries per step.  Inputs are generated on
+the host, copied to HBM before timing, and stay resident.
+
+Output: one JSON line with whole-job throughput in Gqueries/s (12 algorithmic
+bytes per query: an 8-byte target read, a 4-byte index written), the HBM
+roofline fraction of the dominant kernel (timed per launch with HIP events on
+the launch stream), per-kernel comparisons on the same data, and the CPU
+oracle timed on the host's cores over a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-kernels]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+METRIC = "Gqueries/s and % HBM roofline, bit-exact idx; learned+batched vs plain search"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_QUERY = 12
+TABLE_SIZES = (100, 300, 1000)
+ORDERS = ("random", "smooth")
+M = 10**8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_2112_03229_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(f"{kernel}|{workload}")
+    if not ent or ent.get("source_digest") != kernel_source_digest():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(tables, host_targets, budget_s: float = 15.0):
+    """The CPU oracle (plain linear count) on all host cores, on a bounded
+    sample of every (table, order) pair of the workload."""
+    import oracle
+    threads = oracle.default_threads()
+    # calibrate every (table, order) pair on a small slice, then size one
+    # common sample so that the whole measurement takes about budget_s
+    per_q = 0.0
+    for table in tables:
+        for order in ORDERS:
+            cal = np.ascontiguousarray(host_targets[order][:400000])
+            t0 = time.perf_counter()
+            oracle.search_lt(table, cal, threads=threads)
+            per_q += (time.perf_counter() - t0) / cal.shape[0]
+    per_pair = int(min(M, max(100000, budget_s / per_q)))
+    total_q, total_s = 0, 0.0
+    for table in tables:
+        for order in ORDERS:
+            x = host_targets[order]
+            start = (x.shape[0] - per_pair) // 2
+            sample = np.ascontiguousarray(x[start:start + per_pair])
+            t0 = time.perf_counter()
+            _, used = oracle.search_lt(table, sample, threads=threads, return_threads=True)
+            total_s += time.perf_counter() - t0
+            total_q += per_pair
+    return {
+        "value": total_q / total_s / 1e9,
+        "unit": "Gqueries/s",
+        "cores": int(used),
+        "kind": "oracle",
+        "sample": f"{per_pair} contiguous targets from the middle of each of the 6 "
+                  f"(table, order) target arrays ({total_q} queries, {total_s:.1f} s); "
+                  f"plain linear count scan, {used} threads",
+        "host_cpu": _cpu_model(),
+    }
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_calibration(torch) -> None:
+    """A plain 1 GiB device-to-device copy, launched 3 times: under rocprofv3
+    --pmc its FETCH_SIZE / WRITE_SIZE per dispatch give the scale between the
+    counters and true HBM bytes (1 GiB read and 1 GiB written per dispatch)."""
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 8, "dispatches": 3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-kernels", action="store_true",
+                    help="skip the per-kernel comparison after the timed region")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of known size (HBM counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); the search shards by target ranges with no exchange "
+              "step, so per-GPU throughput is the single-GPU figure.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2112_03229_amd import binding, inputs
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    binding.lib()
+
+    log("bench: generating inputs")
+    tables = [inputs.single_table(n) for n in TABLE_SIZES]
+    host = {}
+    for order in ORDERS:
+        buf = torch.empty(M, dtype=torch.float64).pin_memory()
+        # the three tables share the range [1e-8, 1e6], hence one target array per order
+        inputs.table_targets(tables[0], M, seed=2112, kind=order, out=buf.numpy())
+        host[order] = buf
+    d_tables = [torch.from_numpy(t).to(dev) for t in tables]
+    d_x = {o: host[o].to(dev, non_blocking=True) for o in ORDERS}
+    d_out = {(n, o): torch.empty(M, dtype=torch.int32, device=dev)
+             for n in TABLE_SIZES for o in ORDERS}
+    torch.cuda.synchronize()
+
+    pairs = [(i, o) for i in range(len(TABLE_SIZES)) for o in ORDERS]
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        for j, (i, o) in enumerate(pairs):
+            if events is not None:
+                events[j][0].record(stream)
+            binding.search_sorted_batch(d_tables[i], d_x[o], d_out[(TABLE_SIZES[i], o)])
+            if events is not None:
+                events[j][1].record(stream)
+
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    log(f"bench: timing {args.steps} steps")
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
+           for _ in pairs] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [e[0].elapsed_time(e[1]) for st in ev for e in st]
+    avg_launch_ms = float(np.mean(launch_ms))
+    queries_per_step = len(pairs) * M
+    ms_per_step = wall * 1e3 / args.steps
+    value = queries_per_step * args.steps / wall / 1e9
+
+    kernel = "single_kernel<exphash>"
+    achieved = M * BYTES_PER_QUERY / (avg_launch_ms * 1e-3) / 1e9
+    workload = "single-1e8"
+    traffic = measured_traffic(kernel, workload)
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gqueries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "single tables n=100,300,1000 (log-uniform on [1e-8,1e6]); "
+                        "1e8 float64 targets per table and order; orders: i.i.d. log-uniform "
+                        "and smooth sorted walk; automatically chosen kernel",
+            "tables": list(TABLE_SIZES),
+            "targets_per_launch": M,
+            "launches_per_step": len(pairs),
+            "bytes_per_query": BYTES_PER_QUERY,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": kernel,
+            "algorithmic_bytes_per_launch": M * BYTES_PER_QUERY,
+            "avg_launch_ms": round(avg_launch_ms, 4),
+        },
+    }
+
+    if not args.no_kernels:
+        log("bench: per-kernel comparison")
+        comp = {}
+        for (i, o) in pairs:
+            row = {}
+            for algo in ("binary", "ballot", "exphash"):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                out = d_out[(TABLE_SIZES[i], o)]
+                binding.search_with(d_tables[i], d_x[o], algo, -1, out)
+                e0.record(stream)
+                reps = 3
+                for _ in range(reps):
+                    binding.search_with(d_tables[i], d_x[o], algo, -1, out)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                row[algo] = round(M / (ms * 1e-3) / 1e9, 2)
+            comp[f"n={TABLE_SIZES[i]}/{o}"] = row
+        result["kernels_gqps"] = comp
+
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(tables, {o: host[o].numpy() for o in ORDERS})
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -91,8 +91,10 @@ typedef enum {
                                     0 (default) = auto */
     SS_OPT_GRID_BLOCKS = 5,      /* workgroups per launch; 0 (default) = fill
                                     the device (persistent grid) */
-    SS_OPT_CHECK_POINTERS = 6    /* 1 (default): verify that buffers are
+    SS_OPT_CHECK_POINTERS = 6,   /* 1 (default): verify that buffers are
                                     device memory before launching; 0: skip */
+    SS_OPT_TARGETS_PER_LANE = 7  /* targets each lane keeps in flight per
+                                    tile: 4 or 8; 0 (default) = auto */
 } ss_option;
 
 /* Human-readable message for the calling thread's most recent error
@@ -153,9 +155,11 @@ SS_API int ss_validate_table(const double *table, int64_t n, int64_t *bad_index_
  *   bucket_bits : s in 0..20, or -1 to use the single-table path's automatic
  *                 choice for bin cap `cap`
  *   counts      : device, int32, room for `cap` entries
- *   info_out    : host, 4 int64: {s, kmin, nb, max entries in one bin}
+ *   info_out    : host, 4 int64: {s, kmin, nb, K} with K the most entries
+ *                 in one bin, reported as 9 when 9 or more
  * Requires 1 <= n <= 65535 and a[0] with a clear sign bit.  If nb + 1 > cap
- * returns SS_ERR_INVALID_ARG.  SYNCHRONOUS. */
+ * returns SS_ERR_INVALID_ARG.  For a table that violates the sort
+ * precondition some entries of counts may be left unwritten.  SYNCHRONOUS. */
 SS_API int ss_exphash_bins(const double *table, int64_t n, int bucket_bits, int32_t *counts,
                     int64_t cap, int64_t *info_out /* host, 4 entries */);
 

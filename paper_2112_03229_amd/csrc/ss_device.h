@@ -81,29 +81,38 @@ __device__ __forceinline__ HashParams choose_hash(const double* a, int n, int bi
   }
 }
 
-// Builds C[0..nb] in LDS by gap filling (each bin written by the table entry
-// that opens it; no atomics), then the largest bin occupancy K.  `scratch`
-// is one int of LDS.  Must be called by the whole workgroup.  For a table
-// that violates the sort precondition C stays within [0, n].
+// Builds C[0..nb] by gap filling: entry i writes C[b] = i for every bin b it
+// opens, i.e. b in (key bin of a[i-1], key bin of a[i]], and C[nb] = n.  For
+// a sorted table every b is written exactly once (no atomics, no clearing
+// pass).  K, the most entries sharing one bin, is the longest run of equal
+// keys, measured per entry by looking back at most SS_SCAN_MAX entries
+// (K = SS_SCAN_MAX + 1 stands for "longer").  `scratch` is one int; the whole
+// workgroup must call.  A table that violates the sort precondition can
+// leave bins unwritten: readers clamp C values to [0, n].
 template <typename CT>
 __device__ __forceinline__ void build_bins(const double* __restrict__ sa, int n, HashParams& hp,
                                            CT* __restrict__ C, int* scratch) {
   const int nt = blockDim.x, tid = threadIdx.x;
-  for (int b = tid; b <= hp.nb; b += nt) C[b] = 0;
   if (tid == 0) *scratch = 0;
-  __syncthreads();
+  __syncthreads();  // (callers stage the table before; one barrier suffices)
+  int run_max = 0;
   for (int i = tid; i < n; i += nt) {
     const int kb = clampi(hash_key(sa[i], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
     const int kp =
         i == 0 ? -1 : clampi(hash_key(sa[i - 1], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
     for (int b = kp + 1; b <= kb; ++b) C[b] = (CT)i;
+    int run = 1;
+    if (kp == kb) {
+      run = 2;
+      while (run <= SS_SCAN_MAX && i - run >= 0 &&
+             clampi(hash_key(sa[i - run], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin == kb)
+        ++run;
+    }
+    run_max = max(run_max, run);
   }
   if (tid == 0) C[hp.nb] = (CT)n;
-  __syncthreads();
-  int mx = 0;
-  for (int b = tid; b < hp.nb; b += nt) mx = max(mx, (int)C[b + 1] - (int)C[b]);
-  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
-  if ((tid & 63) == 0) atomicMax(scratch, mx);
+  for (int o = 32; o > 0; o >>= 1) run_max = max(run_max, __shfl_xor(run_max, o));
+  if ((tid & 63) == 0) atomicMax(scratch, run_max);
   __syncthreads();
   hp.K = __builtin_amdgcn_readfirstlane(*scratch);
 }
@@ -156,22 +165,27 @@ __device__ __forceinline__ void search_binary_global(const double* __restrict__ 
 // linear scan (Sec. 3.4's interior search) of the bin.  Entries after the bin
 // have larger keys, hence larger values, so a fixed-length scan of K entries
 // (K = largest bin) counts exactly the bin's entries below x.  Bins longer
-// than SS_SCAN_MAX are searched by bisection inside [C[b], C[b+1]).
+// than SS_SCAN_MAX are searched by bisection inside [C[b], C[b+1]).  C values
+// are clamped to [0, n] so that even a table violating the sort precondition
+// reads only the staged table and its padding.
 // NaN targets need the one select: their key lands in the last bin.
 // ---------------------------------------------------------------------------
 template <int Q>
 __device__ __forceinline__ void search_exphash(const double* __restrict__ sa,
-                                               const uint16_t* __restrict__ C,
+                                               const uint16_t* __restrict__ C, int n,
                                                const HashParams& hp, const double (&x)[Q],
                                                int (&r)[Q]) {
-  int j0[Q], cnt[Q];
+  int b[Q], j0[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int b = clampi(hash_key(x[q], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
-    j0[q] = C[b];
-    cnt[q] = 0;
+    b[q] = clampi(hash_key(x[q], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
+    j0[q] = min((int)C[b[q]], n);
   }
   if (hp.K <= SS_SCAN_MAX) {
+    int cnt[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) cnt[q] = 0;
+#pragma nounroll
     for (int k = 0; k < hp.K; ++k) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) cnt[q] += (sa[j0[q] + k] < x[q]) ? 1 : 0;
@@ -179,23 +193,24 @@ __device__ __forceinline__ void search_exphash(const double* __restrict__ sa,
 #pragma unroll
     for (int q = 0; q < Q; ++q) r[q] = (x[q] != x[q]) ? -1 : j0[q] + cnt[q] - 1;
   } else {
-    // bisection inside the bin: largest pos in [lo, hi] with a[pos-1] < x
+    // long bins: bisection inside [C[b], C[b+1]) -- the largest pos in
+    // [lo, hi] with a[pos-1] < x, by binary lifting with steps P, P/2, .., 1
+    // where P is the largest power of two <= n (>= every bin length)
     int hi[Q], pos[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int b = clampi(hash_key(x[q], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
-      hi[q] = C[b + 1];
+      hi[q] = min(max((int)C[b[q] + 1], j0[q]), n);
       pos[q] = j0[q];
     }
     int step = 1;
-    while (step * 2 <= hp.K) step *= 2;
+    while (step * 2 <= n) step *= 2;
     for (; step >= 1; step >>= 1) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int cand = pos[q] + step;
         const int ridx = max(min(cand, hi[q]) - 1, 0);
-        const bool take = (cand <= hi[q]) && (sa[ridx] < x[q]);
-        pos[q] = take ? cand : pos[q];
+        const bool lt = sa[ridx] < x[q];
+        pos[q] = ((cand <= hi[q]) & lt) ? cand : pos[q];
       }
     }
 #pragma unroll

@@ -20,6 +20,7 @@ std::atomic<int64_t> g_bucket_cap{0};
 std::atomic<int64_t> g_block_size{0};
 std::atomic<int64_t> g_grid_blocks{0};
 std::atomic<int64_t> g_check_pointers{1};
+std::atomic<int64_t> g_targets_per_lane{0};
 
 std::mutex g_dev_mu;
 std::map<int, DeviceInfo> g_dev_cache;
@@ -51,6 +52,7 @@ int64_t option(int opt) {
     case SS_OPT_BLOCK_SIZE: return g_block_size.load();
     case SS_OPT_GRID_BLOCKS: return g_grid_blocks.load();
     case SS_OPT_CHECK_POINTERS: return g_check_pointers.load();
+    case SS_OPT_TARGETS_PER_LANE: return g_targets_per_lane.load();
     default: return 0;
   }
 }
@@ -176,6 +178,11 @@ int ss_set_option(int opt, int64_t v) {
       if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_CHECK_POINTERS: 0 or 1");
       ss::g_check_pointers = v;
       return SS_OK;
+    case SS_OPT_TARGETS_PER_LANE:
+      if (v != 0 && v != 4 && v != 8)
+        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_TARGETS_PER_LANE: expected 0, 4 or 8");
+      ss::g_targets_per_lane = v;
+      return SS_OK;
     default:
       return ss::fail(SS_ERR_INVALID_ARG, "unknown option");
   }
@@ -190,6 +197,7 @@ int ss_get_option(int opt, int64_t* value_out) {
     case SS_OPT_BLOCK_SIZE:
     case SS_OPT_GRID_BLOCKS:
     case SS_OPT_CHECK_POINTERS:
+    case SS_OPT_TARGETS_PER_LANE:
       *value_out = ss::option(opt);
       return SS_OK;
     default:

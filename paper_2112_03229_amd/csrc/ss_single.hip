@@ -18,8 +18,15 @@
 
 namespace ss {
 
-constexpr int kQ = 8;                 // targets per lane per tile
-constexpr int kDefaultBlock = 256;    // threads per workgroup
+constexpr int kDefaultQ = 8;          // targets per lane per tile
+constexpr int kDefaultBlock = 512;    // threads per workgroup
+// Tiles per workgroup of the default grid.  A grid several times larger
+// than the resident workgroup count lets the dispatcher balance CUs that
+// run at different speeds (a strictly persistent grid loses ~10% to its
+// slowest workgroups); the exponent hash keeps more tiles per workgroup to
+// amortise its per-workgroup bin build.
+constexpr int kTilesPerBlockHash = 6;
+constexpr int kTilesPerBlockOther = 3;
 constexpr size_t kStageLimit = 65536; // LDS bytes a single-table launch may use
 
 struct SingleArgs {
@@ -34,46 +41,87 @@ struct SingleArgs {
   int scr_off;  // byte offset of one int of LDS scratch
 };
 
-// Streams the tiles assigned to this workgroup through `search`.
+// Loads one tile slot set: slot q of lane t is target base + q*nt.  A full
+// tile uses plain non-temporal loads; the ragged last tile clamps the index
+// (so every load stays in bounds and none is predicated) and turns the
+// missing targets into NaN, which every search handles.
+template <int Q>
+__device__ __forceinline__ void load_tile(const double* __restrict__ x, int64_t m, int64_t base,
+                                          int nt, bool full, double (&xv)[Q]) {
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) xv[q] = __builtin_nontemporal_load(x + base + (int64_t)q * nt);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t k = base + (int64_t)q * nt;
+      const double v = x[k < m ? k : m - 1];
+      xv[q] = k < m ? v : __builtin_nan("");
+    }
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void store_tile(int32_t* __restrict__ out, int64_t m, int64_t base,
+                                           int nt, bool full, const int (&r)[Q]) {
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(r[q], out + base + (int64_t)q * nt);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t k = base + (int64_t)q * nt;
+      if (k < m) out[k] = r[q];
+    }
+  }
+}
+
+// Streams the tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... through
+// `search`, software-pipelined: the next tile's targets are in flight while
+// the current tile is searched and stored.
+// The caller issues the first tile's loads (first_tile) before its own setup
+// (table staging, bin build) so that their latency overlaps that setup.
+template <int Q>
+__device__ __forceinline__ void first_tile(const double* __restrict__ x, int64_t m,
+                                           double (&cur)[Q]) {
+  const int nt = blockDim.x;
+  const int64_t per_tile = (int64_t)nt * Q;
+  const int64_t t = blockIdx.x;
+  if (t * per_tile < m) load_tile<Q>(x, m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= m, cur);
+}
+
 template <int Q, typename Search>
 __device__ __forceinline__ void stream_tiles(const double* __restrict__ x, int64_t m,
-                                             int32_t* __restrict__ out, Search&& search) {
+                                             int32_t* __restrict__ out, double (&cur)[Q],
+                                             Search&& search) {
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
   const int64_t ntiles = (m + per_tile - 1) / per_tile;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t base = t * per_tile + threadIdx.x;
-    double xv[Q];
+  int64_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  double nxt[Q];
+  for (;;) {
+    const int64_t tn = t + gridDim.x;
+    const bool has_next = tn < ntiles;
+    if (has_next) load_tile<Q>(x, m, tn * per_tile + threadIdx.x, nt, (tn + 1) * per_tile <= m, nxt);
     int r[Q];
-    if ((t + 1) * per_tile <= m) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) xv[q] = __builtin_nontemporal_load(x + base + (int64_t)q * nt);
-      search(xv, r);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(r[q], out + base + (int64_t)q * nt);
-    } else {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int64_t k = base + (int64_t)q * nt;
-        xv[q] = k < m ? x[k] : __builtin_nan("");
-      }
-      search(xv, r);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int64_t k = base + (int64_t)q * nt;
-        if (k < m) out[k] = r[q];
-      }
-    }
+    search(cur, r);
+    store_tile<Q>(out, m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= m, r);
+    if (!has_next) break;
+    for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+    t = tn;
   }
 }
 
 template <int ALGO, int Q>
 __global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
+  double cur[Q];
+  first_tile<Q>(a.x, a.m, cur);
   if constexpr (ALGO == SS_ALGO_BINARY_GLOBAL) {
     const double* __restrict__ tab = a.table;
     const int n = a.n;
-    stream_tiles<Q>(a.x, a.m, a.out, [&](const double(&xv)[Q], int(&r)[Q]) {
+    stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
       search_binary_global<Q>(tab, n, xv, r);
     });
     return;
@@ -88,20 +136,20 @@ __global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
       HashParams hp = choose_hash(sa, n, a.bits, a.cap);
       if (hp.ok) {
         build_bins(sa, n, hp, C, scratch);
-        stream_tiles<Q>(a.x, a.m, a.out, [&](const double(&xv)[Q], int(&r)[Q]) {
-          search_exphash<Q>(sa, C, hp, xv, r);
+        stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
+          search_exphash<Q>(sa, C, n, hp, xv, r);
         });
         return;
       }
       // not applicable (negative entries, unordered keys): bisection below
     }
     if constexpr (ALGO == SS_ALGO_BALLOT) {
-      stream_tiles<Q>(a.x, a.m, a.out, [&](const double(&xv)[Q], int(&r)[Q]) {
+      stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
         search_ballot<Q>(sa, n, xv, r);
       });
       return;
     }
-    stream_tiles<Q>(a.x, a.m, a.out, [&](const double(&xv)[Q], int(&r)[Q]) {
+    stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
       search_binary<Q>(sa, n, xv, r);
     });
   }
@@ -205,11 +253,17 @@ int launch_single(const double* table, int64_t n, const double* x, int64_t m, in
   if ((rc = plan_single(n, algo, (int)option(SS_OPT_BUCKET_CAP), &p)) != SS_OK) return rc;
   int nt = (int)option(SS_OPT_BLOCK_SIZE);
   if (nt == 0) nt = kDefaultBlock;
-  const void* kern = single_kernel_ptr<kQ>(p.algo);
-  const int64_t per_tile = (int64_t)nt * kQ;
+  int q = (int)option(SS_OPT_TARGETS_PER_LANE);
+  if (q == 0) q = kDefaultQ;
+  const void* kern = q == 4 ? single_kernel_ptr<4>(p.algo) : single_kernel_ptr<8>(p.algo);
+  const int64_t per_tile = (int64_t)nt * q;
   const int64_t ntiles = (m + per_tile - 1) / per_tile;
   int64_t grid = option(SS_OPT_GRID_BLOCKS);
-  if (grid <= 0) grid = (int64_t)blocks_per_cu(kern, nt, p.lds) * di.num_cus;
+  if (grid <= 0) {
+    const int64_t resident = (int64_t)blocks_per_cu(kern, nt, p.lds) * di.num_cus;
+    const int tpb = p.algo == SS_ALGO_EXPHASH ? kTilesPerBlockHash : kTilesPerBlockOther;
+    grid = std::max<int64_t>(resident, ntiles / tpb);
+  }
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
   SingleArgs a{table, x, out, m, (int)n, bits, p.cap, p.c_off, p.scr_off};
   void* args[] = {&a};
