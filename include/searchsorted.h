@@ -163,6 +163,91 @@ SS_API int ss_validate_table(const double *table, int64_t n, int64_t *bad_index_
 SS_API int ss_exphash_bins(const double *table, int64_t n, int bucket_bits, int32_t *counts,
                     int64_t cap, int64_t *info_out /* host, 4 entries */);
 
+/* ---------------------------------------------------------------------------
+ * Many tables in one launch (batched) and paired lookups.
+ *
+ * A plan is built once per set of tables (the setup the paper pays once per
+ * table load, Sec. 5.3) and then searched many times.  Building it copies
+ * the tables to the host once, lets the autotuner choose, per table, the
+ * kernel (exponent hash or bisection), the hash's bin bits and the chunk of
+ * targets a workgroup takes at a time, builds the exponent-hash bin tables
+ * on the device, and prepares a HIP graph that runs the whole batch as one
+ * persistent launch over a work queue.  Plans own device memory; the tables
+ * are referenced (not copied) and must stay valid and unchanged while the
+ * plan is used.  A plan may be used from one thread at a time.
+ * ------------------------------------------------------------------------- */
+typedef struct ss_plan ss_plan;
+
+/* Plan for T tables stored back to back (CSR):
+ *   tables    : device, float64; table t is tables[table_off[t] .. table_off[t+1])
+ *   table_off : host, T+1 non-decreasing int64 offsets, table_off[0] == 0;
+ *               each table holds at most 65535 entries and must be sorted
+ *   T         : 1 <= T <= 2^20
+ *   query_off : host, T+1 non-decreasing int64 offsets, query_off[0] == 0;
+ *               the targets (and indices) of table t are positions
+ *               query_off[t] .. query_off[t+1] of the arrays passed to
+ *               ss_multi_search
+ *   out       : host, receives the plan
+ * SYNCHRONOUS (device work on the current stream, then waits). */
+SS_API int ss_multi_plan_create(const double *tables, const int64_t *table_off, int32_t T,
+                                const int64_t *query_off, ss_plan **out);
+
+/* out_idx[k] = idx_t(targets[k]) for every k in [query_off[t], query_off[t+1]),
+ * where idx_t is the operation defined at the top of this header applied to
+ * table t.  targets: device float64 [query_off[T]]; out_idx: device int32,
+ * same length, not overlapping.  Asynchronous on the current stream (one
+ * graph launch). */
+SS_API int ss_multi_search(ss_plan *plan, const double *targets, int32_t *out_idx);
+
+/* Paired lookup (the density and temperature axes of EOS tables, Sec. 1):
+ * M materials, each with a density table and a temperature table (CSR as
+ * above, each <= 65535 entries), and pair_off (host, M+1) grouping the
+ * query pairs by material.  ss_pair_search writes, for every pair k of
+ * material j, out_rho[k] = idx over density table j of rho[k] and
+ * out_t[k] = idx over temperature table j of temp[k], in one launch. */
+SS_API int ss_pair_plan_create(const double *rho_tables, const int64_t *rho_off,
+                               const double *t_tables, const int64_t *t_off, int32_t M,
+                               const int64_t *pair_off, ss_plan **out);
+SS_API int ss_pair_search(ss_plan *plan, const double *rho, const double *temp,
+                          int32_t *out_rho, int32_t *out_t);
+
+SS_API int ss_plan_destroy(ss_plan *plan);
+
+/* What the autotuner chose, for inspection (host output):
+ *   SS_PLAN_ALGOS  : int32 per table (ss_algo); paired plans list the
+ *                    density tables, then the temperature tables
+ *   SS_PLAN_BITS   : int32 per table (bin bits s, -1 for bisection)
+ *   SS_PLAN_SUMMARY: 8 int64 {tables, chunks, chunk_targets, grid, block,
+ *                    lds_bytes, max bin occupancy, graph uses}
+ * `cap` is the number of elements `out` can hold. */
+typedef enum { SS_PLAN_ALGOS = 1, SS_PLAN_BITS = 2, SS_PLAN_SUMMARY = 3 } ss_plan_query;
+SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner.  Plans choose each table's kernel, exponent-hash bin bits and
+ * the work-queue chunk size from a cost model (device-wide nanoseconds per
+ * query: memory = 12 B / stream bandwidth; compute = fixed + per-step terms
+ * of bisection and of the in-bin scan).  The model starts from built-in
+ * coefficients; ss_tuner_calibrate measures them on the current device, and
+ * the model can be saved to / loaded from a small JSON file (the library
+ * also loads the file named by the environment variable SS_TUNER_CACHE, if
+ * set, on first use).  Plans built earlier keep their choices.
+ * ------------------------------------------------------------------------- */
+
+/* Runs the calibration microbenchmarks on the current device and stream
+ * (about 1.5 GiB of temporary device memory, well under a second).
+ * SYNCHRONOUS. */
+SS_API int ss_tuner_calibrate(void);
+
+/* coeffs (host) receives 7 doubles: {stream GB/s, hash fixed ns, hash ns per
+ * scanned entry, bisection fixed ns, bisection ns per step, ns per KB
+ * restaged, calibrated flag}.  count must be >= 7. */
+SS_API int ss_tuner_get(double *coeffs, int count);
+
+/* Saves / loads the model as JSON at a host file path. */
+SS_API int ss_tuner_save(const char *path);
+SS_API int ss_tuner_load(const char *path);
+
 #ifdef __cplusplus
 }
 #endif

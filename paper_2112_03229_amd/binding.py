@@ -77,6 +77,10 @@ def _register_extra(L) -> None:
         "ss_plan_info": [P, I, P, I64],
         "ss_pair_plan_create": [P, P, P, P, I32, P, ctypes.POINTER(P)],
         "ss_pair_search": [P, P, P, P, P],
+        "ss_tuner_calibrate": [],
+        "ss_tuner_get": [P, I],
+        "ss_tuner_save": [ctypes.c_char_p],
+        "ss_tuner_load": [ctypes.c_char_p],
         "ss_learned_build": [P, I64, P, ctypes.POINTER(P)],
         "ss_learned_search": [P, P, I64, P],
         "ss_learned_info": [P, P],
@@ -183,3 +187,156 @@ def exphash_bins(table: torch.Tensor, bucket_bits: int = -1, cap: int = 1 << 16)
                                 info))
     s, kmin, nb, kmax_occ = (int(v) for v in info)
     return {"bits": s, "kmin": kmin, "nb": nb, "max_occupancy": kmax_occ}, counts[:nb + 1]
+
+
+# ---------------------------------------------------------------------------
+# plans: many tables (batched) and paired lookups
+# ---------------------------------------------------------------------------
+
+PLAN_ALGOS, PLAN_BITS, PLAN_SUMMARY = 1, 2, 3
+SUMMARY_KEYS = ("tables", "chunks", "chunk_targets", "grid", "block", "lds_bytes",
+                "max_bin", "graph_uses")
+
+
+def _host_offsets(off, name):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    if a.ndim != 1 or a.shape[0] < 2:
+        raise ValueError(f"{name} must be a 1-D array of at least 2 offsets")
+    return a
+
+
+def _off_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class _Plan:
+    _handle = None
+
+    def close(self) -> None:
+        if self._handle is not None and self._handle.value:
+            lib().ss_plan_destroy(self._handle)
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        import numpy as np
+        T = self.num_descriptors
+        algos = np.zeros(T, dtype=np.int32)
+        bits = np.zeros(T, dtype=np.int32)
+        summ = np.zeros(8, dtype=np.int64)
+        check(lib().ss_plan_info(self._handle, PLAN_ALGOS, _off_ptr(algos), T))
+        check(lib().ss_plan_info(self._handle, PLAN_BITS, _off_ptr(bits), T))
+        check(lib().ss_plan_info(self._handle, PLAN_SUMMARY, _off_ptr(summ), 8))
+        out = dict(zip(SUMMARY_KEYS, (int(v) for v in summ)))
+        out["algos"] = algos
+        out["bits"] = bits
+        return out
+
+
+class MultiPlan(_Plan):
+    """Many tables searched in one launch (see ss_multi_plan_create)."""
+
+    def __init__(self, tables: torch.Tensor, table_off, query_off):
+        _need(tables, torch.float64, "tables")
+        self._toff = _host_offsets(table_off, "table_off")
+        self._qoff = _host_offsets(query_off, "query_off")
+        if self._toff.shape != self._qoff.shape:
+            raise ValueError("table_off and query_off must have the same length")
+        self.num_descriptors = self._toff.shape[0] - 1
+        self.num_queries = int(self._qoff[-1])
+        self._tables = tables  # referenced by the plan: keep alive
+        h = ctypes.c_void_p()
+        use_current_stream()
+        check(lib().ss_multi_plan_create(_ptr(tables), _off_ptr(self._toff), self.num_descriptors,
+                                         _off_ptr(self._qoff), ctypes.byref(h)))
+        self._handle = h
+
+    def search(self, targets: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _need(targets, torch.float64, "targets")
+        if targets.numel() != self.num_queries:
+            raise ValueError(f"expected {self.num_queries} targets, got {targets.numel()}")
+        if out is None:
+            out = torch.empty(self.num_queries, dtype=torch.int32, device=targets.device)
+        _need(out, torch.int32, "out")
+        if out.numel() != self.num_queries:
+            raise ValueError("out must have one entry per target")
+        use_current_stream()
+        check(lib().ss_multi_search(self._handle, _ptr(targets), _ptr(out)))
+        return out
+
+
+class PairPlan(_Plan):
+    """Paired density/temperature lookups per material (ss_pair_plan_create)."""
+
+    def __init__(self, rho_tables: torch.Tensor, rho_off, t_tables: torch.Tensor, t_off,
+                 pair_off):
+        _need(rho_tables, torch.float64, "rho_tables")
+        _need(t_tables, torch.float64, "t_tables")
+        self._roff = _host_offsets(rho_off, "rho_off")
+        self._toff = _host_offsets(t_off, "t_off")
+        self._poff = _host_offsets(pair_off, "pair_off")
+        M = self._roff.shape[0] - 1
+        if self._toff.shape[0] != M + 1 or self._poff.shape[0] != M + 1:
+            raise ValueError("offset arrays must all have M+1 entries")
+        self.num_materials = M
+        self.num_descriptors = 2 * M
+        self.num_queries = int(self._poff[-1])
+        self._tables = (rho_tables, t_tables)
+        h = ctypes.c_void_p()
+        use_current_stream()
+        check(lib().ss_pair_plan_create(_ptr(rho_tables), _off_ptr(self._roff), _ptr(t_tables),
+                                        _off_ptr(self._toff), M, _off_ptr(self._poff),
+                                        ctypes.byref(h)))
+        self._handle = h
+
+    def search(self, rho: torch.Tensor, temp: torch.Tensor, out_rho: torch.Tensor | None = None,
+               out_t: torch.Tensor | None = None):
+        _need(rho, torch.float64, "rho")
+        _need(temp, torch.float64, "temp")
+        m = self.num_queries
+        if rho.numel() != m or temp.numel() != m:
+            raise ValueError(f"expected {m} pairs")
+        if out_rho is None:
+            out_rho = torch.empty(m, dtype=torch.int32, device=rho.device)
+        if out_t is None:
+            out_t = torch.empty(m, dtype=torch.int32, device=rho.device)
+        _need(out_rho, torch.int32, "out_rho")
+        _need(out_t, torch.int32, "out_t")
+        use_current_stream()
+        check(lib().ss_pair_search(self._handle, _ptr(rho), _ptr(temp), _ptr(out_rho),
+                                   _ptr(out_t)))
+        return out_rho, out_t
+
+
+# ---------------------------------------------------------------------------
+# autotuner model
+# ---------------------------------------------------------------------------
+
+TUNER_KEYS = ("stream_gbs", "hash_base_ns", "hash_per_k_ns", "bin_base_ns", "bin_per_step_ns",
+              "stage_ns_per_kb", "calibrated")
+
+
+def tuner_calibrate() -> dict:
+    use_current_stream()
+    check(lib().ss_tuner_calibrate())
+    return tuner_get()
+
+
+def tuner_get() -> dict:
+    buf = (ctypes.c_double * 7)()
+    check(lib().ss_tuner_get(buf, 7))
+    return dict(zip(TUNER_KEYS, list(buf)))
+
+
+def tuner_save(path: str) -> None:
+    check(lib().ss_tuner_save(os.fsencode(path)))
+
+
+def tuner_load(path: str) -> None:
+    check(lib().ss_tuner_load(os.fsencode(path)))

@@ -267,4 +267,45 @@ __device__ __forceinline__ void search_ballot(const double* __restrict__ sa, int
   for (int q = 0; q < Q; ++q) r[q] = (x[q] != x[q]) ? -1 : lo + cnt[q] - 1;
 }
 
+// ---------------------------------------------------------------------------
+// Streaming targets (a3) and indices (a6).
+// ---------------------------------------------------------------------------
+// Loads one tile slot set: slot q of lane t is target base + q*nt.  A full
+// tile uses plain non-temporal loads; the ragged last tile clamps the index
+// (so every load stays in bounds and none is predicated) and turns the
+// missing targets into NaN, which every search handles.
+template <int Q>
+__device__ __forceinline__ void load_tile(const double* __restrict__ x, int64_t m, int64_t base,
+                                          int nt, bool full, double (&xv)[Q]) {
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) xv[q] = __builtin_nontemporal_load(x + base + (int64_t)q * nt);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t k = base + (int64_t)q * nt;
+      const double v = x[k < m ? k : m - 1];
+      xv[q] = k < m ? v : __builtin_nan("");
+    }
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void store_tile(int32_t* __restrict__ out, int64_t m, int64_t base,
+                                           int nt, bool full, const int (&r)[Q]) {
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(r[q], out + base + (int64_t)q * nt);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t k = base + (int64_t)q * nt;
+      if (k < m) out[k] = r[q];
+    }
+  }
+}
+
+// Streams the tiles t = blockIdx.x, blockIdx.x + gridDim.x, ... through
+// `search`, software-pipelined: the next tile's targets are in flight while
+// the current tile is searched and stored.
 }  // namespace ss

@@ -1,0 +1,50 @@
+// Autotuner: a cost model of the search kernels, calibrated by device
+// microbenchmarks, that picks each table's kernel, exponent-hash bin bits
+// and the plan's chunk size.
+#pragma once
+
+#include <stdint.h>
+#include <stddef.h>
+
+namespace ss {
+
+// Device-wide costs in nanoseconds per query at full occupancy.  A query's
+// time is max(memory, compute): memory = 12 bytes / stream bandwidth,
+// compute from the per-kernel terms below.
+struct TunerModel {
+  double stream_gbs = 6200.0;        // sustained bytes/ns of a 12 B/query stream
+  double hash_base_ns = 0.6e-3;      // exponent hash: key, bin read, select
+  double hash_per_k_ns = 0.15e-3;    // per entry of the fixed in-bin scan
+  double bin_base_ns = 0.5e-3;       // bisection: final compare and select
+  double bin_per_step_ns = 0.10e-3;  // per bisection step
+  double stage_ns_per_kb = 50.0;     // one workgroup restaging 1 KB of LDS
+  int calibrated = 0;                // 1 once measured on this device
+};
+
+struct TunedTable {
+  int n = 0;
+  int algo = 1;        // SS_ALGO_BINARY or SS_ALGO_EXPHASH
+  int bits = -1;       // s for the exponent hash
+  int kmin = 0, kmaxc = 0, nb = 0;
+  int K = 0;           // longest bin (exact)
+  double est_ns = 0;   // modelled ns per query (compute part)
+};
+
+// The process-wide model (defaults until calibrated or loaded).
+const TunerModel& tuner_model();
+
+// Chooses the kernel and bin bits for one table of n entries; the bin table
+// may take at most `bins_budget` bytes of LDS.
+TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bins_budget);
+
+// Targets per work-queue chunk for a plan of `total` queries: long enough
+// that restaging `stage_bytes` of LDS costs at most ~2% of the chunk's
+// streaming time on one of `workgroups` concurrent workgroups, short enough
+// to leave several chunks per workgroup; a multiple of `per_tile`.
+int64_t choose_chunk_targets(const TunerModel& model, int64_t total, int per_tile,
+                             size_t stage_bytes, int workgroups);
+
+// Longest run of equal exponent-hash keys (the largest bin) at bits s.
+int host_longest_bin(const double* a, int n, int s);
+
+}  // namespace ss

@@ -1,0 +1,370 @@
+// Autotuner: cost model, per-table choices, device calibration and the
+// model's JSON cache.
+//
+// Per table the tuner enumerates bisection and the exponent hash at every
+// bin-bit count s in 0..20 whose table + bin table fit the LDS budget,
+// computes the longest bin K(s) exactly from the table, and keeps the
+// choice with the lowest modelled compute cost per query (every choice
+// moves the same 12 bytes per query, so memory time does not discriminate;
+// lower compute leaves issue slots for the memory pipeline).  Ties go to
+// fewer bins (less LDS to stage).  The model's coefficients are measured by
+// ss_tuner_calibrate on the current device: a long HBM stream for the
+// bandwidth, then bisection over tables of 64..4096 entries and the
+// exponent hash at several K on cache-resident targets, fitted by least
+// squares.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ss_device.h"
+#include "ss_host.h"
+#include "ss_tuner.h"
+
+namespace ss {
+
+int launch_single(const double* table, int64_t n, const double* x, int64_t m, int32_t* out,
+                  int algo, int bits);
+
+namespace {
+std::mutex g_tuner_mu;
+TunerModel g_model;
+bool g_model_init = false;
+std::string g_model_arch;
+
+int hi_word_host(double v) {
+  uint64_t u;
+  std::memcpy(&u, &v, 8);
+  return (int)(int32_t)(uint32_t)(u >> 32);
+}
+
+int ceil_log2(int n) {
+  int s = 0;
+  while ((1 << s) < n) ++s;
+  return s;
+}
+
+// Bisection steps the kernel executes for n entries (uniform loop length).
+int bisect_steps(int n) {
+  int steps = 0;
+  for (int len = n; len > 1; len -= len >> 1) ++steps;
+  return steps;
+}
+
+bool parse_key(const std::string& text, const char* key, double* out) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = text.find(k);
+  if (p == std::string::npos) return false;
+  p = text.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  char* end = nullptr;
+  const double v = std::strtod(text.c_str() + p + 1, &end);
+  if (end == text.c_str() + p + 1) return false;
+  *out = v;
+  return true;
+}
+
+int load_file(const char* path, TunerModel* m, std::string* arch) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  TunerModel t;
+  double cal = 0;
+  if (!parse_key(text, "stream_gbs", &t.stream_gbs) ||
+      !parse_key(text, "hash_base_ns", &t.hash_base_ns) ||
+      !parse_key(text, "hash_per_k_ns", &t.hash_per_k_ns) ||
+      !parse_key(text, "bin_base_ns", &t.bin_base_ns) ||
+      !parse_key(text, "bin_per_step_ns", &t.bin_per_step_ns) ||
+      !parse_key(text, "stage_ns_per_kb", &t.stage_ns_per_kb) ||
+      !parse_key(text, "calibrated", &cal))
+    return fail(SS_ERR_INVALID_ARG, std::string("malformed tuner cache ") + path);
+  if (!(t.stream_gbs > 0) || !(t.hash_base_ns >= 0) || !(t.bin_per_step_ns >= 0))
+    return fail(SS_ERR_INVALID_ARG, std::string("implausible tuner cache ") + path);
+  t.calibrated = cal != 0;
+  const size_t a = text.find("\"arch\"");
+  if (a != std::string::npos) {
+    const size_t q0 = text.find('"', text.find(':', a) + 1);
+    const size_t q1 = q0 == std::string::npos ? q0 : text.find('"', q0 + 1);
+    if (q1 != std::string::npos) *arch = text.substr(q0 + 1, q1 - q0 - 1);
+  }
+  *m = t;
+  return SS_OK;
+}
+
+void init_model_locked() {
+  if (g_model_init) return;
+  g_model_init = true;
+  const char* path = std::getenv("SS_TUNER_CACHE");
+  if (path && *path) {
+    TunerModel m;
+    std::string arch;
+    if (load_file(path, &m, &arch) == SS_OK) {
+      g_model = m;
+      g_model_arch = arch;
+    }
+    clear_error();
+  }
+}
+
+}  // namespace
+
+const TunerModel& tuner_model() {
+  std::lock_guard<std::mutex> lk(g_tuner_mu);
+  init_model_locked();
+  return g_model;
+}
+
+int host_longest_bin(const double* a, int n, int s) {
+  if (n <= 0) return 0;
+  const int sh = SS_MAX_BITS - s;
+  const int kmin = hi_word_host(a[0]) >> sh, kmax = hi_word_host(a[n - 1]) >> sh;
+  auto key = [&](double v) { return std::min(std::max(hi_word_host(v) >> sh, kmin), kmax); };
+  int best = 1, run = 1;
+  int prev = key(a[0]);
+  for (int i = 1; i < n; ++i) {
+    const int k = key(a[i]);
+    run = (k == prev) ? run + 1 : 1;
+    best = std::max(best, run);
+    prev = k;
+  }
+  return best;
+}
+
+TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bins_budget) {
+  TunedTable best;
+  best.n = n;
+  best.algo = SS_ALGO_BINARY;
+  best.est_ns = model.bin_base_ns + model.bin_per_step_ns * bisect_steps(n);
+  if (n < 1 || n > 65535) return best;
+  const int h0 = hi_word_host(a[0]), h1 = hi_word_host(a[n - 1]);
+  if (h0 < 0 || h1 < h0) return best;
+  for (int s = 0; s <= SS_MAX_BITS; ++s) {
+    const int sh = SS_MAX_BITS - s;
+    const int kmin = h0 >> sh, kmax = h1 >> sh;
+    const int64_t nb = (int64_t)kmax - kmin + 1;
+    if ((size_t)(nb + 1) * 2 + 16 > bins_budget || nb > 65535) break;
+    const int K = host_longest_bin(a, n, s);
+    const double cost =
+        K <= SS_SCAN_MAX
+            ? model.hash_base_ns + model.hash_per_k_ns * K
+            : model.hash_base_ns + model.bin_per_step_ns * (ceil_log2(n) + 1);
+    // strictly better only: among equal costs the fewest bins win
+    if (cost < best.est_ns * (1.0 - 1e-9)) {
+      best.algo = SS_ALGO_EXPHASH;
+      best.bits = s;
+      best.kmin = kmin;
+      best.kmaxc = kmax;
+      best.nb = (int)nb;
+      best.K = K;
+      best.est_ns = cost;
+    }
+  }
+  return best;
+}
+
+int64_t choose_chunk_targets(const TunerModel& model, int64_t total, int per_tile,
+                             size_t stage_bytes, int workgroups) {
+  workgroups = std::max(workgroups, 1);
+  // one workgroup's share of the stream, in queries per ns
+  const double wg_rate = model.stream_gbs / 12.0 / workgroups;
+  const double stage_ns = model.stage_ns_per_kb * (double)stage_bytes / 1024.0;
+  int64_t c = (int64_t)(stage_ns / 0.02 * wg_rate);
+  // at least 8 chunks per workgroup when the batch is large enough
+  c = std::min<int64_t>(c, std::max<int64_t>(total / (8LL * workgroups), per_tile));
+  c = std::max<int64_t>(c, 4 * (int64_t)per_tile);
+  c = std::min<int64_t>(c, 256 * (int64_t)per_tile);
+  c = (c + per_tile - 1) / per_tile * per_tile;
+  return c;
+}
+
+namespace {
+
+__global__ void calib_fill(double* x, int64_t m, double lo2, double span2, uint64_t seed) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    uint64_t z = seed + (uint64_t)i * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    z ^= z >> 31;
+    const double u = (double)(z >> 11) * 0x1.0p-53;
+    x[i] = exp2(lo2 + span2 * u);
+  }
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+int time_search(const double* table, int n, const double* x, int64_t m, int32_t* out, int algo,
+                int bits, int reps, double* ns_per_query) {
+  hipStream_t st = current_stream();
+  hipEvent_t e0, e1;
+  SS_TRY_HIP(hipEventCreate(&e0));
+  SS_TRY_HIP(hipEventCreate(&e1));
+  int rc = launch_single(table, n, x, m, out, algo, bits);  // warm-up
+  if (rc == SS_OK) {
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < reps && rc == SS_OK; ++r) rc = launch_single(table, n, x, m, out, algo, bits);
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *ns_per_query = (double)ms * 1e6 / reps / (double)m;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+// least-squares line y = c0 + c1 x
+void fit_line(const std::vector<double>& x, const std::vector<double>& y, double* c0, double* c1) {
+  const double n = (double)x.size();
+  double sx = 0, sy = 0, sxx = 0, sxy = 0;
+  for (size_t i = 0; i < x.size(); ++i) {
+    sx += x[i];
+    sy += y[i];
+    sxx += x[i] * x[i];
+    sxy += x[i] * y[i];
+  }
+  const double d = n * sxx - sx * sx;
+  *c1 = d > 0 ? (n * sxy - sx * sy) / d : 0.0;
+  *c0 = (sy - *c1 * sx) / n;
+  if (*c1 < 0) {
+    *c1 = 0;
+    *c0 = sy / n;
+  }
+  if (*c0 < 0) *c0 = 0;
+}
+
+}  // namespace
+
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" {
+
+int ss_tuner_calibrate(void) {
+  clear_error();
+  DeviceInfo di;
+  int rc = device_info(&di);
+  if (rc != SS_OK) return rc;
+  hipStream_t st = current_stream();
+  const int64_t big = (int64_t)1 << 27;    // 1 GiB of targets: HBM stream
+  const int64_t small = (int64_t)1 << 21;  // 16 MiB: stays in the last-level cache
+  DevBuf xb, ob, tb;
+  SS_TRY_HIP(hipMalloc(&xb.p, big * 8));
+  SS_TRY_HIP(hipMalloc(&ob.p, big * 4));
+  SS_TRY_HIP(hipMalloc(&tb.p, 4096 * 8));
+  double* x = static_cast<double*>(xb.p);
+  int32_t* out = static_cast<int32_t*>(ob.p);
+  double* tab = static_cast<double*>(tb.p);
+  hipLaunchKernelGGL(calib_fill, dim3(4096), dim3(256), 0, st, x, big, 0.0, 32.0, 12345ULL);
+  SS_TRY_HIP(hipGetLastError());
+
+  auto put_table = [&](int n) -> int {
+    std::vector<double> h(n);
+    for (int i = 0; i < n; ++i) h[i] = std::exp2(32.0 * (i + 0.5) / n);
+    SS_TRY_HIP(hipMemcpyAsync(tab, h.data(), 8 * n, hipMemcpyHostToDevice, st));
+    SS_TRY_HIP(hipStreamSynchronize(st));
+    return SS_OK;
+  };
+
+  TunerModel m = tuner_model();
+  // 1. streaming bandwidth: a one-entry table makes the search trivial
+  double ns = 0;
+  if ((rc = put_table(1)) != SS_OK) return rc;
+  if ((rc = time_search(tab, 1, x, big, out, SS_ALGO_BINARY, -1, 3, &ns)) != SS_OK) return rc;
+  m.stream_gbs = 12.0 / ns;
+  // 2. bisection on cache-resident targets
+  std::vector<double> sx, sy;
+  for (int n : {64, 256, 1024, 4096}) {
+    if ((rc = put_table(n)) != SS_OK) return rc;
+    if ((rc = time_search(tab, n, x, small, out, SS_ALGO_BINARY, -1, 10, &ns)) != SS_OK) return rc;
+    sx.push_back(bisect_steps(n));
+    sy.push_back(ns);
+  }
+  fit_line(sx, sy, &m.bin_base_ns, &m.bin_per_step_ns);
+  // 3. exponent hash at several longest-bin lengths (32 entries per binade)
+  std::vector<double> kx, ky;
+  if ((rc = put_table(1024)) != SS_OK) return rc;
+  std::vector<double> h(1024);
+  for (int i = 0; i < 1024; ++i) h[i] = std::exp2(32.0 * (i + 0.5) / 1024);
+  for (int s : {2, 3, 4, 5, 6}) {
+    const int K = host_longest_bin(h.data(), 1024, s);
+    if (K > SS_SCAN_MAX) continue;
+    if ((rc = time_search(tab, 1024, x, small, out, SS_ALGO_EXPHASH, s, 10, &ns)) != SS_OK) return rc;
+    kx.push_back(K);
+    ky.push_back(ns);
+  }
+  if (kx.size() >= 2) fit_line(kx, ky, &m.hash_base_ns, &m.hash_per_k_ns);
+  m.calibrated = 1;
+  std::lock_guard<std::mutex> lk(g_tuner_mu);
+  g_model = m;
+  g_model_init = true;
+  g_model_arch = di.arch;
+  return SS_OK;
+}
+
+int ss_tuner_get(double* coeffs, int count) {
+  clear_error();
+  if (!coeffs || count < 7) return fail(SS_ERR_INVALID_ARG, "need room for 7 coefficients");
+  const TunerModel m = tuner_model();
+  coeffs[0] = m.stream_gbs;
+  coeffs[1] = m.hash_base_ns;
+  coeffs[2] = m.hash_per_k_ns;
+  coeffs[3] = m.bin_base_ns;
+  coeffs[4] = m.bin_per_step_ns;
+  coeffs[5] = m.stage_ns_per_kb;
+  coeffs[6] = m.calibrated;
+  return SS_OK;
+}
+
+int ss_tuner_save(const char* path) {
+  clear_error();
+  if (!path) return fail(SS_ERR_INVALID_ARG, "path is null");
+  TunerModel m;
+  std::string arch;
+  {
+    std::lock_guard<std::mutex> lk(g_tuner_mu);
+    init_model_locked();
+    m = g_model;
+    arch = g_model_arch;
+  }
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  std::fprintf(f,
+               "{\n  \"arch\": \"%s\",\n  \"stream_gbs\": %.17g,\n  \"hash_base_ns\": %.17g,\n"
+               "  \"hash_per_k_ns\": %.17g,\n  \"bin_base_ns\": %.17g,\n"
+               "  \"bin_per_step_ns\": %.17g,\n  \"stage_ns_per_kb\": %.17g,\n"
+               "  \"calibrated\": %d\n}\n",
+               arch.c_str(), m.stream_gbs, m.hash_base_ns, m.hash_per_k_ns, m.bin_base_ns,
+               m.bin_per_step_ns, m.stage_ns_per_kb, m.calibrated);
+  const bool ok = std::fclose(f) == 0;
+  return ok ? SS_OK : fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+}
+
+int ss_tuner_load(const char* path) {
+  clear_error();
+  if (!path) return fail(SS_ERR_INVALID_ARG, "path is null");
+  TunerModel m;
+  std::string arch;
+  int rc = load_file(path, &m, &arch);
+  if (rc != SS_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_tuner_mu);
+  g_model = m;
+  g_model_init = true;
+  g_model_arch = arch;
+  return SS_OK;
+}
+
+}  // extern "C"

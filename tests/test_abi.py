@@ -77,3 +77,48 @@ def test_host_pointers_are_rejected(L):
     # either way a status code, never a crash
     assert rc in (-2, -3, -4)
     assert L.ss_last_error()
+
+
+def test_tuner_model_save_load_roundtrip(L, tmp_path):
+    from paper_2112_03229_amd import binding as b
+    before = b.tuner_get()
+    assert before["stream_gbs"] > 0 and before["calibrated"] in (0.0, 1.0)
+    path = tmp_path / "model.json"
+    b.tuner_save(str(path))
+    # an edited coefficient is picked up on load, the original restores it
+    text = path.read_text()
+    edited = tmp_path / "edited.json"
+    edited.write_text(text.replace(f'"stream_gbs": {before["stream_gbs"]:.17g}',
+                                   '"stream_gbs": 1234.5'))
+    b.tuner_load(str(edited))
+    assert b.tuner_get()["stream_gbs"] == 1234.5
+    b.tuner_load(str(path))
+    assert b.tuner_get() == before
+    # a malformed file is rejected and leaves the model unchanged
+    bad = tmp_path / "bad.json"
+    bad.write_text('{ "stream_gbs": 5 }')
+    with pytest.raises(b.SearchSortedError):
+        b.tuner_load(str(bad))
+    with pytest.raises(b.SearchSortedError):
+        b.tuner_load(str(tmp_path / "missing.json"))
+    assert b.tuner_get() == before
+
+
+def test_plan_argument_errors(L):
+    import numpy as np
+    P = ctypes.c_void_p
+    h = ctypes.c_void_p()
+    off_bad = np.array([0, 5, 3], dtype=np.int64)
+    off_ok = np.array([0, 5, 10], dtype=np.int64)
+    assert L.ss_multi_plan_create(P(0x10000), off_bad.ctypes.data_as(P), 2,
+                                  off_ok.ctypes.data_as(P), ctypes.byref(h)) == -1
+    assert L.ss_multi_plan_create(P(0x10000), off_ok.ctypes.data_as(P), 0,
+                                  off_ok.ctypes.data_as(P), ctypes.byref(h)) == -1
+    assert L.ss_multi_plan_create(P(0x10000), off_ok.ctypes.data_as(P), 2,
+                                  off_ok.ctypes.data_as(P), None) == -1
+    long_off = np.array([0, 70000], dtype=np.int64)
+    assert L.ss_multi_plan_create(P(0x10000), long_off.ctypes.data_as(P), 1,
+                                  off_ok.ctypes.data_as(P), ctypes.byref(h)) == -1
+    assert L.ss_multi_search(None, P(0x10000), P(0x20000)) == -1
+    assert L.ss_pair_search(None, P(0x10000), P(0x20000), P(0x30000), P(0x40000)) == -1
+    assert L.ss_plan_destroy(None) == 0

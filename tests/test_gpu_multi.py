@@ -1,0 +1,208 @@
+"""GPU parity of the batched (many tables, one launch) and paired searches.
+
+Each table's slice of the output must equal the oracle's definition applied
+to that table alone (composition), bit for bit.  Full-size workloads (512
+tables with ~7.4e8 targets; 4096 materials with 1e9 pairs) are checked on
+every index with the bracket property and on a seeded sample with the
+oracle's definition.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def binding(gpu):
+    from paper_2112_03229_amd import binding as b
+    return b
+
+
+def odd_batch(inputs_mod, seed=5):
+    """A batch mixing generated log tables with edge tables: a single entry,
+    an empty table, negative entries, duplicates, and empty target slices."""
+    base = inputs_mod.batched_layout(seed=seed, num_tables=24, query_scale=2e-3)
+    tabs = [base.table(t) for t in range(base.num_tables)]
+    counts = list(np.diff(base.query_off))
+    extra = [
+        (np.array([1.0]), 3001),
+        (np.zeros(0), 777),
+        (np.array([-5.0, -1.0, -0.0, 0.0, 2.0, 1e10]), 4096),
+        (np.repeat(np.array([1e-3, 1.0, 7.0]), [30, 2, 40]), 5000),
+        (inputs_mod.single_table(1000), 0),
+        (inputs_mod.single_table(2000), 70001),
+        (np.array([0.0, 5e-324, 1e-310, 1.0]), 999),
+    ]
+    for t, c in extra:
+        tabs.append(t.astype(np.float64))
+        counts.append(c)
+    toff = np.zeros(len(tabs) + 1, dtype=np.int64)
+    toff[1:] = np.cumsum([t.shape[0] for t in tabs])
+    qoff = np.zeros(len(tabs) + 1, dtype=np.int64)
+    qoff[1:] = np.cumsum(counts)
+    tables = np.concatenate(tabs)
+    # targets: log-uniform around each table, with exact hits and specials
+    x = np.empty(qoff[-1])
+    for t in range(len(tabs)):
+        q0, q1 = qoff[t], qoff[t + 1]
+        if q1 == q0:
+            continue
+        tab = tabs[t]
+        lo, hi = (0.5 * abs(tab[0]) + 1e-300, 2.0 * abs(tab[-1]) + 1e-300) if tab.size else (1e-3, 1e3)
+        lo, hi = min(lo, hi), max(lo, hi)
+        seg = inputs_mod.log_uniform(seed + t, 3, lo, max(hi, lo * 10), q1 - q0)
+        if tab.size:
+            k = np.arange(0, q1 - q0, 5)
+            seg[k] = tab[k % tab.size]
+        seg[::7] *= -1.0 if tab.size and tab[0] < 0 else 1.0
+        sp = inputs_mod.special_values()
+        seg[:min(sp.size, seg.size)] = sp[:min(sp.size, seg.size)]
+        x[q0:q1] = seg
+    return tables, toff, qoff, x
+
+
+def test_batched_composition(binding, gpu, oracle_mod, inputs_mod):
+    tables, toff, qoff, x = odd_batch(inputs_mod)
+    want = oracle_mod.search_lt_segments(tables, toff, x, qoff)
+    say(f"case batched T={toff.size - 1} m={x.size}")
+    plan = binding.MultiPlan(torch.from_numpy(tables).to(gpu), toff, qoff)
+    xt = torch.from_numpy(x).to(gpu)
+    out = plan.search(xt)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], want[bad[:5]], x[bad[:5]])
+    info = plan.info()
+    T = toff.size - 1
+    assert info["tables"] == T and info["graph_uses"] == 1
+    # generated log tables hash; the table with negative entries bisects
+    assert info["algos"][0] == binding.ALGO_EXPHASH
+    assert info["algos"][T - 5] == binding.ALGO_BINARY
+    # repeat (graph replay), then new buffers (graph parameter update)
+    out.fill_(-7)
+    plan.search(xt, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    x2 = x.copy()
+    x2[::3] = np.where(np.isfinite(x2[::3]), x2[::3] * 0.75, x2[::3])
+    want2 = oracle_mod.search_lt_segments(tables, toff, x2, qoff)
+    out2 = plan.search(torch.from_numpy(x2).to(gpu))
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.cpu().numpy(), want2)
+    assert plan.info()["graph_uses"] == 3
+    plan.close()
+
+
+def test_batched_rejects_bad_arguments(binding, gpu, inputs_mod):
+    t = torch.from_numpy(inputs_mod.single_table(100)).to(gpu)
+    with pytest.raises(binding.SearchSortedError):
+        binding.MultiPlan(t, [0, 50, 40], [0, 10, 20])       # decreasing table offsets
+    with pytest.raises(binding.SearchSortedError):
+        binding.MultiPlan(t, [1, 100], [0, 10])               # offsets must start at 0
+    big = torch.zeros(70000, dtype=torch.float64, device=gpu)
+    with pytest.raises(binding.SearchSortedError):
+        binding.MultiPlan(big, [0, 70000], [0, 10])           # table over 65535 entries
+    plan = binding.MultiPlan(t, [0, 100], [0, 10])
+    with pytest.raises(ValueError):
+        plan.search(torch.zeros(11, dtype=torch.float64, device=gpu))
+
+
+def test_paired_composition(binding, gpu, oracle_mod, inputs_mod):
+    pairs = inputs_mod.paired_layout(seed=9, materials=96, total_pairs=2 * 10**6)
+    rho, temp = inputs_mod.paired_targets(pairs, seed=9)
+    rho[:4] = [np.nan, -1.0, np.inf, 0.0]
+    want_r = oracle_mod.search_lt_segments(pairs.rho.tables, pairs.rho.table_off, rho,
+                                           pairs.rho.query_off)
+    want_t = oracle_mod.search_lt_segments(pairs.temp.tables, pairs.temp.table_off, temp,
+                                           pairs.temp.query_off)
+    say(f"case paired M={pairs.num_materials} pairs={pairs.num_pairs}")
+    plan = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(gpu), pairs.rho.table_off,
+                            torch.from_numpy(pairs.temp.tables).to(gpu), pairs.temp.table_off,
+                            pairs.rho.query_off)
+    out_r, out_t = plan.search(torch.from_numpy(rho).to(gpu), torch.from_numpy(temp).to(gpu))
+    torch.cuda.synchronize()
+    assert np.array_equal(out_r.cpu().numpy(), want_r)
+    assert np.array_equal(out_t.cpu().numpy(), want_t)
+    info = plan.info()
+    assert info["tables"] == 2 * pairs.num_materials
+    algos = info["algos"]
+    assert np.all((algos == binding.ALGO_EXPHASH) | (algos == binding.ALGO_BINARY))
+    assert np.count_nonzero(algos == binding.ALGO_EXPHASH) > algos.size // 2
+    assert np.all((info["bits"] >= 0) == (algos == binding.ALGO_EXPHASH))
+
+
+def test_tuner_calibration_roundtrip(binding, gpu, oracle_mod, inputs_mod, tmp_path):
+    coeffs = binding.tuner_calibrate()
+    say(f"tuner: {coeffs}")
+    assert coeffs["calibrated"] == 1.0
+    assert 1000 < coeffs["stream_gbs"] < 20000
+    assert coeffs["bin_per_step_ns"] >= 0 and coeffs["hash_per_k_ns"] >= 0
+    path = str(tmp_path / "tuner.json")
+    binding.tuner_save(path)
+    binding.tuner_load(path)
+    assert binding.tuner_get() == coeffs
+    # a plan tuned with the calibrated model is still exact
+    batch = inputs_mod.batched_layout(seed=21, num_tables=16, query_scale=1e-3)
+    x = inputs_mod.batched_targets(batch, seed=21)
+    plan = binding.MultiPlan(torch.from_numpy(batch.tables).to(gpu), batch.table_off,
+                             batch.query_off)
+    got = plan.search(torch.from_numpy(x).to(gpu)).cpu().numpy()
+    want = oracle_mod.search_lt_segments(batch.tables, batch.table_off, x, batch.query_off)
+    assert np.array_equal(got, want)
+
+
+def test_full_size_batched(binding, gpu, oracle_mod, inputs_mod):
+    """512 tables, n uniform on 20..2000, ~7.4e8 targets, one launch."""
+    batch = inputs_mod.batched_layout()
+    m = batch.num_queries
+    say(f"case full batched T=512 m={m}")
+    host = torch.empty(m, dtype=torch.float64).pin_memory()
+    x = inputs_mod.batched_targets(batch, out=host.numpy())
+    plan = binding.MultiPlan(torch.from_numpy(batch.tables).to(gpu), batch.table_off,
+                             batch.query_off)
+    xt = host.to(gpu, non_blocking=True)
+    out = plan.search(xt)
+    got = out.cpu().numpy()
+    del xt, out
+    bad, first = oracle_mod.check_bracket_segments(batch.tables, batch.table_off, x,
+                                                   batch.query_off, got)
+    assert bad == 0, first
+    pos = np.sort((inputs_mod.uniform(512, 97, 400000) * m).astype(np.int64))
+    seg = np.searchsorted(batch.query_off, pos, side="right") - 1
+    for t in np.unique(seg)[:512]:
+        p = pos[seg == t]
+        tab = batch.table(t)
+        assert np.array_equal(got[p], oracle_mod.search_lt_at(tab, x, p)), t
+
+
+def test_full_size_paired(binding, gpu, oracle_mod, inputs_mod):
+    """4096 materials (density 50..4000 entries, temperature 20..1000), 1e9
+    pairs, both searches in one launch."""
+    pairs = inputs_mod.paired_layout()
+    m = pairs.num_pairs
+    say(f"case full paired M=4096 pairs={m}")
+    hr = torch.empty(m, dtype=torch.float64).pin_memory()
+    ht = torch.empty(m, dtype=torch.float64).pin_memory()
+    rho, temp = inputs_mod.paired_targets(pairs, out_rho=hr.numpy(), out_t=ht.numpy())
+    plan = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(gpu), pairs.rho.table_off,
+                            torch.from_numpy(pairs.temp.tables).to(gpu), pairs.temp.table_off,
+                            pairs.rho.query_off)
+    dr, dt = hr.to(gpu, non_blocking=True), ht.to(gpu, non_blocking=True)
+    out_r, out_t = plan.search(dr, dt)
+    got_r = out_r.cpu().numpy()
+    got_t = out_t.cpu().numpy()
+    del dr, dt, out_r, out_t
+    for name, b, x, got in (("rho", pairs.rho, rho, got_r), ("temp", pairs.temp, temp, got_t)):
+        say(f"check {name}")
+        bad, first = oracle_mod.check_bracket_segments(b.tables, b.table_off, x, b.query_off, got)
+        assert bad == 0, (name, first)
+        pos = np.sort((inputs_mod.uniform(4096, 98, 200000) * m).astype(np.int64))
+        seg = np.searchsorted(b.query_off, pos, side="right") - 1
+        for t in np.unique(seg)[::8]:
+            p = pos[seg == t]
+            assert np.array_equal(got[p], oracle_mod.search_lt_at(b.table(t), x, p)), (name, t)
