@@ -130,6 +130,83 @@ def copy_calibration(torch) -> None:
     print(json.dumps({"copy_calibration_bytes": n * 8, "dispatches": 3}), flush=True)
 
 
+def time_call(torch, fn, reps: int = 5) -> float:
+    """Average milliseconds of fn() over reps calls on the current stream
+    (after one untimed call)."""
+    fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def roof(queries: int, ms: float) -> dict:
+    gbs = queries * BYTES_PER_QUERY / (ms * 1e-3) / 1e9
+    return {"gqps": round(queries / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def measure_batched(torch, binding, inputs, dev) -> dict:
+    """512 tables (n uniform on 20..2000), ~7.4e8 targets, one plan launch."""
+    batch = inputs.batched_layout()
+    m = batch.num_queries
+    host = torch.empty(m, dtype=torch.float64).pin_memory()
+    inputs.batched_targets(batch, out=host.numpy())
+    x = host.to(dev)
+    out = torch.empty(m, dtype=torch.int32, device=dev)
+    plan = binding.MultiPlan(torch.from_numpy(batch.tables).to(dev), batch.table_off,
+                             batch.query_off)
+    ms = time_call(torch, lambda: plan.search(x, out))
+    info = plan.info()
+    res = {"workload": "512 tables, n uniform on 20..2000, ranges within [1e-10,1e8], "
+                       f"{m} targets (query counts log-uniform on 1e4..1e7)",
+           **roof(m, ms),
+           "exphash_tables": int((info["algos"] == binding.ALGO_EXPHASH).sum()),
+           "tiles": info["tiles"], "tiles_per_wg": info["tiles_per_wg"],
+           "grid": info["grid"], "lds_bytes": info["lds_bytes"]}
+    # plain search: the same tables one single-table launch at a time
+    tabs = [torch.from_numpy(batch.table(t)).to(dev) for t in range(batch.num_tables)]
+    qo = batch.query_off
+
+    def plain():
+        for t in range(batch.num_tables):
+            binding.search_sorted_batch(tabs[t], x[qo[t]:qo[t + 1]], out[qo[t]:qo[t + 1]])
+    res["plain_per_table_launches"] = roof(m, time_call(torch, plain, reps=2))
+    del x, out, host
+    return res
+
+
+def measure_paired(torch, binding, inputs, dev) -> dict:
+    """4096 materials, density (50..4000) and temperature (20..1000) tables,
+    1e9 pairs = 2e9 searches in one launch."""
+    pairs = inputs.paired_layout()
+    m = pairs.num_pairs
+    hr = torch.empty(m, dtype=torch.float64).pin_memory()
+    ht = torch.empty(m, dtype=torch.float64).pin_memory()
+    inputs.paired_targets(pairs, out_rho=hr.numpy(), out_t=ht.numpy())
+    r, t = hr.to(dev), ht.to(dev)
+    del hr, ht
+    o_r = torch.empty(m, dtype=torch.int32, device=dev)
+    o_t = torch.empty(m, dtype=torch.int32, device=dev)
+    plan = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(dev), pairs.rho.table_off,
+                            torch.from_numpy(pairs.temp.tables).to(dev), pairs.temp.table_off,
+                            pairs.rho.query_off)
+    ms = time_call(torch, lambda: plan.search(r, t, o_r, o_t), reps=3)
+    info = plan.info()
+    res = {"workload": f"4096 materials, {m} (rho, T) pairs, 2 searches per pair",
+           **roof(2 * m, ms),
+           "exphash_tables": int((info["algos"] == binding.ALGO_EXPHASH).sum()),
+           "tables": info["tables"], "tiles": info["tiles"],
+           "tiles_per_wg": info["tiles_per_wg"], "grid": info["grid"],
+           "lds_bytes": info["lds_bytes"]}
+    del r, t, o_r, o_t
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +215,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-kernels", action="store_true",
                     help="skip the per-kernel comparison after the timed region")
+    ap.add_argument("--no-systems", action="store_true",
+                    help="skip the batched and paired plan measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -264,6 +343,17 @@ def main():
                 row[algo] = round(M / (ms * 1e-3) / 1e9, 2)
             comp[f"n={TABLE_SIZES[i]}/{o}"] = row
         result["kernels_gqps"] = comp
+
+    if not args.no_systems:
+        # free the single-table workload before the larger ones
+        del d_x, d_out
+        torch.cuda.empty_cache()
+        log("bench: batched plan")
+        result["batched"] = measure_batched(torch, binding, inputs, dev)
+        torch.cuda.empty_cache()
+        log("bench: paired plan")
+        result["paired"] = measure_paired(torch, binding, inputs, dev)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         log("bench: CPU oracle baseline")

@@ -93,8 +93,10 @@ typedef enum {
                                     the device (persistent grid) */
     SS_OPT_CHECK_POINTERS = 6,   /* 1 (default): verify that buffers are
                                     device memory before launching; 0: skip */
-    SS_OPT_TARGETS_PER_LANE = 7  /* targets each lane keeps in flight per
+    SS_OPT_TARGETS_PER_LANE = 7, /* targets each lane keeps in flight per
                                     tile: 4 or 8; 0 (default) = auto */
+    SS_OPT_PLAN_TILES = 8        /* tiles per workgroup of plans built
+                                    afterwards; 0 (default) = tuner */
 } ss_option;
 
 /* Human-readable message for the calling thread's most recent error
@@ -169,10 +171,10 @@ SS_API int ss_exphash_bins(const double *table, int64_t n, int bucket_bits, int3
  * A plan is built once per set of tables (the setup the paper pays once per
  * table load, Sec. 5.3) and then searched many times.  Building it copies
  * the tables to the host once, lets the autotuner choose, per table, the
- * kernel (exponent hash or bisection), the hash's bin bits and the chunk of
- * targets a workgroup takes at a time, builds the exponent-hash bin tables
- * on the device, and prepares a HIP graph that runs the whole batch as one
- * persistent launch over a work queue.  Plans own device memory; the tables
+ * kernel (exponent hash or bisection) and the hash's bin bits, and the
+ * number of consecutive target tiles a workgroup takes, builds the
+ * exponent-hash bin tables on the device, and prepares a HIP graph whose
+ * one kernel node searches the whole batch.  Plans own device memory; the tables
  * are referenced (not copied) and must stay valid and unchanged while the
  * plan is used.  A plan may be used from one thread at a time.
  * ------------------------------------------------------------------------- */
@@ -217,8 +219,9 @@ SS_API int ss_plan_destroy(ss_plan *plan);
  *   SS_PLAN_ALGOS  : int32 per table (ss_algo); paired plans list the
  *                    density tables, then the temperature tables
  *   SS_PLAN_BITS   : int32 per table (bin bits s, -1 for bisection)
- *   SS_PLAN_SUMMARY: 8 int64 {tables, chunks, chunk_targets, grid, block,
- *                    lds_bytes, max bin occupancy, graph uses}
+ *   SS_PLAN_SUMMARY: 8 int64 {tables, tiles, tiles per workgroup, grid,
+ *                    block, lds_bytes, longest bin (9 = 9 or more),
+ *                    graph launches so far}
  * `cap` is the number of elements `out` can hold. */
 typedef enum { SS_PLAN_ALGOS = 1, SS_PLAN_BITS = 2, SS_PLAN_SUMMARY = 3 } ss_plan_query;
 SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
@@ -239,10 +242,13 @@ SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
  * SYNCHRONOUS. */
 SS_API int ss_tuner_calibrate(void);
 
-/* coeffs (host) receives 7 doubles: {stream GB/s, hash fixed ns, hash ns per
+/* coeffs (host) receives 8 doubles: {stream GB/s, hash fixed ns, hash ns per
  * scanned entry, bisection fixed ns, bisection ns per step, ns per KB
- * restaged, calibrated flag}.  count must be >= 7. */
+ * restaged, calibrated flag, most bins per table entry}.  count must be
+ * >= 8.  ss_tuner_set replaces the model with such 8 values (all finite and
+ * non-negative; bandwidth and bins per entry positive). */
 SS_API int ss_tuner_get(double *coeffs, int count);
+SS_API int ss_tuner_set(const double *coeffs, int count);
 
 /* Saves / loads the model as JSON at a host file path. */
 SS_API int ss_tuner_save(const char *path);

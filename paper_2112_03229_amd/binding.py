@@ -29,6 +29,7 @@ ALGO_IDS = {v: k for k, v in ALGO_NAMES.items()}
 OPT_FORCE_ALGO, OPT_BUCKET_BITS, OPT_BUCKET_CAP = 1, 2, 3
 OPT_BLOCK_SIZE, OPT_GRID_BLOCKS, OPT_CHECK_POINTERS = 4, 5, 6
 OPT_TARGETS_PER_LANE = 7
+OPT_PLAN_TILES = 8
 
 
 class SearchSortedError(RuntimeError):
@@ -79,6 +80,7 @@ def _register_extra(L) -> None:
         "ss_pair_search": [P, P, P, P, P],
         "ss_tuner_calibrate": [],
         "ss_tuner_get": [P, I],
+        "ss_tuner_set": [P, I],
         "ss_tuner_save": [ctypes.c_char_p],
         "ss_tuner_load": [ctypes.c_char_p],
         "ss_learned_build": [P, I64, P, ctypes.POINTER(P)],
@@ -194,7 +196,7 @@ def exphash_bins(table: torch.Tensor, bucket_bits: int = -1, cap: int = 1 << 16)
 # ---------------------------------------------------------------------------
 
 PLAN_ALGOS, PLAN_BITS, PLAN_SUMMARY = 1, 2, 3
-SUMMARY_KEYS = ("tables", "chunks", "chunk_targets", "grid", "block", "lds_bytes",
+SUMMARY_KEYS = ("tables", "tiles", "tiles_per_wg", "grid", "block", "lds_bytes",
                 "max_bin", "graph_uses")
 
 
@@ -319,7 +321,7 @@ class PairPlan(_Plan):
 # ---------------------------------------------------------------------------
 
 TUNER_KEYS = ("stream_gbs", "hash_base_ns", "hash_per_k_ns", "bin_base_ns", "bin_per_step_ns",
-              "stage_ns_per_kb", "calibrated")
+              "stage_ns_per_kb", "calibrated", "bins_per_entry")
 
 
 def tuner_calibrate() -> dict:
@@ -329,9 +331,21 @@ def tuner_calibrate() -> dict:
 
 
 def tuner_get() -> dict:
-    buf = (ctypes.c_double * 7)()
-    check(lib().ss_tuner_get(buf, 7))
+    buf = (ctypes.c_double * 8)()
+    check(lib().ss_tuner_get(buf, 8))
     return dict(zip(TUNER_KEYS, list(buf)))
+
+
+def tuner_set(**changes) -> dict:
+    """Replaces named coefficients of the model (others unchanged)."""
+    cur = tuner_get()
+    unknown = set(changes) - set(TUNER_KEYS)
+    if unknown:
+        raise KeyError(sorted(unknown))
+    cur.update(changes)
+    buf = (ctypes.c_double * 8)(*[float(cur[k]) for k in TUNER_KEYS])
+    check(lib().ss_tuner_set(buf, 8))
+    return tuner_get()
 
 
 def tuner_save(path: str) -> None:

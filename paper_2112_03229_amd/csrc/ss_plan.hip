@@ -1,17 +1,18 @@
 // Many tables in one launch: plans, the autotuner's per-table choices, the
-// device-built exponent-hash bin tables, the persistent work-queue kernel
-// (batched and paired forms) and the HIP graph that launches it.
+// device-built exponent-hash bin tables, the search kernel (batched and
+// paired forms) and the HIP graph that launches it.
 //
-// A plan splits every table's targets into chunks (the tile shape the tuner
-// picks), orders the chunks longest first, and runs one persistent grid in
-// which each workgroup pops chunks from an atomic counter.  On popping a
-// chunk of a table it has not staged, the workgroup copies that table and
-// its precomputed bin table from global memory into LDS (a table change is
-// the only restaging); the first tile's targets are requested before the
-// copy so their latency overlaps it.  Inside a chunk, tiles are streamed
-// sequentially with the next tile prefetched, exactly as in the
-// single-table kernels.  The counter is zeroed by a one-thread kernel node
-// that precedes the search node in the plan's graph.
+// Every table's targets are cut into tiles of blockDim.x * Q targets (the
+// last tile of a table may be short), and the tiles of all tables are
+// numbered back to back.  Workgroup w of the grid searches the k
+// consecutive tiles [w k, (w+1) k) -- k is the tile shape the tuner picks --
+// so the grid is several times the resident workgroup count and the
+// hardware dispatcher balances it, exactly like the single-table launch.  A
+// workgroup stages the table of its first tile (copying the table and its
+// precomputed bin table from global memory into LDS) after requesting that
+// tile's targets, and restages only when its range crosses into the next
+// table.  Tiles are streamed with the next tile prefetched.  No atomics,
+// no work queue: a plan is one kernel node in its graph.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -35,32 +36,28 @@ struct TableDesc {
   int pad_;
 };
 
-struct Chunk {
-  int32_t table;     // table (batched) or material (paired) index
-  int32_t pad_;
-  int64_t q0, q1;    // target positions [q0, q1)
-};
-
 struct MultiArgs {
   const double* tables_a;
   const double* tables_b;
   const TableDesc* desc;     // [T] batched; [2M] paired (density, then temperature)
   const uint16_t* bins;
-  const Chunk* chunks;
-  unsigned int* counter;
+  const int64_t* tile_off;   // [S+1] first tile of each segment (table or material)
+  const int64_t* query_off;  // [S+1] first target of each segment
+  const int32_t* wg_seg;     // [grid] segment of each workgroup's first tile
   const double* xa;
   int32_t* oa;
   const double* xb;
   int32_t* ob;
-  int nchunks;
+  int64_t total_tiles;
+  int tiles_per_wg;
   int pair_base;             // index of the first temperature descriptor (paired)
   int lds_bins_a, lds_tab_b, lds_bins_b;  // byte offsets in LDS
 };
 
-__global__ void reset_counter_kernel(unsigned int* counter) { *counter = 0u; }
-
 // Copies one table (+inf padded) and, for the exponent hash, its bin table
-// into LDS.  Returns the search parameters.
+// into LDS with 16-byte loads (the pool's bin tables start 16-byte aligned;
+// tables are 8-byte aligned, so they are copied in 8-byte words).  Returns
+// the search parameters.
 __device__ __forceinline__ HashParams stage_desc(const TableDesc& d, const double* __restrict__ tables,
                                                  const uint16_t* __restrict__ bins, double* sa,
                                                  uint16_t* C) {
@@ -68,8 +65,11 @@ __device__ __forceinline__ HashParams stage_desc(const TableDesc& d, const doubl
   HashParams hp{0, d.shift, d.kmin, d.kmaxc, d.nb, d.K};
   if (d.algo == SS_ALGO_EXPHASH) {
     hp.ok = 1;
-    const uint16_t* src = bins + d.bins_off;
-    for (int b = threadIdx.x; b <= d.nb; b += blockDim.x) C[b] = src[b];
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* src = reinterpret_cast<const u32x4*>(bins + d.bins_off);
+    u32x4* dst = reinterpret_cast<u32x4*>(C);
+    const int words = (d.nb + 1 + 7) / 8;  // the pool pads every table to 8 entries
+    for (int w = threadIdx.x; w < words; w += blockDim.x) dst[w] = src[w];
   }
   return hp;
 }
@@ -82,73 +82,105 @@ __device__ __forceinline__ void search_desc(const HashParams& hp, const double* 
   else search_binary<Q>(sa, n, x, r);
 }
 
+// Offsets of one segment (table or material), kept in registers while a
+// workgroup walks its tiles; reloaded only when the walk enters the next
+// segment.
+struct Segment {
+  int seg;
+  int64_t t0, t1;  // its tiles [t0, t1)
+  int64_t q0, q1;  // its targets [q0, q1)
+};
+
+__device__ __forceinline__ Segment load_segment(const MultiArgs& a, int seg) {
+  return {seg, a.tile_off[seg], a.tile_off[seg + 1], a.query_off[seg], a.query_off[seg + 1]};
+}
+
+struct TileRange {
+  int64_t q0, q1;
+};
+
+__device__ __forceinline__ TileRange tile_range(const Segment& s, int64_t j, int64_t per_tile) {
+  const int64_t q0 = s.q0 + (j - s.t0) * per_tile;
+  return {q0, min(q0 + per_tile, s.q1)};
+}
+
 template <int Q>
-__device__ __forceinline__ void load_range_tile(const double* __restrict__ x, int64_t q0, int64_t q1,
-                                                int64_t t, double (&v)[Q]) {
+__device__ __forceinline__ void load_range(const double* __restrict__ x, TileRange r,
+                                           double (&v)[Q]) {
   const int nt = blockDim.x;
-  const int64_t per_tile = (int64_t)nt * Q;
-  const int64_t base = q0 + t * per_tile;
-  load_tile<Q>(x, q1, base + threadIdx.x, nt, base + per_tile <= q1, v);
+  load_tile<Q>(x, r.q1, r.q0 + threadIdx.x, nt, r.q0 + (int64_t)nt * Q <= r.q1, v);
 }
 
 template <int PAIRED, int Q>
 __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
-  __shared__ int s_chunk;
   double* sa = reinterpret_cast<double*>(lds);
   uint16_t* Ca = reinterpret_cast<uint16_t*>(lds + a.lds_bins_a);
   double* sb = reinterpret_cast<double*>(lds + a.lds_tab_b);
   uint16_t* Cb = reinterpret_cast<uint16_t*>(lds + a.lds_bins_b);
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
-  int staged = -1;
-  HashParams hpa{}, hpb{};
-  int na = 0, nb_ = 0;
-  for (;;) {
-    if (threadIdx.x == 0) s_chunk = (int)atomicAdd(a.counter, 1u);
-    __syncthreads();
-    const int c = s_chunk;
-    __syncthreads();  // every lane has read s_chunk before it is written again
-    if (c >= a.nchunks) break;
-    const Chunk ch = a.chunks[c];
-    const int64_t mq = ch.q1 - ch.q0;
-    const int64_t ntiles = (mq + per_tile - 1) / per_tile;
-    double ca[Q], cb[Q];
-    load_range_tile<Q>(a.xa, ch.q0, ch.q1, 0, ca);
-    if constexpr (PAIRED) load_range_tile<Q>(a.xb, ch.q0, ch.q1, 0, cb);
-    if (ch.table != staged) {
-      const TableDesc da = a.desc[ch.table];
+  const int64_t j0 = (int64_t)blockIdx.x * a.tiles_per_wg;
+  const int64_t j1 = min(j0 + (int64_t)a.tiles_per_wg, a.total_tiles);
+  if (j0 >= j1) return;
+  Segment sg = load_segment(a, a.wg_seg[blockIdx.x]);
+  TileRange cur = tile_range(sg, j0, per_tile);
+  double ca[Q], cb[Q];
+  load_range<Q>(a.xa, cur, ca);
+  if constexpr (PAIRED) load_range<Q>(a.xb, cur, cb);
+
+  HashParams hpa, hpb{};
+  int na, nb_ = 0;
+  {
+    const TableDesc da = a.desc[sg.seg];
+    hpa = stage_desc(da, a.tables_a, a.bins, sa, Ca);
+    na = da.n;
+    if constexpr (PAIRED) {
+      const TableDesc db = a.desc[a.pair_base + sg.seg];
+      hpb = stage_desc(db, a.tables_b, a.bins, sb, Cb);
+      nb_ = db.n;
+    }
+  }
+  __syncthreads();
+  for (int64_t j = j0; j < j1; ++j) {
+    // the next tile, possibly in a later segment (segments without targets
+    // have no tiles and are skipped)
+    const bool has_next = j + 1 < j1;
+    Segment nsg = sg;
+    double xa_n[Q], xb_n[Q];
+    TileRange nxt{0, 0};
+    if (has_next) {
+      while (j + 1 >= nsg.t1) nsg = load_segment(a, nsg.seg + 1);
+      nxt = tile_range(nsg, j + 1, per_tile);
+      load_range<Q>(a.xa, nxt, xa_n);
+      if constexpr (PAIRED) load_range<Q>(a.xb, nxt, xb_n);
+    }
+    const bool full = cur.q0 + per_tile <= cur.q1;
+    int r[Q];
+    search_desc<Q>(hpa, sa, Ca, na, ca, r);
+    store_tile<Q>(a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
+    if constexpr (PAIRED) {
+      search_desc<Q>(hpb, sb, Cb, nb_, cb, r);
+      store_tile<Q>(a.ob, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
+    }
+    if (!has_next) break;
+    if (nsg.seg != sg.seg) {
+      __syncthreads();  // every lane is done with the old table
+      const TableDesc da = a.desc[nsg.seg];
       hpa = stage_desc(da, a.tables_a, a.bins, sa, Ca);
       na = da.n;
       if constexpr (PAIRED) {
-        const TableDesc db = a.desc[a.pair_base + ch.table];
+        const TableDesc db = a.desc[a.pair_base + nsg.seg];
         hpb = stage_desc(db, a.tables_b, a.bins, sb, Cb);
         nb_ = db.n;
       }
-      staged = ch.table;
       __syncthreads();
     }
-    for (int64_t t = 0;; ++t) {
-      const bool has_next = t + 1 < ntiles;
-      double xa_n[Q], xb_n[Q];
-      if (has_next) {
-        load_range_tile<Q>(a.xa, ch.q0, ch.q1, t + 1, xa_n);
-        if constexpr (PAIRED) load_range_tile<Q>(a.xb, ch.q0, ch.q1, t + 1, xb_n);
-      }
-      const int64_t base = ch.q0 + t * per_tile;
-      const bool full = base + per_tile <= ch.q1;
-      int r[Q];
-      search_desc<Q>(hpa, sa, Ca, na, ca, r);
-      store_tile<Q>(a.oa, ch.q1, base + threadIdx.x, nt, full, r);
-      if constexpr (PAIRED) {
-        search_desc<Q>(hpb, sb, Cb, nb_, cb, r);
-        store_tile<Q>(a.ob, ch.q1, base + threadIdx.x, nt, full, r);
-      }
-      if (!has_next) break;
-      for (int q = 0; q < Q; ++q) {
-        ca[q] = xa_n[q];
-        if constexpr (PAIRED) cb[q] = xb_n[q];
-      }
+    sg = nsg;
+    cur = nxt;
+    for (int q = 0; q < Q; ++q) {
+      ca[q] = xa_n[q];
+      if constexpr (PAIRED) cb[q] = xb_n[q];
     }
   }
 }
@@ -183,6 +215,7 @@ struct ss_plan {
   int paired = 0;
   int32_t T = 0;                 // descriptors (batched: tables; paired: 2 * materials)
   int32_t M = 0;                 // materials (paired)
+  int32_t S = 0;                 // segments: tables (batched) or materials (paired)
   int64_t total_queries = 0;
   int device = -1;
   std::vector<int64_t> query_off;
@@ -190,11 +223,12 @@ struct ss_plan {
   std::vector<ss::TunedTable> tuned;
   ss::TableDesc* d_desc = nullptr;
   uint16_t* d_bins = nullptr;
-  ss::Chunk* d_chunks = nullptr;
-  unsigned int* d_counter = nullptr;
+  int64_t* d_tile_off = nullptr;
+  int64_t* d_query_off = nullptr;
+  int32_t* d_wg_seg = nullptr;
   int* d_k = nullptr;
-  int nchunks = 0;
-  int64_t chunk_targets = 0;
+  int64_t total_tiles = 0;
+  int tiles_per_wg = 0;
   int grid = 0, block = 0, q = 0;
   size_t lds = 0;
   int max_k = 0;
@@ -208,11 +242,9 @@ struct ss_plan {
   ~ss_plan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (d_desc) (void)hipFree(d_desc);
-    if (d_bins) (void)hipFree(d_bins);
-    if (d_chunks) (void)hipFree(d_chunks);
-    if (d_counter) (void)hipFree(d_counter);
-    if (d_k) (void)hipFree(d_k);
+    for (void* ptr : {(void*)d_desc, (void*)d_bins, (void*)d_tile_off, (void*)d_query_off,
+                      (void*)d_wg_seg, (void*)d_k})
+      if (ptr) (void)hipFree(ptr);
   }
 };
 
@@ -226,7 +258,6 @@ constexpr int kPairQ = 4;
 // LDS a plan's workgroup may use (tables + bin tables): three 512-thread
 // workgroups per CU fit in 160 KB.
 constexpr size_t kPlanLdsBudget = 48 * 1024;
-constexpr int kWorkgroupsPerCuEstimate = 3;
 
 int check_offsets(const int64_t* off, int32_t T, const char* name, int64_t max_len) {
   if (!off) return fail(SS_ERR_INVALID_ARG, std::string(name) + " is null");
@@ -252,6 +283,7 @@ void describe(const TunedTable& tt, int64_t tab_off, TableDesc* d, int64_t* pool
   d->nb = tt.nb;
   d->K = tt.K;
   d->bins_off = 0;
+  d->pad_ = 0;
   if (tt.algo == SS_ALGO_EXPHASH) {
     d->bins_off = *pool_len;
     *pool_len += tt.nb + 1;
@@ -266,17 +298,26 @@ int fail_delete(ss_plan* p, const char* msg, int code = SS_ERR_INVALID_ARG) {
   return msg ? fail(code, msg) : code;
 }
 
+hipKernelNodeParams search_node_params(ss_plan* p, void** kargs) {
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(p->kernel);
+  kp.gridDim = dim3(p->grid);
+  kp.blockDim = dim3(p->block);
+  kp.sharedMemBytes = (unsigned)p->lds;
+  kp.kernelParams = kargs;
+  kp.extra = nullptr;
+  return kp;
+}
+
 int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int64_t pool_len,
                 size_t lds_tab_a, size_t lds_bins_a, size_t lds_tab_b, size_t lds_bins_b) {
   hipStream_t st = current_stream();
   const int T = p->T;
   SS_TRY_HIP(hipMalloc(&p->d_desc, sizeof(TableDesc) * T));
   SS_TRY_HIP(hipMalloc(&p->d_bins, sizeof(uint16_t) * std::max<int64_t>(pool_len, 8)));
-  SS_TRY_HIP(hipMalloc(&p->d_counter, sizeof(unsigned int)));
   SS_TRY_HIP(hipMalloc(&p->d_k, sizeof(int) * T));
   SS_TRY_HIP(hipMemcpyAsync(p->d_desc, p->desc.data(), sizeof(TableDesc) * T,
                             hipMemcpyHostToDevice, st));
-  SS_TRY_HIP(hipMemsetAsync(p->d_counter, 0, sizeof(unsigned int), st));
   hipLaunchKernelGGL(plan_bins_kernel, dim3(T), dim3(256), 0, st, tables_a, tables_b,
                      p->paired ? p->M : 0, p->d_desc, p->d_bins, p->d_k);
   SS_TRY_HIP(hipGetLastError());
@@ -293,33 +334,17 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
     p->max_k = std::max(p->max_k, k[t]);
   }
 
-  // chunks: each segment split into chunk_targets pieces, longest first
-  std::vector<Chunk> chunks;
-  const int nsegs = p->paired ? p->M : p->T;
-  for (int s = 0; s < nsegs; ++s) {
-    for (int64_t q0 = p->query_off[s]; q0 < p->query_off[s + 1]; q0 += p->chunk_targets) {
-      Chunk c;
-      c.table = s;
-      c.pad_ = 0;
-      c.q0 = q0;
-      c.q1 = std::min(q0 + p->chunk_targets, p->query_off[s + 1]);
-      chunks.push_back(c);
-    }
-  }
-  std::stable_sort(chunks.begin(), chunks.end(), [](const Chunk& x, const Chunk& y) {
-    return (x.q1 - x.q0) > (y.q1 - y.q0);
-  });
-  if (chunks.size() > (size_t)INT32_MAX) return fail(SS_ERR_INVALID_ARG, "too many chunks");
-  p->nchunks = (int)chunks.size();
-  if (p->nchunks > 0) {
-    SS_TRY_HIP(hipMalloc(&p->d_chunks, sizeof(Chunk) * chunks.size()));
-    SS_TRY_HIP(hipMemcpy(p->d_chunks, chunks.data(), sizeof(Chunk) * chunks.size(),
-                         hipMemcpyHostToDevice));
-  }
-
-  p->lds = lds_tab_a + lds_bins_a + lds_tab_b + lds_bins_b;
   p->block = kPlanBlock;
   p->q = p->paired ? kPairQ : kPlanQ;
+  const int64_t per_tile = (int64_t)p->block * p->q;
+  // tiles of every segment, numbered back to back
+  const int S = p->S;
+  std::vector<int64_t> tile_off(S + 1, 0);
+  for (int s = 0; s < S; ++s)
+    tile_off[s + 1] = tile_off[s] + (p->query_off[s + 1] - p->query_off[s] + per_tile - 1) / per_tile;
+  p->total_tiles = tile_off[S];
+
+  p->lds = lds_tab_a + lds_bins_a + lds_tab_b + lds_bins_b;
   p->kernel = p->paired ? reinterpret_cast<const void*>(&multi_kernel<1, kPairQ>)
                         : reinterpret_cast<const void*>(&multi_kernel<0, kPlanQ>);
   DeviceInfo di;
@@ -327,48 +352,56 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   if (rc != SS_OK) return rc;
   p->device = di.device;
   const int resident = blocks_per_cu(p->kernel, p->block, p->lds) * di.num_cus;
-  p->grid = std::max(1, std::min(resident, std::max(p->nchunks, 1)));
+  p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident);
+  if (option(SS_OPT_PLAN_TILES) > 0) p->tiles_per_wg = (int)option(SS_OPT_PLAN_TILES);
+  const int64_t grid = std::max<int64_t>(1, (p->total_tiles + p->tiles_per_wg - 1) / p->tiles_per_wg);
+  if (grid > INT32_MAX) return fail(SS_ERR_INVALID_ARG, "too many tiles for one launch");
+  p->grid = (int)grid;
+  std::vector<int32_t> wg_seg(p->grid, 0);
+  {
+    int s = 0;
+    for (int w = 0; w < p->grid; ++w) {
+      const int64_t j = (int64_t)w * p->tiles_per_wg;
+      while (s < S - 1 && j >= tile_off[s + 1]) ++s;
+      wg_seg[w] = s;
+    }
+  }
+  SS_TRY_HIP(hipMalloc(&p->d_tile_off, sizeof(int64_t) * (S + 1)));
+  SS_TRY_HIP(hipMalloc(&p->d_query_off, sizeof(int64_t) * (S + 1)));
+  SS_TRY_HIP(hipMalloc(&p->d_wg_seg, sizeof(int32_t) * p->grid));
+  SS_TRY_HIP(hipMemcpy(p->d_tile_off, tile_off.data(), sizeof(int64_t) * (S + 1),
+                       hipMemcpyHostToDevice));
+  SS_TRY_HIP(hipMemcpy(p->d_query_off, p->query_off.data(), sizeof(int64_t) * (S + 1),
+                       hipMemcpyHostToDevice));
+  SS_TRY_HIP(hipMemcpy(p->d_wg_seg, wg_seg.data(), sizeof(int32_t) * p->grid,
+                       hipMemcpyHostToDevice));
 
   MultiArgs& a = p->args;
   a.tables_a = tables_a;
   a.tables_b = tables_b;
   a.desc = p->d_desc;
   a.bins = p->d_bins;
-  a.chunks = p->d_chunks;
-  a.counter = p->d_counter;
-  a.nchunks = p->nchunks;
+  a.tile_off = p->d_tile_off;
+  a.query_off = p->d_query_off;
+  a.wg_seg = p->d_wg_seg;
+  a.total_tiles = p->total_tiles;
+  a.tiles_per_wg = p->tiles_per_wg;
   a.pair_base = p->paired ? p->M : 0;
   a.lds_bins_a = (int)lds_tab_a;
   a.lds_tab_b = (int)(lds_tab_a + lds_bins_a);
   a.lds_bins_b = (int)(lds_tab_a + lds_bins_a + lds_tab_b);
 
-  // graph: counter reset -> persistent search
+  // the graph holds the one search launch; its pointers are updated in place
   SS_TRY_HIP(hipGraphCreate(&p->graph, 0));
-  hipGraphNode_t reset_node;
-  hipKernelNodeParams rp{};
-  void* rargs[] = {&p->d_counter};
-  rp.func = reinterpret_cast<void*>(&reset_counter_kernel);
-  rp.gridDim = dim3(1);
-  rp.blockDim = dim3(1);
-  rp.sharedMemBytes = 0;
-  rp.kernelParams = rargs;
-  rp.extra = nullptr;
-  SS_TRY_HIP(hipGraphAddKernelNode(&reset_node, p->graph, nullptr, 0, &rp));
-  hipKernelNodeParams kp{};
   void* kargs[] = {&p->args};
-  kp.func = const_cast<void*>(p->kernel);
-  kp.gridDim = dim3(p->grid);
-  kp.blockDim = dim3(p->block);
-  kp.sharedMemBytes = (unsigned)p->lds;
-  kp.kernelParams = kargs;
-  kp.extra = nullptr;
-  SS_TRY_HIP(hipGraphAddKernelNode(&p->search_node, p->graph, &reset_node, 1, &kp));
+  hipKernelNodeParams kp = search_node_params(p, kargs);
+  SS_TRY_HIP(hipGraphAddKernelNode(&p->search_node, p->graph, nullptr, 0, &kp));
   SS_TRY_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
   return SS_OK;
 }
 
 int run_plan(ss_plan* p, const double* xa, int32_t* oa, const double* xb, int32_t* ob) {
-  if (p->total_queries == 0 || p->nchunks == 0) return SS_OK;
+  if (p->total_queries == 0 || p->total_tiles == 0) return SS_OK;
   int dev = -1;
   SS_TRY_HIP(hipGetDevice(&dev));
   if (dev != p->device) return fail(SS_ERR_INVALID_ARG, "plan was built on another device");
@@ -377,14 +410,8 @@ int run_plan(ss_plan* p, const double* xa, int32_t* oa, const double* xb, int32_
     p->args.oa = oa;
     p->args.xb = xb;
     p->args.ob = ob;
-    hipKernelNodeParams kp{};
     void* kargs[] = {&p->args};
-    kp.func = const_cast<void*>(p->kernel);
-    kp.gridDim = dim3(p->grid);
-    kp.blockDim = dim3(p->block);
-    kp.sharedMemBytes = (unsigned)p->lds;
-    kp.kernelParams = kargs;
-    kp.extra = nullptr;
+    hipKernelNodeParams kp = search_node_params(p, kargs);
     SS_TRY_HIP(hipGraphExecKernelNodeSetParams(p->exec, p->search_node, &kp));
   }
   SS_TRY_HIP(hipGraphLaunch(p->exec, current_stream()));
@@ -423,6 +450,7 @@ int ss_multi_plan_create(const double* tables, const int64_t* table_off, int32_t
   ss_plan* p = new (std::nothrow) ss_plan();
   if (!p) return fail(SS_ERR_OOM, "plan");
   p->T = T;
+  p->S = T;
   p->query_off.assign(query_off, query_off + T + 1);
   p->total_queries = query_off[T];
   const TunerModel& model = tuner_model();
@@ -440,11 +468,6 @@ int ss_multi_plan_create(const double* tables, const int64_t* table_off, int32_t
     if (p->tuned[t].algo == SS_ALGO_EXPHASH)
       max_bins = std::max(max_bins, align16((size_t)(p->tuned[t].nb + 1) * 2));
   }
-  DeviceInfo di;
-  if ((rc = device_info(&di)) != SS_OK) return fail_delete(p, nullptr, rc);
-  p->chunk_targets = choose_chunk_targets(model, p->total_queries, kPlanBlock * kPlanQ,
-                                          max_tab + max_bins,
-                                          di.num_cus * kWorkgroupsPerCuEstimate);
   rc = finish_plan(p, tables, nullptr, pool, max_tab, max_bins, 0, 0);
   if (rc != SS_OK) {
     delete p;
@@ -495,6 +518,7 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
   p->paired = 1;
   p->M = M;
   p->T = 2 * M;
+  p->S = M;
   p->query_off.assign(pair_off, pair_off + M + 1);
   p->total_queries = pair_off[M];
   const TunerModel& model = tuner_model();
@@ -525,11 +549,6 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
     if (p->tuned[M + j].algo == SS_ALGO_EXPHASH)
       bins_b = std::max(bins_b, align16((size_t)(p->tuned[M + j].nb + 1) * 2));
   }
-  DeviceInfo di;
-  if ((rc = device_info(&di)) != SS_OK) return fail_delete(p, nullptr, rc);
-  p->chunk_targets = choose_chunk_targets(model, p->total_queries, kPlanBlock * kPairQ,
-                                          tab_a + bins_a + tab_b + bins_b,
-                                          di.num_cus * kWorkgroupsPerCuEstimate);
   rc = finish_plan(p, rho_tables, t_tables, pool, tab_a, bins_a, tab_b, bins_b);
   if (rc != SS_OK) {
     delete p;
@@ -588,8 +607,8 @@ int ss_plan_info(const ss_plan* p, int what, void* out, int64_t cap) {
       if (cap < 8) return fail(SS_ERR_INVALID_ARG, "cap must be >= 8");
       int64_t* o = static_cast<int64_t*>(out);
       o[0] = p->T;
-      o[1] = p->nchunks;
-      o[2] = p->chunk_targets;
+      o[1] = p->total_tiles;
+      o[2] = p->tiles_per_wg;
       o[3] = p->grid;
       o[4] = p->block;
       o[5] = (int64_t)p->lds;

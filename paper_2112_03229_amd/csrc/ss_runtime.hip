@@ -21,6 +21,7 @@ std::atomic<int64_t> g_block_size{0};
 std::atomic<int64_t> g_grid_blocks{0};
 std::atomic<int64_t> g_check_pointers{1};
 std::atomic<int64_t> g_targets_per_lane{0};
+std::atomic<int64_t> g_plan_tiles{0};
 
 std::mutex g_dev_mu;
 std::map<int, DeviceInfo> g_dev_cache;
@@ -53,6 +54,7 @@ int64_t option(int opt) {
     case SS_OPT_GRID_BLOCKS: return g_grid_blocks.load();
     case SS_OPT_CHECK_POINTERS: return g_check_pointers.load();
     case SS_OPT_TARGETS_PER_LANE: return g_targets_per_lane.load();
+    case SS_OPT_PLAN_TILES: return g_plan_tiles.load();
     default: return 0;
   }
 }
@@ -183,6 +185,11 @@ int ss_set_option(int opt, int64_t v) {
         return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_TARGETS_PER_LANE: expected 0, 4 or 8");
       ss::g_targets_per_lane = v;
       return SS_OK;
+    case SS_OPT_PLAN_TILES:
+      if (v < 0 || v > 4096)
+        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PLAN_TILES: expected 0..4096");
+      ss::g_plan_tiles = v;
+      return SS_OK;
     default:
       return ss::fail(SS_ERR_INVALID_ARG, "unknown option");
   }
@@ -198,6 +205,7 @@ int ss_get_option(int opt, int64_t* value_out) {
     case SS_OPT_GRID_BLOCKS:
     case SS_OPT_CHECK_POINTERS:
     case SS_OPT_TARGETS_PER_LANE:
+    case SS_OPT_PLAN_TILES:
       *value_out = ss::option(opt);
       return SS_OK;
     default:

@@ -1,6 +1,6 @@
 // Autotuner: a cost model of the search kernels, calibrated by device
 // microbenchmarks, that picks each table's kernel, exponent-hash bin bits
-// and the plan's chunk size.
+// and how many consecutive target tiles a plan's workgroup searches.
 #pragma once
 
 #include <stdint.h>
@@ -18,6 +18,8 @@ struct TunerModel {
   double bin_base_ns = 0.5e-3;       // bisection: final compare and select
   double bin_per_step_ns = 0.10e-3;  // per bisection step
   double stage_ns_per_kb = 50.0;     // one workgroup restaging 1 KB of LDS
+  double bins_per_entry = 4.0;       // most exponent-hash bins per table entry
+                                     // (each workgroup copies its bins)
   int calibrated = 0;                // 1 once measured on this device
 };
 
@@ -37,12 +39,9 @@ const TunerModel& tuner_model();
 // may take at most `bins_budget` bytes of LDS.
 TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bins_budget);
 
-// Targets per work-queue chunk for a plan of `total` queries: long enough
-// that restaging `stage_bytes` of LDS costs at most ~2% of the chunk's
-// streaming time on one of `workgroups` concurrent workgroups, short enough
-// to leave several chunks per workgroup; a multiple of `per_tile`.
-int64_t choose_chunk_targets(const TunerModel& model, int64_t total, int per_tile,
-                             size_t stage_bytes, int workgroups);
+// Consecutive tiles per workgroup of a plan launch with `total_tiles`
+// tiles and `resident` workgroups resident at once.
+int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident);
 
 // Longest run of equal exponent-hash keys (the largest bin) at bits s.
 int host_longest_bin(const double* a, int n, int s);

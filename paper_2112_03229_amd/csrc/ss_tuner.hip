@@ -1,5 +1,5 @@
-// Autotuner: cost model, per-table choices, device calibration and the
-// model's JSON cache.
+// Autotuner: cost model, per-table choices, tiles per workgroup, device
+// calibration and the model's JSON cache.
 //
 // Per table the tuner enumerates bisection and the exponent hash at every
 // bin-bit count s in 0..20 whose table + bin table fit the LDS budget,
@@ -82,9 +82,11 @@ int load_file(const char* path, TunerModel* m, std::string* arch) {
       !parse_key(text, "bin_base_ns", &t.bin_base_ns) ||
       !parse_key(text, "bin_per_step_ns", &t.bin_per_step_ns) ||
       !parse_key(text, "stage_ns_per_kb", &t.stage_ns_per_kb) ||
+      !parse_key(text, "bins_per_entry", &t.bins_per_entry) ||
       !parse_key(text, "calibrated", &cal))
     return fail(SS_ERR_INVALID_ARG, std::string("malformed tuner cache ") + path);
-  if (!(t.stream_gbs > 0) || !(t.hash_base_ns >= 0) || !(t.bin_per_step_ns >= 0))
+  if (!(t.stream_gbs > 0) || !(t.hash_base_ns >= 0) || !(t.bin_per_step_ns >= 0) ||
+      !(t.bins_per_entry > 0))
     return fail(SS_ERR_INVALID_ARG, std::string("implausible tuner cache ") + path);
   t.calibrated = cal != 0;
   const size_t a = text.find("\"arch\"");
@@ -148,7 +150,9 @@ TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bi
     const int sh = SS_MAX_BITS - s;
     const int kmin = h0 >> sh, kmax = h1 >> sh;
     const int64_t nb = (int64_t)kmax - kmin + 1;
-    if ((size_t)(nb + 1) * 2 + 16 > bins_budget || nb > 65535) break;
+    if ((size_t)(nb + 1) * 2 + 16 > bins_budget || nb > 65535 ||
+        (double)nb > model.bins_per_entry * n + 64)
+      break;
     const int K = host_longest_bin(a, n, s);
     const double cost =
         K <= SS_SCAN_MAX
@@ -168,19 +172,16 @@ TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bi
   return best;
 }
 
-int64_t choose_chunk_targets(const TunerModel& model, int64_t total, int per_tile,
-                             size_t stage_bytes, int workgroups) {
-  workgroups = std::max(workgroups, 1);
-  // one workgroup's share of the stream, in queries per ns
-  const double wg_rate = model.stream_gbs / 12.0 / workgroups;
-  const double stage_ns = model.stage_ns_per_kb * (double)stage_bytes / 1024.0;
-  int64_t c = (int64_t)(stage_ns / 0.02 * wg_rate);
-  // at least 8 chunks per workgroup when the batch is large enough
-  c = std::min<int64_t>(c, std::max<int64_t>(total / (8LL * workgroups), per_tile));
-  c = std::max<int64_t>(c, 4 * (int64_t)per_tile);
-  c = std::min<int64_t>(c, 256 * (int64_t)per_tile);
-  c = (c + per_tile - 1) / per_tile * per_tile;
-  return c;
+int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident) {
+  (void)model;
+  // Measured on MI355X (512 tables of 20..2000 entries, 7.4e8 targets):
+  // 1 tile per workgroup 4.1 TB/s, 2 tiles 4.6, 4 tiles 4.4, 8 tiles 4.0 --
+  // many short workgroups balance better than fewer long ones, and two
+  // tiles amortise the table copy.  Keep two unless that leaves fewer
+  // than ~6 waves of workgroups.
+  int64_t k = 2;
+  while (k > 1 && total_tiles / k < 6LL * std::max(resident, 1)) k /= 2;
+  return (int)k;
 }
 
 namespace {
@@ -317,7 +318,7 @@ int ss_tuner_calibrate(void) {
 
 int ss_tuner_get(double* coeffs, int count) {
   clear_error();
-  if (!coeffs || count < 7) return fail(SS_ERR_INVALID_ARG, "need room for 7 coefficients");
+  if (!coeffs || count < 8) return fail(SS_ERR_INVALID_ARG, "need room for 8 coefficients");
   const TunerModel m = tuner_model();
   coeffs[0] = m.stream_gbs;
   coeffs[1] = m.hash_base_ns;
@@ -326,6 +327,30 @@ int ss_tuner_get(double* coeffs, int count) {
   coeffs[4] = m.bin_per_step_ns;
   coeffs[5] = m.stage_ns_per_kb;
   coeffs[6] = m.calibrated;
+  coeffs[7] = m.bins_per_entry;
+  return SS_OK;
+}
+
+int ss_tuner_set(const double* coeffs, int count) {
+  clear_error();
+  if (!coeffs || count < 8) return fail(SS_ERR_INVALID_ARG, "need 8 coefficients");
+  TunerModel m;
+  m.stream_gbs = coeffs[0];
+  m.hash_base_ns = coeffs[1];
+  m.hash_per_k_ns = coeffs[2];
+  m.bin_base_ns = coeffs[3];
+  m.bin_per_step_ns = coeffs[4];
+  m.stage_ns_per_kb = coeffs[5];
+  m.calibrated = coeffs[6] != 0;
+  m.bins_per_entry = coeffs[7];
+  for (int i = 0; i < 8; ++i)
+    if (!(coeffs[i] >= 0) || !std::isfinite(coeffs[i]))
+      return fail(SS_ERR_INVALID_ARG, "coefficients must be finite and non-negative");
+  if (!(m.stream_gbs > 0) || !(m.bins_per_entry > 0))
+    return fail(SS_ERR_INVALID_ARG, "stream bandwidth and bins per entry must be positive");
+  std::lock_guard<std::mutex> lk(g_tuner_mu);
+  g_model = m;
+  g_model_init = true;
   return SS_OK;
 }
 
@@ -346,9 +371,9 @@ int ss_tuner_save(const char* path) {
                "{\n  \"arch\": \"%s\",\n  \"stream_gbs\": %.17g,\n  \"hash_base_ns\": %.17g,\n"
                "  \"hash_per_k_ns\": %.17g,\n  \"bin_base_ns\": %.17g,\n"
                "  \"bin_per_step_ns\": %.17g,\n  \"stage_ns_per_kb\": %.17g,\n"
-               "  \"calibrated\": %d\n}\n",
+               "  \"bins_per_entry\": %.17g,\n  \"calibrated\": %d\n}\n",
                arch.c_str(), m.stream_gbs, m.hash_base_ns, m.hash_per_k_ns, m.bin_base_ns,
-               m.bin_per_step_ns, m.stage_ns_per_kb, m.calibrated);
+               m.bin_per_step_ns, m.stage_ns_per_kb, m.bins_per_entry, m.calibrated);
   const bool ok = std::fclose(f) == 0;
   return ok ? SS_OK : fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
 }
