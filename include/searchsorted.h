@@ -227,6 +227,83 @@ typedef enum { SS_PLAN_ALGOS = 1, SS_PLAN_BITS = 2, SS_PLAN_SUMMARY = 3 } ss_pla
 SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
 
 /* ---------------------------------------------------------------------------
+ * Learned index (not in the paper; the nearest analogue is the logarithm
+ * hash of Sec. 3.4, an analytic model of a table's position as a function
+ * of log x).  A per-table model predicts where x falls; a verified, bounded
+ * search corrects the prediction; the plain search is the fallback, so the
+ * result is always exactly the operation defined at the top of this header.
+ *
+ * Model: an FP32 multilayer perceptron 1 -> 32 -> 32 -> 1 with ReLU hidden
+ * layers.  Input z = (log2 x - log2 a[0]) / (log2 a[n-1] - log2 a[0]),
+ * computed in FP32 from x rounded to FP32.  Output p estimates i / (n-1) for
+ * x = a[i] (the table's CDF).  Parameters (1153 floats, in this order):
+ *   w1[32], b1[32], W2[32][32] (row k holds the weights into hidden unit k
+ *   of layer 2), b2[32], w3[32], b3.
+ * Training: full-batch Adam on the mean squared error over the n table
+ * entries, `steps` steps at learning rate `lr` (beta1 0.9, beta2 0.999,
+ * eps 1e-8, cosine-decayed rate), parameters initialised from `seed`; run by
+ * one workgroup with deterministic, fixed-order reductions.
+ * Search: g = floor(p (n-1)) clamped to [-1, n-1]; the window
+ * [L, R] = [g - E, g + E] clamped to [-1, n-1] is accepted if
+ * (L == -1 or a[L] < x) and (R == n-1 or x <= a[R+1]); the index is then
+ * found by bisection inside it, otherwise by bisection over the whole table.
+ * E = 1 + the largest |g(x) - idx(x)| over the entries, their upward
+ * neighbours and the log-midpoints between entries, measured on the device
+ * with the search's own prediction code.
+ * ------------------------------------------------------------------------- */
+typedef struct ss_learned ss_learned;
+
+typedef struct {
+    int32_t steps;     /* Adam steps; 0 keeps the initial parameters */
+    float lr;          /* peak learning rate (> 0) */
+    uint64_t seed;     /* initialisation seed */
+} ss_mlp_opts;
+
+#define SS_MLP_PARAMS 1153
+
+/* Trains a model for the table (device, n entries, sorted, 2 <= n <= 65535,
+ * a[0] > 0, all finite) and measures E.  opts may be NULL for the defaults
+ * {steps 3000, lr 0.01, seed 1}.  The table is referenced, not copied, and
+ * must stay valid while the handle is used.  SYNCHRONOUS. */
+SS_API int ss_learned_build(const double *table, int64_t n, const ss_mlp_opts *opts,
+                            ss_learned **out);
+
+/* Same, with given parameters instead of training (weights: host, 1153
+ * floats); E is measured for this table. */
+SS_API int ss_learned_from_weights(const double *table, int64_t n, const float *weights,
+                                   ss_learned **out);
+
+/* out_idx[k] = idx(targets[k]) through the learned index; asynchronous. */
+SS_API int ss_learned_search(ss_learned *h, const double *targets, int64_t m,
+                             int32_t *out_idx);
+
+/* Model outputs p(x) * (n-1) (the predicted fractional position) for each
+ * target (device in, device out); asynchronous. */
+SS_API int ss_learned_predict(ss_learned *h, const double *x, int64_t m, float *out_pos);
+
+/* info (host, 6 doubles): {E, n, steps, final training loss, log2 a[0],
+ * 1 / (log2 a[n-1] - log2 a[0])}.  SYNCHRONOUS only in that it reads the
+ * handle's host copy. */
+SS_API int ss_learned_info(const ss_learned *h, double *info, int count);
+
+/* Targets of the most recent ss_learned_search that failed the window
+ * check and were answered by the fallback.  SYNCHRONOUS (waits for the
+ * current stream). */
+SS_API int ss_learned_fallbacks(ss_learned *h, int64_t *count);
+
+/* Copies the 1153 parameters (host out, cap >= 1153). */
+SS_API int ss_learned_weights(const ss_learned *h, float *out, int64_t cap);
+
+/* Full-batch gradient of the training loss at the given parameters (host
+ * in, 1153 floats; host out, 1153 floats, same layout) for this table,
+ * computed by the training kernel's code.  For checking the training
+ * arithmetic.  SYNCHRONOUS. */
+SS_API int ss_mlp_gradient(const double *table, int64_t n, const float *weights,
+                           float *grad_out, double *loss_out);
+
+SS_API int ss_learned_destroy(ss_learned *h);
+
+/* ---------------------------------------------------------------------------
  * Autotuner.  Plans choose each table's kernel, exponent-hash bin bits and
  * the work-queue chunk size from a cost model (device-wide nanoseconds per
  * query: memory = 12 B / stream bandwidth; compute = fixed + per-step terms

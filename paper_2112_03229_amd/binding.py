@@ -84,11 +84,13 @@ def _register_extra(L) -> None:
         "ss_tuner_save": [ctypes.c_char_p],
         "ss_tuner_load": [ctypes.c_char_p],
         "ss_learned_build": [P, I64, P, ctypes.POINTER(P)],
+        "ss_learned_from_weights": [P, I64, P, ctypes.POINTER(P)],
         "ss_learned_search": [P, P, I64, P],
-        "ss_learned_info": [P, P],
+        "ss_learned_info": [P, P, I],
         "ss_learned_fallbacks": [P, ctypes.POINTER(I64)],
         "ss_learned_predict": [P, P, I64, P],
         "ss_learned_weights": [P, P, I64],
+        "ss_mlp_gradient": [P, I64, P, P, P],
         "ss_learned_destroy": [P],
     }
     for name, argtypes in sigs.items():
@@ -354,3 +356,101 @@ def tuner_save(path: str) -> None:
 
 def tuner_load(path: str) -> None:
     check(lib().ss_tuner_load(os.fsencode(path)))
+
+
+# ---------------------------------------------------------------------------
+# learned index
+# ---------------------------------------------------------------------------
+
+MLP_PARAMS = 1153
+
+
+class MlpOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("lr", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class LearnedIndex:
+    """Per-table learned index (see ss_learned_build).  Build from a table
+    (trains on the device) or from given weights."""
+
+    def __init__(self, table: torch.Tensor, steps: int = 3000, lr: float = 0.01, seed: int = 1,
+                 weights=None):
+        import numpy as np
+        _need(table, torch.float64, "table")
+        self._table = table
+        self.n = table.numel()
+        h = ctypes.c_void_p()
+        use_current_stream()
+        if weights is None:
+            opts = MlpOpts(int(steps), float(lr), int(seed))
+            check(lib().ss_learned_build(_ptr(table), self.n, ctypes.byref(opts), ctypes.byref(h)))
+        else:
+            w = np.ascontiguousarray(weights, dtype=np.float32)
+            if w.shape != (MLP_PARAMS,):
+                raise ValueError(f"weights must have {MLP_PARAMS} entries")
+            check(lib().ss_learned_from_weights(_ptr(table), self.n,
+                                                w.ctypes.data_as(ctypes.c_void_p),
+                                                ctypes.byref(h)))
+        self._handle = h
+
+    def close(self) -> None:
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            lib().ss_learned_destroy(self._handle)
+        self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def search(self, targets: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _need(targets, torch.float64, "targets")
+        if out is None:
+            out = torch.empty(targets.numel(), dtype=torch.int32, device=targets.device)
+        _need(out, torch.int32, "out")
+        if out.numel() != targets.numel():
+            raise ValueError("out must have one entry per target")
+        use_current_stream()
+        check(lib().ss_learned_search(self._handle, _ptr(targets), targets.numel(), _ptr(out)))
+        return out
+
+    def predict(self, x: torch.Tensor) -> torch.Tensor:
+        _need(x, torch.float64, "x")
+        out = torch.empty(x.numel(), dtype=torch.float32, device=x.device)
+        use_current_stream()
+        check(lib().ss_learned_predict(self._handle, _ptr(x), x.numel(), _ptr(out)))
+        return out
+
+    def info(self) -> dict:
+        buf = (ctypes.c_double * 6)()
+        check(lib().ss_learned_info(self._handle, buf, 6))
+        return {"E": int(buf[0]), "n": int(buf[1]), "steps": int(buf[2]), "loss": buf[3],
+                "u0": buf[4], "inv": buf[5]}
+
+    def fallbacks(self) -> int:
+        v = ctypes.c_int64()
+        use_current_stream()
+        check(lib().ss_learned_fallbacks(self._handle, ctypes.byref(v)))
+        return v.value
+
+    def weights(self):
+        import numpy as np
+        w = np.empty(MLP_PARAMS, dtype=np.float32)
+        check(lib().ss_learned_weights(self._handle, w.ctypes.data_as(ctypes.c_void_p),
+                                       MLP_PARAMS))
+        return w
+
+
+def mlp_gradient(table: torch.Tensor, weights):
+    """(loss, gradient) of the training loss at `weights`, from the device
+    training kernel's arithmetic."""
+    import numpy as np
+    _need(table, torch.float64, "table")
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    g = np.empty(MLP_PARAMS, dtype=np.float32)
+    loss = ctypes.c_double()
+    use_current_stream()
+    check(lib().ss_mlp_gradient(_ptr(table), table.numel(), w.ctypes.data_as(ctypes.c_void_p),
+                                g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss)))
+    return loss.value, g

@@ -1,0 +1,717 @@
+// Learned index: an FP32 1-32-32-1 ReLU position model per table, trained on
+// the device on the table's CDF, with a device-measured error bound and a
+// verified bounded search (exact by construction; bisection is the fallback).
+//
+// Kernels:
+//   train_kernel   one workgroup per table: full-batch Adam, points in
+//                  batches of 256 (one per lane); per batch, phase A stores
+//                  each point's activations and back-propagated errors in
+//                  LDS, phase B sums every parameter's gradient over the
+//                  batch in a fixed order (deterministic).
+//   bound_kernel   E = 1 + max |g(x) - idx(x)| over the probes.
+//   learned_kernel the search: table in LDS, parameters read with scalar
+//                  loads (uniform across the wavefront), Q targets per lane.
+//   predict_kernel the model's fractional position for inspection.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ss_device.h"
+#include "ss_host.h"
+
+namespace ss {
+
+constexpr int kH = 32;
+constexpr int kOffW1 = 0, kOffB1 = 32, kOffW2 = 64, kOffB2 = 64 + kH * kH, kOffW3 = kOffB2 + kH,
+              kOffB3 = kOffW3 + kH, kNP = kOffB3 + 1;
+static_assert(kNP == SS_MLP_PARAMS, "parameter layout");
+constexpr int kTrainThreads = 256;  // also the batch size
+
+// Model input: z = (log2 x - u0) * inv, in FP32 from x rounded to FP32.
+__device__ __forceinline__ float model_input(double x, float u0, float inv) {
+  return (__log2f((float)x) - u0) * inv;
+}
+
+// Forward pass for Q inputs at once (the search's and the bound's code).
+// P may live in global memory (read with scalar loads) or LDS.
+template <int Q>
+__device__ __forceinline__ void mlp_eval(const float* __restrict__ P, const float (&z)[Q],
+                                         float (&out)[Q]) {
+  float h1[Q][kH];
+#pragma unroll
+  for (int j = 0; j < kH; ++j) {
+    const float w = P[kOffW1 + j], b = P[kOffB1 + j];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) h1[q][j] = fmaxf(fmaf(w, z[q], b), 0.0f);
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) out[q] = P[kOffB3];
+#pragma unroll
+  for (int k = 0; k < kH; ++k) {
+    float acc[Q];
+    const float b2 = P[kOffB2 + k];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = b2;
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+      const float w = P[kOffW2 + kH * k + j];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) acc[q] = fmaf(w, h1[q][j], acc[q]);
+    }
+    const float w3 = P[kOffW3 + k];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) out[q] = fmaf(w3, fmaxf(acc[q], 0.0f), out[q]);
+  }
+}
+
+// Predicted index g = floor(p (n-1)) clamped to [-1, n-1].  Any p, even NaN
+// or inf, yields a valid index (fmaxf/fminf return the bound for NaN).
+__device__ __forceinline__ int predicted_index(float p, int n) {
+  const float g = floorf(p * (float)(n - 1));
+  return (int)fminf(fmaxf(g, -1.0f), (float)(n - 1));
+}
+
+// ---------------------------------------------------------------------------
+// Training.
+// ---------------------------------------------------------------------------
+
+struct TrainArgs {
+  const double* table;
+  int n;
+  int steps;       // 0 with grad_out set: one gradient only
+  float lr;
+  uint64_t seed;
+  float u0, inv;
+  float* params;   // [kNP] in: initial values unless init_from_seed; out: trained
+  int init_from_seed;
+  float* grad_out; // [kNP] or null
+  float* loss_out; // [1]: final loss (mean squared error)
+};
+
+__device__ __forceinline__ float uhash(uint64_t seed, uint64_t i) {
+  uint64_t z = seed * 0x9e3779b97f4a7c15ULL + (i + 1) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  z ^= z >> 31;
+  return (float)(z >> 40) * 0x1.0p-24f;  // [0, 1)
+}
+
+struct TrainLds {
+  float P[kNP];
+  float m[kNP];
+  float v[kNP];
+  float h1[kTrainThreads][kH];
+  float h2[kTrainThreads][kH];
+  float d2[kTrainThreads][kH];   // dLoss / d(pre-activation of layer 2)
+  float d1[kTrainThreads][kH];   // dLoss / d(pre-activation of layer 1)
+  float z[kTrainThreads];
+  float g[kTrainThreads];        // dLoss / dp
+  float red[kTrainThreads];
+};
+
+__global__ __launch_bounds__(kTrainThreads) void train_kernel(TrainArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  TrainLds& L = *reinterpret_cast<TrainLds*>(lds_raw);
+  const int tid = threadIdx.x;
+  const int n = a.n;
+  for (int i = tid; i < kNP; i += kTrainThreads) {
+    float val;
+    if (a.init_from_seed) {
+      const float u = uhash(a.seed, (uint64_t)i);
+      if (i < kOffB1) {                 // slopes: +-(0.5 .. 4.5)
+        const float sgn = uhash(a.seed ^ 0x5bd1e995ULL, (uint64_t)i) < 0.5f ? -1.0f : 1.0f;
+        val = sgn * (0.5f + 4.0f * u);
+      } else if (i < kOffW2) {          // ReLU kinks spread over z in [0, 1]
+        const int j = i - kOffB1;
+        const float sgn = uhash(a.seed ^ 0x5bd1e995ULL, (uint64_t)j) < 0.5f ? -1.0f : 1.0f;
+        const float w = sgn * (0.5f + 4.0f * uhash(a.seed, (uint64_t)j));
+        val = -w * u;
+      } else if (i < kOffB2) {
+        val = (2.0f * u - 1.0f) * 0.4330127f;  // sqrt(6 / 32)
+      } else if (i < kOffW3) {
+        val = 0.1f;
+      } else if (i < kOffB3) {
+        val = (2.0f * u - 1.0f) * 0.4330127f;
+      } else {
+        val = 0.5f;
+      }
+    } else {
+      val = a.params[i];
+    }
+    L.P[i] = val;
+    L.m[i] = 0.0f;
+    L.v[i] = 0.0f;
+  }
+  __syncthreads();
+  const float inv_n = 1.0f / (float)n;
+  const float inv_nm1 = 1.0f / (float)(n - 1);
+  const int nbatch = (n + kTrainThreads - 1) / kTrainThreads;
+  const int total_steps = a.steps > 0 ? a.steps : 1;
+  for (int step = 1; step <= total_steps; ++step) {
+    float grad[(kNP + kTrainThreads - 1) / kTrainThreads];
+#pragma unroll
+    for (int r = 0; r < (kNP + kTrainThreads - 1) / kTrainThreads; ++r) grad[r] = 0.0f;
+    float sq = 0.0f;
+    for (int bt = 0; bt < nbatch; ++bt) {
+      // phase A: one point per lane
+      const int i = bt * kTrainThreads + tid;
+      if (i < n) {
+        const float zi = model_input(a.table[i], a.u0, a.inv);
+        float h1[kH];
+#pragma unroll
+        for (int j = 0; j < kH; ++j) h1[j] = fmaxf(fmaf(L.P[kOffW1 + j], zi, L.P[kOffB1 + j]), 0.0f);
+        float p = L.P[kOffB3];
+        float h2[kH];
+#pragma unroll
+        for (int k = 0; k < kH; ++k) {
+          float acc = L.P[kOffB2 + k];
+#pragma unroll
+          for (int j = 0; j < kH; ++j) acc = fmaf(L.P[kOffW2 + kH * k + j], h1[j], acc);
+          h2[k] = fmaxf(acc, 0.0f);
+          p = fmaf(L.P[kOffW3 + k], h2[k], p);
+        }
+        const float err = p - (float)i * inv_nm1;
+        sq = fmaf(err, err, sq);
+        const float gi = 2.0f * err * inv_n;
+        float d2[kH];
+#pragma unroll
+        for (int k = 0; k < kH; ++k) d2[k] = h2[k] > 0.0f ? gi * L.P[kOffW3 + k] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < kH; ++j) {
+          float s = 0.0f;
+#pragma unroll
+          for (int k = 0; k < kH; ++k) s = fmaf(L.P[kOffW2 + kH * k + j], d2[k], s);
+          L.d1[tid][j] = h1[j] > 0.0f ? s : 0.0f;
+          L.h1[tid][j] = h1[j];
+        }
+#pragma unroll
+        for (int k = 0; k < kH; ++k) {
+          L.h2[tid][k] = h2[k];
+          L.d2[tid][k] = d2[k];
+        }
+        L.z[tid] = zi;
+        L.g[tid] = gi;
+      } else {
+#pragma unroll
+        for (int j = 0; j < kH; ++j) {
+          L.h1[tid][j] = 0.0f;
+          L.h2[tid][j] = 0.0f;
+          L.d1[tid][j] = 0.0f;
+          L.d2[tid][j] = 0.0f;
+        }
+        L.z[tid] = 0.0f;
+        L.g[tid] = 0.0f;
+      }
+      __syncthreads();
+      // phase B: every parameter's gradient, summed over the batch in order
+      const int rows = min(kTrainThreads, n - bt * kTrainThreads);
+#pragma unroll
+      for (int r = 0; r < (kNP + kTrainThreads - 1) / kTrainThreads; ++r) {
+        const int pi = tid + r * kTrainThreads;
+        if (pi >= kNP) break;
+        float s = 0.0f;
+        if (pi < kOffB1) {
+          const int j = pi - kOffW1;
+          for (int t = 0; t < rows; ++t) s = fmaf(L.d1[t][j], L.z[t], s);
+        } else if (pi < kOffW2) {
+          const int j = pi - kOffB1;
+          for (int t = 0; t < rows; ++t) s += L.d1[t][j];
+        } else if (pi < kOffB2) {
+          const int k = (pi - kOffW2) / kH, j = (pi - kOffW2) % kH;
+          for (int t = 0; t < rows; ++t) s = fmaf(L.d2[t][k], L.h1[t][j], s);
+        } else if (pi < kOffW3) {
+          const int k = pi - kOffB2;
+          for (int t = 0; t < rows; ++t) s += L.d2[t][k];
+        } else if (pi < kOffB3) {
+          const int k = pi - kOffW3;
+          for (int t = 0; t < rows; ++t) s = fmaf(L.g[t], L.h2[t][k], s);
+        } else {
+          for (int t = 0; t < rows; ++t) s += L.g[t];
+        }
+        grad[r] += s;
+      }
+      __syncthreads();
+    }
+    if (a.steps <= 0 || step == total_steps) {
+      // loss: fixed-order tree reduction of the lanes' sums
+      L.red[tid] = sq;
+      __syncthreads();
+      for (int o = kTrainThreads / 2; o > 0; o >>= 1) {
+        if (tid < o) L.red[tid] += L.red[tid + o];
+        __syncthreads();
+      }
+      if (tid == 0 && a.loss_out) a.loss_out[0] = L.red[0] * inv_n;
+      __syncthreads();
+    }
+    if (a.steps <= 0) {
+#pragma unroll
+      for (int r = 0; r < (kNP + kTrainThreads - 1) / kTrainThreads; ++r) {
+        const int pi = tid + r * kTrainThreads;
+        if (pi < kNP && a.grad_out) a.grad_out[pi] = grad[r];
+      }
+      break;
+    }
+    // Adam with bias correction and a cosine-decayed rate
+    const float lr_t = a.lr * 0.5f * (1.0f + cosf(3.14159265f * (float)(step - 1) / (float)total_steps));
+    const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+#pragma unroll
+    for (int r = 0; r < (kNP + kTrainThreads - 1) / kTrainThreads; ++r) {
+      const int pi = tid + r * kTrainThreads;
+      if (pi >= kNP) break;
+      const float gr = grad[r];
+      const float mm = 0.9f * L.m[pi] + 0.1f * gr;
+      const float vv = 0.999f * L.v[pi] + 0.001f * gr * gr;
+      L.m[pi] = mm;
+      L.v[pi] = vv;
+      L.P[pi] -= lr_t * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < kNP; i += kTrainThreads) a.params[i] = L.P[i];
+}
+
+// ---------------------------------------------------------------------------
+// Error bound over probes: every entry, its upward neighbour, and the
+// log-midpoint to the next entry.  The true index comes from bisection.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int exact_index(const double* __restrict__ a, int n, double x) {
+  int base = 0, len = n;
+  while (len > 1) {
+    const int half = len >> 1;
+    base = (a[base + half] < x) ? base + half : base;
+    len -= half;
+  }
+  return base + (a[base] < x ? 1 : 0) - 1;
+}
+
+__global__ void bound_kernel(const double* __restrict__ a, int n, const float* __restrict__ P,
+                             float u0, float inv, int* worst) {
+  int local = 0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double probe[3];
+    probe[0] = a[i];
+    probe[1] = nextafter(a[i], __builtin_inf());
+    probe[2] = i + 1 < n ? sqrt(a[i]) * sqrt(a[i + 1]) : a[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float z[1] = {model_input(probe[c], u0, inv)}, p[1];
+      mlp_eval<1>(P, z, p);
+      const int g = predicted_index(p[0], n);
+      local = max(local, abs(g - exact_index(a, n, probe[c])));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(worst, local);
+}
+
+// ---------------------------------------------------------------------------
+// Search.
+// ---------------------------------------------------------------------------
+
+struct LearnedArgs {
+  const double* table;
+  const float* P;
+  const double* x;
+  int32_t* out;
+  unsigned long long* fallbacks;
+  int64_t m;
+  int n;
+  int E;
+  float u0, inv;
+};
+
+template <int Q>
+__device__ __forceinline__ void search_learned(const double* __restrict__ sa, int n,
+                                               const float* __restrict__ P, int E, float u0,
+                                               float inv, const double (&x)[Q], int (&r)[Q],
+                                               int (&fell_back)[Q]) {
+  float z[Q], p[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) z[q] = model_input(x[q], u0, inv);
+  mlp_eval<Q>(P, z, p);
+  int step = 1;
+  while (step * 2 <= 2 * E + 1) step *= 2;  // >= half the window length
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int g = predicted_index(p[q], n);
+    const int L = max(g - E, -1), R = min(g + E, n - 1);
+    const bool lo_ok = L < 0 || sa[max(L, 0)] < x[q];
+    const bool hi_ok = R >= n - 1 || x[q] <= sa[min(R + 1, n - 1)];
+    fell_back[q] = !(lo_ok && hi_ok);
+    if (lo_ok && hi_ok) {
+      // largest pos in [L+1, R+1] with a[pos-1] < x (all of a[..L] are < x)
+      int pos = L + 1;
+      for (int s = step; s >= 1; s >>= 1) {
+        const int cand = pos + s;
+        const int ridx = max(min(cand, R + 1) - 1, 0);
+        pos = ((cand <= R + 1) & (sa[ridx] < x[q])) ? cand : pos;
+      }
+      r[q] = pos - 1;
+    } else {
+      int base = 0, len = n;
+      while (len > 1) {
+        const int half = len >> 1;
+        base = (sa[base + half] < x[q]) ? base + half : base;
+        len -= half;
+      }
+      r[q] = base + (sa[base] < x[q] ? 1 : 0) - 1;
+    }
+  }
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  double* sa = reinterpret_cast<double*>(lds);
+  const int nt = blockDim.x;
+  const int64_t per_tile = (int64_t)nt * Q;
+  const int64_t ntiles = (a.m + per_tile - 1) / per_tile;
+  int64_t t = blockIdx.x;
+  double cur[Q];
+  if (t < ntiles) load_tile<Q>(a.x, a.m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= a.m, cur);
+  stage_table(sa, a.table, a.n);
+  __syncthreads();
+  int fb = 0;
+  for (; t < ntiles; t += gridDim.x) {
+    const int64_t tn = t + gridDim.x;
+    double nxt[Q];
+    if (tn < ntiles) load_tile<Q>(a.x, a.m, tn * per_tile + threadIdx.x, nt, (tn + 1) * per_tile <= a.m, nxt);
+    int r[Q], fell[Q];
+    search_learned<Q>(sa, a.n, a.P, a.E, a.u0, a.inv, cur, r, fell);
+    const int64_t base = t * per_tile + threadIdx.x;
+    const bool full = (t + 1) * per_tile <= a.m;
+    // lanes past the end of the ragged last tile searched a stand-in
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fb += (full || base + (int64_t)q * nt < a.m) ? fell[q] : 0;
+    store_tile<Q>(a.out, a.m, base, nt, full, r);
+    for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
+  }
+  // one atomic per wavefront
+  unsigned long long w = (unsigned long long)fb;
+  for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+  if ((threadIdx.x & 63) == 0 && w) atomicAdd(a.fallbacks, w);
+}
+
+__global__ void clear_counter_kernel(unsigned long long* c) { *c = 0ull; }
+
+__global__ void predict_kernel(const float* __restrict__ P, const double* __restrict__ x,
+                               int64_t m, float* __restrict__ out, float u0, float inv, int n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    float z[1] = {model_input(x[i], u0, inv)}, p[1];
+    mlp_eval<1>(P, z, p);
+    out[i] = p[0] * (float)(n - 1);
+  }
+}
+
+}  // namespace ss
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+
+struct ss_learned {
+  const double* table = nullptr;
+  int n = 0;
+  float u0 = 0, inv = 0;
+  int E = 0;
+  int steps = 0;
+  double loss = 0;
+  int device = -1;
+  float* d_params = nullptr;
+  unsigned long long* d_fallbacks = nullptr;
+  std::vector<float> params;
+  ~ss_learned() {
+    if (d_params) (void)hipFree(d_params);
+    if (d_fallbacks) (void)hipFree(d_fallbacks);
+  }
+};
+
+namespace ss {
+namespace {
+
+constexpr int kLearnedQ = 2;
+constexpr int kLearnedBlock = 256;
+
+int check_learned_table(const double* table, int64_t n, std::vector<double>* host) {
+  if (n < 2 || n > 65535) return fail(SS_ERR_INVALID_ARG, "n must be in 2..65535");
+  int rc = check_span(table, n, sizeof(double), alignof(double), "table");
+  if (rc != SS_OK) return rc;
+  if ((rc = check_device_ptr(table, "table")) != SS_OK) return rc;
+  host->resize(n);
+  hipStream_t st = current_stream();
+  SS_TRY_HIP(hipMemcpyAsync(host->data(), table, 8 * n, hipMemcpyDeviceToHost, st));
+  SS_TRY_HIP(hipStreamSynchronize(st));
+  const double a0 = (*host)[0], a1 = (*host)[n - 1];
+  if (!(a0 > 0) || !std::isfinite(a1) || !(a1 > a0))
+    return fail(SS_ERR_INVALID_ARG, "learned index needs 0 < a[0] < a[n-1] < inf");
+  return SS_OK;
+}
+
+// u0 / inv are computed on the device with the model's own log2 so that
+// table entries map to exactly 0 and (nearly) 1.
+__global__ void norm_kernel(const double* a, int n, float* out) {
+  const float l0 = __log2f((float)a[0]);
+  const float l1 = __log2f((float)a[n - 1]);
+  out[0] = l0;
+  out[1] = l1 > l0 ? 1.0f / (l1 - l0) : 1.0f;
+}
+
+int make_handle(const double* table, int64_t n, ss_learned** h) {
+  ss_learned* p = new (std::nothrow) ss_learned();
+  if (!p) return fail(SS_ERR_OOM, "learned handle");
+  p->table = table;
+  p->n = (int)n;
+  *h = p;
+  return SS_OK;
+}
+
+int measure_bound(ss_learned* h) {
+  hipStream_t st = current_stream();
+  int* d_worst = nullptr;
+  SS_TRY_HIP(hipMalloc(&d_worst, sizeof(int)));
+  int worst = 0;
+  hipError_t e = hipMemcpyAsync(d_worst, &worst, sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    const int blocks = std::min(1024, (h->n + 255) / 256);
+    hipLaunchKernelGGL(bound_kernel, dim3(blocks), dim3(256), 0, st, h->table, h->n, h->d_params,
+                       h->u0, h->inv, d_worst);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&worst, d_worst, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_worst);
+  if (e != hipSuccess) return hip_fail(e, "error bound");
+  h->E = worst + 1;
+  return SS_OK;
+}
+
+int setup_norm(ss_learned* h) {
+  hipStream_t st = current_stream();
+  float* d = nullptr;
+  SS_TRY_HIP(hipMalloc(&d, 2 * sizeof(float)));
+  float hv[2] = {0, 0};
+  hipLaunchKernelGGL(norm_kernel, dim3(1), dim3(1), 0, st, h->table, h->n, d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(hv, d, sizeof(hv), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "normalisation");
+  h->u0 = hv[0];
+  h->inv = hv[1];
+  return SS_OK;
+}
+
+int run_train(const double* table, int n, float u0, float inv, float* d_params, int steps,
+              float lr, uint64_t seed, int init_from_seed, float* d_grad, double* loss) {
+  hipStream_t st = current_stream();
+  float* d_loss = nullptr;
+  SS_TRY_HIP(hipMalloc(&d_loss, sizeof(float)));
+  TrainArgs a{table, n, steps, lr, seed, u0, inv, d_params, init_from_seed, d_grad, d_loss};
+  const size_t lds = sizeof(TrainLds);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&train_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) {
+    (void)hipFree(d_loss);
+    return hip_fail(e, "training kernel LDS size");
+  }
+  hipLaunchKernelGGL(train_kernel, dim3(1), dim3(kTrainThreads), lds, st, a);
+  e = hipGetLastError();
+  float lv = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&lv, d_loss, sizeof(float), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_loss);
+  if (e != hipSuccess) return hip_fail(e, "training");
+  if (loss) *loss = lv;
+  return SS_OK;
+}
+
+int finish_learned(ss_learned* h) {
+  SS_TRY_HIP(hipMalloc(&h->d_fallbacks, sizeof(unsigned long long)));
+  SS_TRY_HIP(hipMemset(h->d_fallbacks, 0, sizeof(unsigned long long)));
+  h->params.resize(kNP);
+  SS_TRY_HIP(hipMemcpy(h->params.data(), h->d_params, sizeof(float) * kNP, hipMemcpyDeviceToHost));
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  h->device = dev;
+  return measure_bound(h);
+}
+
+}  // namespace
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" {
+
+int ss_learned_build(const double* table, int64_t n, const ss_mlp_opts* opts, ss_learned** out) {
+  clear_error();
+  if (!out) return fail(SS_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  ss_mlp_opts o{3000, 0.01f, 1};
+  if (opts) o = *opts;
+  if (o.steps < 0 || o.steps > 1000000) return fail(SS_ERR_INVALID_ARG, "steps: 0..1e6");
+  if (!(o.lr > 0) || !std::isfinite(o.lr)) return fail(SS_ERR_INVALID_ARG, "lr must be > 0");
+  std::vector<double> host;
+  int rc = check_learned_table(table, n, &host);
+  if (rc != SS_OK) return rc;
+  ss_learned* h = nullptr;
+  if ((rc = make_handle(table, n, &h)) != SS_OK) return rc;
+  h->steps = o.steps;
+  rc = setup_norm(h);
+  if (rc == SS_OK) {
+    hipError_t e = hipMalloc(&h->d_params, sizeof(float) * kNP);
+    rc = e == hipSuccess ? SS_OK : hip_fail(e, "hipMalloc(params)");
+  }
+  if (rc == SS_OK)
+    rc = run_train(table, h->n, h->u0, h->inv, h->d_params, o.steps, o.lr, o.seed, 1, nullptr,
+                   &h->loss);
+  if (rc == SS_OK) rc = finish_learned(h);
+  if (rc != SS_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SS_OK;
+}
+
+int ss_learned_from_weights(const double* table, int64_t n, const float* weights,
+                            ss_learned** out) {
+  clear_error();
+  if (!out || !weights) return fail(SS_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  std::vector<double> host;
+  int rc = check_learned_table(table, n, &host);
+  if (rc != SS_OK) return rc;
+  ss_learned* h = nullptr;
+  if ((rc = make_handle(table, n, &h)) != SS_OK) return rc;
+  rc = setup_norm(h);
+  if (rc == SS_OK) {
+    hipError_t e = hipMalloc(&h->d_params, sizeof(float) * kNP);
+    if (e == hipSuccess)
+      e = hipMemcpy(h->d_params, weights, sizeof(float) * kNP, hipMemcpyHostToDevice);
+    rc = e == hipSuccess ? SS_OK : hip_fail(e, "parameters");
+  }
+  if (rc == SS_OK) rc = finish_learned(h);
+  if (rc != SS_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SS_OK;
+}
+
+int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* out_idx) {
+  clear_error();
+  if (!h) return fail(SS_ERR_INVALID_ARG, "handle is null");
+  int rc = check_span(targets, m, 8, 8, "targets");
+  if (rc == SS_OK) rc = check_span(out_idx, m, 4, 4, "out_idx");
+  if (rc != SS_OK) return rc;
+  hipStream_t st = current_stream();
+  hipLaunchKernelGGL(clear_counter_kernel, dim3(1), dim3(1), 0, st, h->d_fallbacks);
+  SS_TRY_HIP(hipGetLastError());
+  if (m == 0) return SS_OK;
+  if (overlaps(out_idx, (size_t)m * 4, targets, (size_t)m * 8))
+    return fail(SS_ERR_INVALID_ARG, "out_idx overlaps targets");
+  if ((rc = check_device_ptr(targets, "targets")) != SS_OK ||
+      (rc = check_device_ptr(out_idx, "out_idx")) != SS_OK)
+    return rc;
+  DeviceInfo di;
+  if ((rc = device_info(&di)) != SS_OK) return rc;
+  const size_t lds = ((size_t)(h->n + SS_PAD) * 8 + 15) / 16 * 16;
+  const void* kern = reinterpret_cast<const void*>(&learned_kernel<kLearnedQ>);
+  const int64_t per_tile = (int64_t)kLearnedBlock * kLearnedQ;
+  const int64_t ntiles = (m + per_tile - 1) / per_tile;
+  int64_t grid = (int64_t)blocks_per_cu(kern, kLearnedBlock, lds) * di.num_cus * 4;
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
+  LearnedArgs a{h->table, h->d_params, targets, out_idx, h->d_fallbacks, m, h->n, h->E, h->u0, h->inv};
+  void* args[] = {&a};
+  SS_TRY_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(kLearnedBlock), args, lds, st));
+  return SS_OK;
+}
+
+int ss_learned_predict(ss_learned* h, const double* x, int64_t m, float* out_pos) {
+  clear_error();
+  if (!h) return fail(SS_ERR_INVALID_ARG, "handle is null");
+  int rc = check_span(x, m, 8, 8, "x");
+  if (rc == SS_OK) rc = check_span(out_pos, m, 4, 4, "out_pos");
+  if (rc != SS_OK || m == 0) return rc;
+  if ((rc = check_device_ptr(x, "x")) != SS_OK || (rc = check_device_ptr(out_pos, "out_pos")) != SS_OK)
+    return rc;
+  const int64_t blocks = std::min<int64_t>((m + 255) / 256, 8192);
+  hipLaunchKernelGGL(predict_kernel, dim3((unsigned)blocks), dim3(256), 0, current_stream(),
+                     h->d_params, x, m, out_pos, h->u0, h->inv, h->n);
+  SS_TRY_HIP(hipGetLastError());
+  return SS_OK;
+}
+
+int ss_learned_info(const ss_learned* h, double* info, int count) {
+  clear_error();
+  if (!h || !info || count < 6) return fail(SS_ERR_INVALID_ARG, "need a handle and 6 slots");
+  info[0] = h->E;
+  info[1] = h->n;
+  info[2] = h->steps;
+  info[3] = h->loss;
+  info[4] = h->u0;
+  info[5] = h->inv;
+  return SS_OK;
+}
+
+int ss_learned_fallbacks(ss_learned* h, int64_t* count) {
+  clear_error();
+  if (!h || !count) return fail(SS_ERR_INVALID_ARG, "null argument");
+  unsigned long long v = 0;
+  hipStream_t st = current_stream();
+  SS_TRY_HIP(hipMemcpyAsync(&v, h->d_fallbacks, sizeof(v), hipMemcpyDeviceToHost, st));
+  SS_TRY_HIP(hipStreamSynchronize(st));
+  *count = (int64_t)v;
+  return SS_OK;
+}
+
+int ss_learned_weights(const ss_learned* h, float* out, int64_t cap) {
+  clear_error();
+  if (!h || !out || cap < kNP) return fail(SS_ERR_INVALID_ARG, "need a handle and 1153 slots");
+  std::memcpy(out, h->params.data(), sizeof(float) * kNP);
+  return SS_OK;
+}
+
+int ss_mlp_gradient(const double* table, int64_t n, const float* weights, float* grad_out,
+                    double* loss_out) {
+  clear_error();
+  if (!weights || !grad_out) return fail(SS_ERR_INVALID_ARG, "null argument");
+  std::vector<double> host;
+  int rc = check_learned_table(table, n, &host);
+  if (rc != SS_OK) return rc;
+  ss_learned tmp;
+  tmp.table = table;
+  tmp.n = (int)n;
+  if ((rc = setup_norm(&tmp)) != SS_OK) return rc;
+  float *d_p = nullptr, *d_g = nullptr;
+  SS_TRY_HIP(hipMalloc(&d_p, sizeof(float) * kNP));
+  hipError_t e = hipMalloc(&d_g, sizeof(float) * kNP);
+  if (e == hipSuccess) e = hipMemcpy(d_p, weights, sizeof(float) * kNP, hipMemcpyHostToDevice);
+  double loss = 0;
+  if (e == hipSuccess) rc = run_train(table, tmp.n, tmp.u0, tmp.inv, d_p, 0, 1.0f, 0, 0, d_g, &loss);
+  else rc = hip_fail(e, "gradient buffers");
+  if (rc == SS_OK) {
+    e = hipMemcpy(grad_out, d_g, sizeof(float) * kNP, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = hip_fail(e, "gradient copy");
+  }
+  (void)hipFree(d_p);
+  if (d_g) (void)hipFree(d_g);
+  if (rc == SS_OK && loss_out) *loss_out = loss;
+  return rc;
+}
+
+int ss_learned_destroy(ss_learned* h) {
+  clear_error();
+  delete h;
+  return SS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+"""GPU tests of the learned index.
+
+* Indices: bit-exact against the oracle's definition, for trained models,
+  for deliberately useless models (zero, huge and NaN weights force the
+  fallback), and at the full 1e8-target size (bracket check on every index
+  plus an oracle sample).
+* Model arithmetic: the device forward pass against the float64 oracle
+  forward on the same weights; the training kernel's gradient against the
+  oracle's back-propagation.
+* Error bound: every table entry's prediction lies within E - 1 of its index.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import learned as OL
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def binding(gpu):
+    from paper_2112_03229_amd import binding as b
+    return b
+
+
+@pytest.fixture(scope="module")
+def trained(binding, gpu, inputs_mod):
+    table = inputs_mod.learned_table()
+    t = torch.from_numpy(table).to(gpu)
+    say("case build n=2000 steps=3000")
+    li = binding.LearnedIndex(t, steps=3000, lr=0.01, seed=1)
+    return table, t, li
+
+
+def targets_for(inputs_mod, table, m, seed):
+    x = inputs_mod.table_targets(table, m, seed=seed)
+    n = table.shape[0]
+    k = np.arange(0, m, 9)
+    x[k] = table[k % n]
+    k = np.arange(4, m, 13)
+    x[k] = np.nextafter(table[k % n], np.inf)
+    sp = inputs_mod.special_values()
+    x[1:1 + sp.size] = sp
+    return x
+
+
+def test_trained_model_is_exact(binding, gpu, oracle_mod, inputs_mod, trained):
+    table, t, li = trained
+    info = li.info()
+    say(f"learned: {info}")
+    assert info["n"] == 2000 and info["E"] >= 1 and info["loss"] < 1e-3
+    x = targets_for(inputs_mod, table, 300001, seed=3)
+    want = oracle_mod.search_lt(table, x)
+    got = li.search(torch.from_numpy(x).to(gpu)).cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], want[bad[:5]], x[bad[:5]])
+    fb = li.fallbacks()
+    say(f"fallbacks {fb} of {x.size}")
+    # only the special values (NaN, non-positive, outside FP32) should miss
+    assert fb <= 64
+
+
+def test_error_bound_covers_every_entry(binding, gpu, oracle_mod, trained):
+    table, t, li = trained
+    E = li.info()["E"]
+    pos = li.predict(t).cpu().numpy().astype(np.float64)
+    g = np.clip(np.floor(pos), -1, table.size - 1)
+    idx = oracle_mod.search_lt(table, table)
+    assert np.max(np.abs(g - idx)) <= E - 1
+
+
+def test_forward_matches_oracle(binding, gpu, inputs_mod, trained):
+    table, t, li = trained
+    w = li.weights().astype(np.float64)
+    x = inputs_mod.table_targets(table, 20000, seed=5)
+    pos = li.predict(torch.from_numpy(x).to(gpu)).cpu().numpy().astype(np.float64)
+    want = OL.forward(w, OL.model_input(x, table)) * (table.size - 1)
+    # FP32 forward (1088 FMAs, FP32 log2 of x rounded to FP32) vs float64:
+    # agreement to a small fraction of one table position
+    err = np.abs(pos - want)
+    say(f"forward max abs err (positions): {err.max():.3e}")
+    assert err.max() < 0.05
+
+
+@pytest.mark.parametrize("which", ["init", "trained"])
+def test_training_gradient_matches_oracle(binding, gpu, inputs_mod, trained, which):
+    table, t, li = trained
+    if which == "init":
+        w = binding.LearnedIndex(t, steps=0, seed=7).weights()
+    else:
+        w = li.weights()
+    loss_dev, g_dev = binding.mlp_gradient(t, w)
+    w64 = w.astype(np.float64)
+    loss_ref, g_ref = OL.loss_and_grad(w64, table)
+    say(f"{which}: loss dev {loss_dev:.6e} ref {loss_ref:.6e}")
+    assert abs(loss_dev - loss_ref) <= 1e-4 * loss_ref + 1e-9
+    # tolerance from the arithmetic: FP32 forward and backward (about 1e3
+    # dependent operations per point, eps 6e-8) plus the FP32 log2 of the
+    # input, relative to the cancellation-free size of each gradient term
+    scale = OL.grad_scale(w64, table)
+    err = np.abs(g_dev - g_ref)
+    say(f"{which}: worst err/scale {np.max(err / np.maximum(scale, 1e-30)):.3e}")
+    assert np.all(err <= 1e-3 * scale + 1e-12), int(np.argmax(err - 1e-3 * scale))
+
+
+def test_training_is_deterministic(binding, gpu, inputs_mod):
+    table = inputs_mod.single_table(300)
+    t = torch.from_numpy(table).to(gpu)
+    a = binding.LearnedIndex(t, steps=200, seed=3).weights()
+    b = binding.LearnedIndex(t, steps=200, seed=3).weights()
+    c = binding.LearnedIndex(t, steps=200, seed=4).weights()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("kind", ["zero", "huge", "nan", "untrained"])
+def test_useless_models_stay_exact(binding, gpu, oracle_mod, inputs_mod, kind):
+    table = inputs_mod.learned_table()
+    t = torch.from_numpy(table).to(gpu)
+    if kind == "untrained":
+        li = binding.LearnedIndex(t, steps=0, seed=2)
+    else:
+        w = np.zeros(binding.MLP_PARAMS, dtype=np.float32)
+        if kind == "huge":
+            w[:] = np.random.default_rng(0).normal(0, 1e6, w.size).astype(np.float32)
+        if kind == "nan":
+            w[::7] = np.nan
+        li = binding.LearnedIndex(t, weights=w)
+    x = targets_for(inputs_mod, table, 100003, seed=11)
+    want = oracle_mod.search_lt(table, x)
+    got = li.search(torch.from_numpy(x).to(gpu)).cpu().numpy()
+    assert np.array_equal(got, want), kind
+    say(f"{kind}: E={li.info()['E']} fallbacks={li.fallbacks()}")
+
+
+def test_small_tables_and_ragged_sizes(binding, gpu, oracle_mod, inputs_mod):
+    for n in (2, 3, 17, 100, 1000):
+        table = inputs_mod.single_table(n) if n > 2 else np.array([1e-3, 5.0])
+        t = torch.from_numpy(table).to(gpu)
+        li = binding.LearnedIndex(t, steps=300, seed=n)
+        for m in (1, 511, 512, 513, 4099):
+            x = targets_for(inputs_mod, table, max(m, 32), seed=m)[:m]
+            want = oracle_mod.search_lt(table, x)
+            assert np.array_equal(li.search(torch.from_numpy(x).to(gpu)).cpu().numpy(), want)
+
+
+def test_rejects_bad_tables(binding, gpu):
+    neg = torch.tensor([-1.0, 2.0, 3.0], dtype=torch.float64, device=gpu)
+    with pytest.raises(binding.SearchSortedError):
+        binding.LearnedIndex(neg, steps=1)
+    one = torch.tensor([1.0], dtype=torch.float64, device=gpu)
+    with pytest.raises(binding.SearchSortedError):
+        binding.LearnedIndex(one, steps=1)
+
+
+def test_full_size_learned(binding, gpu, oracle_mod, inputs_mod, trained):
+    """n = 2000, 1e8 log-uniform targets: every index bracket-checked, a
+    seeded sample compared with the definition."""
+    table, t, li = trained
+    m = 10**8
+    host = torch.empty(m, dtype=torch.float64).pin_memory()
+    x = inputs_mod.table_targets(table, m, seed=2000, out=host.numpy())
+    say("case full learned n=2000 m=1e8")
+    got = li.search(host.to(gpu)).cpu().numpy()
+    bad, first = oracle_mod.check_bracket(table, x, got)
+    assert bad == 0, first
+    pos = (inputs_mod.uniform(2000, 96, 200000) * m).astype(np.int64)
+    assert np.array_equal(got[pos], oracle_mod.search_lt_at(table, x, pos))
+    say(f"fallbacks {li.fallbacks()} of {m}")
