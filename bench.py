@@ -207,6 +207,43 @@ def measure_paired(torch, binding, inputs, dev) -> dict:
     return res
 
 
+# FP32 work of one learned-index query: the MLP's 32 + 1024 + 32 multiply-adds
+# (2 flops each); the window check and bisection are not counted.
+MLP_FLOPS_PER_QUERY = 2 * (32 + 32 * 32 + 32)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def measure_learned(torch, binding, inputs, dev) -> dict:
+    """One 2000-entry table, 1e8 log-uniform targets: the learned index
+    (trained on the device) against the plain search on the same data."""
+    table = inputs.learned_table()
+    t = torch.from_numpy(table).to(dev)
+    host = torch.empty(M, dtype=torch.float64).pin_memory()
+    inputs.table_targets(table, M, seed=2000, out=host.numpy())
+    x = host.to(dev)
+    out = torch.empty(M, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    li = binding.LearnedIndex(t, steps=3000, lr=0.01, seed=1)
+    build_s = time.perf_counter() - t0
+    ms_l = time_call(torch, lambda: li.search(x, out), reps=3)
+    fallbacks = li.fallbacks()
+    ms_p = time_call(torch, lambda: binding.search_sorted_batch(t, x, out), reps=5)
+    info = li.info()
+    tflops = MLP_FLOPS_PER_QUERY * M / (ms_l * 1e-3) / 1e12
+    res = {"workload": "one 2000-entry table (log-uniform on [1e-8,1e6]), 1e8 targets",
+           "learned": {**roof(M, ms_l), "E": info["E"], "fallbacks": fallbacks,
+                       "train_loss": info["loss"], "build_s": round(build_s, 3),
+                       "alu_roofline": {"bound": "alu", "achieved": round(tflops, 2),
+                                        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                        "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                                        "flops_per_query": MLP_FLOPS_PER_QUERY}},
+           "plain": roof(M, ms_p)}
+    li.close()
+    del x, out, host
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,7 +253,7 @@ def main():
     ap.add_argument("--no-kernels", action="store_true",
                     help="skip the per-kernel comparison after the timed region")
     ap.add_argument("--no-systems", action="store_true",
-                    help="skip the batched and paired plan measurements")
+                    help="skip the batched, paired and learned measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -353,6 +390,9 @@ def main():
         torch.cuda.empty_cache()
         log("bench: paired plan")
         result["paired"] = measure_paired(torch, binding, inputs, dev)
+        torch.cuda.empty_cache()
+        log("bench: learned index")
+        result["learned"] = measure_learned(torch, binding, inputs, dev)
         torch.cuda.empty_cache()
 
     if not args.no_cpu:

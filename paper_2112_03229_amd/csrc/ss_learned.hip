@@ -36,10 +36,10 @@ __device__ __forceinline__ float model_input(double x, float u0, float inv) {
 }
 
 // Forward pass for Q inputs at once (the search's and the bound's code).
-// P may live in global memory (read with scalar loads) or LDS.
-template <int Q>
-__device__ __forceinline__ void mlp_eval(const float* __restrict__ P, const float (&z)[Q],
-                                         float (&out)[Q]) {
+// P points to the 1153 parameters in any address space; the search passes a
+// constant-address-space pointer so that they are read with scalar loads.
+template <int Q, typename PT>
+__device__ __forceinline__ void mlp_eval(PT P, const float (&z)[Q], float (&out)[Q]) {
   float h1[Q][kH];
 #pragma unroll
   for (int j = 0; j < kH; ++j) {
@@ -49,7 +49,9 @@ __device__ __forceinline__ void mlp_eval(const float* __restrict__ P, const floa
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) out[q] = P[kOffB3];
-#pragma unroll
+  // one row of layer-2 weights per iteration (rolled loop): only 32
+  // parameters are live in SGPRs at a time
+#pragma nounroll
   for (int k = 0; k < kH; ++k) {
     float acc[Q];
     const float b2 = P[kOffB2 + k];
@@ -325,9 +327,11 @@ struct LearnedArgs {
   float u0, inv;
 };
 
+typedef const __attribute__((address_space(4))) float* ConstFloatPtr;
+
 template <int Q>
 __device__ __forceinline__ void search_learned(const double* __restrict__ sa, int n,
-                                               const float* __restrict__ P, int E, float u0,
+                                               ConstFloatPtr P, int E, float u0,
                                                float inv, const double (&x)[Q], int (&r)[Q],
                                                int (&fell_back)[Q]) {
   float z[Q], p[Q];
@@ -381,8 +385,14 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
     const int64_t tn = t + gridDim.x;
     double nxt[Q];
     if (tn < ntiles) load_tile<Q>(a.x, a.m, tn * per_tile + threadIdx.x, nt, (tn + 1) * per_tile <= a.m, nxt);
+    // The parameters are read with scalar loads inside every tile: hidden
+    // from loop-invariant hoisting (1153 values do not fit in SGPRs, and
+    // parking them in VGPR lanes costs one extra VALU op per multiply-add).
+    const float* Pg = a.P;
+    asm volatile("" : "+s"(Pg));
+    ConstFloatPtr P = (ConstFloatPtr)Pg;
     int r[Q], fell[Q];
-    search_learned<Q>(sa, a.n, a.P, a.E, a.u0, a.inv, cur, r, fell);
+    search_learned<Q>(sa, a.n, P, a.E, a.u0, a.inv, cur, r, fell);
     const int64_t base = t * per_tile + threadIdx.x;
     const bool full = (t + 1) * per_tile <= a.m;
     // lanes past the end of the ragged last tile searched a stand-in
