@@ -176,7 +176,32 @@ def measure_batched(torch, binding, inputs, dev) -> dict:
         for t in range(batch.num_tables):
             binding.search_sorted_batch(tabs[t], x[qo[t]:qo[t + 1]], out[qo[t]:qo[t + 1]])
     res["plain_per_table_launches"] = roof(m, time_call(torch, plain, reps=2))
+    res["learned"] = measure_learned_plan(
+        torch, binding, lambda: binding.MultiPlan(torch.from_numpy(batch.tables).to(dev),
+                                                  batch.table_off, batch.query_off),
+        lambda pl: pl.search(x, out), m)
     del x, out, host
+    return res
+
+
+def measure_learned_plan(torch, binding, make, run, queries: int) -> dict:
+    """Same plan with every eligible table given a learned model (trained on
+    the device when the plan is built)."""
+    binding.set_option(binding.OPT_PLAN_LEARNED, 1)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = make()
+        build_s = time.perf_counter() - t0
+    finally:
+        binding.set_option(binding.OPT_PLAN_LEARNED, 0)
+    ms = time_call(torch, lambda: run(plan), reps=2)
+    info = plan.info()
+    res = {**roof(queries, ms), "build_s": round(build_s, 2),
+           "learned_tables": int((info["algos"] == binding.ALGO_LEARNED).sum()),
+           "fallbacks": plan.fallbacks(),
+           "alu_tflops": round(MLP_FLOPS_PER_QUERY * queries / (ms * 1e-3) / 1e12, 2)}
+    plan.close()
     return res
 
 
@@ -203,6 +228,12 @@ def measure_paired(torch, binding, inputs, dev) -> dict:
            "tables": info["tables"], "tiles": info["tiles"],
            "tiles_per_wg": info["tiles_per_wg"], "grid": info["grid"],
            "lds_bytes": info["lds_bytes"]}
+    res["learned"] = measure_learned_plan(
+        torch, binding,
+        lambda: binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(dev), pairs.rho.table_off,
+                                 torch.from_numpy(pairs.temp.tables).to(dev),
+                                 pairs.temp.table_off, pairs.rho.query_off),
+        lambda pl: pl.search(r, t, o_r, o_t), 2 * m)
     del r, t, o_r, o_t
     return res
 

@@ -75,8 +75,10 @@ typedef enum {
     SS_ALGO_EXPHASH = 3,     /* exponent hash (Sec. 3.5): bin by the float64
                                 exponent bits (plus optional leading fraction
                                 bits), then a linear scan inside the bin */
-    SS_ALGO_BINARY_GLOBAL = 4 /* bisection reading the table from global
+    SS_ALGO_BINARY_GLOBAL = 4, /* bisection reading the table from global
                                 memory (tables too large for LDS) */
+    SS_ALGO_LEARNED = 5      /* learned index (see ss_learned_build); in
+                                plans, when SS_OPT_PLAN_LEARNED is set */
 } ss_algo;
 
 /* Process-wide tuning options (ss_set_option / ss_get_option). */
@@ -95,8 +97,15 @@ typedef enum {
                                     device memory before launching; 0: skip */
     SS_OPT_TARGETS_PER_LANE = 7, /* targets each lane keeps in flight per
                                     tile: 4 or 8; 0 (default) = auto */
-    SS_OPT_PLAN_TILES = 8        /* tiles per workgroup of plans built
+    SS_OPT_PLAN_TILES = 8,       /* tiles per workgroup of plans built
                                     afterwards; 0 (default) = tuner */
+    SS_OPT_PLAN_LEARNED = 9,     /* 1: plans built afterwards give every
+                                    eligible table (2 <= n, 0 < a[0] <
+                                    a[n-1] < inf) a learned model trained on
+                                    the device at plan creation; 0 (default):
+                                    exponent hash / bisection per the tuner */
+    SS_OPT_LEARNED_STEPS = 10    /* Adam steps of plan models; 0 (default)
+                                    = 500 */
 } ss_option;
 
 /* Human-readable message for the calling thread's most recent error
@@ -215,9 +224,15 @@ SS_API int ss_pair_search(ss_plan *plan, const double *rho, const double *temp,
 
 SS_API int ss_plan_destroy(ss_plan *plan);
 
+/* Targets of the most recent search of a plan with learned tables that
+ * failed the window check and were answered by bisection (0 for plans
+ * without learned tables).  SYNCHRONOUS (waits for the current stream). */
+SS_API int ss_plan_fallbacks(ss_plan *plan, int64_t *count);
+
 /* What the autotuner chose, for inspection (host output):
- *   SS_PLAN_ALGOS  : int32 per table (ss_algo); paired plans list the
- *                    density tables, then the temperature tables
+ *   SS_PLAN_ALGOS  : int32 per table (ss_algo: binary, exphash or
+ *                    learned); paired plans list the density tables, then
+ *                    the temperature tables
  *   SS_PLAN_BITS   : int32 per table (bin bits s, -1 for bisection)
  *   SS_PLAN_SUMMARY: 8 int64 {tables, tiles, tiles per workgroup, grid,
  *                    block, lds_bytes, longest bin (9 = 9 or more),

@@ -22,14 +22,16 @@ STATUS_NAMES = {
 }
 
 ALGO_AUTO, ALGO_BINARY, ALGO_BALLOT, ALGO_EXPHASH, ALGO_BINARY_GLOBAL = 0, 1, 2, 3, 4
+ALGO_LEARNED = 5
 ALGO_NAMES = {ALGO_AUTO: "auto", ALGO_BINARY: "binary", ALGO_BALLOT: "ballot",
-              ALGO_EXPHASH: "exphash", ALGO_BINARY_GLOBAL: "binary_global"}
+              ALGO_EXPHASH: "exphash", ALGO_BINARY_GLOBAL: "binary_global",
+              ALGO_LEARNED: "learned"}
 ALGO_IDS = {v: k for k, v in ALGO_NAMES.items()}
 
 OPT_FORCE_ALGO, OPT_BUCKET_BITS, OPT_BUCKET_CAP = 1, 2, 3
 OPT_BLOCK_SIZE, OPT_GRID_BLOCKS, OPT_CHECK_POINTERS = 4, 5, 6
 OPT_TARGETS_PER_LANE = 7
-OPT_PLAN_TILES = 8
+OPT_PLAN_TILES, OPT_PLAN_LEARNED, OPT_LEARNED_STEPS = 8, 9, 10
 
 
 class SearchSortedError(RuntimeError):
@@ -76,6 +78,7 @@ def _register_extra(L) -> None:
         "ss_multi_search": [P, P, P],
         "ss_plan_destroy": [P],
         "ss_plan_info": [P, I, P, I64],
+        "ss_plan_fallbacks": [P, ctypes.POINTER(I64)],
         "ss_pair_plan_create": [P, P, P, P, I32, P, ctypes.POINTER(P)],
         "ss_pair_search": [P, P, P, P, P],
         "ss_tuner_calibrate": [],
@@ -227,6 +230,12 @@ class _Plan:
             self.close()
         except Exception:
             pass
+
+    def fallbacks(self) -> int:
+        v = ctypes.c_int64()
+        use_current_stream()
+        check(lib().ss_plan_fallbacks(self._handle, ctypes.byref(v)))
+        return v.value
 
     def info(self) -> dict:
         import numpy as np

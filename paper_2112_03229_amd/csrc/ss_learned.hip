@@ -21,67 +21,17 @@
 
 #include "ss_device.h"
 #include "ss_host.h"
+#include "ss_mlp.h"
+#include "ss_learned.h"
 
 namespace ss {
-
-constexpr int kH = 32;
-constexpr int kOffW1 = 0, kOffB1 = 32, kOffW2 = 64, kOffB2 = 64 + kH * kH, kOffW3 = kOffB2 + kH,
-              kOffB3 = kOffW3 + kH, kNP = kOffB3 + 1;
-static_assert(kNP == SS_MLP_PARAMS, "parameter layout");
-constexpr int kTrainThreads = 256;  // also the batch size
-
-// Model input: z = (log2 x - u0) * inv, in FP32 from x rounded to FP32.
-__device__ __forceinline__ float model_input(double x, float u0, float inv) {
-  return (__log2f((float)x) - u0) * inv;
-}
-
-// Forward pass for Q inputs at once (the search's and the bound's code).
-// P points to the 1153 parameters in any address space; the search passes a
-// constant-address-space pointer so that they are read with scalar loads.
-template <int Q, typename PT>
-__device__ __forceinline__ void mlp_eval(PT P, const float (&z)[Q], float (&out)[Q]) {
-  float h1[Q][kH];
-#pragma unroll
-  for (int j = 0; j < kH; ++j) {
-    const float w = P[kOffW1 + j], b = P[kOffB1 + j];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) h1[q][j] = fmaxf(fmaf(w, z[q], b), 0.0f);
-  }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) out[q] = P[kOffB3];
-  // one row of layer-2 weights per iteration (rolled loop): only 32
-  // parameters are live in SGPRs at a time
-#pragma nounroll
-  for (int k = 0; k < kH; ++k) {
-    float acc[Q];
-    const float b2 = P[kOffB2 + k];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] = b2;
-#pragma unroll
-    for (int j = 0; j < kH; ++j) {
-      const float w = P[kOffW2 + kH * k + j];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) acc[q] = fmaf(w, h1[q][j], acc[q]);
-    }
-    const float w3 = P[kOffW3 + k];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) out[q] = fmaf(w3, fmaxf(acc[q], 0.0f), out[q]);
-  }
-}
-
-// Predicted index g = floor(p (n-1)) clamped to [-1, n-1].  Any p, even NaN
-// or inf, yields a valid index (fmaxf/fminf return the bound for NaN).
-__device__ __forceinline__ int predicted_index(float p, int n) {
-  const float g = floorf(p * (float)(n - 1));
-  return (int)fminf(fmaxf(g, -1.0f), (float)(n - 1));
-}
 
 // ---------------------------------------------------------------------------
 // Training.
 // ---------------------------------------------------------------------------
 
 struct TrainArgs {
-  const double* table;
+  const double* table;   // the table's first entry
   int n;
   int steps;       // 0 with grad_out set: one gradient only
   float lr;
@@ -114,9 +64,9 @@ struct TrainLds {
   float red[kTrainThreads];
 };
 
-__global__ __launch_bounds__(kTrainThreads) void train_kernel(TrainArgs a) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  TrainLds& L = *reinterpret_cast<TrainLds*>(lds_raw);
+// Trains (or, with steps == 0, differentiates) one table's model; called by
+// a whole workgroup of kTrainThreads lanes.
+__device__ void train_body(TrainLds& L, const TrainArgs& a) {
   const int tid = threadIdx.x;
   const int n = a.n;
   for (int i = tid; i < kNP; i += kTrainThreads) {
@@ -275,6 +225,24 @@ __global__ __launch_bounds__(kTrainThreads) void train_kernel(TrainArgs a) {
   for (int i = tid; i < kNP; i += kTrainThreads) a.params[i] = L.P[i];
 }
 
+
+__global__ __launch_bounds__(kTrainThreads) void train_kernel(TrainArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  train_body(*reinterpret_cast<TrainLds*>(lds_raw), a);
+}
+
+// One workgroup per slot (table) of a plan: trains every model at once.
+__global__ __launch_bounds__(kTrainThreads) void train_many_kernel(
+    const double* tables_a, const double* tables_b, const LearnedSlot* slots, float* pool,
+    int steps, float lr, uint64_t seed) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const LearnedSlot sl = slots[blockIdx.x];
+  TrainArgs a{(sl.which ? tables_b : tables_a) + sl.tab_off, sl.n, steps, lr,
+              seed ^ (0x9e3779b97f4a7c15ULL * (uint64_t)(blockIdx.x + 1)), sl.u0, sl.inv,
+              pool + sl.p_off, 1, nullptr, nullptr};
+  train_body(*reinterpret_cast<TrainLds*>(lds_raw), a);
+}
+
 // ---------------------------------------------------------------------------
 // Error bound over probes: every entry, its upward neighbour, and the
 // log-midpoint to the next entry.  The true index comes from bisection.
@@ -290,25 +258,63 @@ __device__ __forceinline__ int exact_index(const double* __restrict__ a, int n, 
   return base + (a[base] < x ? 1 : 0) - 1;
 }
 
+// Largest |g(x) - idx(x)| over the three probes of entry i.
+__device__ __forceinline__ int probe_error(const double* __restrict__ a, int n,
+                                           const float* __restrict__ P, float u0, float inv,
+                                           int i) {
+  double probe[3];
+  probe[0] = a[i];
+  probe[1] = nextafter(a[i], __builtin_inf());
+  probe[2] = i + 1 < n ? sqrt(a[i]) * sqrt(a[i + 1]) : a[i];
+  int worst = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float z[1] = {model_input(probe[c], u0, inv)}, p[1];
+    mlp_eval<1>(P, z, p);
+    const int g = predicted_index(p[0], n);
+    worst = max(worst, abs(g - exact_index(a, n, probe[c])));
+  }
+  return worst;
+}
+
 __global__ void bound_kernel(const double* __restrict__ a, int n, const float* __restrict__ P,
                              float u0, float inv, int* worst) {
   int local = 0;
   const int stride = gridDim.x * blockDim.x;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double probe[3];
-    probe[0] = a[i];
-    probe[1] = nextafter(a[i], __builtin_inf());
-    probe[2] = i + 1 < n ? sqrt(a[i]) * sqrt(a[i + 1]) : a[i];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float z[1] = {model_input(probe[c], u0, inv)}, p[1];
-      mlp_eval<1>(P, z, p);
-      const int g = predicted_index(p[0], n);
-      local = max(local, abs(g - exact_index(a, n, probe[c])));
-    }
-  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    local = max(local, probe_error(a, n, P, u0, inv, i));
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(worst, local);
+}
+
+// Per-slot versions for plans: normalisation (one lane per slot) and the
+// error bound (one workgroup per slot).
+__global__ void norm_many_kernel(const double* tables_a, const double* tables_b,
+                                 LearnedSlot* slots, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const LearnedSlot sl = slots[i];
+  const double* a = (sl.which ? tables_b : tables_a) + sl.tab_off;
+  const float l0 = __log2f((float)a[0]);
+  const float l1 = __log2f((float)a[sl.n - 1]);
+  slots[i].u0 = l0;
+  slots[i].inv = l1 > l0 ? 1.0f / (l1 - l0) : 1.0f;
+}
+
+__global__ void bound_many_kernel(const double* tables_a, const double* tables_b,
+                                  LearnedSlot* slots, const float* pool) {
+  __shared__ int worst;
+  const LearnedSlot sl = slots[blockIdx.x];
+  const double* a = (sl.which ? tables_b : tables_a) + sl.tab_off;
+  if (threadIdx.x == 0) worst = 0;
+  __syncthreads();
+  int local = 0;
+  for (int i = threadIdx.x; i < sl.n; i += blockDim.x)
+    local = max(local, probe_error(a, sl.n, pool + sl.p_off, sl.u0, sl.inv, i));
+  for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(&worst, local);
+  __syncthreads();
+  if (threadIdx.x == 0) slots[blockIdx.x].E = worst + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -326,47 +332,6 @@ struct LearnedArgs {
   int E;
   float u0, inv;
 };
-
-typedef const __attribute__((address_space(4))) float* ConstFloatPtr;
-
-template <int Q>
-__device__ __forceinline__ void search_learned(const double* __restrict__ sa, int n,
-                                               ConstFloatPtr P, int E, float u0,
-                                               float inv, const double (&x)[Q], int (&r)[Q],
-                                               int (&fell_back)[Q]) {
-  float z[Q], p[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) z[q] = model_input(x[q], u0, inv);
-  mlp_eval<Q>(P, z, p);
-  int step = 1;
-  while (step * 2 <= 2 * E + 1) step *= 2;  // >= half the window length
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int g = predicted_index(p[q], n);
-    const int L = max(g - E, -1), R = min(g + E, n - 1);
-    const bool lo_ok = L < 0 || sa[max(L, 0)] < x[q];
-    const bool hi_ok = R >= n - 1 || x[q] <= sa[min(R + 1, n - 1)];
-    fell_back[q] = !(lo_ok && hi_ok);
-    if (lo_ok && hi_ok) {
-      // largest pos in [L+1, R+1] with a[pos-1] < x (all of a[..L] are < x)
-      int pos = L + 1;
-      for (int s = step; s >= 1; s >>= 1) {
-        const int cand = pos + s;
-        const int ridx = max(min(cand, R + 1) - 1, 0);
-        pos = ((cand <= R + 1) & (sa[ridx] < x[q])) ? cand : pos;
-      }
-      r[q] = pos - 1;
-    } else {
-      int base = 0, len = n;
-      while (len > 1) {
-        const int half = len >> 1;
-        base = (sa[base + half] < x[q]) ? base + half : base;
-        len -= half;
-      }
-      r[q] = base + (sa[base] < x[q] ? 1 : 0) - 1;
-    }
-  }
-}
 
 template <int Q>
 __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
@@ -553,6 +518,49 @@ int finish_learned(ss_learned* h) {
 }
 
 }  // namespace
+
+bool learned_eligible(const double* a, int64_t n) {
+  return n >= 2 && n <= 65535 && a[0] > 0 && std::isfinite(a[n - 1]) && a[n - 1] > a[0];
+}
+
+int learned_train_slots(const double* tables_a, const double* tables_b,
+                        std::vector<LearnedSlot>& slots, float* d_pool, int steps, float lr,
+                        uint64_t seed) {
+  if (slots.empty()) return SS_OK;
+  hipStream_t st = current_stream();
+  const int count = (int)slots.size();
+  LearnedSlot* d_slots = nullptr;
+  SS_TRY_HIP(hipMalloc(&d_slots, sizeof(LearnedSlot) * count));
+  const size_t lds = sizeof(TrainLds);
+  hipError_t e = hipMemcpyAsync(d_slots, slots.data(), sizeof(LearnedSlot) * count,
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(norm_many_kernel, dim3((count + 255) / 256), dim3(256), 0, st, tables_a,
+                       tables_b, d_slots, count);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&train_many_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(train_many_kernel, dim3(count), dim3(kTrainThreads), lds, st, tables_a,
+                       tables_b, d_slots, d_pool, steps, lr, seed);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(bound_many_kernel, dim3(count), dim3(256), 0, st, tables_a, tables_b,
+                       d_slots, d_pool);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(slots.data(), d_slots, sizeof(LearnedSlot) * count,
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_slots);
+  if (e != hipSuccess) return hip_fail(e, "training plan models");
+  return SS_OK;
+}
+
 }  // namespace ss
 
 using namespace ss;

@@ -23,6 +23,8 @@
 
 #include "ss_device.h"
 #include "ss_host.h"
+#include "ss_learned.h"
+#include "ss_mlp.h"
 #include "ss_tuner.h"
 
 namespace ss {
@@ -30,10 +32,12 @@ namespace ss {
 struct TableDesc {
   int64_t tab_off;   // first entry in the tables array
   int64_t bins_off;  // first entry in the bin pool (exponent hash), else 0
+  int64_t p_off;     // first parameter in the model pool (learned), else 0
   int n;
-  int algo;          // SS_ALGO_BINARY or SS_ALGO_EXPHASH
+  int algo;          // SS_ALGO_BINARY, SS_ALGO_EXPHASH or SS_ALGO_LEARNED
   int shift, kmin, kmaxc, nb, K;
-  int pad_;
+  int E;             // learned: error bound
+  float u0, inv;     // learned: input normalisation
 };
 
 struct MultiArgs {
@@ -44,6 +48,8 @@ struct MultiArgs {
   const int64_t* tile_off;   // [S+1] first tile of each segment (table or material)
   const int64_t* query_off;  // [S+1] first target of each segment
   const int32_t* wg_seg;     // [grid] segment of each workgroup's first tile
+  const float* params;       // model pool (plans with learned tables)
+  unsigned long long* fallbacks;  // learned window misses of the last search
   const double* xa;
   int32_t* oa;
   const double* xb;
@@ -54,32 +60,57 @@ struct MultiArgs {
   int lds_bins_a, lds_tab_b, lds_bins_b;  // byte offsets in LDS
 };
 
+// What a workgroup keeps about the table it has staged.
+struct Staged {
+  HashParams hp;   // exponent hash (hp.ok) ...
+  int learned;     // ... or learned model ...
+  int n;           // ... or bisection
+  int E;
+  float u0, inv;
+  int64_t p_off;
+};
+
 // Copies one table (+inf padded) and, for the exponent hash, its bin table
 // into LDS with 16-byte loads (the pool's bin tables start 16-byte aligned;
-// tables are 8-byte aligned, so they are copied in 8-byte words).  Returns
-// the search parameters.
-__device__ __forceinline__ HashParams stage_desc(const TableDesc& d, const double* __restrict__ tables,
-                                                 const uint16_t* __restrict__ bins, double* sa,
-                                                 uint16_t* C) {
+// tables are 8-byte aligned, so they are copied in 8-byte words).
+__device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* __restrict__ tables,
+                                             const uint16_t* __restrict__ bins, double* sa,
+                                             uint16_t* C) {
   stage_table(sa, tables + d.tab_off, d.n);
-  HashParams hp{0, d.shift, d.kmin, d.kmaxc, d.nb, d.K};
+  Staged st{{0, d.shift, d.kmin, d.kmaxc, d.nb, d.K}, d.algo == SS_ALGO_LEARNED, d.n, d.E,
+            d.u0, d.inv, d.p_off};
   if (d.algo == SS_ALGO_EXPHASH) {
-    hp.ok = 1;
+    st.hp.ok = 1;
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     const u32x4* src = reinterpret_cast<const u32x4*>(bins + d.bins_off);
     u32x4* dst = reinterpret_cast<u32x4*>(C);
     const int words = (d.nb + 1 + 7) / 8;  // the pool pads every table to 8 entries
     for (int w = threadIdx.x; w < words; w += blockDim.x) dst[w] = src[w];
   }
-  return hp;
+  return st;
 }
 
-template <int Q>
-__device__ __forceinline__ void search_desc(const HashParams& hp, const double* sa,
-                                            const uint16_t* C, int n, const double (&x)[Q],
-                                            int (&r)[Q]) {
-  if (hp.ok) search_exphash<Q>(sa, C, n, hp, x, r);
-  else search_binary<Q>(sa, n, x, r);
+template <int Q, int LEARN>
+__device__ __forceinline__ void search_staged(const Staged& st, const double* sa,
+                                              const uint16_t* C, const float* params,
+                                              const double (&x)[Q], int (&r)[Q], int (&fell)[Q]) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) fell[q] = 0;
+  if constexpr (LEARN) {
+    if (st.learned) {
+      // scalar loads of the parameters, one row at a time (see ss_mlp.h);
+      // the address is workgroup-uniform, made explicit for the compiler
+      const uint64_t addr = reinterpret_cast<uint64_t>(params + st.p_off);
+      const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
+      const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
+      const float* Pg = reinterpret_cast<const float*>(((uint64_t)hi << 32) | lo);
+      asm volatile("" : "+s"(Pg));
+      search_learned<Q>(sa, st.n, (ConstFloatPtr)Pg, st.E, st.u0, st.inv, x, r, fell);
+      return;
+    }
+  }
+  if (st.hp.ok) search_exphash<Q>(sa, C, st.n, st.hp, x, r);
+  else search_binary<Q>(sa, st.n, x, r);
 }
 
 // Offsets of one segment (table or material), kept in registers while a
@@ -111,7 +142,7 @@ __device__ __forceinline__ void load_range(const double* __restrict__ x, TileRan
   load_tile<Q>(x, r.q1, r.q0 + threadIdx.x, nt, r.q0 + (int64_t)nt * Q <= r.q1, v);
 }
 
-template <int PAIRED, int Q>
+template <int PAIRED, int Q, int LEARN>
 __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   double* sa = reinterpret_cast<double*>(lds);
@@ -129,19 +160,11 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   load_range<Q>(a.xa, cur, ca);
   if constexpr (PAIRED) load_range<Q>(a.xb, cur, cb);
 
-  HashParams hpa, hpb{};
-  int na, nb_ = 0;
-  {
-    const TableDesc da = a.desc[sg.seg];
-    hpa = stage_desc(da, a.tables_a, a.bins, sa, Ca);
-    na = da.n;
-    if constexpr (PAIRED) {
-      const TableDesc db = a.desc[a.pair_base + sg.seg];
-      hpb = stage_desc(db, a.tables_b, a.bins, sb, Cb);
-      nb_ = db.n;
-    }
-  }
+  Staged sta, stb{};
+  sta = stage_desc(a.desc[sg.seg], a.tables_a, a.bins, sa, Ca);
+  if constexpr (PAIRED) stb = stage_desc(a.desc[a.pair_base + sg.seg], a.tables_b, a.bins, sb, Cb);
   __syncthreads();
+  int fallbacks = 0;
   for (int64_t j = j0; j < j1; ++j) {
     // the next tile, possibly in a later segment (segments without targets
     // have no tiles and are skipped)
@@ -156,24 +179,29 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
       if constexpr (PAIRED) load_range<Q>(a.xb, nxt, xb_n);
     }
     const bool full = cur.q0 + per_tile <= cur.q1;
-    int r[Q];
-    search_desc<Q>(hpa, sa, Ca, na, ca, r);
+    int r[Q], fell[Q];
+    search_staged<Q, LEARN>(sta, sa, Ca, a.params, ca, r, fell);
     store_tile<Q>(a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
+    if constexpr (LEARN) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        fallbacks += (full || cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1) ? fell[q] : 0;
+    }
     if constexpr (PAIRED) {
-      search_desc<Q>(hpb, sb, Cb, nb_, cb, r);
+      search_staged<Q, LEARN>(stb, sb, Cb, a.params, cb, r, fell);
       store_tile<Q>(a.ob, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
+      if constexpr (LEARN) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+          fallbacks += (full || cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1) ? fell[q] : 0;
+      }
     }
     if (!has_next) break;
     if (nsg.seg != sg.seg) {
       __syncthreads();  // every lane is done with the old table
-      const TableDesc da = a.desc[nsg.seg];
-      hpa = stage_desc(da, a.tables_a, a.bins, sa, Ca);
-      na = da.n;
-      if constexpr (PAIRED) {
-        const TableDesc db = a.desc[a.pair_base + nsg.seg];
-        hpb = stage_desc(db, a.tables_b, a.bins, sb, Cb);
-        nb_ = db.n;
-      }
+      sta = stage_desc(a.desc[nsg.seg], a.tables_a, a.bins, sa, Ca);
+      if constexpr (PAIRED)
+        stb = stage_desc(a.desc[a.pair_base + nsg.seg], a.tables_b, a.bins, sb, Cb);
       __syncthreads();
     }
     sg = nsg;
@@ -183,7 +211,14 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
       if constexpr (PAIRED) cb[q] = xb_n[q];
     }
   }
+  if constexpr (LEARN) {
+    unsigned long long w = (unsigned long long)fallbacks;
+    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+    if ((threadIdx.x & 63) == 0 && w) atomicAdd(a.fallbacks, w);
+  }
 }
+
+__global__ void plan_clear_kernel(unsigned long long* c) { *c = 0ull; }
 
 // Builds every exponent-hash table's bins into the pool (one workgroup per
 // table) with the same routine the single-table kernels run in LDS, and
@@ -227,6 +262,9 @@ struct ss_plan {
   int64_t* d_query_off = nullptr;
   int32_t* d_wg_seg = nullptr;
   int* d_k = nullptr;
+  float* d_pool = nullptr;                 // learned models
+  unsigned long long* d_fallbacks = nullptr;
+  int learned_tables = 0;
   int64_t total_tiles = 0;
   int tiles_per_wg = 0;
   int grid = 0, block = 0, q = 0;
@@ -236,6 +274,7 @@ struct ss_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraphNode_t search_node = nullptr;
+  hipGraphNode_t clear_node = nullptr;
   int64_t graph_uses = 0;
   const void* kernel = nullptr;
 
@@ -243,7 +282,7 @@ struct ss_plan {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (void* ptr : {(void*)d_desc, (void*)d_bins, (void*)d_tile_off, (void*)d_query_off,
-                      (void*)d_wg_seg, (void*)d_k})
+                      (void*)d_wg_seg, (void*)d_k, (void*)d_pool, (void*)d_fallbacks})
       if (ptr) (void)hipFree(ptr);
   }
 };
@@ -255,6 +294,8 @@ namespace {
 constexpr int kPlanBlock = 512;
 constexpr int kPlanQ = 8;
 constexpr int kPairQ = 4;
+constexpr int kLearnedPlanQ = 2;          // the model's registers limit Q
+constexpr int kDefaultPlanLearnedSteps = 500;
 // LDS a plan's workgroup may use (tables + bin tables): three 512-thread
 // workgroups per CU fit in 160 KB.
 constexpr size_t kPlanLdsBudget = 48 * 1024;
@@ -283,7 +324,9 @@ void describe(const TunedTable& tt, int64_t tab_off, TableDesc* d, int64_t* pool
   d->nb = tt.nb;
   d->K = tt.K;
   d->bins_off = 0;
-  d->pad_ = 0;
+  d->p_off = 0;
+  d->E = 0;
+  d->u0 = d->inv = 0.0f;
   if (tt.algo == SS_ALGO_EXPHASH) {
     d->bins_off = *pool_len;
     *pool_len += tt.nb + 1;
@@ -296,6 +339,51 @@ size_t align16(size_t v) { return (v + 15) / 16 * 16; }
 int fail_delete(ss_plan* p, const char* msg, int code = SS_ERR_INVALID_ARG) {
   delete p;
   return msg ? fail(code, msg) : code;
+}
+
+// Gives every eligible table a learned model (SS_OPT_PLAN_LEARNED): trains
+// them all in one launch and records each model's normalisation and bound.
+// host_a / host_b are host copies of the two tables arrays.
+int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
+                  const std::vector<double>& host_a, const std::vector<double>& host_b) {
+  std::vector<LearnedSlot> slots;
+  std::vector<int> slot_desc;
+  for (int t = 0; t < p->T; ++t) {
+    TableDesc& d = p->desc[t];
+    const int which = (p->paired && t >= p->M) ? 1 : 0;
+    const double* h = (which ? host_b.data() : host_a.data()) + d.tab_off;
+    if (!learned_eligible(h, d.n)) continue;
+    LearnedSlot sl{};
+    sl.tab_off = d.tab_off;
+    sl.p_off = (int64_t)slots.size() * kNP;
+    sl.n = d.n;
+    sl.which = which;
+    slots.push_back(sl);
+    slot_desc.push_back(t);
+  }
+  if (slots.empty()) return SS_OK;
+  SS_TRY_HIP(hipMalloc(&p->d_pool, sizeof(float) * kNP * slots.size()));
+  SS_TRY_HIP(hipMalloc(&p->d_fallbacks, sizeof(unsigned long long)));
+  SS_TRY_HIP(hipMemset(p->d_fallbacks, 0, sizeof(unsigned long long)));
+  int steps = (int)option(SS_OPT_LEARNED_STEPS);
+  if (steps <= 0) steps = kDefaultPlanLearnedSteps;
+  int rc = learned_train_slots(tables_a, tables_b, slots, p->d_pool, steps, 0.01f, 1);
+  if (rc != SS_OK) return rc;
+  for (size_t i = 0; i < slots.size(); ++i) {
+    const int t = slot_desc[i];
+    TableDesc& d = p->desc[t];
+    d.algo = SS_ALGO_LEARNED;
+    d.bins_off = 0;
+    d.nb = d.K = 0;
+    d.p_off = slots[i].p_off;
+    d.E = slots[i].E;
+    d.u0 = slots[i].u0;
+    d.inv = slots[i].inv;
+    p->tuned[t].algo = SS_ALGO_LEARNED;
+    p->tuned[t].bits = -1;
+  }
+  p->learned_tables = (int)slots.size();
+  return SS_OK;
 }
 
 hipKernelNodeParams search_node_params(ss_plan* p, void** kargs) {
@@ -335,7 +423,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   }
 
   p->block = kPlanBlock;
-  p->q = p->paired ? kPairQ : kPlanQ;
+  p->q = p->learned_tables > 0 ? kLearnedPlanQ : (p->paired ? kPairQ : kPlanQ);
   const int64_t per_tile = (int64_t)p->block * p->q;
   // tiles of every segment, numbered back to back
   const int S = p->S;
@@ -345,8 +433,12 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   p->total_tiles = tile_off[S];
 
   p->lds = lds_tab_a + lds_bins_a + lds_tab_b + lds_bins_b;
-  p->kernel = p->paired ? reinterpret_cast<const void*>(&multi_kernel<1, kPairQ>)
-                        : reinterpret_cast<const void*>(&multi_kernel<0, kPlanQ>);
+  if (p->learned_tables > 0)
+    p->kernel = p->paired ? reinterpret_cast<const void*>(&multi_kernel<1, kLearnedPlanQ, 1>)
+                          : reinterpret_cast<const void*>(&multi_kernel<0, kLearnedPlanQ, 1>);
+  else
+    p->kernel = p->paired ? reinterpret_cast<const void*>(&multi_kernel<1, kPairQ, 0>)
+                          : reinterpret_cast<const void*>(&multi_kernel<0, kPlanQ, 0>);
   DeviceInfo di;
   int rc = device_info(&di);
   if (rc != SS_OK) return rc;
@@ -384,6 +476,8 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   a.tile_off = p->d_tile_off;
   a.query_off = p->d_query_off;
   a.wg_seg = p->d_wg_seg;
+  a.params = p->d_pool;
+  a.fallbacks = p->d_fallbacks;
   a.total_tiles = p->total_tiles;
   a.tiles_per_wg = p->tiles_per_wg;
   a.pair_base = p->paired ? p->M : 0;
@@ -391,11 +485,26 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   a.lds_tab_b = (int)(lds_tab_a + lds_bins_a);
   a.lds_bins_b = (int)(lds_tab_a + lds_bins_a + lds_tab_b);
 
-  // the graph holds the one search launch; its pointers are updated in place
+  // the graph holds the one search launch (preceded, with learned tables, by
+  // a one-thread node clearing the fallback counter); pointers are updated
+  // in place
   SS_TRY_HIP(hipGraphCreate(&p->graph, 0));
   void* kargs[] = {&p->args};
   hipKernelNodeParams kp = search_node_params(p, kargs);
-  SS_TRY_HIP(hipGraphAddKernelNode(&p->search_node, p->graph, nullptr, 0, &kp));
+  if (p->learned_tables > 0) {
+    hipKernelNodeParams cp{};
+    void* cargs[] = {&p->d_fallbacks};
+    cp.func = reinterpret_cast<void*>(&plan_clear_kernel);
+    cp.gridDim = dim3(1);
+    cp.blockDim = dim3(1);
+    cp.sharedMemBytes = 0;
+    cp.kernelParams = cargs;
+    cp.extra = nullptr;
+    SS_TRY_HIP(hipGraphAddKernelNode(&p->clear_node, p->graph, nullptr, 0, &cp));
+    SS_TRY_HIP(hipGraphAddKernelNode(&p->search_node, p->graph, &p->clear_node, 1, &kp));
+  } else {
+    SS_TRY_HIP(hipGraphAddKernelNode(&p->search_node, p->graph, nullptr, 0, &kp));
+  }
   SS_TRY_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
   return SS_OK;
 }
@@ -467,6 +576,13 @@ int ss_multi_plan_create(const double* tables, const int64_t* table_off, int32_t
     describe(p->tuned[t], table_off[t], &p->desc[t], &pool);
     if (p->tuned[t].algo == SS_ALGO_EXPHASH)
       max_bins = std::max(max_bins, align16((size_t)(p->tuned[t].nb + 1) * 2));
+  }
+  if (option(SS_OPT_PLAN_LEARNED)) {
+    if ((rc = apply_learned(p, tables, nullptr, host, host)) != SS_OK) return fail_delete(p, nullptr, rc);
+    max_bins = 0;
+    for (int t = 0; t < T; ++t)
+      if (p->desc[t].algo == SS_ALGO_EXPHASH)
+        max_bins = std::max(max_bins, align16((size_t)(p->desc[t].nb + 1) * 2));
   }
   rc = finish_plan(p, tables, nullptr, pool, max_tab, max_bins, 0, 0);
   if (rc != SS_OK) {
@@ -549,6 +665,17 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
     if (p->tuned[M + j].algo == SS_ALGO_EXPHASH)
       bins_b = std::max(bins_b, align16((size_t)(p->tuned[M + j].nb + 1) * 2));
   }
+  if (option(SS_OPT_PLAN_LEARNED)) {
+    if ((rc = apply_learned(p, rho_tables, t_tables, hr, ht)) != SS_OK)
+      return fail_delete(p, nullptr, rc);
+    bins_a = bins_b = 0;
+    for (int j = 0; j < M; ++j) {
+      if (p->desc[j].algo == SS_ALGO_EXPHASH)
+        bins_a = std::max(bins_a, align16((size_t)(p->desc[j].nb + 1) * 2));
+      if (p->desc[M + j].algo == SS_ALGO_EXPHASH)
+        bins_b = std::max(bins_b, align16((size_t)(p->desc[M + j].nb + 1) * 2));
+    }
+  }
   rc = finish_plan(p, rho_tables, t_tables, pool, tab_a, bins_a, tab_b, bins_b);
   if (rc != SS_OK) {
     delete p;
@@ -587,6 +714,19 @@ int ss_pair_search(ss_plan* p, const double* rho, const double* temp, int32_t* o
 int ss_plan_destroy(ss_plan* p) {
   clear_error();
   delete p;
+  return SS_OK;
+}
+
+int ss_plan_fallbacks(ss_plan* p, int64_t* count) {
+  clear_error();
+  if (!p || !count) return fail(SS_ERR_INVALID_ARG, "null argument");
+  *count = 0;
+  if (!p->d_fallbacks) return SS_OK;
+  unsigned long long v = 0;
+  hipStream_t st = current_stream();
+  SS_TRY_HIP(hipMemcpyAsync(&v, p->d_fallbacks, sizeof(v), hipMemcpyDeviceToHost, st));
+  SS_TRY_HIP(hipStreamSynchronize(st));
+  *count = (int64_t)v;
   return SS_OK;
 }
 

@@ -22,6 +22,8 @@ std::atomic<int64_t> g_grid_blocks{0};
 std::atomic<int64_t> g_check_pointers{1};
 std::atomic<int64_t> g_targets_per_lane{0};
 std::atomic<int64_t> g_plan_tiles{0};
+std::atomic<int64_t> g_plan_learned{0};
+std::atomic<int64_t> g_learned_steps{0};
 
 std::mutex g_dev_mu;
 std::map<int, DeviceInfo> g_dev_cache;
@@ -55,6 +57,8 @@ int64_t option(int opt) {
     case SS_OPT_CHECK_POINTERS: return g_check_pointers.load();
     case SS_OPT_TARGETS_PER_LANE: return g_targets_per_lane.load();
     case SS_OPT_PLAN_TILES: return g_plan_tiles.load();
+    case SS_OPT_PLAN_LEARNED: return g_plan_learned.load();
+    case SS_OPT_LEARNED_STEPS: return g_learned_steps.load();
     default: return 0;
   }
 }
@@ -153,7 +157,8 @@ int ss_set_option(int opt, int64_t v) {
   switch (opt) {
     case SS_OPT_FORCE_ALGO:
       if (v < SS_ALGO_AUTO || v > SS_ALGO_BINARY_GLOBAL)
-        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_FORCE_ALGO: unknown algorithm");
+        return ss::fail(SS_ERR_INVALID_ARG,
+                        "SS_OPT_FORCE_ALGO: unknown single-table algorithm");
       ss::g_force_algo = v;
       return SS_OK;
     case SS_OPT_BUCKET_BITS:
@@ -190,6 +195,15 @@ int ss_set_option(int opt, int64_t v) {
         return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PLAN_TILES: expected 0..4096");
       ss::g_plan_tiles = v;
       return SS_OK;
+    case SS_OPT_PLAN_LEARNED:
+      if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PLAN_LEARNED: 0 or 1");
+      ss::g_plan_learned = v;
+      return SS_OK;
+    case SS_OPT_LEARNED_STEPS:
+      if (v < 0 || v > 1000000)
+        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_LEARNED_STEPS: expected 0..1e6");
+      ss::g_learned_steps = v;
+      return SS_OK;
     default:
       return ss::fail(SS_ERR_INVALID_ARG, "unknown option");
   }
@@ -206,6 +220,8 @@ int ss_get_option(int opt, int64_t* value_out) {
     case SS_OPT_CHECK_POINTERS:
     case SS_OPT_TARGETS_PER_LANE:
     case SS_OPT_PLAN_TILES:
+    case SS_OPT_PLAN_LEARNED:
+    case SS_OPT_LEARNED_STEPS:
       *value_out = ss::option(opt);
       return SS_OK;
     default:

@@ -206,3 +206,59 @@ def test_full_size_paired(binding, gpu, oracle_mod, inputs_mod):
         for t in np.unique(seg)[::8]:
             p = pos[seg == t]
             assert np.array_equal(got[p], oracle_mod.search_lt_at(b.table(t), x, p)), (name, t)
+
+
+def test_learned_batched_plan_is_exact(binding, gpu, oracle_mod, inputs_mod):
+    """Every eligible table gets a device-trained model; ineligible ones
+    (negative entries, a single entry, empty) keep the tuner's kernel."""
+    tables, toff, qoff, x = odd_batch(inputs_mod, seed=12)
+    want = oracle_mod.search_lt_segments(tables, toff, x, qoff)
+    try:
+        binding.set_option(binding.OPT_PLAN_LEARNED, 1)
+        binding.set_option(binding.OPT_LEARNED_STEPS, 300)
+        say(f"case learned batched T={toff.size - 1}")
+        plan = binding.MultiPlan(torch.from_numpy(tables).to(gpu), toff, qoff)
+    finally:
+        binding.set_option(binding.OPT_PLAN_LEARNED, 0)
+        binding.set_option(binding.OPT_LEARNED_STEPS, 0)
+    out = plan.search(torch.from_numpy(x).to(gpu))
+    got = out.cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], want[bad[:5]], x[bad[:5]])
+    info = plan.info()
+    T = toff.size - 1
+    algos = info["algos"]
+    assert algos[0] == binding.ALGO_LEARNED
+    assert algos[T - 5] != binding.ALGO_LEARNED    # negative entries
+    assert algos[T - 6] != binding.ALGO_LEARNED    # empty table
+    assert algos[T - 7] != binding.ALGO_LEARNED    # single entry
+    say(f"learned tables {int((algos == binding.ALGO_LEARNED).sum())} of {T}, "
+        f"fallbacks {plan.fallbacks()} of {x.size}")
+    # replay: still exact, fallback counter restarts
+    out.fill_(-3)
+    plan.search(torch.from_numpy(x).to(gpu), out)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_learned_paired_plan_is_exact(binding, gpu, oracle_mod, inputs_mod):
+    pairs = inputs_mod.paired_layout(seed=13, materials=48, total_pairs=10**6)
+    rho, temp = inputs_mod.paired_targets(pairs, seed=13)
+    rho[:3] = [np.nan, 0.0, np.inf]
+    want_r = oracle_mod.search_lt_segments(pairs.rho.tables, pairs.rho.table_off, rho,
+                                           pairs.rho.query_off)
+    want_t = oracle_mod.search_lt_segments(pairs.temp.tables, pairs.temp.table_off, temp,
+                                           pairs.temp.query_off)
+    try:
+        binding.set_option(binding.OPT_PLAN_LEARNED, 1)
+        binding.set_option(binding.OPT_LEARNED_STEPS, 300)
+        plan = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(gpu), pairs.rho.table_off,
+                                torch.from_numpy(pairs.temp.tables).to(gpu),
+                                pairs.temp.table_off, pairs.rho.query_off)
+    finally:
+        binding.set_option(binding.OPT_PLAN_LEARNED, 0)
+        binding.set_option(binding.OPT_LEARNED_STEPS, 0)
+    out_r, out_t = plan.search(torch.from_numpy(rho).to(gpu), torch.from_numpy(temp).to(gpu))
+    assert np.array_equal(out_r.cpu().numpy(), want_r)
+    assert np.array_equal(out_t.cpu().numpy(), want_t)
+    assert np.all(plan.info()["algos"] == binding.ALGO_LEARNED)
+    say(f"paired learned fallbacks {plan.fallbacks()} of {2 * pairs.num_pairs}")
