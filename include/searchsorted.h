@@ -104,8 +104,11 @@ typedef enum {
                                     a[n-1] < inf) a learned model trained on
                                     the device at plan creation; 0 (default):
                                     exponent hash / bisection per the tuner */
-    SS_OPT_LEARNED_STEPS = 10    /* Adam steps of plan models; 0 (default)
+    SS_OPT_LEARNED_STEPS = 10,   /* Adam steps of plan models; 0 (default)
                                     = 500 */
+    SS_OPT_PLAN_XCD = 11         /* workgroup-to-XCD mapping of plans built
+                                    afterwards: 0 (default) = contiguous
+                                    tile ranges per XCD, 1 = dispatch order */
 } ss_option;
 
 /* Human-readable message for the calling thread's most recent error

@@ -2,9 +2,10 @@
 // device-built exponent-hash bin tables, the search kernel (batched and
 // paired forms) and the HIP graph that launches it.
 //
-// Every table's targets are cut into tiles of blockDim.x * Q targets (the
-// last tile of a table may be short), and the tiles of all tables are
-// numbered back to back.  Workgroup w of the grid searches the k
+// Every table's targets are cut into tiles at absolute multiples of
+// blockDim.x * Q target positions (so a table's first and last tiles may be
+// short and every other tile is aligned: its loads and stores cover whole
+// cache lines), and the tiles of all tables are numbered back to back.  Workgroup w of the grid searches the k
 // consecutive tiles [w k, (w+1) k) -- k is the tile shape the tuner picks --
 // so the grid is several times the resident workgroup count and the
 // hardware dispatcher balances it, exactly like the single-table launch.  A
@@ -40,6 +41,18 @@ struct TableDesc {
   float u0, inv;     // learned: input normalisation
 };
 
+// Everything a workgroup needs to issue its first target loads, in one
+// 32-byte record: its first tile's target range, its segment's target end
+// and how many of its tiles lie in that segment.
+struct WgStart {
+  int64_t seg_q0;    // the segment's first target
+  int64_t seg_q1;    // end of the segment's targets
+  int32_t seg;       // segment (table or material) of the first tile
+  int32_t first;     // index of the first tile within the segment
+  int32_t seg_tiles; // tiles of the segment
+  int32_t pad_;
+};
+
 struct MultiArgs {
   const double* tables_a;
   const double* tables_b;
@@ -47,7 +60,7 @@ struct MultiArgs {
   const uint16_t* bins;
   const int64_t* tile_off;   // [S+1] first tile of each segment (table or material)
   const int64_t* query_off;  // [S+1] first target of each segment
-  const int32_t* wg_seg;     // [grid] segment of each workgroup's first tile
+  const struct WgStart* wg_start;  // [num_wg] where each workgroup starts
   const float* params;       // model pool (plans with learned tables)
   unsigned long long* fallbacks;  // learned window misses of the last search
   const double* xa;
@@ -56,6 +69,8 @@ struct MultiArgs {
   int32_t* ob;
   int64_t total_tiles;
   int tiles_per_wg;
+  int num_wg;                // workgroups with work (the grid may be padded)
+  int xcd_groups;            // > 1: workgroup ids remapped per XCD (see below)
   int pair_base;             // index of the first temperature descriptor (paired)
   int lds_bins_a, lds_tab_b, lds_bins_b;  // byte offsets in LDS
 };
@@ -130,9 +145,11 @@ struct TileRange {
   int64_t q0, q1;
 };
 
+// Tile j of segment s: the part of aligned block (q0 / per_tile) + (j - t0)
+// that lies inside the segment.
 __device__ __forceinline__ TileRange tile_range(const Segment& s, int64_t j, int64_t per_tile) {
-  const int64_t q0 = s.q0 + (j - s.t0) * per_tile;
-  return {q0, min(q0 + per_tile, s.q1)};
+  const int64_t b = s.q0 / per_tile + (j - s.t0);
+  return {max(s.q0, b * per_tile), min((b + 1) * per_tile, s.q1)};
 }
 
 template <int Q>
@@ -151,14 +168,35 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   uint16_t* Cb = reinterpret_cast<uint16_t*>(lds + a.lds_bins_b);
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
-  const int64_t j0 = (int64_t)blockIdx.x * a.tiles_per_wg;
+  // Workgroup b runs on XCD b mod X (the dispatcher's round robin).  With
+  // X = xcd_groups > 1 the grid is padded to a multiple of X and block b
+  // takes logical range (b mod X) * (grid / X) + b / X, so each XCD sweeps
+  // one contiguous part of the tile space and the tables it stages stay in
+  // its own L2.
+  int wid = blockIdx.x;
+  if (a.xcd_groups > 1) {
+    const int per = gridDim.x / a.xcd_groups;
+    wid = (blockIdx.x % a.xcd_groups) * per + blockIdx.x / a.xcd_groups;
+  }
+  if (wid >= a.num_wg) return;
+  const int64_t j0 = (int64_t)wid * a.tiles_per_wg;
   const int64_t j1 = min(j0 + (int64_t)a.tiles_per_wg, a.total_tiles);
   if (j0 >= j1) return;
-  Segment sg = load_segment(a, a.wg_seg[blockIdx.x]);
-  TileRange cur = tile_range(sg, j0, per_tile);
-  double ca[Q], cb[Q];
+  const WgStart ws = a.wg_start[wid];
+  // Tiles j, j+1 and j+2 are in flight at once: the targets of the two
+  // tiles after the one being searched are already being loaded.
+  Segment sg{ws.seg, j0 - ws.first, j0 - ws.first + ws.seg_tiles, ws.seg_q0, ws.seg_q1};
+  Segment sg1 = sg, sg2 = sg;
+  TileRange cur = tile_range(sg, j0, per_tile), nx1{0, 0}, nx2{0, 0};
+  double ca[Q], cb[Q], ca1[Q], cb1[Q];
   load_range<Q>(a.xa, cur, ca);
   if constexpr (PAIRED) load_range<Q>(a.xb, cur, cb);
+  if (j0 + 1 < j1) {
+    while (j0 + 1 >= sg1.t1) sg1 = load_segment(a, sg1.seg + 1);
+    nx1 = tile_range(sg1, j0 + 1, per_tile);
+    load_range<Q>(a.xa, nx1, ca1);
+    if constexpr (PAIRED) load_range<Q>(a.xb, nx1, cb1);
+  }
 
   Staged sta, stb{};
   sta = stage_desc(a.desc[sg.seg], a.tables_a, a.bins, sa, Ca);
@@ -166,19 +204,15 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   __syncthreads();
   int fallbacks = 0;
   for (int64_t j = j0; j < j1; ++j) {
-    // the next tile, possibly in a later segment (segments without targets
-    // have no tiles and are skipped)
-    const bool has_next = j + 1 < j1;
-    Segment nsg = sg;
-    double xa_n[Q], xb_n[Q];
-    TileRange nxt{0, 0};
-    if (has_next) {
-      while (j + 1 >= nsg.t1) nsg = load_segment(a, nsg.seg + 1);
-      nxt = tile_range(nsg, j + 1, per_tile);
-      load_range<Q>(a.xa, nxt, xa_n);
-      if constexpr (PAIRED) load_range<Q>(a.xb, nxt, xb_n);
+    double ca2[Q], cb2[Q];
+    if (j + 2 < j1) {
+      sg2 = sg1;
+      while (j + 2 >= sg2.t1) sg2 = load_segment(a, sg2.seg + 1);
+      nx2 = tile_range(sg2, j + 2, per_tile);
+      load_range<Q>(a.xa, nx2, ca2);
+      if constexpr (PAIRED) load_range<Q>(a.xb, nx2, cb2);
     }
-    const bool full = cur.q0 + per_tile <= cur.q1;
+    const bool full = cur.q0 + per_tile == cur.q1;
     int r[Q], fell[Q];
     search_staged<Q, LEARN>(sta, sa, Ca, a.params, ca, r, fell);
     store_tile<Q>(a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
@@ -196,19 +230,25 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
           fallbacks += (full || cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1) ? fell[q] : 0;
       }
     }
-    if (!has_next) break;
-    if (nsg.seg != sg.seg) {
+    if (j + 1 >= j1) break;
+    if (sg1.seg != sg.seg) {
       __syncthreads();  // every lane is done with the old table
-      sta = stage_desc(a.desc[nsg.seg], a.tables_a, a.bins, sa, Ca);
+      sta = stage_desc(a.desc[sg1.seg], a.tables_a, a.bins, sa, Ca);
       if constexpr (PAIRED)
-        stb = stage_desc(a.desc[a.pair_base + nsg.seg], a.tables_b, a.bins, sb, Cb);
+        stb = stage_desc(a.desc[a.pair_base + sg1.seg], a.tables_b, a.bins, sb, Cb);
       __syncthreads();
     }
-    sg = nsg;
-    cur = nxt;
+    sg = sg1;
+    sg1 = sg2;
+    cur = nx1;
+    nx1 = nx2;
     for (int q = 0; q < Q; ++q) {
-      ca[q] = xa_n[q];
-      if constexpr (PAIRED) cb[q] = xb_n[q];
+      ca[q] = ca1[q];
+      ca1[q] = ca2[q];
+      if constexpr (PAIRED) {
+        cb[q] = cb1[q];
+        cb1[q] = cb2[q];
+      }
     }
   }
   if constexpr (LEARN) {
@@ -260,13 +300,14 @@ struct ss_plan {
   uint16_t* d_bins = nullptr;
   int64_t* d_tile_off = nullptr;
   int64_t* d_query_off = nullptr;
-  int32_t* d_wg_seg = nullptr;
+  ss::WgStart* d_wg_start = nullptr;
   int* d_k = nullptr;
   float* d_pool = nullptr;                 // learned models
   unsigned long long* d_fallbacks = nullptr;
   int learned_tables = 0;
   int64_t total_tiles = 0;
   int tiles_per_wg = 0;
+  int num_wg = 0, xcd_groups = 1;
   int grid = 0, block = 0, q = 0;
   size_t lds = 0;
   int max_k = 0;
@@ -282,7 +323,7 @@ struct ss_plan {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (void* ptr : {(void*)d_desc, (void*)d_bins, (void*)d_tile_off, (void*)d_query_off,
-                      (void*)d_wg_seg, (void*)d_k, (void*)d_pool, (void*)d_fallbacks})
+                      (void*)d_wg_start, (void*)d_k, (void*)d_pool, (void*)d_fallbacks})
       if (ptr) (void)hipFree(ptr);
   }
 };
@@ -296,6 +337,7 @@ constexpr int kPlanQ = 8;
 constexpr int kPairQ = 4;
 constexpr int kLearnedPlanQ = 2;          // the model's registers limit Q
 constexpr int kDefaultPlanLearnedSteps = 500;
+constexpr int kXcds = 8;                  // accelerator complex dies of an MI355X
 // LDS a plan's workgroup may use (tables + bin tables): three 512-thread
 // workgroups per CU fit in 160 KB.
 constexpr size_t kPlanLdsBudget = 48 * 1024;
@@ -422,14 +464,16 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
     p->max_k = std::max(p->max_k, k[t]);
   }
 
-  p->block = kPlanBlock;
+  p->block = option(SS_OPT_BLOCK_SIZE) > 0 ? (int)option(SS_OPT_BLOCK_SIZE) : kPlanBlock;
   p->q = p->learned_tables > 0 ? kLearnedPlanQ : (p->paired ? kPairQ : kPlanQ);
   const int64_t per_tile = (int64_t)p->block * p->q;
   // tiles of every segment, numbered back to back
   const int S = p->S;
   std::vector<int64_t> tile_off(S + 1, 0);
-  for (int s = 0; s < S; ++s)
-    tile_off[s + 1] = tile_off[s] + (p->query_off[s + 1] - p->query_off[s] + per_tile - 1) / per_tile;
+  for (int s = 0; s < S; ++s) {
+    const int64_t q0 = p->query_off[s], q1 = p->query_off[s + 1];
+    tile_off[s + 1] = tile_off[s] + (q1 > q0 ? (q1 - 1) / per_tile - q0 / per_tile + 1 : 0);
+  }
   p->total_tiles = tile_off[S];
 
   p->lds = lds_tab_a + lds_bins_a + lds_tab_b + lds_bins_b;
@@ -446,26 +490,38 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   const int resident = blocks_per_cu(p->kernel, p->block, p->lds) * di.num_cus;
   p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident);
   if (option(SS_OPT_PLAN_TILES) > 0) p->tiles_per_wg = (int)option(SS_OPT_PLAN_TILES);
-  const int64_t grid = std::max<int64_t>(1, (p->total_tiles + p->tiles_per_wg - 1) / p->tiles_per_wg);
+  const int64_t num_wg =
+      std::max<int64_t>(1, (p->total_tiles + p->tiles_per_wg - 1) / p->tiles_per_wg);
+  const int xcd = (int)option(SS_OPT_PLAN_XCD);
+  const int groups = xcd == 1 ? 1 : kXcds;
+  const int64_t grid = (num_wg + groups - 1) / groups * groups;
   if (grid > INT32_MAX) return fail(SS_ERR_INVALID_ARG, "too many tiles for one launch");
   p->grid = (int)grid;
-  std::vector<int32_t> wg_seg(p->grid, 0);
+  p->num_wg = (int)num_wg;
+  p->xcd_groups = groups;
+  std::vector<WgStart> wg_start(p->num_wg);
   {
     int s = 0;
-    for (int w = 0; w < p->grid; ++w) {
+    for (int w = 0; w < p->num_wg; ++w) {
       const int64_t j = (int64_t)w * p->tiles_per_wg;
       while (s < S - 1 && j >= tile_off[s + 1]) ++s;
-      wg_seg[w] = s;
+      WgStart& st = wg_start[w];
+      st.seg = s;
+      st.seg_q0 = p->query_off[s];
+      st.seg_q1 = p->query_off[s + 1];
+      st.first = (int32_t)(j - tile_off[s]);
+      st.seg_tiles = (int32_t)(tile_off[s + 1] - tile_off[s]);
+      st.pad_ = 0;
     }
   }
   SS_TRY_HIP(hipMalloc(&p->d_tile_off, sizeof(int64_t) * (S + 1)));
   SS_TRY_HIP(hipMalloc(&p->d_query_off, sizeof(int64_t) * (S + 1)));
-  SS_TRY_HIP(hipMalloc(&p->d_wg_seg, sizeof(int32_t) * p->grid));
+  SS_TRY_HIP(hipMalloc(&p->d_wg_start, sizeof(WgStart) * p->num_wg));
   SS_TRY_HIP(hipMemcpy(p->d_tile_off, tile_off.data(), sizeof(int64_t) * (S + 1),
                        hipMemcpyHostToDevice));
   SS_TRY_HIP(hipMemcpy(p->d_query_off, p->query_off.data(), sizeof(int64_t) * (S + 1),
                        hipMemcpyHostToDevice));
-  SS_TRY_HIP(hipMemcpy(p->d_wg_seg, wg_seg.data(), sizeof(int32_t) * p->grid,
+  SS_TRY_HIP(hipMemcpy(p->d_wg_start, wg_start.data(), sizeof(WgStart) * p->num_wg,
                        hipMemcpyHostToDevice));
 
   MultiArgs& a = p->args;
@@ -475,11 +531,13 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   a.bins = p->d_bins;
   a.tile_off = p->d_tile_off;
   a.query_off = p->d_query_off;
-  a.wg_seg = p->d_wg_seg;
+  a.wg_start = p->d_wg_start;
   a.params = p->d_pool;
   a.fallbacks = p->d_fallbacks;
   a.total_tiles = p->total_tiles;
   a.tiles_per_wg = p->tiles_per_wg;
+  a.num_wg = p->num_wg;
+  a.xcd_groups = p->xcd_groups;
   a.pair_base = p->paired ? p->M : 0;
   a.lds_bins_a = (int)lds_tab_a;
   a.lds_tab_b = (int)(lds_tab_a + lds_bins_a);

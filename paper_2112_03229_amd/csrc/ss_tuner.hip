@@ -174,13 +174,13 @@ TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bi
 
 int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident) {
   (void)model;
-  // Measured on MI355X (512 tables of 20..2000 entries, 7.4e8 targets):
-  // 1 tile per workgroup 4.1 TB/s, 2 tiles 4.6, 4 tiles 4.4, 8 tiles 4.0 --
-  // many short workgroups balance better than fewer long ones, and two
-  // tiles amortise the table copy.  Keep two unless that leaves fewer
-  // than ~6 waves of workgroups.
-  int64_t k = 2;
-  while (k > 1 && total_tiles / k < 6LL * std::max(resident, 1)) k /= 2;
+  // Measured on MI355X with two tiles prefetched ahead and tiles aligned
+  // to absolute positions (512 tables of 20..2000 entries, 7.4e8 targets):
+  // 2 tiles per workgroup 5.16 TB/s, 3 tiles 5.67, 4 tiles 5.72, 6 tiles
+  // 5.68 (4096 materials, 1e9 pairs: 4.52, 4.75, 4.87, 4.91).  Keep four
+  // unless that leaves fewer than ~6 waves of workgroups.
+  int64_t k = 4;
+  while (k > 1 && total_tiles / k < 6LL * std::max(resident, 1)) --k;
   return (int)k;
 }
 
