@@ -42,28 +42,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_digest() -> str:
+# Sources each profiled kernel is compiled from: a counter record in
+# profiles/traffic.json is used only while these files are unchanged.
+KERNEL_SOURCES = {
+    "single": ("csrc/ss_single.hip", "csrc/ss_device.h", "csrc/ss_host.h"),
+    "plan": ("csrc/ss_plan.hip", "csrc/ss_device.h", "csrc/ss_host.h", "csrc/ss_mlp.h",
+             "csrc/ss_learned.h", "csrc/ss_tuner.h"),
+    "learned": ("csrc/ss_learned.hip", "csrc/ss_device.h", "csrc/ss_host.h", "csrc/ss_mlp.h",
+                "csrc/ss_learned.h"),
+}
+
+
+def kernel_source_digest(group: str) -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(HERE, "paper_2112_03229_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    pkg = os.path.join(HERE, "paper_2112_03229_amd")
+    for name in KERNEL_SOURCES[group]:
+        with open(os.path.join(pkg, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(key: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the current sources of that kernel; else None."""
     path = os.path.join(HERE, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    ent = rec.get(f"{kernel}|{workload}")
-    if not ent or ent.get("source_digest") != kernel_source_digest():
+    ent = rec.get(key)
+    if not ent or ent.get("source_digest") != kernel_source_digest(ent.get("sources", "single")):
         return None
     return ent.get("bytes_per_launch")
 
@@ -167,7 +177,8 @@ def measure_batched(torch, binding, inputs, dev) -> dict:
            **roof(m, ms),
            "exphash_tables": int((info["algos"] == binding.ALGO_EXPHASH).sum()),
            "tiles": info["tiles"], "tiles_per_wg": info["tiles_per_wg"],
-           "grid": info["grid"], "lds_bytes": info["lds_bytes"]}
+           "grid": info["grid"], "lds_bytes": info["lds_bytes"],
+           "traffic": measured_traffic("multi_kernel<batched>|batched-512")}
     # plain search: the same tables one single-table launch at a time
     tabs = [torch.from_numpy(batch.table(t)).to(dev) for t in range(batch.num_tables)]
     qo = batch.query_off
@@ -227,7 +238,19 @@ def measure_paired(torch, binding, inputs, dev) -> dict:
            "exphash_tables": int((info["algos"] == binding.ALGO_EXPHASH).sum()),
            "tables": info["tables"], "tiles": info["tiles"],
            "tiles_per_wg": info["tiles_per_wg"], "grid": info["grid"],
-           "lds_bytes": info["lds_bytes"]}
+           "lds_bytes": info["lds_bytes"],
+           "traffic": measured_traffic("multi_kernel<paired>|paired-4096")}
+    plan.close()
+    # the other launch form: both axes of a tile of pairs in one workgroup
+    binding.set_option(binding.OPT_PAIR_JOINT, 1)
+    try:
+        joint = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(dev), pairs.rho.table_off,
+                                 torch.from_numpy(pairs.temp.tables).to(dev),
+                                 pairs.temp.table_off, pairs.rho.query_off)
+    finally:
+        binding.set_option(binding.OPT_PAIR_JOINT, 0)
+    res["joint_form"] = roof(2 * m, time_call(torch, lambda: joint.search(r, t, o_r, o_t), reps=3))
+    joint.close()
     res["learned"] = measure_learned_plan(
         torch, binding,
         lambda: binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(dev), pairs.rho.table_off,
@@ -236,6 +259,81 @@ def measure_paired(torch, binding, inputs, dev) -> dict:
         lambda pl: pl.search(r, t, o_r, o_t), 2 * m)
     del r, t, o_r, o_t
     return res
+
+
+SMALL_M = 10**6
+SMALL_BUFFERS = 48
+SMALL_CALLS = 192
+
+
+def measure_small(torch, binding, inputs, dev) -> dict:
+    """A 64-entry table with 1e6 targets per call.  (i) Latency of one call:
+    host clock from the call to the end of the synchronisation, and the
+    kernel alone by HIP events.  (ii) Steady throughput of back-to-back calls
+    replayed from one captured HIP graph that rotates over 48 distinct target
+    buffers (48 x 12 MB = 576 MB, more than twice the 256 MB last-level
+    cache), so that no call finds its targets left in cache by the previous
+    one.  Every call is the same single-table call; the graph's outputs are
+    compared with eager calls on the same buffers."""
+    table = inputs.single64_table()
+    t = torch.from_numpy(table).to(dev)
+    host = torch.empty(SMALL_BUFFERS * SMALL_M, dtype=torch.float64).pin_memory()
+    inputs.table_targets(table, host.numel(), seed=64, out=host.numpy())
+    x = host.to(dev).view(SMALL_BUFFERS, SMALL_M)
+    del host
+    out = torch.empty(SMALL_BUFFERS, SMALL_M, dtype=torch.int32, device=dev)
+    ref = torch.empty_like(out)
+    for b in range(SMALL_BUFFERS):
+        binding.search_sorted_batch(t, x[b], ref[b])
+    torch.cuda.synchronize()
+
+    lat = []
+    for k in range(200):
+        b = k % SMALL_BUFFERS
+        t0 = time.perf_counter()
+        binding.search_sorted_batch(t, x[b], out[b])
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(SMALL_BUFFERS)]
+    for b in range(SMALL_BUFFERS):
+        ev[b][0].record()
+        binding.search_sorted_batch(t, x[b], out[b])
+        ev[b][1].record()
+        torch.cuda.synchronize()
+    kern_us = [e0.elapsed_time(e1) * 1e3 for e0, e1 in ev]
+
+    # eager back-to-back calls, for comparison with the graph
+    ms_eager = time_call(torch, lambda: [binding.search_sorted_batch(t, x[b], out[b])
+                                         for b in range(SMALL_BUFFERS)], reps=4) / SMALL_BUFFERS
+
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        binding.search_sorted_batch(t, x[0], out[0])
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, capture_error_mode="relaxed"):
+        for k in range(SMALL_CALLS):
+            b = k % SMALL_BUFFERS
+            binding.search_sorted_batch(t, x[b], out[b])
+    replays_ok = True
+    for _ in range(2):
+        out.fill_(-7)
+        g.replay()
+        torch.cuda.synchronize()
+        replays_ok &= bool(torch.equal(out, ref))
+    ms_graph = time_call(torch, g.replay, reps=10) / SMALL_CALLS
+    del g
+    return {"workload": "one 64-entry table (jittered log grid on [1e-6,1e4]), 1e6 targets "
+                        "per call, 48 rotating target buffers",
+            "latency_us": {"call_to_sync_median": round(float(np.median(lat)) * 1e6, 1),
+                           "call_to_sync_min": round(float(np.min(lat)) * 1e6, 1),
+                           "kernel_median": round(float(np.median(kern_us)), 2)},
+            "eager_back_to_back": roof(SMALL_M, ms_eager),
+            "graph_back_to_back": {**roof(SMALL_M, ms_graph), "calls": SMALL_CALLS,
+                                   "buffers": SMALL_BUFFERS, "matches_eager": replays_ok}}
 
 
 # FP32 work of one learned-index query: the MLP's 32 + 1024 + 32 multiply-adds
@@ -354,8 +452,7 @@ def main():
 
     kernel = "single_kernel<exphash>"
     achieved = M * BYTES_PER_QUERY / (avg_launch_ms * 1e-3) / 1e9
-    workload = "single-1e8"
-    traffic = measured_traffic(kernel, workload)
+    traffic = measured_traffic("single_kernel<exphash>|single-1e8")
     result = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -415,6 +512,9 @@ def main():
     if not args.no_systems:
         # free the single-table workload before the larger ones
         del d_x, d_out
+        torch.cuda.empty_cache()
+        log("bench: small table, graph-replayed calls")
+        result["small"] = measure_small(torch, binding, inputs, dev)
         torch.cuda.empty_cache()
         log("bench: batched plan")
         result["batched"] = measure_batched(torch, binding, inputs, dev)

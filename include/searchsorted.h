@@ -89,8 +89,9 @@ typedef enum {
                                     table so the bin count fits the cap */
     SS_OPT_BUCKET_CAP = 3,       /* max bins of the exponent hash in the
                                     single-table path; 0 (default) = auto */
-    SS_OPT_BLOCK_SIZE = 4,       /* threads per workgroup: 256, 512 or 1024;
-                                    0 (default) = auto */
+    SS_OPT_BLOCK_SIZE = 4,       /* threads per workgroup of single-table
+                                    launches and of plans built afterwards:
+                                    256, 512 or 1024; 0 (default) = auto */
     SS_OPT_GRID_BLOCKS = 5,      /* workgroups per launch; 0 (default) = fill
                                     the device (persistent grid) */
     SS_OPT_CHECK_POINTERS = 6,   /* 1 (default): verify that buffers are
@@ -106,9 +107,16 @@ typedef enum {
                                     exponent hash / bisection per the tuner */
     SS_OPT_LEARNED_STEPS = 10,   /* Adam steps of plan models; 0 (default)
                                     = 500 */
-    SS_OPT_PLAN_XCD = 11         /* workgroup-to-XCD mapping of plans built
+    SS_OPT_PLAN_XCD = 11,        /* workgroup-to-XCD mapping of plans built
                                     afterwards: 0 (default) = contiguous
                                     tile ranges per XCD, 1 = dispatch order */
+    SS_OPT_PAIR_JOINT = 12       /* paired plans built afterwards: 0
+                                    (default) = the density and temperature
+                                    searches run as 2M independent segments
+                                    of one launch, one table staged per
+                                    workgroup; 1 = each workgroup searches
+                                    both axes of its pairs with both of the
+                                    material's tables staged */
 } ss_option;
 
 /* Human-readable message for the calling thread's most recent error

@@ -53,6 +53,14 @@ struct WgStart {
   int32_t pad_;
 };
 
+// Launch forms of the plan kernel.
+enum PlanMode {
+  kBatched = 0,    // one target array, one table per segment
+  kPairJoint = 1,  // paired: a workgroup searches a tile of both axes (both tables staged)
+  kPairSplit = 2,  // paired: the density searches and the temperature searches are
+                   // 2M segments of one launch, one table staged per workgroup
+};
+
 struct MultiArgs {
   const double* tables_a;
   const double* tables_b;
@@ -72,6 +80,9 @@ struct MultiArgs {
   int num_wg;                // workgroups with work (the grid may be padded)
   int xcd_groups;            // > 1: workgroup ids remapped per XCD (see below)
   int pair_base;             // index of the first temperature descriptor (paired)
+  int64_t split;             // kPairSplit: temperature segments' targets start here in
+                             // the segment offsets (targets of segment s >= pair_base
+                             // are xb[query_off[s] - split ...])
   int lds_bins_a, lds_tab_b, lds_bins_b;  // byte offsets in LDS
 };
 
@@ -130,15 +141,21 @@ __device__ __forceinline__ void search_staged(const Staged& st, const double* sa
 
 // Offsets of one segment (table or material), kept in registers while a
 // workgroup walks its tiles; reloaded only when the walk enters the next
-// segment.
+// segment.  Target positions are relative to the segment's own target
+// array (part 0: xa/oa, part 1: xb/ob in the split paired form).
 struct Segment {
   int seg;
+  int part;
   int64_t t0, t1;  // its tiles [t0, t1)
   int64_t q0, q1;  // its targets [q0, q1)
 };
 
+template <int MODE>
 __device__ __forceinline__ Segment load_segment(const MultiArgs& a, int seg) {
-  return {seg, a.tile_off[seg], a.tile_off[seg + 1], a.query_off[seg], a.query_off[seg + 1]};
+  const int part = MODE == kPairSplit && seg >= a.pair_base;
+  const int64_t base = part ? a.split : 0;
+  return {seg, part, a.tile_off[seg], a.tile_off[seg + 1], a.query_off[seg] - base,
+          a.query_off[seg + 1] - base};
 }
 
 struct TileRange {
@@ -159,8 +176,10 @@ __device__ __forceinline__ void load_range(const double* __restrict__ x, TileRan
   load_tile<Q>(x, r.q1, r.q0 + threadIdx.x, nt, r.q0 + (int64_t)nt * Q <= r.q1, v);
 }
 
-template <int PAIRED, int Q, int LEARN>
+template <int MODE, int Q, int LEARN>
 __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
+  constexpr bool PAIRED = MODE == kPairJoint;
+  constexpr bool SPLIT = MODE == kPairSplit;
   extern __shared__ __align__(16) unsigned char lds[];
   double* sa = reinterpret_cast<double*>(lds);
   uint16_t* Ca = reinterpret_cast<uint16_t*>(lds + a.lds_bins_a);
@@ -185,21 +204,22 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   const WgStart ws = a.wg_start[wid];
   // Tiles j, j+1 and j+2 are in flight at once: the targets of the two
   // tiles after the one being searched are already being loaded.
-  Segment sg{ws.seg, j0 - ws.first, j0 - ws.first + ws.seg_tiles, ws.seg_q0, ws.seg_q1};
+  Segment sg{ws.seg, SPLIT && ws.seg >= a.pair_base, j0 - ws.first,
+             j0 - ws.first + ws.seg_tiles, ws.seg_q0, ws.seg_q1};
   Segment sg1 = sg, sg2 = sg;
   TileRange cur = tile_range(sg, j0, per_tile), nx1{0, 0}, nx2{0, 0};
   double ca[Q], cb[Q], ca1[Q], cb1[Q];
-  load_range<Q>(a.xa, cur, ca);
+  load_range<Q>(SPLIT && sg.part ? a.xb : a.xa, cur, ca);
   if constexpr (PAIRED) load_range<Q>(a.xb, cur, cb);
   if (j0 + 1 < j1) {
-    while (j0 + 1 >= sg1.t1) sg1 = load_segment(a, sg1.seg + 1);
+    while (j0 + 1 >= sg1.t1) sg1 = load_segment<MODE>(a, sg1.seg + 1);
     nx1 = tile_range(sg1, j0 + 1, per_tile);
-    load_range<Q>(a.xa, nx1, ca1);
+    load_range<Q>(SPLIT && sg1.part ? a.xb : a.xa, nx1, ca1);
     if constexpr (PAIRED) load_range<Q>(a.xb, nx1, cb1);
   }
 
   Staged sta, stb{};
-  sta = stage_desc(a.desc[sg.seg], a.tables_a, a.bins, sa, Ca);
+  sta = stage_desc(a.desc[sg.seg], SPLIT && sg.part ? a.tables_b : a.tables_a, a.bins, sa, Ca);
   if constexpr (PAIRED) stb = stage_desc(a.desc[a.pair_base + sg.seg], a.tables_b, a.bins, sb, Cb);
   __syncthreads();
   int fallbacks = 0;
@@ -207,15 +227,15 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     double ca2[Q], cb2[Q];
     if (j + 2 < j1) {
       sg2 = sg1;
-      while (j + 2 >= sg2.t1) sg2 = load_segment(a, sg2.seg + 1);
+      while (j + 2 >= sg2.t1) sg2 = load_segment<MODE>(a, sg2.seg + 1);
       nx2 = tile_range(sg2, j + 2, per_tile);
-      load_range<Q>(a.xa, nx2, ca2);
+      load_range<Q>(SPLIT && sg2.part ? a.xb : a.xa, nx2, ca2);
       if constexpr (PAIRED) load_range<Q>(a.xb, nx2, cb2);
     }
     const bool full = cur.q0 + per_tile == cur.q1;
     int r[Q], fell[Q];
     search_staged<Q, LEARN>(sta, sa, Ca, a.params, ca, r, fell);
-    store_tile<Q>(a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
+    store_tile<Q>(SPLIT && sg.part ? a.ob : a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
     if constexpr (LEARN) {
 #pragma unroll
       for (int q = 0; q < Q; ++q)
@@ -233,7 +253,8 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     if (j + 1 >= j1) break;
     if (sg1.seg != sg.seg) {
       __syncthreads();  // every lane is done with the old table
-      sta = stage_desc(a.desc[sg1.seg], a.tables_a, a.bins, sa, Ca);
+      sta = stage_desc(a.desc[sg1.seg], SPLIT && sg1.part ? a.tables_b : a.tables_a, a.bins,
+                       sa, Ca);
       if constexpr (PAIRED)
         stb = stage_desc(a.desc[a.pair_base + sg1.seg], a.tables_b, a.bins, sb, Cb);
       __syncthreads();
@@ -288,9 +309,12 @@ __global__ __launch_bounds__(256) void plan_bins_kernel(const double* __restrict
 
 struct ss_plan {
   int paired = 0;
+  int mode = 0;                  // ss::PlanMode
+  int64_t split = 0;             // kPairSplit: offset of the temperature segments' targets
   int32_t T = 0;                 // descriptors (batched: tables; paired: 2 * materials)
   int32_t M = 0;                 // materials (paired)
-  int32_t S = 0;                 // segments: tables (batched) or materials (paired)
+  int32_t S = 0;                 // segments: tables (batched), materials (joint paired) or
+                                 // 2 * materials (split paired)
   int64_t total_queries = 0;
   int device = -1;
   std::vector<int64_t> query_off;
@@ -465,24 +489,36 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   }
 
   p->block = option(SS_OPT_BLOCK_SIZE) > 0 ? (int)option(SS_OPT_BLOCK_SIZE) : kPlanBlock;
-  p->q = p->learned_tables > 0 ? kLearnedPlanQ : (p->paired ? kPairQ : kPlanQ);
+  p->q = p->learned_tables > 0 ? kLearnedPlanQ : (p->mode == kPairJoint ? kPairQ : kPlanQ);
   const int64_t per_tile = (int64_t)p->block * p->q;
-  // tiles of every segment, numbered back to back
+  // tiles of every segment, numbered back to back; a segment's positions are
+  // taken relative to the start of its own target array
   const int S = p->S;
+  auto seg_base = [&](int s) -> int64_t {
+    return p->mode == kPairSplit && s >= p->M ? p->split : 0;
+  };
   std::vector<int64_t> tile_off(S + 1, 0);
   for (int s = 0; s < S; ++s) {
-    const int64_t q0 = p->query_off[s], q1 = p->query_off[s + 1];
+    const int64_t q0 = p->query_off[s] - seg_base(s), q1 = p->query_off[s + 1] - seg_base(s);
     tile_off[s + 1] = tile_off[s] + (q1 > q0 ? (q1 - 1) / per_tile - q0 / per_tile + 1 : 0);
   }
   p->total_tiles = tile_off[S];
 
   p->lds = lds_tab_a + lds_bins_a + lds_tab_b + lds_bins_b;
-  if (p->learned_tables > 0)
-    p->kernel = p->paired ? reinterpret_cast<const void*>(&multi_kernel<1, kLearnedPlanQ, 1>)
-                          : reinterpret_cast<const void*>(&multi_kernel<0, kLearnedPlanQ, 1>);
-  else
-    p->kernel = p->paired ? reinterpret_cast<const void*>(&multi_kernel<1, kPairQ, 0>)
-                          : reinterpret_cast<const void*>(&multi_kernel<0, kPlanQ, 0>);
+  const bool learned = p->learned_tables > 0;
+  switch (p->mode) {
+    case kPairJoint:
+      p->kernel = learned ? reinterpret_cast<const void*>(&multi_kernel<kPairJoint, kLearnedPlanQ, 1>)
+                          : reinterpret_cast<const void*>(&multi_kernel<kPairJoint, kPairQ, 0>);
+      break;
+    case kPairSplit:
+      p->kernel = learned ? reinterpret_cast<const void*>(&multi_kernel<kPairSplit, kLearnedPlanQ, 1>)
+                          : reinterpret_cast<const void*>(&multi_kernel<kPairSplit, kPlanQ, 0>);
+      break;
+    default:
+      p->kernel = learned ? reinterpret_cast<const void*>(&multi_kernel<kBatched, kLearnedPlanQ, 1>)
+                          : reinterpret_cast<const void*>(&multi_kernel<kBatched, kPlanQ, 0>);
+  }
   DeviceInfo di;
   int rc = device_info(&di);
   if (rc != SS_OK) return rc;
@@ -507,8 +543,8 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
       while (s < S - 1 && j >= tile_off[s + 1]) ++s;
       WgStart& st = wg_start[w];
       st.seg = s;
-      st.seg_q0 = p->query_off[s];
-      st.seg_q1 = p->query_off[s + 1];
+      st.seg_q0 = p->query_off[s] - seg_base(s);
+      st.seg_q1 = p->query_off[s + 1] - seg_base(s);
       st.first = (int32_t)(j - tile_off[s]);
       st.seg_tiles = (int32_t)(tile_off[s + 1] - tile_off[s]);
       st.pad_ = 0;
@@ -539,6 +575,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   a.num_wg = p->num_wg;
   a.xcd_groups = p->xcd_groups;
   a.pair_base = p->paired ? p->M : 0;
+  a.split = p->split;
   a.lds_bins_a = (int)lds_tab_a;
   a.lds_tab_b = (int)(lds_tab_a + lds_bins_a);
   a.lds_bins_b = (int)(lds_tab_a + lds_bins_a + lds_tab_b);
@@ -690,11 +727,21 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
   ss_plan* p = new (std::nothrow) ss_plan();
   if (!p) return fail(SS_ERR_OOM, "plan");
   p->paired = 1;
+  p->mode = option(SS_OPT_PAIR_JOINT) ? kPairJoint : kPairSplit;
   p->M = M;
   p->T = 2 * M;
-  p->S = M;
-  p->query_off.assign(pair_off, pair_off + M + 1);
   p->total_queries = pair_off[M];
+  if (p->mode == kPairJoint) {
+    p->S = M;
+    p->query_off.assign(pair_off, pair_off + M + 1);
+  } else {
+    // segments 0..M-1: density axis; M..2M-1: temperature axis, whose
+    // offsets continue after the last pair
+    p->S = 2 * M;
+    p->split = pair_off[M];
+    p->query_off.assign(pair_off, pair_off + M + 1);
+    for (int j = 1; j <= M; ++j) p->query_off.push_back(p->split + pair_off[j]);
+  }
   const TunerModel& model = tuner_model();
   p->desc.resize(2 * M);
   p->tuned.resize(2 * M);
@@ -703,11 +750,19 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
     tab_a = std::max(tab_a, align16((size_t)(rho_off[j + 1] - rho_off[j] + SS_PAD) * 8));
     tab_b = std::max(tab_b, align16((size_t)(t_off[j + 1] - t_off[j] + SS_PAD) * 8));
   }
-  if (tab_a + tab_b > kPlanLdsBudget) return fail_delete(p, "tables too large for LDS");
-  // the bin budget is split in proportion to the two axes' largest tables
-  const size_t bins_total = kPlanLdsBudget - tab_a - tab_b;
-  const size_t budget_a = bins_total * tab_a / (tab_a + tab_b);
-  const size_t budget_b = bins_total - budget_a;
+  size_t budget_a, budget_b;
+  if (p->mode == kPairJoint) {
+    if (tab_a + tab_b > kPlanLdsBudget) return fail_delete(p, "tables too large for LDS");
+    // the bin budget is split in proportion to the two axes' largest tables
+    const size_t bins_total = kPlanLdsBudget - tab_a - tab_b;
+    budget_a = bins_total * tab_a / (tab_a + tab_b);
+    budget_b = bins_total - budget_a;
+  } else {
+    // one table at a time: either axis may use what the largest table leaves
+    tab_a = tab_b = std::max(tab_a, tab_b);
+    if (tab_a > kPlanLdsBudget) return fail_delete(p, "tables too large for LDS");
+    budget_a = budget_b = kPlanLdsBudget - tab_a;
+  }
   int64_t pool = 0;
   for (int j = 0; j < M; ++j) {
     const int n = (int)(rho_off[j + 1] - rho_off[j]);
@@ -734,7 +789,10 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
         bins_b = std::max(bins_b, align16((size_t)(p->desc[M + j].nb + 1) * 2));
     }
   }
-  rc = finish_plan(p, rho_tables, t_tables, pool, tab_a, bins_a, tab_b, bins_b);
+  if (p->mode == kPairJoint)
+    rc = finish_plan(p, rho_tables, t_tables, pool, tab_a, bins_a, tab_b, bins_b);
+  else
+    rc = finish_plan(p, rho_tables, t_tables, pool, tab_a, std::max(bins_a, bins_b), 0, 0);
   if (rc != SS_OK) {
     delete p;
     return rc;

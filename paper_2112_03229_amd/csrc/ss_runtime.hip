@@ -25,6 +25,7 @@ std::atomic<int64_t> g_plan_tiles{0};
 std::atomic<int64_t> g_plan_learned{0};
 std::atomic<int64_t> g_learned_steps{0};
 std::atomic<int64_t> g_plan_xcd{0};
+std::atomic<int64_t> g_pair_joint{0};
 
 std::mutex g_dev_mu;
 std::map<int, DeviceInfo> g_dev_cache;
@@ -61,6 +62,7 @@ int64_t option(int opt) {
     case SS_OPT_PLAN_LEARNED: return g_plan_learned.load();
     case SS_OPT_LEARNED_STEPS: return g_learned_steps.load();
     case SS_OPT_PLAN_XCD: return g_plan_xcd.load();
+    case SS_OPT_PAIR_JOINT: return g_pair_joint.load();
     default: return 0;
   }
 }
@@ -210,6 +212,10 @@ int ss_set_option(int opt, int64_t v) {
       if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PLAN_XCD: 0 or 1");
       ss::g_plan_xcd = v;
       return SS_OK;
+    case SS_OPT_PAIR_JOINT:
+      if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PAIR_JOINT: 0 or 1");
+      ss::g_pair_joint = v;
+      return SS_OK;
     default:
       return ss::fail(SS_ERR_INVALID_ARG, "unknown option");
   }
@@ -229,6 +235,7 @@ int ss_get_option(int opt, int64_t* value_out) {
     case SS_OPT_PLAN_LEARNED:
     case SS_OPT_LEARNED_STEPS:
     case SS_OPT_PLAN_XCD:
+    case SS_OPT_PAIR_JOINT:
       *value_out = ss::option(opt);
       return SS_OK;
     default:

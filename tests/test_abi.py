@@ -40,8 +40,11 @@ def test_version_and_options(L):
     b.set_option(b.OPT_BUCKET_BITS, 5)
     assert b.get_option(b.OPT_BUCKET_BITS) == 5
     b.set_option(b.OPT_BUCKET_BITS, -1)
+    b.set_option(b.OPT_PAIR_JOINT, 1)
+    assert b.get_option(b.OPT_PAIR_JOINT) == 1
+    b.set_option(b.OPT_PAIR_JOINT, 0)
     for opt, bad in ((b.OPT_FORCE_ALGO, 9), (b.OPT_BUCKET_BITS, 21), (b.OPT_BLOCK_SIZE, 100),
-                     (b.OPT_CHECK_POINTERS, 2), (999, 0)):
+                     (b.OPT_CHECK_POINTERS, 2), (b.OPT_PAIR_JOINT, 2), (999, 0)):
         with pytest.raises(b.SearchSortedError) as e:
             b.set_option(opt, bad)
         assert e.value.code == -1

@@ -112,19 +112,50 @@ def test_batched_rejects_bad_arguments(binding, gpu, inputs_mod):
         plan.search(torch.zeros(11, dtype=torch.float64, device=gpu))
 
 
-def test_paired_composition(binding, gpu, oracle_mod, inputs_mod):
-    pairs = inputs_mod.paired_layout(seed=9, materials=96, total_pairs=2 * 10**6)
+@pytest.fixture(params=[0, 1], ids=["split", "joint"])
+def pair_form(request, binding):
+    """Both launch forms of paired plans: the density and temperature
+    searches as 2M independent segments (default), or one workgroup per tile
+    of pairs with both tables staged."""
+    binding.set_option(binding.OPT_PAIR_JOINT, request.param)
+    yield request.param
+    binding.set_option(binding.OPT_PAIR_JOINT, 0)
+
+
+def ragged_pairs(inputs_mod, seed, materials, total_pairs):
+    """A paired layout whose pair counts include empty and one-pair
+    materials and whose total is not a multiple of any tile or line size."""
+    from paper_2112_03229_amd.inputs import Batch, Paired
+    pairs = inputs_mod.paired_layout(seed=seed, materials=materials, total_pairs=total_pairs)
+    counts = np.diff(pairs.rho.query_off)
+    counts[[0, 5, materials // 2]] = 0
+    counts[[1, 6, materials - 1]] = [1, 3, 4099]
+    poff = np.zeros(materials + 1, dtype=np.int64)
+    poff[1:] = np.cumsum(counts)
+    r, t = pairs.rho, pairs.temp
+    return Paired(Batch(r.tables, r.table_off, poff, r.lo, r.hi),
+                  Batch(t.tables, t.table_off, poff.copy(), t.lo, t.hi))
+
+
+@pytest.mark.parametrize("layout", ["regular", "ragged"])
+def test_paired_composition(binding, gpu, oracle_mod, inputs_mod, pair_form, layout):
+    if layout == "regular":
+        pairs = inputs_mod.paired_layout(seed=9, materials=96, total_pairs=2 * 10**6)
+    else:
+        pairs = ragged_pairs(inputs_mod, 19, 80, 10**6 + 13)
     rho, temp = inputs_mod.paired_targets(pairs, seed=9)
     rho[:4] = [np.nan, -1.0, np.inf, 0.0]
+    temp[-3:] = [np.nan, -np.inf, 5e-324]
     want_r = oracle_mod.search_lt_segments(pairs.rho.tables, pairs.rho.table_off, rho,
                                            pairs.rho.query_off)
     want_t = oracle_mod.search_lt_segments(pairs.temp.tables, pairs.temp.table_off, temp,
                                            pairs.temp.query_off)
-    say(f"case paired M={pairs.num_materials} pairs={pairs.num_pairs}")
+    say(f"case paired {layout} form={pair_form} M={pairs.num_materials} pairs={pairs.num_pairs}")
     plan = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(gpu), pairs.rho.table_off,
                             torch.from_numpy(pairs.temp.tables).to(gpu), pairs.temp.table_off,
                             pairs.rho.query_off)
-    out_r, out_t = plan.search(torch.from_numpy(rho).to(gpu), torch.from_numpy(temp).to(gpu))
+    dr, dt = torch.from_numpy(rho).to(gpu), torch.from_numpy(temp).to(gpu)
+    out_r, out_t = plan.search(dr, dt)
     torch.cuda.synchronize()
     assert np.array_equal(out_r.cpu().numpy(), want_r)
     assert np.array_equal(out_t.cpu().numpy(), want_t)
@@ -134,6 +165,16 @@ def test_paired_composition(binding, gpu, oracle_mod, inputs_mod):
     assert np.all((algos == binding.ALGO_EXPHASH) | (algos == binding.ALGO_BINARY))
     assert np.count_nonzero(algos == binding.ALGO_EXPHASH) > algos.size // 2
     assert np.all((info["bits"] >= 0) == (algos == binding.ALGO_EXPHASH))
+    # graph replay into the same outputs, then new output buffers
+    out_r.fill_(-7)
+    out_t.fill_(-7)
+    plan.search(dr, dt, out_r, out_t)
+    assert np.array_equal(out_r.cpu().numpy(), want_r)
+    assert np.array_equal(out_t.cpu().numpy(), want_t)
+    o2r, o2t = plan.search(dr, dt)
+    assert np.array_equal(o2r.cpu().numpy(), want_r)
+    assert np.array_equal(o2t.cpu().numpy(), want_t)
+    plan.close()
 
 
 def test_tuner_calibration_roundtrip(binding, gpu, oracle_mod, inputs_mod, tmp_path):
@@ -180,12 +221,12 @@ def test_full_size_batched(binding, gpu, oracle_mod, inputs_mod):
         assert np.array_equal(got[p], oracle_mod.search_lt_at(tab, x, p)), t
 
 
-def test_full_size_paired(binding, gpu, oracle_mod, inputs_mod):
+def test_full_size_paired(binding, gpu, oracle_mod, inputs_mod, pair_form):
     """4096 materials (density 50..4000 entries, temperature 20..1000), 1e9
     pairs, both searches in one launch."""
     pairs = inputs_mod.paired_layout()
     m = pairs.num_pairs
-    say(f"case full paired M=4096 pairs={m}")
+    say(f"case full paired form={pair_form} M=4096 pairs={m}")
     hr = torch.empty(m, dtype=torch.float64).pin_memory()
     ht = torch.empty(m, dtype=torch.float64).pin_memory()
     rho, temp = inputs_mod.paired_targets(pairs, out_rho=hr.numpy(), out_t=ht.numpy())
@@ -240,8 +281,8 @@ def test_learned_batched_plan_is_exact(binding, gpu, oracle_mod, inputs_mod):
     assert np.array_equal(out.cpu().numpy(), want)
 
 
-def test_learned_paired_plan_is_exact(binding, gpu, oracle_mod, inputs_mod):
-    pairs = inputs_mod.paired_layout(seed=13, materials=48, total_pairs=10**6)
+def test_learned_paired_plan_is_exact(binding, gpu, oracle_mod, inputs_mod, pair_form):
+    pairs = ragged_pairs(inputs_mod, 13, 48, 10**6 + 5)
     rho, temp = inputs_mod.paired_targets(pairs, seed=13)
     rho[:3] = [np.nan, 0.0, np.inf]
     want_r = oracle_mod.search_lt_segments(pairs.rho.tables, pairs.rho.table_off, rho,
@@ -261,4 +302,4 @@ def test_learned_paired_plan_is_exact(binding, gpu, oracle_mod, inputs_mod):
     assert np.array_equal(out_r.cpu().numpy(), want_r)
     assert np.array_equal(out_t.cpu().numpy(), want_t)
     assert np.all(plan.info()["algos"] == binding.ALGO_LEARNED)
-    say(f"paired learned fallbacks {plan.fallbacks()} of {2 * pairs.num_pairs}")
+    say(f"paired learned form={pair_form} fallbacks {plan.fallbacks()} of {2 * pairs.num_pairs}")
