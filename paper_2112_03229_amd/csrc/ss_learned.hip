@@ -9,8 +9,8 @@
 //                  LDS, phase B sums every parameter's gradient over the
 //                  batch in a fixed order (deterministic).
 //   bound_kernel   E = 1 + max |g(x) - idx(x)| over the probes.
-//   learned_kernel the search: table in LDS, parameters read with scalar
-//                  loads (uniform across the wavefront), Q targets per lane.
+//   learned_kernel the search: table and model in LDS, the model's middle
+//                  layer on the matrix cores, Q targets per lane.
 //   predict_kernel the model's fractional position for inspection.
 #include <algorithm>
 #include <cmath>
@@ -258,31 +258,40 @@ __device__ __forceinline__ int exact_index(const double* __restrict__ a, int n, 
   return base + (a[base] < x ? 1 : 0) - 1;
 }
 
-// Largest |g(x) - idx(x)| over the three probes of entry i.
-__device__ __forceinline__ int probe_error(const double* __restrict__ a, int n,
-                                           const float* __restrict__ P, float u0, float inv,
-                                           int i) {
+// Largest |g(x) - idx(x)| over the three probes of entry i, with the
+// search's own forward pass (so every lane of the wavefront calls it; lanes
+// without an entry pass valid = false and get 0).
+__device__ __forceinline__ int probe_error(const double* __restrict__ a, int n, const float* m,
+                                           float u0, float inv, int i, bool valid) {
+  const int e = valid ? i : 0;
   double probe[3];
-  probe[0] = a[i];
-  probe[1] = nextafter(a[i], __builtin_inf());
-  probe[2] = i + 1 < n ? sqrt(a[i]) * sqrt(a[i + 1]) : a[i];
+  probe[0] = a[e];
+  probe[1] = nextafter(a[e], __builtin_inf());
+  probe[2] = e + 1 < n ? sqrt(a[e]) * sqrt(a[e + 1]) : a[e];
   int worst = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    float z[1] = {model_input(probe[c], u0, inv)}, p[1];
-    mlp_eval<1>(P, z, p);
-    const int g = predicted_index(p[0], n);
+    const float p = mlp_eval_wave(m, model_input(probe[c], u0, inv));
+    const int g = predicted_index(p, n);
     worst = max(worst, abs(g - exact_index(a, n, probe[c])));
   }
-  return worst;
+  return valid ? worst : 0;
 }
 
-__global__ void bound_kernel(const double* __restrict__ a, int n, const float* __restrict__ P,
-                             float u0, float inv, int* worst) {
+__global__ __launch_bounds__(256) void bound_kernel(const double* __restrict__ a, int n,
+                                                    const float* __restrict__ P, float u0,
+                                                    float inv, int* worst) {
+  __shared__ __align__(16) float model[kModelFloats];
+  stage_model(model, P);
+  __syncthreads();
   int local = 0;
   const int stride = gridDim.x * blockDim.x;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    local = max(local, probe_error(a, n, P, u0, inv, i));
+  // the loop bound is uniform across the workgroup: every lane takes part
+  // in every forward pass
+  for (int base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    const int i = base + threadIdx.x;
+    local = max(local, probe_error(a, n, model, u0, inv, i, i < n));
+  }
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(worst, local);
 }
@@ -301,16 +310,21 @@ __global__ void norm_many_kernel(const double* tables_a, const double* tables_b,
   slots[i].inv = l1 > l0 ? 1.0f / (l1 - l0) : 1.0f;
 }
 
-__global__ void bound_many_kernel(const double* tables_a, const double* tables_b,
-                                  LearnedSlot* slots, const float* pool) {
+__global__ __launch_bounds__(256) void bound_many_kernel(const double* tables_a,
+                                                         const double* tables_b,
+                                                         LearnedSlot* slots, const float* pool) {
   __shared__ int worst;
+  __shared__ __align__(16) float model[kModelFloats];
   const LearnedSlot sl = slots[blockIdx.x];
   const double* a = (sl.which ? tables_b : tables_a) + sl.tab_off;
+  stage_model(model, pool + sl.p_off);
   if (threadIdx.x == 0) worst = 0;
   __syncthreads();
   int local = 0;
-  for (int i = threadIdx.x; i < sl.n; i += blockDim.x)
-    local = max(local, probe_error(a, sl.n, pool + sl.p_off, sl.u0, sl.inv, i));
+  for (int base = 0; base < sl.n; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    local = max(local, probe_error(a, sl.n, model, sl.u0, sl.inv, i, i < sl.n));
+  }
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(&worst, local);
   __syncthreads();
@@ -331,6 +345,7 @@ struct LearnedArgs {
   int n;
   int E;
   float u0, inv;
+  int model_off;  // byte offset of the model's LDS image (after the table)
 };
 
 template <int Q>
@@ -340,24 +355,20 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
   const int64_t ntiles = (a.m + per_tile - 1) / per_tile;
+  float* model = reinterpret_cast<float*>(lds + a.model_off);
   int64_t t = blockIdx.x;
   double cur[Q];
   if (t < ntiles) load_tile<Q>(a.x, a.m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= a.m, cur);
   stage_table(sa, a.table, a.n);
+  stage_model(model, a.P);
   __syncthreads();
   int fb = 0;
   for (; t < ntiles; t += gridDim.x) {
     const int64_t tn = t + gridDim.x;
     double nxt[Q];
     if (tn < ntiles) load_tile<Q>(a.x, a.m, tn * per_tile + threadIdx.x, nt, (tn + 1) * per_tile <= a.m, nxt);
-    // The parameters are read with scalar loads inside every tile: hidden
-    // from loop-invariant hoisting (1153 values do not fit in SGPRs, and
-    // parking them in VGPR lanes costs one extra VALU op per multiply-add).
-    const float* Pg = a.P;
-    asm volatile("" : "+s"(Pg));
-    ConstFloatPtr P = (ConstFloatPtr)Pg;
     int r[Q], fell[Q];
-    search_learned<Q>(sa, a.n, P, a.E, a.u0, a.inv, cur, r, fell);
+    search_learned<Q>(sa, a.n, model, a.E, a.u0, a.inv, cur, r, fell);
     const int64_t base = t * per_tile + threadIdx.x;
     const bool full = (t + 1) * per_tile <= a.m;
     // lanes past the end of the ragged last tile searched a stand-in
@@ -374,13 +385,18 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
 
 __global__ void clear_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
-__global__ void predict_kernel(const float* __restrict__ P, const double* __restrict__ x,
-                               int64_t m, float* __restrict__ out, float u0, float inv, int n) {
+__global__ __launch_bounds__(256) void predict_kernel(const float* __restrict__ P,
+                                                      const double* __restrict__ x, int64_t m,
+                                                      float* __restrict__ out, float u0,
+                                                      float inv, int n) {
+  __shared__ __align__(16) float model[kModelFloats];
+  stage_model(model, P);
+  __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
-    float z[1] = {model_input(x[i], u0, inv)}, p[1];
-    mlp_eval<1>(P, z, p);
-    out[i] = p[0] * (float)(n - 1);
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+    const int64_t i = base + threadIdx.x;
+    const float p = mlp_eval_wave(model, model_input(x[i < m ? i : 0], u0, inv));
+    if (i < m) out[i] = p * (float)(n - 1);
   }
 }
 
@@ -641,13 +657,15 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
     return rc;
   DeviceInfo di;
   if ((rc = device_info(&di)) != SS_OK) return rc;
-  const size_t lds = ((size_t)(h->n + SS_PAD) * 8 + 15) / 16 * 16;
+  const size_t tab = ((size_t)(h->n + SS_PAD) * 8 + 15) / 16 * 16;
+  const size_t lds = tab + kModelBytes;
   const void* kern = reinterpret_cast<const void*>(&learned_kernel<kLearnedQ>);
   const int64_t per_tile = (int64_t)kLearnedBlock * kLearnedQ;
   const int64_t ntiles = (m + per_tile - 1) / per_tile;
   int64_t grid = (int64_t)blocks_per_cu(kern, kLearnedBlock, lds) * di.num_cus * 4;
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
-  LearnedArgs a{h->table, h->d_params, targets, out_idx, h->d_fallbacks, m, h->n, h->E, h->u0, h->inv};
+  LearnedArgs a{h->table, h->d_params, targets, out_idx, h->d_fallbacks, m, h->n, h->E, h->u0, h->inv,
+                (int)tab};
   void* args[] = {&a};
   SS_TRY_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(kLearnedBlock), args, lds, st));
   return SS_OK;

@@ -84,27 +84,30 @@ struct MultiArgs {
                              // the segment offsets (targets of segment s >= pair_base
                              // are xb[query_off[s] - split ...])
   int lds_bins_a, lds_tab_b, lds_bins_b;  // byte offsets in LDS
+  int lds_model_a, lds_model_b;           // learned models' LDS images
 };
 
 // What a workgroup keeps about the table it has staged.
 struct Staged {
   HashParams hp;   // exponent hash (hp.ok) ...
-  int learned;     // ... or learned model ...
+  int learned;     // ... or learned model (its image staged in LDS) ...
   int n;           // ... or bisection
   int E;
   float u0, inv;
-  int64_t p_off;
 };
 
 // Copies one table (+inf padded) and, for the exponent hash, its bin table
 // into LDS with 16-byte loads (the pool's bin tables start 16-byte aligned;
-// tables are 8-byte aligned, so they are copied in 8-byte words).
+// tables are 8-byte aligned, so they are copied in 8-byte words); for a
+// learned table, its model's LDS image.
 __device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* __restrict__ tables,
-                                             const uint16_t* __restrict__ bins, double* sa,
-                                             uint16_t* C) {
+                                             const uint16_t* __restrict__ bins,
+                                             const float* __restrict__ params, double* sa,
+                                             uint16_t* C, float* model) {
   stage_table(sa, tables + d.tab_off, d.n);
   Staged st{{0, d.shift, d.kmin, d.kmaxc, d.nb, d.K}, d.algo == SS_ALGO_LEARNED, d.n, d.E,
-            d.u0, d.inv, d.p_off};
+            d.u0, d.inv};
+  if (d.algo == SS_ALGO_LEARNED) stage_model(model, params + d.p_off);
   if (d.algo == SS_ALGO_EXPHASH) {
     st.hp.ok = 1;
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -118,20 +121,13 @@ __device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* _
 
 template <int Q, int LEARN>
 __device__ __forceinline__ void search_staged(const Staged& st, const double* sa,
-                                              const uint16_t* C, const float* params,
+                                              const uint16_t* C, const float* model,
                                               const double (&x)[Q], int (&r)[Q], int (&fell)[Q]) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) fell[q] = 0;
   if constexpr (LEARN) {
-    if (st.learned) {
-      // scalar loads of the parameters, one row at a time (see ss_mlp.h);
-      // the address is workgroup-uniform, made explicit for the compiler
-      const uint64_t addr = reinterpret_cast<uint64_t>(params + st.p_off);
-      const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
-      const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
-      const float* Pg = reinterpret_cast<const float*>(((uint64_t)hi << 32) | lo);
-      asm volatile("" : "+s"(Pg));
-      search_learned<Q>(sa, st.n, (ConstFloatPtr)Pg, st.E, st.u0, st.inv, x, r, fell);
+    if (st.learned) {  // uniform across the workgroup
+      search_learned<Q>(sa, st.n, model, st.E, st.u0, st.inv, x, r, fell);
       return;
     }
   }
@@ -176,8 +172,11 @@ __device__ __forceinline__ void load_range(const double* __restrict__ x, TileRan
   load_tile<Q>(x, r.q1, r.q0 + threadIdx.x, nt, r.q0 + (int64_t)nt * Q <= r.q1, v);
 }
 
+// Plans with learned tables launch at most 512 threads per workgroup: the
+// model's matrix-core accumulators need more than the 128 registers per
+// lane that 1024-thread workgroups leave.
 template <int MODE, int Q, int LEARN>
-__global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
+__global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) {
   constexpr bool PAIRED = MODE == kPairJoint;
   constexpr bool SPLIT = MODE == kPairSplit;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -185,6 +184,8 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   uint16_t* Ca = reinterpret_cast<uint16_t*>(lds + a.lds_bins_a);
   double* sb = reinterpret_cast<double*>(lds + a.lds_tab_b);
   uint16_t* Cb = reinterpret_cast<uint16_t*>(lds + a.lds_bins_b);
+  float* Ma = reinterpret_cast<float*>(lds + a.lds_model_a);
+  float* Mb = reinterpret_cast<float*>(lds + a.lds_model_b);
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
   // Workgroup b runs on XCD b mod X (the dispatcher's round robin).  With
@@ -219,8 +220,10 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   }
 
   Staged sta, stb{};
-  sta = stage_desc(a.desc[sg.seg], SPLIT && sg.part ? a.tables_b : a.tables_a, a.bins, sa, Ca);
-  if constexpr (PAIRED) stb = stage_desc(a.desc[a.pair_base + sg.seg], a.tables_b, a.bins, sb, Cb);
+  sta = stage_desc(a.desc[sg.seg], SPLIT && sg.part ? a.tables_b : a.tables_a, a.bins, a.params,
+                   sa, Ca, Ma);
+  if constexpr (PAIRED)
+    stb = stage_desc(a.desc[a.pair_base + sg.seg], a.tables_b, a.bins, a.params, sb, Cb, Mb);
   __syncthreads();
   int fallbacks = 0;
   for (int64_t j = j0; j < j1; ++j) {
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     }
     const bool full = cur.q0 + per_tile == cur.q1;
     int r[Q], fell[Q];
-    search_staged<Q, LEARN>(sta, sa, Ca, a.params, ca, r, fell);
+    search_staged<Q, LEARN>(sta, sa, Ca, Ma, ca, r, fell);
     store_tile<Q>(SPLIT && sg.part ? a.ob : a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
     if constexpr (LEARN) {
 #pragma unroll
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
         fallbacks += (full || cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1) ? fell[q] : 0;
     }
     if constexpr (PAIRED) {
-      search_staged<Q, LEARN>(stb, sb, Cb, a.params, cb, r, fell);
+      search_staged<Q, LEARN>(stb, sb, Cb, Mb, cb, r, fell);
       store_tile<Q>(a.ob, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
       if constexpr (LEARN) {
 #pragma unroll
@@ -254,9 +257,10 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     if (sg1.seg != sg.seg) {
       __syncthreads();  // every lane is done with the old table
       sta = stage_desc(a.desc[sg1.seg], SPLIT && sg1.part ? a.tables_b : a.tables_a, a.bins,
-                       sa, Ca);
+                       a.params, sa, Ca, Ma);
       if constexpr (PAIRED)
-        stb = stage_desc(a.desc[a.pair_base + sg1.seg], a.tables_b, a.bins, sb, Cb);
+        stb = stage_desc(a.desc[a.pair_base + sg1.seg], a.tables_b, a.bins, a.params, sb, Cb,
+                         Mb);
       __syncthreads();
     }
     sg = sg1;
@@ -489,6 +493,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   }
 
   p->block = option(SS_OPT_BLOCK_SIZE) > 0 ? (int)option(SS_OPT_BLOCK_SIZE) : kPlanBlock;
+  if (p->learned_tables > 0) p->block = std::min(p->block, kPlanBlock);
   p->q = p->learned_tables > 0 ? kLearnedPlanQ : (p->mode == kPairJoint ? kPairQ : kPlanQ);
   const int64_t per_tile = (int64_t)p->block * p->q;
   // tiles of every segment, numbered back to back; a segment's positions are
@@ -506,6 +511,14 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
 
   p->lds = lds_tab_a + lds_bins_a + lds_tab_b + lds_bins_b;
   const bool learned = p->learned_tables > 0;
+  int model_a = (int)p->lds, model_b = (int)p->lds;
+  if (learned) {  // one model image per staged table
+    p->lds += kModelBytes;
+    if (p->mode == kPairJoint) {
+      model_b = (int)p->lds;
+      p->lds += kModelBytes;
+    }
+  }
   switch (p->mode) {
     case kPairJoint:
       p->kernel = learned ? reinterpret_cast<const void*>(&multi_kernel<kPairJoint, kLearnedPlanQ, 1>)
@@ -579,6 +592,8 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   a.lds_bins_a = (int)lds_tab_a;
   a.lds_tab_b = (int)(lds_tab_a + lds_bins_a);
   a.lds_bins_b = (int)(lds_tab_a + lds_bins_a + lds_tab_b);
+  a.lds_model_a = model_a;
+  a.lds_model_b = model_b;
 
   // the graph holds the one search launch (preceded, with learned tables, by
   // a one-thread node clearing the fallback counter); pointers are updated
