@@ -7,7 +7,9 @@
 //                  batches of 256 (one per lane); per batch, phase A stores
 //                  each point's activations and back-propagated errors in
 //                  LDS, phase B sums every parameter's gradient over the
-//                  batch in a fixed order (deterministic).
+//                  batch in a fixed order (deterministic): the 1024 W2
+//                  gradients as a 32 x 256 x 32 product on the matrix
+//                  cores, the other 129 one thread each.
 //   bound_kernel   E = 1 + max |g(x) - idx(x)| over the probes.
 //   learned_kernel the search: table and model in LDS, the model's middle
 //                  layer on the matrix cores, Q targets per lane.
@@ -51,16 +53,20 @@ __device__ __forceinline__ float uhash(uint64_t seed, uint64_t i) {
   return (float)(z >> 40) * 0x1.0p-24f;  // [0, 1)
 }
 
+// Rows of the per-point arrays are padded to 33 floats: a lane writing its
+// own row then hits a different bank from its neighbours.
+constexpr int kRow = kH + 1;
+
 struct TrainLds {
   float P[kNP];
   float m[kNP];
   float v[kNP];
-  float h1[kTrainThreads][kH];
-  float h2[kTrainThreads][kH];
-  float d2[kTrainThreads][kH];   // dLoss / d(pre-activation of layer 2)
-  float d1[kTrainThreads][kH];   // dLoss / d(pre-activation of layer 1)
+  float h1[kTrainThreads][kRow];
+  float h2[kTrainThreads][kRow];
+  float d2[kTrainThreads][kRow];   // dLoss / d(pre-activation of layer 2)
+  float d1[kTrainThreads][kRow];   // dLoss / d(pre-activation of layer 1)
   float z[kTrainThreads];
-  float g[kTrainThreads];        // dLoss / dp
+  float g[kTrainThreads];          // dLoss / dp
   float red[kTrainThreads];
 };
 
@@ -102,88 +108,99 @@ __device__ void train_body(TrainLds& L, const TrainArgs& a) {
   const float inv_nm1 = 1.0f / (float)(n - 1);
   const int nbatch = (n + kTrainThreads - 1) / kTrainThreads;
   const int total_steps = a.steps > 0 ? a.steps : 1;
+  // Gradient ownership: wave w holds the W2 gradients of the 16 x 16
+  // quadrant (units k in [16 (w / 2), +16), inputs j in [16 (w mod 2), +16))
+  // in the accumulator of a v_mfma_f32_16x16x4f32 chain, lane l's register r
+  // being entry (k0 + 4 (l / 16) + r, j0 + l mod 16); threads 0..128 hold
+  // the other 129 parameters' gradients (w1, b1, b2, w3, b3).
+  static_assert(kTrainThreads == 256, "four wavefronts, one W2 quadrant each");
+  const int wave = tid >> 6, lane = tid & 63;
+  const int k0 = (wave >> 1) * 16, j0 = (wave & 1) * 16;
+  const int small_pi = tid < 64 ? tid : tid < 96 ? kOffB2 + (tid - 64)
+                     : tid < 128 ? kOffW3 + (tid - 96) : kOffB3;
   for (int step = 1; step <= total_steps; ++step) {
-    float grad[(kNP + kTrainThreads - 1) / kTrainThreads];
-#pragma unroll
-    for (int r = 0; r < (kNP + kTrainThreads - 1) / kTrainThreads; ++r) grad[r] = 0.0f;
+    v4f gw2 = {0.0f, 0.0f, 0.0f, 0.0f};
+    float gsmall = 0.0f;
     float sq = 0.0f;
     for (int bt = 0; bt < nbatch; ++bt) {
-      // phase A: one point per lane
+      // phase A: one point per lane.  Loops over units are rolled so that
+      // only h1 and the back-propagated sums live in registers; the rest of
+      // each point's activations goes straight to its LDS row.
       const int i = bt * kTrainThreads + tid;
+      float* h1row = L.h1[tid];
+      float* h2row = L.h2[tid];
+      float* d1row = L.d1[tid];
+      float* d2row = L.d2[tid];
       if (i < n) {
         const float zi = model_input(a.table[i], a.u0, a.inv);
         float h1[kH];
 #pragma unroll
-        for (int j = 0; j < kH; ++j) h1[j] = fmaxf(fmaf(L.P[kOffW1 + j], zi, L.P[kOffB1 + j]), 0.0f);
+        for (int j = 0; j < kH; ++j) {
+          h1[j] = fmaxf(fmaf(L.P[kOffW1 + j], zi, L.P[kOffB1 + j]), 0.0f);
+          h1row[j] = h1[j];
+        }
         float p = L.P[kOffB3];
-        float h2[kH];
-#pragma unroll
+#pragma nounroll
         for (int k = 0; k < kH; ++k) {
           float acc = L.P[kOffB2 + k];
 #pragma unroll
           for (int j = 0; j < kH; ++j) acc = fmaf(L.P[kOffW2 + kH * k + j], h1[j], acc);
-          h2[k] = fmaxf(acc, 0.0f);
-          p = fmaf(L.P[kOffW3 + k], h2[k], p);
+          const float h2k = fmaxf(acc, 0.0f);
+          h2row[k] = h2k;
+          p = fmaf(L.P[kOffW3 + k], h2k, p);
         }
         const float err = p - (float)i * inv_nm1;
         sq = fmaf(err, err, sq);
         const float gi = 2.0f * err * inv_n;
-        float d2[kH];
+        float s[kH];
 #pragma unroll
-        for (int k = 0; k < kH; ++k) d2[k] = h2[k] > 0.0f ? gi * L.P[kOffW3 + k] : 0.0f;
-#pragma unroll
-        for (int j = 0; j < kH; ++j) {
-          float s = 0.0f;
-#pragma unroll
-          for (int k = 0; k < kH; ++k) s = fmaf(L.P[kOffW2 + kH * k + j], d2[k], s);
-          L.d1[tid][j] = h1[j] > 0.0f ? s : 0.0f;
-          L.h1[tid][j] = h1[j];
-        }
-#pragma unroll
+        for (int j = 0; j < kH; ++j) s[j] = 0.0f;
+#pragma nounroll
         for (int k = 0; k < kH; ++k) {
-          L.h2[tid][k] = h2[k];
-          L.d2[tid][k] = d2[k];
+          const float d2k = h2row[k] > 0.0f ? gi * L.P[kOffW3 + k] : 0.0f;
+          d2row[k] = d2k;
+#pragma unroll
+          for (int j = 0; j < kH; ++j) s[j] = fmaf(L.P[kOffW2 + kH * k + j], d2k, s[j]);
         }
+#pragma unroll
+        for (int j = 0; j < kH; ++j) d1row[j] = h1[j] > 0.0f ? s[j] : 0.0f;
         L.z[tid] = zi;
         L.g[tid] = gi;
       } else {
 #pragma unroll
         for (int j = 0; j < kH; ++j) {
-          L.h1[tid][j] = 0.0f;
-          L.h2[tid][j] = 0.0f;
-          L.d1[tid][j] = 0.0f;
-          L.d2[tid][j] = 0.0f;
+          h1row[j] = 0.0f;
+          h2row[j] = 0.0f;
+          d1row[j] = 0.0f;
+          d2row[j] = 0.0f;
         }
         L.z[tid] = 0.0f;
         L.g[tid] = 0.0f;
       }
       __syncthreads();
-      // phase B: every parameter's gradient, summed over the batch in order
+      // phase B: gradients summed over the batch in a fixed order.  W2 (1024
+      // entries): G[k][j] += sum_t d2[t][k] h1[t][j] as rank-4 MFMA steps
+      // over the batch's rows (rows past the table's end hold zeros).
       const int rows = min(kTrainThreads, n - bt * kTrainThreads);
-#pragma unroll
-      for (int r = 0; r < (kNP + kTrainThreads - 1) / kTrainThreads; ++r) {
-        const int pi = tid + r * kTrainThreads;
-        if (pi >= kNP) break;
+      for (int t4 = 0; t4 < rows; t4 += 4) {
+        const int t = t4 + (lane >> 4);
+        gw2 = __builtin_amdgcn_mfma_f32_16x16x4f32(L.d2[t][k0 + (lane & 15)],
+                                                   L.h1[t][j0 + (lane & 15)], gw2, 0, 0, 0);
+      }
+      if (tid <= 128) {
         float s = 0.0f;
-        if (pi < kOffB1) {
-          const int j = pi - kOffW1;
-          for (int t = 0; t < rows; ++t) s = fmaf(L.d1[t][j], L.z[t], s);
-        } else if (pi < kOffW2) {
-          const int j = pi - kOffB1;
-          for (int t = 0; t < rows; ++t) s += L.d1[t][j];
-        } else if (pi < kOffB2) {
-          const int k = (pi - kOffW2) / kH, j = (pi - kOffW2) % kH;
-          for (int t = 0; t < rows; ++t) s = fmaf(L.d2[t][k], L.h1[t][j], s);
-        } else if (pi < kOffW3) {
-          const int k = pi - kOffB2;
-          for (int t = 0; t < rows; ++t) s += L.d2[t][k];
-        } else if (pi < kOffB3) {
-          const int k = pi - kOffW3;
-          for (int t = 0; t < rows; ++t) s = fmaf(L.g[t], L.h2[t][k], s);
+        if (tid < 32) {
+          for (int t = 0; t < rows; ++t) s = fmaf(L.d1[t][tid], L.z[t], s);
+        } else if (tid < 64) {
+          for (int t = 0; t < rows; ++t) s += L.d1[t][tid - 32];
+        } else if (tid < 96) {
+          for (int t = 0; t < rows; ++t) s += L.d2[t][tid - 64];
+        } else if (tid < 128) {
+          for (int t = 0; t < rows; ++t) s = fmaf(L.g[t], L.h2[t][tid - 96], s);
         } else {
           for (int t = 0; t < rows; ++t) s += L.g[t];
         }
-        grad[r] += s;
+        gsmall += s;
       }
       __syncthreads();
     }
@@ -199,27 +216,29 @@ __device__ void train_body(TrainLds& L, const TrainArgs& a) {
       __syncthreads();
     }
     if (a.steps <= 0) {
+      if (a.grad_out) {
 #pragma unroll
-      for (int r = 0; r < (kNP + kTrainThreads - 1) / kTrainThreads; ++r) {
-        const int pi = tid + r * kTrainThreads;
-        if (pi < kNP && a.grad_out) a.grad_out[pi] = grad[r];
+        for (int r = 0; r < 4; ++r)
+          a.grad_out[kOffW2 + kH * (k0 + 4 * (lane >> 4) + r) + j0 + (lane & 15)] = gw2[r];
+        if (tid <= 128) a.grad_out[small_pi] = gsmall;
       }
       break;
     }
-    // Adam with bias correction and a cosine-decayed rate
+    // Adam with bias correction and a cosine-decayed rate, each parameter
+    // updated by the thread that holds its gradient
     const float lr_t = a.lr * 0.5f * (1.0f + cosf(3.14159265f * (float)(step - 1) / (float)total_steps));
     const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
-#pragma unroll
-    for (int r = 0; r < (kNP + kTrainThreads - 1) / kTrainThreads; ++r) {
-      const int pi = tid + r * kTrainThreads;
-      if (pi >= kNP) break;
-      const float gr = grad[r];
+    auto adam = [&](int pi, float gr) {
       const float mm = 0.9f * L.m[pi] + 0.1f * gr;
       const float vv = 0.999f * L.v[pi] + 0.001f * gr * gr;
       L.m[pi] = mm;
       L.v[pi] = vv;
       L.P[pi] -= lr_t * (mm / c1) / (sqrtf(vv / c2) + 1e-8f);
-    }
+    };
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      adam(kOffW2 + kH * (k0 + 4 * (lane >> 4) + r) + j0 + (lane & 15), gw2[r]);
+    if (tid <= 128) adam(small_pi, gsmall);
     __syncthreads();
   }
   for (int i = tid; i < kNP; i += kTrainThreads) a.params[i] = L.P[i];
