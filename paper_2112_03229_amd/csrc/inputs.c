@@ -2,7 +2,7 @@
  * Seeded synthetic input generators (host only).
  *
  * These stand in for the SESAME density and temperature axes and for the
- * target streams searched in them (Sec. 4 and Sec. 5.2-5.4 of the paper:
+ * target streams searched in them (Sec. 4, 5.1, 5.2 and 5.5 of the paper:
  * small sorted, roughly logarithmically distributed float64 tables, and many
  * more targets than table entries).  Nothing in this file performs any part
  * of the search method: it only draws numbers.  Both the device path and the
