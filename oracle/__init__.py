@@ -14,6 +14,9 @@ What it computes (plain definitions, each written out in ``oracle.c``):
   a[n] = +inf; NaN -> -1), which fixes idx uniquely and is O(1) per target.
 * ``exponent_key`` / ``exponent_bins``: the exponent hash of Sec. 3.5 and the
   bin table indexed as in Eq. 3, in prefix-count form (see ``oracle.c``).
+* ``log_hash_base`` / ``log_hash_key`` / ``log_hash_bins``: the logarithm hash
+  of Sec. 3.4 (Eq. 1-3) in float64, keys clamped to [0, |H|-1], and its bin
+  table in prefix-count form.
 * ``mlp_forward`` (in ``learned.py``): the float64 forward pass of the
   1-32-32-1 ReLU position model of the learned index.
 """
@@ -52,6 +55,15 @@ def _load():
     P = ctypes.c_void_p
     I64 = ctypes.c_int64
     lib.oracle_default_threads.restype = ctypes.c_int
+    D = ctypes.c_double
+    lib.oracle_log_hash_base.argtypes = [D, D, I64]
+    lib.oracle_log_hash_base.restype = D
+    lib.oracle_log_hash_raw.argtypes = [D, D, D]
+    lib.oracle_log_hash_raw.restype = I64
+    lib.oracle_log_hash_keys.argtypes = [P, I64, D, D, I64, P]
+    lib.oracle_log_hash_keys.restype = None
+    lib.oracle_log_hash_bins.argtypes = [P, I64, I64, P]
+    lib.oracle_log_hash_bins.restype = I64
     lib.oracle_search_lt.argtypes = [P, I64, P, I64, P, ctypes.c_int]
     lib.oracle_search_lt.restype = ctypes.c_int
     lib.oracle_search_lt_at.argtypes = [P, I64, P, P, I64, P, ctypes.c_int]
@@ -154,6 +166,38 @@ def check_bracket_segments(tables, table_off, targets, query_off, idx, threads: 
 def exponent_key(v: float, s: int) -> int:
     """Exponent-hash key of a non-negative double with s sub-bin bits."""
     return int(_load().oracle_exponent_key(float(v), int(s)))
+
+
+def log_hash_base(xmin: float, xmax: float, H: int) -> float:
+    """Eq. 1: b = 10^((log10 Xmax - log10 Xmin) / |H|)."""
+    lib = _load()
+    return float(lib.oracle_log_hash_base(float(xmin), float(xmax), int(H)))
+
+
+def log_hash_raw(x: float, xmin: float, base: float) -> int:
+    """Eq. 2 before clamping: floor(log_b x) - floor(log_b Xmin)."""
+    return int(_load().oracle_log_hash_raw(float(x), float(xmin), float(base)))
+
+
+def log_hash_key(x, xmin: float, xmax: float, H: int):
+    """Eq. 2 clamped to [0, H-1] (x <= 0 and NaN: 0), for an array of x."""
+    lib = _load()
+    xv = _f64(np.atleast_1d(np.asarray(x, dtype=np.float64)))
+    out = np.empty(xv.shape[0], dtype=np.int64)
+    base = log_hash_base(xmin, xmax, H)
+    lib.oracle_log_hash_keys(_ptr(xv), xv.shape[0], float(xmin), base, int(H), _ptr(out))
+    return out
+
+
+def log_hash_bins(table, H: int):
+    """C with C[i] = #{j : hash(table[j]) < i}, i = 0..H (Eq. 3, prefix form)."""
+    lib = _load()
+    a = _f64(table)
+    C = np.empty(int(H) + 1, dtype=np.int64)
+    r = lib.oracle_log_hash_bins(_ptr(a), a.shape[0], int(H), _ptr(C))
+    if r < 0:
+        raise ValueError("log hash needs 0 < a[0] < a[n-1] < inf and H >= 1")
+    return C
 
 
 def exponent_bins(table, s: int, cap: int = 1 << 22):

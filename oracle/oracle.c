@@ -259,3 +259,55 @@ int64_t oracle_exponent_bins(const double *a, int64_t n, int s, int64_t *C, int6
     }
     return nb;
 }
+
+/* ---- logarithm-hash bins (Sec. 3.4, Eq. 1-3) --------------------------------
+ * For a table with 0 < Xmin = a[0] < Xmax = a[n-1] < inf and |H| bins:
+ *   base     b = 10^((log10 Xmax - log10 Xmin) / |H|)                 (Eq. 1)
+ *   hash(x)    = floor(log_b x) - floor(log_b Xmin),  log_b x = ln x / ln b
+ *                                                                      (Eq. 2)
+ * Eq. 1 puts Xmax itself at hash |H| (outside 0 <= hash < |H|), and
+ * targets outside [Xmin, Xmax] fall outside too, so keys are clamped to
+ * [0, |H| - 1]; x <= 0 and NaN take bin 0.  The bin table is Eq. 3 in
+ * prefix-count form:
+ *   C[i] = #{ j : hash(a[j]) < i },  i = 0 .. |H|
+ * (for a non-empty bin i, C[i] is Eq. 3's smallest index with hash i). */
+double oracle_log_hash_base(double xmin, double xmax, int64_t H) {
+    return pow(10.0, (log10(xmax) - log10(xmin)) / (double)H);
+}
+
+int64_t oracle_log_hash_raw(double x, double xmin, double base) {
+    const double lb = log(base);
+    return (int64_t)(floor(log(x) / lb) - floor(log(xmin) / lb));
+}
+
+int64_t oracle_log_hash_key(double x, double xmin, double base, int64_t H) {
+    if (!(x > 0.0)) return 0;
+    if (isinf(x)) return H - 1;
+    int64_t k = oracle_log_hash_raw(x, xmin, base);
+    if (k < 0) return 0;
+    if (k > H - 1) return H - 1;
+    return k;
+}
+
+void oracle_log_hash_keys(const double *x, int64_t m, double xmin, double base, int64_t H,
+                          int64_t *out) {
+    for (int64_t i = 0; i < m; ++i) out[i] = oracle_log_hash_key(x[i], xmin, base, H);
+}
+
+/* C[0..H] for a sorted table; returns H, -1 if the table does not satisfy
+ * 0 < a[0] < a[n-1] < inf, -2 if it is empty or H < 1. */
+int64_t oracle_log_hash_bins(const double *a, int64_t n, int64_t H, int64_t *C) {
+    if (n < 1 || H < 1) return -2;
+    if (!(a[0] > 0.0) || !(a[n - 1] > a[0]) || isinf(a[n - 1])) return -1;
+    const double base = oracle_log_hash_base(a[0], a[n - 1], H);
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!key) return -3;
+    for (int64_t j = 0; j < n; ++j) key[j] = oracle_log_hash_key(a[j], a[0], base, H);
+    for (int64_t i = 0; i <= H; ++i) {
+        int64_t cnt = 0;
+        for (int64_t j = 0; j < n; ++j) cnt += key[j] < i;
+        C[i] = cnt;
+    }
+    free(key);
+    return H;
+}

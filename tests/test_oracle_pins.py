@@ -184,3 +184,85 @@ def test_exponent_bins_brute_force(oracle_mod, inputs_mod, s):
     assert nb == keys[-1] - keys[0] + 1
     for b in range(nb + 1):
         assert C[b] == np.count_nonzero(keys - kmin < b)
+
+
+# ---------------------------------------------------------------------------
+# Logarithm hash (Sec. 3.4, Eq. 1-3): pinned through the bin edges b^k
+# computed with pow (a route that never takes a logarithm), Eq. 1's closed
+# form and brute-force bin counts.
+# ---------------------------------------------------------------------------
+
+LOG_HASH_CASES = [(3e-6, 5.4e4, 110), (3e-6, 5.4e4, 34), (1e-8, 1e6, 1000), (1.0, 2.0, 64),
+                  (0.5, 3e7, 4096), (1e-300, 1e300, 50)]
+
+
+@pytest.mark.parametrize("xmin,xmax,H", LOG_HASH_CASES)
+def test_log_hash_base_closed_form(oracle_mod, xmin, xmax, H):
+    b = oracle_mod.log_hash_base(xmin, xmax, H)
+    # Eq. 1: b^|H| = Xmax / Xmin (in logarithms where the power overflows)
+    if xmax / xmin < 1e300:
+        assert math.isclose(b ** H, xmax / xmin, rel_tol=1e-10)
+    assert math.isclose(H * math.log(b), math.log(xmax) - math.log(xmin), rel_tol=1e-12)
+    # Eq. 2 at the ends: Xmin hashes to 0; Xmax to |H| before the clamp
+    # (its log lies exactly |H| bases above Xmin's), so into |H| - 1 after
+    assert oracle_mod.log_hash_raw(xmin, xmin, b) == 0
+    assert oracle_mod.log_hash_raw(xmax, xmin, b) in (H - 1, H)
+    assert oracle_mod.log_hash_key(xmax, xmin, xmax, H)[0] == H - 1
+
+
+@pytest.mark.parametrize("xmin,xmax,H", LOG_HASH_CASES)
+def test_log_hash_key_against_pow_edges(oracle_mod, inputs_mod, xmin, xmax, H):
+    """key(x) = i  <=>  b^(F+i) <= x < b^(F+i+1), F = floor(log_b Xmin), for x
+    inside [Xmin, Xmax], except within rounding of an edge."""
+    b = oracle_mod.log_hash_base(xmin, xmax, H)
+    F = math.floor(math.log(xmin) / math.log(b))
+    x = inputs_mod.log_uniform(77, 1, xmin, xmax, 20000)
+    keys = oracle_mod.log_hash_key(x, xmin, xmax, H)
+    checked = 0
+    for xi, k in zip(x, keys):
+        lo, hi = b ** (F + k), b ** (F + k + 1)
+        near = min(abs(xi / lo - 1), abs(xi / hi - 1)) < 1e-9
+        if k == H - 1:
+            hi = math.inf   # the clamp folds the rest into the last bin
+        if not near:
+            assert lo <= xi < hi, (xi, k, lo, hi)
+            checked += 1
+    assert checked > 19000
+
+
+def test_log_hash_specials_and_monotone(oracle_mod, inputs_mod):
+    xmin, xmax, H = 1e-8, 1e6, 500
+    k = oracle_mod.log_hash_key([float("nan"), -1.0, 0.0, 5e-324, 1e-20, float("inf"), 1e300],
+                                xmin, xmax, H)
+    assert list(k) == [0, 0, 0, 0, 0, H - 1, H - 1]
+    x = np.sort(inputs_mod.log_uniform(5, 2, 1e-9, 1e7, 50000))
+    assert np.all(np.diff(oracle_mod.log_hash_key(x, xmin, xmax, H)) >= 0)
+
+
+@pytest.mark.parametrize("n,H", [(110, 110), (100, 400), (1000, 64), (2000, 8192)])
+def test_log_hash_bins_brute_force(oracle_mod, inputs_mod, n, H):
+    table = inputs_mod.single_table(n) if n != 110 else inputs_mod.paper_shape_table()
+    C = oracle_mod.log_hash_bins(table, H)
+    assert C.shape == (H + 1,) and C[0] == 0 and C[-1] == n and np.all(np.diff(C) >= 0)
+    # route 1: per-entry keys, counted one bin at a time
+    keys = oracle_mod.log_hash_key(table, table[0], table[-1], H)
+    for i in range(H + 1):
+        assert C[i] == int(np.count_nonzero(keys < i))
+    # route 2: entries below each interior edge b^(F+i), by pow and a sorted
+    # count; entries within rounding of an edge may sit on either side
+    b = oracle_mod.log_hash_base(table[0], table[-1], H)
+    F = math.floor(math.log(table[0]) / math.log(b))
+    for i in range(1, H):
+        edge = b ** (F + i)
+        below = int(np.searchsorted(table, edge, side="left"))
+        slack = int(np.count_nonzero(np.abs(table / edge - 1) < 1e-9))
+        assert abs(int(C[i]) - below) <= slack, (i, C[i], below)
+
+
+def test_log_hash_paper_table_shape(oracle_mod, inputs_mod):
+    """The paper's density axis shape (110 log-spaced entries over
+    3e-6..5.4e4) with one bin per entry: every bin holds at most a few
+    entries, far fewer than the exponent hash's ~3.2 per binade."""
+    table = inputs_mod.paper_shape_table()
+    C = oracle_mod.log_hash_bins(table, 110)
+    assert np.diff(C).max() <= 3
