@@ -77,8 +77,15 @@ typedef enum {
                                 bits), then a linear scan inside the bin */
     SS_ALGO_BINARY_GLOBAL = 4, /* bisection reading the table from global
                                 memory (tables too large for LDS) */
-    SS_ALGO_LEARNED = 5      /* learned index (see ss_learned_build); in
+    SS_ALGO_LEARNED = 5,     /* learned index (see ss_learned_build); in
                                 plans, when SS_OPT_PLAN_LEARNED is set */
+    SS_ALGO_LOGHASH = 6      /* logarithm hash (Sec. 3.4, Eq. 1-3): |H| bins
+                                of equal width in log x over [a[0], a[n-1]]
+                                (|H| = SS_OPT_BUCKET_CAP, else 4n rounded up
+                                to a power of two in 64..16384), a scan inside
+                                the bin, a bracket check with bisection where
+                                it fails; needs a normal 0 < a[0] < a[n-1] <
+                                inf, else bisection */
 } ss_algo;
 
 /* Process-wide tuning options (ss_set_option / ss_get_option). */
@@ -184,6 +191,24 @@ SS_API int ss_validate_table(const double *table, int64_t n, int64_t *bad_index_
  * precondition some entries of counts may be left unwritten.  SYNCHRONOUS. */
 SS_API int ss_exphash_bins(const double *table, int64_t n, int bucket_bits, int32_t *counts,
                     int64_t cap, int64_t *info_out /* host, 4 entries */);
+
+/* Logarithm-hash bin table of a table, as the search builds it in LDS,
+ * written to device memory for inspection (paper Sec. 3.4, Eq. 1-3, in
+ * prefix-count form).  Eq. 1 sets log2 b = (log2 a[n-1] - log2 a[0]) / nb;
+ * Eq. 2's key floor(log_b x) - floor(log_b a[0]) is evaluated in FP32 as
+ * floor(u(x) S + phi) with u(x) = log2 x - log2 a[0] (exact binary exponent
+ * plus the FP32 log2 of the mantissa), S = 1 / log2 b, phi = frac(log_b
+ * a[0]), clamped to [0, nb - 1]; then
+ *     counts[i] = #{ j : key(a[j]) < i },   i = 0 .. nb.
+ *   nb       : |H|, 1..65535
+ *   counts   : device, int32, nb + 1 entries
+ *   info_out : host, 6 doubles: {nb, K, e0, lm0, S, phi} with K the most
+ *              entries in one bin (9 when 9 or more), e0 the biased exponent
+ *              of a[0] and lm0 the FP32 log2 of its mantissa
+ * Requires 2 <= n <= 65535 and a normal 0 < a[0] < a[n-1] < inf, else
+ * SS_ERR_INVALID_ARG.  SYNCHRONOUS. */
+SS_API int ss_loghash_bins(const double *table, int64_t n, int64_t nb, int32_t *counts,
+                           double *info_out /* host, 6 entries */);
 
 /* ---------------------------------------------------------------------------
  * Many tables in one launch (batched) and paired lookups.

@@ -22,10 +22,10 @@ STATUS_NAMES = {
 }
 
 ALGO_AUTO, ALGO_BINARY, ALGO_BALLOT, ALGO_EXPHASH, ALGO_BINARY_GLOBAL = 0, 1, 2, 3, 4
-ALGO_LEARNED = 5
+ALGO_LEARNED, ALGO_LOGHASH = 5, 6
 ALGO_NAMES = {ALGO_AUTO: "auto", ALGO_BINARY: "binary", ALGO_BALLOT: "ballot",
               ALGO_EXPHASH: "exphash", ALGO_BINARY_GLOBAL: "binary_global",
-              ALGO_LEARNED: "learned"}
+              ALGO_LEARNED: "learned", ALGO_LOGHASH: "loghash"}
 ALGO_IDS = {v: k for k, v in ALGO_NAMES.items()}
 
 OPT_FORCE_ALGO, OPT_BUCKET_BITS, OPT_BUCKET_CAP = 1, 2, 3
@@ -95,6 +95,7 @@ def _register_extra(L) -> None:
         "ss_learned_weights": [P, P, I64],
         "ss_mlp_gradient": [P, I64, P, P, P],
         "ss_learned_destroy": [P],
+        "ss_loghash_bins": [P, I64, I64, P, P],
     }
     for name, argtypes in sigs.items():
         fn = getattr(L, name, None)
@@ -194,6 +195,20 @@ def exphash_bins(table: torch.Tensor, bucket_bits: int = -1, cap: int = 1 << 16)
                                 info))
     s, kmin, nb, kmax_occ = (int(v) for v in info)
     return {"bits": s, "kmin": kmin, "nb": nb, "max_occupancy": kmax_occ}, counts[:nb + 1]
+
+
+def loghash_bins(table: torch.Tensor, nb: int):
+    """Logarithm-hash bin table as built on the device: (info dict, counts)."""
+    _need(table, torch.float64, "table")
+    counts = torch.full((int(nb) + 1,), -7, dtype=torch.int32, device=table.device)
+    info = (ctypes.c_double * 6)()
+    use_current_stream()
+    check(lib().ss_loghash_bins(_ptr(table), table.numel(), int(nb), _ptr(counts), info))
+    keys = ("nb", "max_occupancy", "e0", "lm0", "S", "phi")
+    d = dict(zip(keys, (float(v) for v in info)))
+    for k in ("nb", "max_occupancy", "e0"):
+        d[k] = int(d[k])
+    return d, counts
 
 
 # ---------------------------------------------------------------------------

@@ -1,7 +1,7 @@
 // Single-table search: kernels K1 (bisection), K2 (ballot-bracketed linear
-// scan), K3 (exponent hash) and the global-memory bisection, plus the C ABI
-// entry points search_sorted_batch, ss_search_with, ss_validate_table and
-// ss_exphash_bins.
+// scan), K3 (exponent hash), the logarithm hash and the global-memory
+// bisection, plus the C ABI entry points search_sorted_batch, ss_search_with,
+// ss_validate_table, ss_exphash_bins and ss_loghash_bins.
 //
 // Launch shape: a persistent grid (enough workgroups to fill every CU at the
 // occupancy the LDS footprint allows).  Each workgroup stages the table once
@@ -15,6 +15,7 @@
 
 #include "ss_device.h"
 #include "ss_host.h"
+#include "ss_loghash.h"
 
 namespace ss {
 
@@ -23,8 +24,8 @@ constexpr int kDefaultBlock = 512;    // threads per workgroup
 // Tiles per workgroup of the default grid.  A grid several times larger
 // than the resident workgroup count lets the dispatcher balance CUs that
 // run at different speeds (a strictly persistent grid loses ~10% to its
-// slowest workgroups); the exponent hash keeps more tiles per workgroup to
-// amortise its per-workgroup bin build.
+// slowest workgroups); the hashes keep more tiles per workgroup to amortise
+// their per-workgroup bin build.
 constexpr int kTilesPerBlockHash = 6;
 constexpr int kTilesPerBlockOther = 3;
 constexpr size_t kStageLimit = 65536; // LDS bytes a single-table launch may use
@@ -36,7 +37,7 @@ struct SingleArgs {
   int64_t m;
   int n;
   int bits;     // exponent-hash bits, -1 = automatic
-  int cap;      // exponent-hash bin cap
+  int cap;      // exponent-hash bin cap; logarithm hash: its bin count |H|
   int c_off;    // byte offset of the bin table in LDS
   int scr_off;  // byte offset of one int of LDS scratch
 };
@@ -105,6 +106,19 @@ __global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
       }
       // not applicable (negative entries, unordered keys): bisection below
     }
+    if constexpr (ALGO == SS_ALGO_LOGHASH) {
+      uint16_t* C = reinterpret_cast<uint16_t*>(lds + a.c_off);
+      int* scratch = reinterpret_cast<int*>(lds + a.scr_off);
+      LogHashParams lp = choose_loghash(sa, n, a.cap);
+      if (lp.ok) {
+        build_log_bins(sa, n, lp, C, scratch);
+        stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
+          search_loghash<Q>(sa, C, n, lp, xv, r);
+        });
+        return;
+      }
+      // not applicable (a[0] <= 0 or subnormal, a single value): bisection
+    }
     if constexpr (ALGO == SS_ALGO_BALLOT) {
       stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
         search_ballot<Q>(sa, n, xv, r);
@@ -156,7 +170,7 @@ static int plan_single(int64_t n, int algo, int cap_opt, SinglePlan* p) {
   if (!stageable)
     return fail(SS_ERR_UNSUPPORTED, "table too large to stage in LDS for the forced kernel");
   p->lds = tab_bytes;
-  if (algo == SS_ALGO_EXPHASH) {
+  if (algo == SS_ALGO_EXPHASH || algo == SS_ALGO_LOGHASH) {
     int cap = cap_opt > 0 ? cap_opt : auto_cap(n);
     // shrink the bin cap until table + bins + scratch fit
     while (cap > 16 && tab_bytes + align_up((size_t)(cap + 1) * 2, 16) + 16 > kStageLimit) cap >>= 1;
@@ -180,6 +194,7 @@ static const void* single_kernel_ptr(int algo) {
     case SS_ALGO_EXPHASH: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_EXPHASH, Q>);
     case SS_ALGO_BINARY_GLOBAL:
       return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BINARY_GLOBAL, Q>);
+    case SS_ALGO_LOGHASH: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_LOGHASH, Q>);
     default: return nullptr;
   }
 }
@@ -204,8 +219,8 @@ static int check_single_args(const double* table, int64_t n, const double* x, in
 
 int launch_single(const double* table, int64_t n, const double* x, int64_t m, int32_t* out,
                   int algo, int bits) {
-  if (algo < SS_ALGO_AUTO || algo > SS_ALGO_BINARY_GLOBAL)
-    return fail(SS_ERR_INVALID_ARG, "unknown algorithm");
+  if (algo < SS_ALGO_AUTO || algo > SS_ALGO_LOGHASH || algo == SS_ALGO_LEARNED)
+    return fail(SS_ERR_INVALID_ARG, "unknown single-table algorithm");
   if (bits < -1 || bits > SS_MAX_BITS) return fail(SS_ERR_INVALID_ARG, "bucket_bits: -1..20");
   int rc = check_single_args(table, n, x, m, out);
   if (rc != SS_OK || m == 0) return rc;
@@ -223,7 +238,8 @@ int launch_single(const double* table, int64_t n, const double* x, int64_t m, in
   int64_t grid = option(SS_OPT_GRID_BLOCKS);
   if (grid <= 0) {
     const int64_t resident = (int64_t)blocks_per_cu(kern, nt, p.lds) * di.num_cus;
-    const int tpb = p.algo == SS_ALGO_EXPHASH ? kTilesPerBlockHash : kTilesPerBlockOther;
+    const int tpb = (p.algo == SS_ALGO_EXPHASH || p.algo == SS_ALGO_LOGHASH) ? kTilesPerBlockHash
+                                                                             : kTilesPerBlockOther;
     grid = std::max<int64_t>(resident, ntiles / tpb);
   }
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
@@ -265,6 +281,28 @@ __global__ __launch_bounds__(1024) void bins_kernel(const double* __restrict__ a
     info[1] = hp.kmin;
     info[2] = hp.nb;
     info[3] = hp.K;
+  }
+}
+
+// Log-hash bin table of one table into global memory (one workgroup).
+// info receives {nb, K, e0, lm0, S, phi}, or nb = -1 if not applicable.
+__global__ __launch_bounds__(1024) void log_bins_kernel(const double* __restrict__ a, int n,
+                                                        int nb, int32_t* __restrict__ counts,
+                                                        double* __restrict__ info) {
+  __shared__ int scratch;
+  LogHashParams p = choose_loghash(a, n, nb);
+  if (!p.ok) {
+    if (threadIdx.x == 0) info[0] = -1;
+    return;
+  }
+  build_log_bins(a, n, p, counts, &scratch);
+  if (threadIdx.x == 0) {
+    info[0] = p.nb;
+    info[1] = p.K;
+    info[2] = p.e0;
+    info[3] = p.lm0;
+    info[4] = p.S;
+    info[5] = p.phi;
   }
 }
 
@@ -346,6 +384,38 @@ int ss_exphash_bins(const double* table, int64_t n, int bucket_bits, int32_t* co
     return ss::fail(SS_ERR_INVALID_ARG,
                     "exponent hash not applicable (sign bit of a[0], unordered keys or cap)");
   for (int i = 0; i < 4; ++i) info_out[i] = h_info[i];
+  return SS_OK;
+}
+
+int ss_loghash_bins(const double* table, int64_t n, int64_t nb, int32_t* counts,
+                    double* info_out) {
+  ss::clear_error();
+  if (!info_out) return ss::fail(SS_ERR_INVALID_ARG, "info_out is null");
+  if (n < 2 || n > 65535) return ss::fail(SS_ERR_INVALID_ARG, "n must be in 2..65535");
+  if (nb < 1 || nb > 65535) return ss::fail(SS_ERR_INVALID_ARG, "nb must be in 1..65535");
+  int rc = ss::check_span(table, n, sizeof(double), alignof(double), "table");
+  if (rc == SS_OK) rc = ss::check_span(counts, nb + 1, sizeof(int32_t), alignof(int32_t), "counts");
+  if (rc != SS_OK) return rc;
+  if ((rc = ss::check_device_ptr(table, "table")) != SS_OK) return rc;
+  if ((rc = ss::check_device_ptr(counts, "counts")) != SS_OK) return rc;
+  double* d_info = nullptr;
+  SS_TRY_HIP(hipMalloc(&d_info, 6 * sizeof(double)));
+  hipStream_t st = ss::current_stream();
+  double h_info[6] = {-1, 0, 0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(d_info, h_info, sizeof(h_info), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(ss::log_bins_kernel, dim3(1), dim3(1024), 0, st, table, (int)n, (int)nb,
+                       counts, d_info);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h_info, d_info, sizeof(h_info), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d_info);
+  if (e != hipSuccess) return ss::hip_fail(e, "ss_loghash_bins");
+  if (h_info[0] < 0)
+    return ss::fail(SS_ERR_INVALID_ARG,
+                    "log hash not applicable (needs a normal 0 < a[0] < a[n-1] < inf)");
+  for (int i = 0; i < 6; ++i) info_out[i] = h_info[i];
   return SS_OK;
 }
 

@@ -11,7 +11,7 @@ import torch
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = ["auto", "binary", "ballot", "exphash", "binary_global"]
+ALGOS = ["auto", "binary", "ballot", "exphash", "binary_global", "loghash"]
 TILE = 256 * 8           # targets per workgroup tile at the default launch shape
 
 
@@ -189,6 +189,69 @@ def test_exphash_bins_match_oracle(binding, gpu, oracle_mod, inputs_mod, n, s):
     assert info["max_occupancy"] == min(int(np.diff(C).max()), 9)
 
 
+@pytest.mark.parametrize("n,nb", [(110, 110), (110, 34), (1000, 4096), (2000, 500), (4000, 16384),
+                                  (300, 7)])
+def test_loghash_bins_match_oracle(binding, gpu, oracle_mod, inputs_mod, n, nb):
+    """Device bins against Eq. 1-3 in float64.  The device evaluates the key
+    in FP32, so an entry whose exact log_b value lies within 2e-3 of a bin
+    edge may land in the neighbouring bin; every other entry's bin must be
+    the oracle's."""
+    table = inputs_mod.paper_shape_table() if n == 110 else inputs_mod.single_table(n)
+    info, counts = binding.loghash_bins(torch.from_numpy(table).to(gpu), nb)
+    C = counts.cpu().numpy().astype(np.int64)
+    assert info["nb"] == nb and C[0] == 0 and C[-1] == n and np.all(np.diff(C) >= 0)
+    dev_key = np.searchsorted(C, np.arange(n), side="right") - 1
+    b = oracle_mod.log_hash_base(table[0], table[-1], nb)
+    lb0 = np.log(table[0]) / np.log(b)
+    phi = lb0 - np.floor(lb0)
+    if min(phi, 1 - phi) >= 1e-4:
+        # the oracle's keys (Eq. 2 in float64), and its unfloored values
+        want = oracle_mod.log_hash_key(table, table[0], table[-1], nb)
+        t = np.log(table) / np.log(b) - np.floor(lb0)
+        candidates = [(want, t)]
+    else:
+        # log_b Xmin within rounding of an integer (e.g. the 300-entry table
+        # with 7 bins: b = 100 and Xmin = 1e-8 = b^-4): floor(log_b Xmin) is
+        # ill-conditioned and either neighbour is a correct evaluation of
+        # Eq. 2, so the keys floor(log_b x - log_b Xmin + phi) for phi just
+        # above 0 and just below 1 are both accepted
+        rel = np.log(table / table[0]) / np.log(b)
+        candidates = []
+        for ph in (0.0, 1.0 - 1e-12):
+            t = rel + ph
+            candidates.append((np.clip(np.floor(t), 0, nb - 1).astype(np.int64), t))
+    ok = False
+    for want, t in candidates:
+        near = np.abs(t - np.rint(t)) < 2e-3
+        diff = dev_key - want
+        if np.all(diff[~near] == 0) and np.all(np.abs(diff[near]) <= 1):
+            ok = True
+            break
+    assert ok, np.nonzero(diff[~near])[0][:5]
+    say(f"loghash n={n} nb={nb}: {int(near.sum())} entries near an edge, "
+        f"{int(np.count_nonzero(diff))} in the neighbouring bin, K={info['max_occupancy']}")
+    # the FP32 parameters are Eq. 1's base and Eq. 2's offset
+    assert abs(info["S"] * np.log2(b) - 1.0) < 1e-5
+    dphi = abs(info["phi"] - phi)
+    assert min(dphi, 1 - dphi) < 1e-3
+    if not near.any():
+        assert info["max_occupancy"] == min(int(np.diff(C).max()), 9)
+
+
+@pytest.mark.parametrize("cap", [4, 16, 64, 4096, 65535])
+def test_loghash_bin_counts(binding, gpu, oracle_mod, inputs_mod, cap):
+    """Few bins (long bins: bisection inside the bin) to many."""
+    table = inputs_mod.single_table(2000)
+    x = mixed_targets(inputs_mod, table, 9 * TILE + 1, seed=cap)
+    want = oracle_mod.search_lt(table, x)
+    try:
+        say(f"case loghash bins={cap}")
+        binding.set_option(binding.OPT_BUCKET_CAP, cap)
+        assert np.array_equal(run(binding, gpu, table, x, "loghash"), want), cap
+    finally:
+        binding.set_option(binding.OPT_BUCKET_CAP, 0)
+
+
 def test_validate_table(binding, gpu, inputs_mod):
     table = inputs_mod.single_table(1000)
     t = torch.from_numpy(table).to(gpu)
@@ -238,6 +301,23 @@ def test_non_default_stream_and_graph_replay(binding, gpu, oracle_mod, inputs_mo
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(out2.cpu().numpy(), want), r
+
+
+def test_full_size_loghash(binding, gpu, oracle_mod, inputs_mod):
+    """The log hash forced on the 1000-entry table with 1e8 targets."""
+    table = inputs_mod.single_table(1000)
+    m = 10**8
+    t = torch.from_numpy(table).to(gpu)
+    host = torch.empty(m, dtype=torch.float64).pin_memory()
+    inputs_mod.table_targets(table, m, seed=11, out=host.numpy())
+    say("case full loghash n=1000")
+    out = binding.search_with(t, host.to(gpu), "loghash")
+    got = out.cpu().numpy()
+    x = host.numpy()
+    bad, first = oracle_mod.check_bracket(table, x, got)
+    assert bad == 0, first
+    pos = (inputs_mod.uniform(1000, 98, 200000) * m).astype(np.int64)
+    assert np.array_equal(got[pos], oracle_mod.search_lt_at(table, x, pos))
 
 
 @pytest.mark.parametrize("n", [100, 300, 1000])
