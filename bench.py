@@ -155,10 +155,12 @@ def copy_calibration(torch) -> None:
     print(json.dumps({"copy_calibration_bytes": n * 8, "dispatches": 3}), flush=True)
 
 
-def time_call(torch, fn, reps: int = 5) -> float:
+def time_call(torch, fn, reps: int = 5, warm: int = 3) -> float:
     """Average milliseconds of fn() over reps calls on the current stream
-    (after one untimed call)."""
-    fn()
+    (after `warm` untimed calls: the first passes over freshly allocated
+    multi-GB buffers run several percent slower)."""
+    for _ in range(warm):
+        fn()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()

@@ -537,7 +537,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   if (rc != SS_OK) return rc;
   p->device = di.device;
   const int resident = blocks_per_cu(p->kernel, p->block, p->lds) * di.num_cus;
-  p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident);
+  p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident, S);
   if (option(SS_OPT_PLAN_TILES) > 0) p->tiles_per_wg = (int)option(SS_OPT_PLAN_TILES);
   const int64_t num_wg =
       std::max<int64_t>(1, (p->total_tiles + p->tiles_per_wg - 1) / p->tiles_per_wg);

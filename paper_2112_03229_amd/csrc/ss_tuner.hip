@@ -172,14 +172,20 @@ TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bi
   return best;
 }
 
-int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident) {
+int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident,
+                               int segments) {
   (void)model;
-  // Measured on MI355X with two tiles prefetched ahead and tiles aligned
-  // to absolute positions (512 tables of 20..2000 entries, 7.4e8 targets):
-  // 2 tiles per workgroup 5.16 TB/s, 3 tiles 5.67, 4 tiles 5.72, 6 tiles
-  // 5.68 (4096 materials, 1e9 pairs: 4.52, 4.75, 4.87, 4.91).  Keep four
-  // unless that leaves fewer than ~6 waves of workgroups.
-  int64_t k = 4;
+  // Every workgroup stages its first tile's table before searching, so the
+  // tile count per workgroup trades staging stalls against load balance.
+  // Measured on MI355X (steady state, tiles aligned to absolute positions,
+  // two tiles prefetched): 512 tables with ~350 tiles each: 3 tiles per
+  // workgroup 5.87 TB/s, 4: 5.88, 6: 5.79, 8: 5.71, 12: 5.55; 8192 density
+  // and temperature segments with ~30 tiles each: 4: 5.36, 6: 5.44, 8: 5.45,
+  // 12: 5.40, 16: 5.33.  Short segments (under 64 tiles on average) take 8,
+  // long ones 4, reduced while that leaves fewer than ~6 waves of
+  // workgroups.
+  const int64_t avg = total_tiles / std::max(segments, 1);
+  int64_t k = avg < 64 ? 8 : 4;
   while (k > 1 && total_tiles / k < 6LL * std::max(resident, 1)) --k;
   return (int)k;
 }
