@@ -117,13 +117,21 @@ typedef enum {
     SS_OPT_PLAN_XCD = 11,        /* workgroup-to-XCD mapping of plans built
                                     afterwards: 0 (default) = contiguous
                                     tile ranges per XCD, 1 = dispatch order */
-    SS_OPT_PAIR_JOINT = 12       /* paired plans built afterwards: 0
+    SS_OPT_PAIR_JOINT = 12,      /* paired plans built afterwards: 0
                                     (default) = the density and temperature
                                     searches run as 2M independent segments
                                     of one launch, one table staged per
                                     workgroup; 1 = each workgroup searches
                                     both axes of its pairs with both of the
                                     material's tables staged */
+    SS_OPT_CONVENTION = 13       /* 0 (default): idx(x) = #{a < x} - 1, -1
+                                    when no entry is below x.  1: the
+                                    paper's convention (Sec. 3), the last
+                                    index with a[i] <= x clamped to [0,
+                                    n-1] (NaN gives 0; an empty table -1).
+                                    Read by single-table and learned
+                                    searches at each call and by plans at
+                                    creation */
 } ss_option;
 
 /* Human-readable message for the calling thread's most recent error

@@ -10,6 +10,8 @@ What it computes (plain definitions, each written out in ``oracle.c``):
 * ``search_lt``: idx(x) = #{i : a[i] < x} - 1, the index of the largest table
   entry strictly less than the target (paper Sec. 1; strict "<" and -1 for
   "none").  Every search method of the library must return exactly this.
+* ``search_le_clamped``: the paper's own convention (Sec. 3), the last index
+  with a[i] <= x clamped to [0, n-1]; the library's SS_OPT_CONVENTION mode.
 * ``check_bracket``: the per-target property a[i] < x <= a[i+1] (a[-1] = -inf,
   a[n] = +inf; NaN -> -1), which fixes idx uniquely and is O(1) per target.
 * ``exponent_key`` / ``exponent_bins``: the exponent hash of Sec. 3.5 and the
@@ -64,6 +66,8 @@ def _load():
     lib.oracle_log_hash_keys.restype = None
     lib.oracle_log_hash_bins.argtypes = [P, I64, I64, P]
     lib.oracle_log_hash_bins.restype = I64
+    lib.oracle_search_le_clamped.argtypes = [P, I64, P, I64, P, ctypes.c_int]
+    lib.oracle_search_le_clamped.restype = ctypes.c_int
     lib.oracle_search_lt.argtypes = [P, I64, P, I64, P, ctypes.c_int]
     lib.oracle_search_lt.restype = ctypes.c_int
     lib.oracle_search_lt_at.argtypes = [P, I64, P, P, I64, P, ctypes.c_int]
@@ -100,6 +104,17 @@ def search_lt(table, targets, threads: int = 0, return_threads: bool = False):
     out = np.empty(x.shape[0], dtype=np.int32)
     used = lib.oracle_search_lt(_ptr(a), a.shape[0], _ptr(x), x.shape[0], _ptr(out), threads)
     return (out, used) if return_threads else out
+
+
+def search_le_clamped(table, targets, threads: int = 0):
+    """The paper's convention (Sec. 3): min(max(#{table <= x} - 1, 0), n - 1)
+    as int32 (-1 for an empty table)."""
+    lib = _load()
+    a = _f64(table)
+    x = _f64(targets)
+    out = np.empty(x.shape[0], dtype=np.int32)
+    lib.oracle_search_le_clamped(_ptr(a), a.shape[0], _ptr(x), x.shape[0], _ptr(out), threads)
+    return out
 
 
 def search_lt_at(table, targets, positions, threads: int = 0):

@@ -311,3 +311,38 @@ int64_t oracle_log_hash_bins(const double *a, int64_t n, int64_t H, int64_t *C) 
     free(key);
     return H;
 }
+
+/* ---- the paper's convention (Sec. 3) -----------------------------------------
+ * Sec. 3 states the problem as the index of the last element of X that is
+ * less than or equal to the target, 0 when there is none, and n - 1 for a
+ * target above the last element:
+ *   idx_le(y) = min(max(#{ i : a[i] <= y } - 1, 0), n - 1)
+ * (a NaN target has no element <= it, hence 0; an empty table gives -1). */
+typedef struct {
+    const double *a;
+    int64_t n;
+    const double *x;
+    int32_t *out;
+} le_ctx;
+
+static void le_chunk(void *p, int64_t b, int64_t e, int tid) {
+    (void)tid;
+    le_ctx *c = (le_ctx *)p;
+    for (int64_t k = b; k < e; ++k) {
+        const double xk = c->x[k];
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < c->n; ++i) cnt += (c->a[i] <= xk);
+        int64_t r = cnt - 1;
+        if (c->n > 0) {
+            if (r < 0) r = 0;
+            if (r > c->n - 1) r = c->n - 1;
+        }
+        c->out[k] = (int32_t)r;
+    }
+}
+
+int oracle_search_le_clamped(const double *a, int64_t n, const double *x, int64_t m,
+                             int32_t *out, int threads) {
+    le_ctx c = {a, n, x, out};
+    return run_chunks(threads, m, le_chunk, &c);
+}

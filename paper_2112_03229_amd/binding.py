@@ -32,6 +32,7 @@ OPT_FORCE_ALGO, OPT_BUCKET_BITS, OPT_BUCKET_CAP = 1, 2, 3
 OPT_BLOCK_SIZE, OPT_GRID_BLOCKS, OPT_CHECK_POINTERS = 4, 5, 6
 OPT_TARGETS_PER_LANE = 7
 OPT_PLAN_TILES, OPT_PLAN_LEARNED, OPT_LEARNED_STEPS, OPT_PLAN_XCD, OPT_PAIR_JOINT = 8, 9, 10, 11, 12
+OPT_CONVENTION = 13
 
 
 class SearchSortedError(RuntimeError):

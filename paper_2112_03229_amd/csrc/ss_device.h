@@ -268,6 +268,34 @@ __device__ __forceinline__ void search_ballot(const double* __restrict__ sa, int
 }
 
 // ---------------------------------------------------------------------------
+// The paper's convention (Sec. 3): the last index with a[i] <= x, 0 when
+// there is none, n - 1 above the table, i.e. min(max(#{a <= x} - 1, 0), n-1).
+// Every search above counts a < x; a <= x counts the same as a < up(x), with
+// up(x) the next double above x, for every x except +inf (whose count is n,
+// since tables hold no NaN).  A NaN target stays NaN, counts 0 and gives 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double next_up(double x) {
+  const long long i = __double_as_longlong(x);
+  const double up = __longlong_as_double(i >= 0 ? i + 1 : i - 1);
+  return x == 0.0 ? 0x1p-1074 : up;  // -0.0 and +0.0 step to the smallest subnormal
+}
+
+template <int Q>
+__device__ __forceinline__ void convention_in(const double (&x)[Q], double (&xs)[Q]) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) xs[q] = x[q] == __builtin_inf() ? x[q] : next_up(x[q]);
+}
+
+template <int Q>
+__device__ __forceinline__ void convention_out(int n, const double (&x)[Q], int (&r)[Q]) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int v = x[q] == __builtin_inf() ? n - 1 : r[q];
+    r[q] = n > 0 ? min(max(v, 0), n - 1) : -1;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Streaming targets (a3) and indices (a6).
 // ---------------------------------------------------------------------------
 // Loads one tile slot set: slot q of lane t is target base + q*nt.  A full

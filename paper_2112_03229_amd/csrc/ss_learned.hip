@@ -367,7 +367,7 @@ struct LearnedArgs {
   int model_off;  // byte offset of the model's LDS image (after the table)
 };
 
-template <int Q>
+template <int Q, int CONV>
 __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   double* sa = reinterpret_cast<double*>(lds);
@@ -387,7 +387,14 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
     double nxt[Q];
     if (tn < ntiles) load_tile<Q>(a.x, a.m, tn * per_tile + threadIdx.x, nt, (tn + 1) * per_tile <= a.m, nxt);
     int r[Q], fell[Q];
-    search_learned<Q>(sa, a.n, model, a.E, a.u0, a.inv, cur, r, fell);
+    if constexpr (CONV) {
+      double xs[Q];
+      convention_in<Q>(cur, xs);
+      search_learned<Q>(sa, a.n, model, a.E, a.u0, a.inv, xs, r, fell);
+      convention_out<Q>(a.n, cur, r);
+    } else {
+      search_learned<Q>(sa, a.n, model, a.E, a.u0, a.inv, cur, r, fell);
+    }
     const int64_t base = t * per_tile + threadIdx.x;
     const bool full = (t + 1) * per_tile <= a.m;
     // lanes past the end of the ragged last tile searched a stand-in
@@ -678,7 +685,9 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
   if ((rc = device_info(&di)) != SS_OK) return rc;
   const size_t tab = ((size_t)(h->n + SS_PAD) * 8 + 15) / 16 * 16;
   const size_t lds = tab + kModelBytes;
-  const void* kern = reinterpret_cast<const void*>(&learned_kernel<kLearnedQ>);
+  const void* kern = option(SS_OPT_CONVENTION)
+                         ? reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 1>)
+                         : reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 0>);
   const int64_t per_tile = (int64_t)kLearnedBlock * kLearnedQ;
   const int64_t ntiles = (m + per_tile - 1) / per_tile;
   int64_t grid = (int64_t)blocks_per_cu(kern, kLearnedBlock, lds) * di.num_cus * 4;

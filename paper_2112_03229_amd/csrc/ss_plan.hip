@@ -175,7 +175,23 @@ __device__ __forceinline__ void load_range(const double* __restrict__ x, TileRan
 // Plans with learned tables launch at most 512 threads per workgroup: the
 // model's matrix-core accumulators need more than the 128 registers per
 // lane that 1024-thread workgroups leave.
-template <int MODE, int Q, int LEARN>
+// Searches one tile of targets against a staged table, in the strict
+// convention or (CONV = 1) the paper's.
+template <int Q, int LEARN, int CONV>
+__device__ __forceinline__ void search_tile(const Staged& st, const double* sa, const uint16_t* C,
+                                            const float* model, const double (&x)[Q], int (&r)[Q],
+                                            int (&fell)[Q]) {
+  if constexpr (CONV) {
+    double xs[Q];
+    convention_in<Q>(x, xs);
+    search_staged<Q, LEARN>(st, sa, C, model, xs, r, fell);
+    convention_out<Q>(st.n, x, r);
+  } else {
+    search_staged<Q, LEARN>(st, sa, C, model, x, r, fell);
+  }
+}
+
+template <int MODE, int Q, int LEARN, int CONV>
 __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) {
   constexpr bool PAIRED = MODE == kPairJoint;
   constexpr bool SPLIT = MODE == kPairSplit;
@@ -237,7 +253,7 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
     }
     const bool full = cur.q0 + per_tile == cur.q1;
     int r[Q], fell[Q];
-    search_staged<Q, LEARN>(sta, sa, Ca, Ma, ca, r, fell);
+    search_tile<Q, LEARN, CONV>(sta, sa, Ca, Ma, ca, r, fell);
     store_tile<Q>(SPLIT && sg.part ? a.ob : a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
     if constexpr (LEARN) {
 #pragma unroll
@@ -245,7 +261,7 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
         fallbacks += (full || cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1) ? fell[q] : 0;
     }
     if constexpr (PAIRED) {
-      search_staged<Q, LEARN>(stb, sb, Cb, Mb, cb, r, fell);
+      search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, cb, r, fell);
       store_tile<Q>(a.ob, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
       if constexpr (LEARN) {
 #pragma unroll
@@ -315,6 +331,7 @@ struct ss_plan {
   int paired = 0;
   int mode = 0;                  // ss::PlanMode
   int64_t split = 0;             // kPairSplit: offset of the temperature segments' targets
+  bool convention = false;       // the paper's convention (SS_OPT_CONVENTION at creation)
   int32_t T = 0;                 // descriptors (batched: tables; paired: 2 * materials)
   int32_t M = 0;                 // materials (paired)
   int32_t S = 0;                 // segments: tables (batched), materials (joint paired) or
@@ -456,6 +473,26 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
   return SS_OK;
 }
 
+template <int MODE, int Q, int LEARN>
+const void* plan_kernel_conv(bool conv) {
+  return conv ? reinterpret_cast<const void*>(&multi_kernel<MODE, Q, LEARN, 1>)
+              : reinterpret_cast<const void*>(&multi_kernel<MODE, Q, LEARN, 0>);
+}
+
+const void* plan_kernel(int mode, bool learned, bool conv) {
+  switch (mode) {
+    case kPairJoint:
+      return learned ? plan_kernel_conv<kPairJoint, kLearnedPlanQ, 1>(conv)
+                     : plan_kernel_conv<kPairJoint, kPairQ, 0>(conv);
+    case kPairSplit:
+      return learned ? plan_kernel_conv<kPairSplit, kLearnedPlanQ, 1>(conv)
+                     : plan_kernel_conv<kPairSplit, kPlanQ, 0>(conv);
+    default:
+      return learned ? plan_kernel_conv<kBatched, kLearnedPlanQ, 1>(conv)
+                     : plan_kernel_conv<kBatched, kPlanQ, 0>(conv);
+  }
+}
+
 hipKernelNodeParams search_node_params(ss_plan* p, void** kargs) {
   hipKernelNodeParams kp{};
   kp.func = const_cast<void*>(p->kernel);
@@ -519,19 +556,8 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
       p->lds += kModelBytes;
     }
   }
-  switch (p->mode) {
-    case kPairJoint:
-      p->kernel = learned ? reinterpret_cast<const void*>(&multi_kernel<kPairJoint, kLearnedPlanQ, 1>)
-                          : reinterpret_cast<const void*>(&multi_kernel<kPairJoint, kPairQ, 0>);
-      break;
-    case kPairSplit:
-      p->kernel = learned ? reinterpret_cast<const void*>(&multi_kernel<kPairSplit, kLearnedPlanQ, 1>)
-                          : reinterpret_cast<const void*>(&multi_kernel<kPairSplit, kPlanQ, 0>);
-      break;
-    default:
-      p->kernel = learned ? reinterpret_cast<const void*>(&multi_kernel<kBatched, kLearnedPlanQ, 1>)
-                          : reinterpret_cast<const void*>(&multi_kernel<kBatched, kPlanQ, 0>);
-  }
+  p->convention = option(SS_OPT_CONVENTION) != 0;
+  p->kernel = plan_kernel(p->mode, learned, p->convention);
   DeviceInfo di;
   int rc = device_info(&di);
   if (rc != SS_OK) return rc;

@@ -26,6 +26,7 @@ std::atomic<int64_t> g_plan_learned{0};
 std::atomic<int64_t> g_learned_steps{0};
 std::atomic<int64_t> g_plan_xcd{0};
 std::atomic<int64_t> g_pair_joint{0};
+std::atomic<int64_t> g_convention{0};
 
 std::mutex g_dev_mu;
 std::map<int, DeviceInfo> g_dev_cache;
@@ -63,6 +64,7 @@ int64_t option(int opt) {
     case SS_OPT_LEARNED_STEPS: return g_learned_steps.load();
     case SS_OPT_PLAN_XCD: return g_plan_xcd.load();
     case SS_OPT_PAIR_JOINT: return g_pair_joint.load();
+    case SS_OPT_CONVENTION: return g_convention.load();
     default: return 0;
   }
 }
@@ -216,6 +218,10 @@ int ss_set_option(int opt, int64_t v) {
       if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PAIR_JOINT: 0 or 1");
       ss::g_pair_joint = v;
       return SS_OK;
+    case SS_OPT_CONVENTION:
+      if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_CONVENTION: 0 or 1");
+      ss::g_convention = v;
+      return SS_OK;
     default:
       return ss::fail(SS_ERR_INVALID_ARG, "unknown option");
   }
@@ -236,6 +242,7 @@ int ss_get_option(int opt, int64_t* value_out) {
     case SS_OPT_LEARNED_STEPS:
     case SS_OPT_PLAN_XCD:
     case SS_OPT_PAIR_JOINT:
+    case SS_OPT_CONVENTION:
       *value_out = ss::option(opt);
       return SS_OK;
     default:

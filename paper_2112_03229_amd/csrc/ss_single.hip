@@ -53,9 +53,11 @@ __device__ __forceinline__ void first_tile(const double* __restrict__ x, int64_t
   if (t * per_tile < m) load_tile<Q>(x, m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= m, cur);
 }
 
-template <int Q, typename Search>
+// CONV = 1 answers in the paper's convention (convention_in/_out around the
+// search); n is the table size.
+template <int Q, int CONV, typename Search>
 __device__ __forceinline__ void stream_tiles(const double* __restrict__ x, int64_t m,
-                                             int32_t* __restrict__ out, double (&cur)[Q],
+                                             int32_t* __restrict__ out, double (&cur)[Q], int n,
                                              Search&& search) {
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
@@ -68,7 +70,14 @@ __device__ __forceinline__ void stream_tiles(const double* __restrict__ x, int64
     const bool has_next = tn < ntiles;
     if (has_next) load_tile<Q>(x, m, tn * per_tile + threadIdx.x, nt, (tn + 1) * per_tile <= m, nxt);
     int r[Q];
-    search(cur, r);
+    if constexpr (CONV) {
+      double xs[Q];
+      convention_in<Q>(cur, xs);
+      search(xs, r);
+      convention_out<Q>(n, cur, r);
+    } else {
+      search(cur, r);
+    }
     store_tile<Q>(out, m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= m, r);
     if (!has_next) break;
     for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
@@ -76,7 +85,7 @@ __device__ __forceinline__ void stream_tiles(const double* __restrict__ x, int64
   }
 }
 
-template <int ALGO, int Q>
+template <int ALGO, int Q, int CONV>
 __global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   double cur[Q];
@@ -84,7 +93,7 @@ __global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
   if constexpr (ALGO == SS_ALGO_BINARY_GLOBAL) {
     const double* __restrict__ tab = a.table;
     const int n = a.n;
-    stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
+    stream_tiles<Q, CONV>(a.x, a.m, a.out, cur, a.n, [&](const double(&xv)[Q], int(&r)[Q]) {
       search_binary_global<Q>(tab, n, xv, r);
     });
     return;
@@ -99,7 +108,7 @@ __global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
       HashParams hp = choose_hash(sa, n, a.bits, a.cap);
       if (hp.ok) {
         build_bins(sa, n, hp, C, scratch);
-        stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
+        stream_tiles<Q, CONV>(a.x, a.m, a.out, cur, a.n, [&](const double(&xv)[Q], int(&r)[Q]) {
           search_exphash<Q>(sa, C, n, hp, xv, r);
         });
         return;
@@ -112,7 +121,7 @@ __global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
       LogHashParams lp = choose_loghash(sa, n, a.cap);
       if (lp.ok) {
         build_log_bins(sa, n, lp, C, scratch);
-        stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
+        stream_tiles<Q, CONV>(a.x, a.m, a.out, cur, a.n, [&](const double(&xv)[Q], int(&r)[Q]) {
           search_loghash<Q>(sa, C, n, lp, xv, r);
         });
         return;
@@ -120,12 +129,12 @@ __global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
       // not applicable (a[0] <= 0 or subnormal, a single value): bisection
     }
     if constexpr (ALGO == SS_ALGO_BALLOT) {
-      stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
+      stream_tiles<Q, CONV>(a.x, a.m, a.out, cur, a.n, [&](const double(&xv)[Q], int(&r)[Q]) {
         search_ballot<Q>(sa, n, xv, r);
       });
       return;
     }
-    stream_tiles<Q>(a.x, a.m, a.out, cur, [&](const double(&xv)[Q], int(&r)[Q]) {
+    stream_tiles<Q, CONV>(a.x, a.m, a.out, cur, a.n, [&](const double(&xv)[Q], int(&r)[Q]) {
       search_binary<Q>(sa, n, xv, r);
     });
   }
@@ -186,15 +195,16 @@ static int plan_single(int64_t n, int algo, int cap_opt, SinglePlan* p) {
   return SS_OK;
 }
 
-template <int Q>
+template <int Q, int CONV>
 static const void* single_kernel_ptr(int algo) {
   switch (algo) {
-    case SS_ALGO_BINARY: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BINARY, Q>);
-    case SS_ALGO_BALLOT: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BALLOT, Q>);
-    case SS_ALGO_EXPHASH: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_EXPHASH, Q>);
+    case SS_ALGO_BINARY: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BINARY, Q, CONV>);
+    case SS_ALGO_BALLOT: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BALLOT, Q, CONV>);
+    case SS_ALGO_EXPHASH: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_EXPHASH, Q, CONV>);
     case SS_ALGO_BINARY_GLOBAL:
-      return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BINARY_GLOBAL, Q>);
-    case SS_ALGO_LOGHASH: return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_LOGHASH, Q>);
+      return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BINARY_GLOBAL, Q, CONV>);
+    case SS_ALGO_LOGHASH:
+      return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_LOGHASH, Q, CONV>);
     default: return nullptr;
   }
 }
@@ -232,7 +242,9 @@ int launch_single(const double* table, int64_t n, const double* x, int64_t m, in
   if (nt == 0) nt = kDefaultBlock;
   int q = (int)option(SS_OPT_TARGETS_PER_LANE);
   if (q == 0) q = kDefaultQ;
-  const void* kern = q == 4 ? single_kernel_ptr<4>(p.algo) : single_kernel_ptr<8>(p.algo);
+  const bool conv = option(SS_OPT_CONVENTION) != 0;
+  const void* kern = q == 4 ? (conv ? single_kernel_ptr<4, 1>(p.algo) : single_kernel_ptr<4, 0>(p.algo))
+                            : (conv ? single_kernel_ptr<8, 1>(p.algo) : single_kernel_ptr<8, 0>(p.algo));
   const int64_t per_tile = (int64_t)nt * q;
   const int64_t ntiles = (m + per_tile - 1) / per_tile;
   int64_t grid = option(SS_OPT_GRID_BLOCKS);

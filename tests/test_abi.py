@@ -43,8 +43,15 @@ def test_version_and_options(L):
     b.set_option(b.OPT_PAIR_JOINT, 1)
     assert b.get_option(b.OPT_PAIR_JOINT) == 1
     b.set_option(b.OPT_PAIR_JOINT, 0)
-    for opt, bad in ((b.OPT_FORCE_ALGO, 9), (b.OPT_BUCKET_BITS, 21), (b.OPT_BLOCK_SIZE, 100),
-                     (b.OPT_CHECK_POINTERS, 2), (b.OPT_PAIR_JOINT, 2), (999, 0)):
+    b.set_option(b.OPT_CONVENTION, 1)
+    assert b.get_option(b.OPT_CONVENTION) == 1
+    b.set_option(b.OPT_CONVENTION, 0)
+    b.set_option(b.OPT_FORCE_ALGO, b.ALGO_LOGHASH)
+    b.set_option(b.OPT_FORCE_ALGO, b.ALGO_AUTO)
+    for opt, bad in ((b.OPT_FORCE_ALGO, 9), (b.OPT_FORCE_ALGO, b.ALGO_LEARNED),
+                     (b.OPT_BUCKET_BITS, 21), (b.OPT_BLOCK_SIZE, 100),
+                     (b.OPT_CHECK_POINTERS, 2), (b.OPT_PAIR_JOINT, 2), (b.OPT_CONVENTION, 2),
+                     (999, 0)):
         with pytest.raises(b.SearchSortedError) as e:
             b.set_option(opt, bad)
         assert e.value.code == -1

@@ -266,3 +266,37 @@ def test_log_hash_paper_table_shape(oracle_mod, inputs_mod):
     table = inputs_mod.paper_shape_table()
     C = oracle_mod.log_hash_bins(table, 110)
     assert np.diff(C).max() <= 3
+
+
+# ---------------------------------------------------------------------------
+# The paper's convention (Sec. 3): last index with a[i] <= x, clamped to
+# [0, n-1].  Pinned by bisect.bisect_right and by brute force on tiny tables.
+# ---------------------------------------------------------------------------
+
+def test_paper_convention_against_bisect_right(oracle_mod, inputs_mod):
+    for n in (1, 2, 5, 110, 1000):
+        table = inputs_mod.single_table(n) if n > 1 else np.array([3.0])
+        x = inputs_mod.table_targets(table, 5000, seed=n)
+        x[::7] = table[np.arange(0, 5000, 7) % n]
+        got = oracle_mod.search_le_clamped(table, x)
+        want = [min(max(bisect.bisect_right(list(table), v) - 1, 0), n - 1) for v in x]
+        assert np.array_equal(got, want), n
+
+
+def test_paper_convention_tiny_tables(oracle_mod):
+    alphabet = [-2.0, -0.0, 0.0, 5e-324, 1.0, 3.0, float("inf")]
+    probes = np.array(alphabet + [-float("inf"), 0.5, 2.0, 7.0, float("nan")])
+    for n in range(0, 4):
+        for tab in itertools.combinations_with_replacement(alphabet, n):
+            table = np.array(tab, dtype=np.float64)
+            got = oracle_mod.search_le_clamped(table, probes)
+            for v, g in zip(probes, got):
+                cnt = sum(1 for a in tab if a <= v)
+                want = -1 if n == 0 else min(max(cnt - 1, 0), n - 1)
+                assert g == want, (tab, v, g, want)
+    # the relation to the strict definition: they differ only at exact hits
+    # (x equal to an entry) and below the first entry (-1 versus 0)
+    table = np.array([1.0, 2.0, 2.0, 5.0])
+    x = np.array([0.5, 1.0, 1.5, 2.0, 4.0, 5.0, 9.0])
+    assert list(oracle_mod.search_le_clamped(table, x)) == [0, 0, 0, 2, 2, 3, 3]
+    assert list(oracle_mod.search_lt(table, x)) == [-1, -1, 0, 0, 2, 2, 3]
