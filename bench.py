@@ -353,6 +353,37 @@ def measure_small(torch, binding, inputs, dev) -> dict:
                                    "buffers": SMALL_BUFFERS, "matches_eager": replays_ok}}
 
 
+def measure_small_m(torch, binding, inputs, dev) -> dict:
+    """Per-call time in the small-m regime (m = 1e2..1e4 targets per call),
+    where the per-workgroup setup decides: 64 calls replayed from a HIP
+    graph, for the automatic choice and for each kernel forced, on a
+    110-entry and a 4000-entry table."""
+    res = {}
+    for n, table in ((110, inputs.paper_shape_table()), (4000, inputs.single_table(4000))):
+        t = torch.from_numpy(table).to(dev)
+        for m in (100, 1000, 10000):
+            x = torch.from_numpy(inputs.table_targets(table, m, seed=m)).to(dev)
+            out = torch.empty(m, dtype=torch.int32, device=dev)
+            row = {}
+            for algo in ("auto", "binary", "exphash", "loghash"):
+                def call():
+                    binding.search_with(t, x, algo, -1, out)
+                side = torch.cuda.Stream()
+                side.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(side):
+                    call()
+                torch.cuda.current_stream().wait_stream(side)
+                torch.cuda.synchronize()
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, capture_error_mode="relaxed"):
+                    for _ in range(64):
+                        call()
+                row[algo] = round(time_call(torch, g.replay, reps=5) / 64 * 1e3, 2)
+                del g
+            res[f"n={n}/m={m}"] = row
+    return {"unit": "us per call (graph-replayed)", **res}
+
+
 # FP32 work of one learned-index query: the MLP's 32 + 1024 + 32 multiply-adds
 # (2 flops each); the window check and bisection are not counted.  The 1024
 # of layer 2 run on the matrix cores (FP32 MFMA), the rest on the vector ALUs;
@@ -534,6 +565,7 @@ def main():
         torch.cuda.empty_cache()
         log("bench: small table, graph-replayed calls")
         result["small"] = measure_small(torch, binding, inputs, dev)
+        result["small"]["small_m"] = measure_small_m(torch, binding, inputs, dev)
         torch.cuda.empty_cache()
         log("bench: batched plan")
         result["batched"] = measure_batched(torch, binding, inputs, dev)
