@@ -543,7 +543,7 @@ def main():
         comp = {}
         for (i, o) in pairs:
             row = {}
-            for algo in ("binary", "ballot", "exphash", "loghash"):
+            for algo in ("binary", "ballot", "exphash", "loghash", "skiplist"):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 out = d_out[(TABLE_SIZES[i], o)]

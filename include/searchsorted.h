@@ -79,13 +79,16 @@ typedef enum {
                                 memory (tables too large for LDS) */
     SS_ALGO_LEARNED = 5,     /* learned index (see ss_learned_build); in
                                 plans, when SS_OPT_PLAN_LEARNED is set */
-    SS_ALGO_LOGHASH = 6      /* logarithm hash (Sec. 3.4, Eq. 1-3): |H| bins
+    SS_ALGO_LOGHASH = 6,     /* logarithm hash (Sec. 3.4, Eq. 1-3): |H| bins
                                 of equal width in log x over [a[0], a[n-1]]
                                 (|H| = SS_OPT_BUCKET_CAP, else 4n rounded up
                                 to a power of two in 64..16384), a scan inside
                                 the bin, a bracket check with bisection where
                                 it fails; needs a normal 0 < a[0] < a[n-1] <
                                 inf, else bisection */
+    SS_ALGO_SKIPLIST = 7     /* skiplist (Sec. 3.3): bisection over every 8th
+                                entry (a compact skip table in LDS), then a
+                                count over the 8-entry block */
 } ss_algo;
 
 /* Process-wide tuning options (ss_set_option / ss_get_option). */

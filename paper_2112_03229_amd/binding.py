@@ -22,10 +22,10 @@ STATUS_NAMES = {
 }
 
 ALGO_AUTO, ALGO_BINARY, ALGO_BALLOT, ALGO_EXPHASH, ALGO_BINARY_GLOBAL = 0, 1, 2, 3, 4
-ALGO_LEARNED, ALGO_LOGHASH = 5, 6
+ALGO_LEARNED, ALGO_LOGHASH, ALGO_SKIPLIST = 5, 6, 7
 ALGO_NAMES = {ALGO_AUTO: "auto", ALGO_BINARY: "binary", ALGO_BALLOT: "ballot",
               ALGO_EXPHASH: "exphash", ALGO_BINARY_GLOBAL: "binary_global",
-              ALGO_LEARNED: "learned", ALGO_LOGHASH: "loghash"}
+              ALGO_LEARNED: "learned", ALGO_LOGHASH: "loghash", ALGO_SKIPLIST: "skiplist"}
 ALGO_IDS = {v: k for k, v in ALGO_NAMES.items()}
 
 OPT_FORCE_ALGO, OPT_BUCKET_BITS, OPT_BUCKET_CAP = 1, 2, 3

@@ -162,7 +162,7 @@ int ss_set_stream(void* hip_stream) {
 int ss_set_option(int opt, int64_t v) {
   switch (opt) {
     case SS_OPT_FORCE_ALGO:
-      if (v < SS_ALGO_AUTO || v > SS_ALGO_LOGHASH || v == SS_ALGO_LEARNED)
+      if (v < SS_ALGO_AUTO || v > SS_ALGO_SKIPLIST || v == SS_ALGO_LEARNED)
         return ss::fail(SS_ERR_INVALID_ARG,
                         "SS_OPT_FORCE_ALGO: unknown single-table algorithm");
       ss::g_force_algo = v;

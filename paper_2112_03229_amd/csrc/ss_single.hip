@@ -1,6 +1,6 @@
 // Single-table search: kernels K1 (bisection), K2 (ballot-bracketed linear
-// scan), K3 (exponent hash), the logarithm hash and the global-memory
-// bisection, plus the C ABI entry points search_sorted_batch, ss_search_with,
+// scan), K3 (exponent hash), the logarithm hash, the two-level skiplist and
+// the global-memory bisection, plus the C ABI entry points search_sorted_batch, ss_search_with,
 // ss_validate_table, ss_exphash_bins and ss_loghash_bins.
 //
 // Launch shape: a persistent grid (enough workgroups to fill every CU at the
@@ -16,6 +16,7 @@
 #include "ss_device.h"
 #include "ss_host.h"
 #include "ss_loghash.h"
+#include "ss_skiplist.h"
 
 namespace ss {
 
@@ -128,6 +129,15 @@ __global__ __launch_bounds__(1024) void single_kernel(SingleArgs a) {
       }
       // not applicable (a[0] <= 0 or subnormal, a single value): bisection
     }
+    if constexpr (ALGO == SS_ALGO_SKIPLIST) {
+      double* sk = reinterpret_cast<double*>(lds + a.c_off);
+      build_skip_table(sa, n, sk);
+      __syncthreads();
+      stream_tiles<Q, CONV>(a.x, a.m, a.out, cur, a.n, [&](const double(&xv)[Q], int(&r)[Q]) {
+        search_skiplist<Q>(sa, sk, n, xv, r);
+      });
+      return;
+    }
     if constexpr (ALGO == SS_ALGO_BALLOT) {
       stream_tiles<Q, CONV>(a.x, a.m, a.out, cur, a.n, [&](const double(&xv)[Q], int(&r)[Q]) {
         search_ballot<Q>(sa, n, xv, r);
@@ -189,6 +199,13 @@ static int plan_single(int64_t n, int64_t m, int algo, int cap_opt, SinglePlan* 
   if (!stageable)
     return fail(SS_ERR_UNSUPPORTED, "table too large to stage in LDS for the forced kernel");
   p->lds = tab_bytes;
+  if (algo == SS_ALGO_SKIPLIST) {
+    p->c_off = (int)tab_bytes;
+    p->lds = tab_bytes + align_up((size_t)((n + 7) / 8 + SS_PAD) * sizeof(double), 16);
+    if (p->lds > kStageLimit)
+      return fail(SS_ERR_UNSUPPORTED, "table too large to stage in LDS for the skiplist");
+    return SS_OK;
+  }
   if (algo == SS_ALGO_EXPHASH || algo == SS_ALGO_LOGHASH) {
     int cap = cap_opt > 0 ? cap_opt : auto_cap(n);
     // shrink the bin cap until table + bins + scratch fit
@@ -215,6 +232,8 @@ static const void* single_kernel_ptr(int algo) {
       return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_BINARY_GLOBAL, Q, CONV>);
     case SS_ALGO_LOGHASH:
       return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_LOGHASH, Q, CONV>);
+    case SS_ALGO_SKIPLIST:
+      return reinterpret_cast<const void*>(&single_kernel<SS_ALGO_SKIPLIST, Q, CONV>);
     default: return nullptr;
   }
 }
@@ -239,7 +258,7 @@ static int check_single_args(const double* table, int64_t n, const double* x, in
 
 int launch_single(const double* table, int64_t n, const double* x, int64_t m, int32_t* out,
                   int algo, int bits) {
-  if (algo < SS_ALGO_AUTO || algo > SS_ALGO_LOGHASH || algo == SS_ALGO_LEARNED)
+  if (algo < SS_ALGO_AUTO || algo > SS_ALGO_SKIPLIST || algo == SS_ALGO_LEARNED)
     return fail(SS_ERR_INVALID_ARG, "unknown single-table algorithm");
   if (bits < -1 || bits > SS_MAX_BITS) return fail(SS_ERR_INVALID_ARG, "bucket_bits: -1..20");
   int rc = check_single_args(table, n, x, m, out);

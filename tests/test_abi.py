@@ -47,8 +47,9 @@ def test_version_and_options(L):
     assert b.get_option(b.OPT_CONVENTION) == 1
     b.set_option(b.OPT_CONVENTION, 0)
     b.set_option(b.OPT_FORCE_ALGO, b.ALGO_LOGHASH)
+    b.set_option(b.OPT_FORCE_ALGO, b.ALGO_SKIPLIST)
     b.set_option(b.OPT_FORCE_ALGO, b.ALGO_AUTO)
-    for opt, bad in ((b.OPT_FORCE_ALGO, 9), (b.OPT_FORCE_ALGO, b.ALGO_LEARNED),
+    for opt, bad in ((b.OPT_FORCE_ALGO, 9), (b.OPT_FORCE_ALGO, 8), (b.OPT_FORCE_ALGO, b.ALGO_LEARNED),
                      (b.OPT_BUCKET_BITS, 21), (b.OPT_BLOCK_SIZE, 100),
                      (b.OPT_CHECK_POINTERS, 2), (b.OPT_PAIR_JOINT, 2), (b.OPT_CONVENTION, 2),
                      (999, 0)):
@@ -69,7 +70,8 @@ def test_argument_errors_before_device_work(L):
     assert L.search_sorted_batch(fake, 10, P(0x20004), 10, P(0x90000)) == -1
     assert L.search_sorted_batch(fake, 10, P(0x20000), 10, P(0x20010)) == -1
     assert b"overlap" in L.ss_last_error()
-    assert L.ss_search_with(fake, 10, P(0x20000), 10, P(0x90000), 7, -1) == -1
+    assert L.ss_search_with(fake, 10, P(0x20000), 10, P(0x90000), 8, -1) == -1
+    assert L.ss_search_with(fake, 10, P(0x20000), 10, P(0x90000), 5, -1) == -1
     assert L.ss_search_with(fake, 10, P(0x20000), 10, P(0x90000), 3, 25) == -1
     # m == 0 is a no-op that touches nothing
     assert L.search_sorted_batch(P(0), 0, P(0), 0, P(0)) == 0

@@ -10,7 +10,7 @@ import torch
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = ["auto", "binary", "ballot", "exphash", "binary_global", "loghash"]
+ALGOS = ["auto", "binary", "ballot", "exphash", "binary_global", "loghash", "skiplist"]
 TILE = 512 * 8
 
 

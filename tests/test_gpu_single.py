@@ -11,7 +11,7 @@ import torch
 
 pytestmark = pytest.mark.gpu
 
-ALGOS = ["auto", "binary", "ballot", "exphash", "binary_global", "loghash"]
+ALGOS = ["auto", "binary", "ballot", "exphash", "binary_global", "loghash", "skiplist"]
 TILE = 256 * 8           # targets per workgroup tile at the default launch shape
 
 
