@@ -337,6 +337,18 @@ SS_API int ss_learned_build(const double *table, int64_t n, const ss_mlp_opts *o
 SS_API int ss_learned_from_weights(const double *table, int64_t n, const float *weights,
                                    ss_learned **out);
 
+/* Writes the model to a text file (JSON: format tag, n, E, steps, loss, the
+ * normalisation and the 1153 parameters, each printed so that it reads back
+ * bit-exactly).  SYNCHRONOUS (host file I/O only). */
+SS_API int ss_learned_save(const ss_learned *h, const char *path);
+
+/* Reads a model written by ss_learned_save and attaches it to a table of the
+ * same size (the table the model was trained on, or any other: E is
+ * measured again on the device for this table, so the search stays exact
+ * for any stored model).  Returns SS_ERR_INVALID_ARG for a missing or
+ * malformed file or a size mismatch.  SYNCHRONOUS. */
+SS_API int ss_learned_load(const double *table, int64_t n, const char *path, ss_learned **out);
+
 /* out_idx[k] = idx(targets[k]) through the learned index; asynchronous. */
 SS_API int ss_learned_search(ss_learned *h, const double *targets, int64_t m,
                              int32_t *out_idx);

@@ -97,6 +97,8 @@ def _register_extra(L) -> None:
         "ss_mlp_gradient": [P, I64, P, P, P],
         "ss_learned_destroy": [P],
         "ss_loghash_bins": [P, I64, I64, P, P],
+        "ss_learned_save": [P, ctypes.c_char_p],
+        "ss_learned_load": [P, I64, ctypes.c_char_p, ctypes.POINTER(P)],
     }
     for name, argtypes in sigs.items():
         fn = getattr(L, name, None)
@@ -399,14 +401,16 @@ class LearnedIndex:
     (trains on the device) or from given weights."""
 
     def __init__(self, table: torch.Tensor, steps: int = 3000, lr: float = 0.01, seed: int = 1,
-                 weights=None):
+                 weights=None, path: str | None = None):
         import numpy as np
         _need(table, torch.float64, "table")
         self._table = table
         self.n = table.numel()
         h = ctypes.c_void_p()
         use_current_stream()
-        if weights is None:
+        if path is not None:
+            check(lib().ss_learned_load(_ptr(table), self.n, os.fsencode(path), ctypes.byref(h)))
+        elif weights is None:
             opts = MlpOpts(int(steps), float(lr), int(seed))
             check(lib().ss_learned_build(_ptr(table), self.n, ctypes.byref(opts), ctypes.byref(h)))
         else:
@@ -417,6 +421,14 @@ class LearnedIndex:
                                                 w.ctypes.data_as(ctypes.c_void_p),
                                                 ctypes.byref(h)))
         self._handle = h
+
+    @classmethod
+    def load(cls, table: torch.Tensor, path: str) -> "LearnedIndex":
+        """A model saved with save(), attached to `table` (E measured again)."""
+        return cls(table, path=path)
+
+    def save(self, path: str) -> None:
+        check(lib().ss_learned_save(self._handle, os.fsencode(path)))
 
     def close(self) -> None:
         if getattr(self, "_handle", None) is not None and self._handle.value:

@@ -15,6 +15,8 @@
 //                  layer on the matrix cores, Q targets per lane.
 //   predict_kernel the model's fractional position for inspection.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -663,6 +665,74 @@ int ss_learned_from_weights(const double* table, int64_t n, const float* weights
     return rc;
   }
   *out = h;
+  return SS_OK;
+}
+
+int ss_learned_save(const ss_learned* h, const char* path) {
+  clear_error();
+  if (!h || !path) return fail(SS_ERR_INVALID_ARG, "null argument");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  std::fprintf(f, "{\n \"format\": \"searchsorted-learned-1\",\n \"n\": %d,\n \"E\": %d,\n"
+                  " \"steps\": %d,\n \"loss\": %.17g,\n \"u0\": %.9g,\n \"inv\": %.9g,\n"
+                  " \"weights\": [",
+               h->n, h->E, h->steps, h->loss, (double)h->u0, (double)h->inv);
+  for (int i = 0; i < kNP; ++i)
+    std::fprintf(f, "%s%.9g", i ? ", " : "", (double)h->params[i]);
+  std::fprintf(f, "]\n}\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok ? SS_OK : fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+}
+
+namespace {
+
+// Finds "key": in a saved model and returns a pointer just past the colon.
+const char* find_key(const std::string& text, const char* key) {
+  const std::string k = std::string("\"") + key + "\"";
+  const size_t at = text.find(k);
+  if (at == std::string::npos) return nullptr;
+  const size_t colon = text.find(':', at + k.size());
+  return colon == std::string::npos ? nullptr : text.c_str() + colon + 1;
+}
+
+}  // namespace
+
+int ss_learned_load(const double* table, int64_t n, const char* path, ss_learned** out) {
+  clear_error();
+  if (!out || !path) return fail(SS_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot read ") + path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  if (text.find("\"searchsorted-learned-1\"") == std::string::npos)
+    return fail(SS_ERR_INVALID_ARG, "not a saved learned model");
+  const char* pn = find_key(text, "n");
+  const char* pw = find_key(text, "weights");
+  const char* ps = find_key(text, "steps");
+  const char* pl = find_key(text, "loss");
+  if (!pn || !pw) return fail(SS_ERR_INVALID_ARG, "saved model lacks n or weights");
+  if (std::strtoll(pn, nullptr, 10) != n)
+    return fail(SS_ERR_INVALID_ARG, "saved model was trained on a table of another size");
+  std::vector<float> w(kNP);
+  const char* c = std::strchr(pw, '[');
+  if (!c) return fail(SS_ERR_INVALID_ARG, "malformed weights");
+  ++c;
+  for (int i = 0; i < kNP; ++i) {
+    char* end = nullptr;
+    w[i] = std::strtof(c, &end);
+    if (end == c) return fail(SS_ERR_INVALID_ARG, "malformed weights");
+    c = end;
+    while (*c == ' ' || *c == ',' || *c == '\n') ++c;
+  }
+  if (*c != ']') return fail(SS_ERR_INVALID_ARG, "weights: expected 1153 values");
+  int rc = ss_learned_from_weights(table, n, w.data(), out);
+  if (rc != SS_OK) return rc;
+  if (ps) (*out)->steps = (int)std::strtol(ps, nullptr, 10);
+  if (pl) (*out)->loss = std::strtod(pl, nullptr);
   return SS_OK;
 }
 

@@ -171,3 +171,31 @@ def test_full_size_learned(binding, gpu, oracle_mod, inputs_mod, trained):
     pos = (inputs_mod.uniform(2000, 96, 200000) * m).astype(np.int64)
     assert np.array_equal(got[pos], oracle_mod.search_lt_at(table, x, pos))
     say(f"fallbacks {li.fallbacks()} of {m}")
+
+
+def test_save_and_load(binding, gpu, oracle_mod, inputs_mod, trained, tmp_path):
+    """A saved model reads back bit-exactly; loaded onto its own table it
+    searches exactly with the same bound, and loaded onto another table of
+    the same size E is measured again and the search is still exact."""
+    table, t, li = trained
+    path = str(tmp_path / "model.json")
+    li.save(path)
+    back = binding.LearnedIndex.load(t, path)
+    assert np.array_equal(back.weights().view(np.uint32), li.weights().view(np.uint32))
+    info, info2 = li.info(), back.info()
+    assert info2["E"] == info["E"] and info2["steps"] == info["steps"]
+    x = targets_for(inputs_mod, table, 50001, seed=21)
+    want = oracle_mod.search_lt(table, x)
+    assert np.array_equal(back.search(torch.from_numpy(x).to(gpu)).cpu().numpy(), want)
+    other = inputs_mod.single_table(2000, seed=77)
+    on_other = binding.LearnedIndex.load(torch.from_numpy(other).to(gpu), path)
+    xo = targets_for(inputs_mod, other, 50001, seed=22)
+    got = on_other.search(torch.from_numpy(xo).to(gpu)).cpu().numpy()
+    assert np.array_equal(got, oracle_mod.search_lt(other, xo))
+    say(f"E on its table {info['E']}, on another table {on_other.info()['E']}")
+    with pytest.raises(binding.SearchSortedError):
+        binding.LearnedIndex.load(torch.from_numpy(table[:1000].copy()).to(gpu), path)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"format": "searchsorted-learned-1", "n": 2000, "weights": [1, 2]}')
+    with pytest.raises(binding.SearchSortedError):
+        binding.LearnedIndex.load(t, str(bad))
