@@ -12,6 +12,8 @@ What it computes (plain definitions, each written out in ``oracle.c``):
   "none").  Every search method of the library must return exactly this.
 * ``search_le_clamped``: the paper's own convention (Sec. 3), the last index
   with a[i] <= x clamped to [0, n-1]; the library's SS_OPT_CONVENTION mode.
+* ``interp_pairs``: bilinear interpolation of a material's value grid at each
+  (rho, T) pair after the paired search, the step EOSPAC performs after it.
 * ``check_bracket``: the per-target property a[i] < x <= a[i+1] (a[-1] = -inf,
   a[n] = +inf; NaN -> -1), which fixes idx uniquely and is O(1) per target.
 * ``exponent_key`` / ``exponent_bins``: the exponent hash of Sec. 3.5 and the
@@ -66,6 +68,8 @@ def _load():
     lib.oracle_log_hash_keys.restype = None
     lib.oracle_log_hash_bins.argtypes = [P, I64, I64, P]
     lib.oracle_log_hash_bins.restype = I64
+    lib.oracle_interp_pairs.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P, P, P]
+    lib.oracle_interp_pairs.restype = None
     lib.oracle_search_le_clamped.argtypes = [P, I64, P, I64, P, ctypes.c_int]
     lib.oracle_search_le_clamped.restype = ctypes.c_int
     lib.oracle_search_lt.argtypes = [P, I64, P, I64, P, ctypes.c_int]
@@ -115,6 +119,25 @@ def search_le_clamped(table, targets, threads: int = 0):
     out = np.empty(x.shape[0], dtype=np.int32)
     lib.oracle_search_le_clamped(_ptr(a), a.shape[0], _ptr(x), x.shape[0], _ptr(out), threads)
     return out
+
+
+def interp_pairs(rho_tables, rho_off, t_tables, t_off, pair_off, values, rho, temp):
+    """Bilinear interpolation of each material's grid at its (rho, T) pairs
+    after locating both cells (see ``oracle.c``); returns (f, scale)."""
+    lib = _load()
+    rt, tt, vals = _f64(rho_tables), _f64(t_tables), _f64(values)
+    ro = np.ascontiguousarray(rho_off, dtype=np.int64)
+    to = np.ascontiguousarray(t_off, dtype=np.int64)
+    po = np.ascontiguousarray(pair_off, dtype=np.int64)
+    r, t = _f64(rho), _f64(temp)
+    M = ro.shape[0] - 1
+    assert to.shape[0] == M + 1 and po.shape[0] == M + 1
+    assert vals.shape[0] == int(np.sum(np.diff(ro) * np.diff(to)))
+    out = np.empty(r.shape[0])
+    scale = np.empty(r.shape[0])
+    lib.oracle_interp_pairs(_ptr(rt), _ptr(ro), _ptr(tt), _ptr(to), _ptr(po), M, _ptr(vals),
+                            _ptr(r), _ptr(t), _ptr(out), _ptr(scale))
+    return out, scale
 
 
 def search_lt_at(table, targets, positions, threads: int = 0):

@@ -346,3 +346,50 @@ int oracle_search_le_clamped(const double *a, int64_t n, const double *x, int64_
     le_ctx c = {a, n, x, out};
     return run_chunks(threads, m, le_chunk, &c);
 }
+
+/* ---- bilinear interpolation after the paired search ------------------------
+ * EOSPAC interpolates a material's table F over its density and temperature
+ * axes after finding each target's cell (Sec. 1).  For a pair (r, t) of
+ * material j with axes R[0..nr) and T[0..nt) (strictly increasing, nr, nt
+ * >= 2) and grid F[a][b] = values[a nt + b]:
+ *   i = min(max(#{R < r} - 1, 0), nr - 2),  k = min(max(#{T < t} - 1, 0), nt - 2)
+ *   u = (r - R[i]) / (R[i+1] - R[i]),        v = (t - T[k]) / (T[k+1] - T[k])
+ *   f = (1-u)(1-v) F[i][k] + u(1-v) F[i+1][k] + (1-u) v F[i][k+1] + u v F[i+1][k+1]
+ * (outside the axes the edge cell is extended linearly; NaN gives NaN).
+ * scale = |(1-u)(1-v) F[i][k]| + ... + |u v F[i+1][k+1]| bounds the terms'
+ * size for a rounding tolerance. */
+static int64_t count_lt(const double *a, int64_t n, double x) {
+    int64_t c = 0;
+    for (int64_t i = 0; i < n; ++i) c += a[i] < x;
+    return c;
+}
+
+void oracle_interp_pairs(const double *rho_tables, const int64_t *rho_off, const double *t_tables,
+                         const int64_t *t_off, const int64_t *pair_off, int32_t M,
+                         const double *values, const double *rho, const double *temp,
+                         double *out, double *scale) {
+    int64_t voff = 0;
+    for (int32_t j = 0; j < M; ++j) {
+        const double *R = rho_tables + rho_off[j];
+        const double *T = t_tables + t_off[j];
+        const int64_t nr = rho_off[j + 1] - rho_off[j], nt = t_off[j + 1] - t_off[j];
+        const double *F = values + voff;
+        for (int64_t p = pair_off[j]; p < pair_off[j + 1]; ++p) {
+            int64_t i = count_lt(R, nr, rho[p]) - 1, k = count_lt(T, nt, temp[p]) - 1;
+            if (i < 0) i = 0;
+            if (i > nr - 2) i = nr - 2;
+            if (k < 0) k = 0;
+            if (k > nt - 2) k = nt - 2;
+            const double u = (rho[p] - R[i]) / (R[i + 1] - R[i]);
+            const double v = (temp[p] - T[k]) / (T[k + 1] - T[k]);
+            const double w00 = (1 - u) * (1 - v), w10 = u * (1 - v), w01 = (1 - u) * v,
+                         w11 = u * v;
+            const double f00 = F[i * nt + k], f10 = F[(i + 1) * nt + k],
+                         f01 = F[i * nt + k + 1], f11 = F[(i + 1) * nt + k + 1];
+            out[p] = w00 * f00 + w10 * f10 + w01 * f01 + w11 * f11;
+            if (scale)
+                scale[p] = fabs(w00 * f00) + fabs(w10 * f10) + fabs(w01 * f01) + fabs(w11 * f11);
+        }
+        voff += nr * nt;
+    }
+}

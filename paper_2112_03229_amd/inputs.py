@@ -274,6 +274,52 @@ def paired_layout(seed: int = 4096, materials: int = 4096, total_pairs: int = 10
     return Paired(rho, temp)
 
 
+@dataclass
+class Interp:
+    """Paired axes plus one value grid per material (row-major, density-major:
+    values[voff[j] + a * n_t + b] is material j's value at (rho_a, T_b))."""
+    pairs: Paired
+    values: np.ndarray
+    value_off: np.ndarray
+
+
+def interp_layout(seed: int = 1024, materials: int = 1024, total_pairs: int = 10**9,
+                  n_rho=(50, 150), n_t=(20, 100)) -> Interp:
+    """Axes shaped like SESAME tables (about 100 x 60 points), the paired
+    layout's ranges and pair counts, and a smooth synthetic value grid per
+    material: f = c0 + c1 L + c2 M + c3 L M + 0.05 sin(7 L) with L = log10 rho,
+    M = log10 T and coefficients drawn per material (numbers, not a method)."""
+    base = paired_layout(seed=seed, materials=materials, total_pairs=total_pairs)
+    nr = _int_uniform(seed, S_SIZES, materials, n_rho[0], n_rho[1])
+    nt = _int_uniform(seed + 1, S_SIZES, materials, n_t[0], n_t[1])
+    pr, qr = _ranges(seed, S_RANGES, materials)
+    pt, qt = _ranges(seed + 1, S_RANGES, materials)
+    rtabs, roff = _tables_from(seed, nr, pr, qr, S_TABLE)
+    ttabs, toff = _tables_from(seed + 1, nt, pt, qt, S_TABLE2)
+    for tabs, off in ((rtabs, roff), (ttabs, toff)):
+        for j in range(materials):
+            a = tabs[off[j]:off[j + 1]]
+            assert np.all(a[1:] > a[:-1]), "axes must be strictly increasing"
+    coef = uniform(seed, S_COUNTS + 10, 4 * materials, threads=1).reshape(materials, 4) * 2 - 1
+    voff = np.zeros(materials + 1, dtype=np.int64)
+    voff[1:] = np.cumsum(nr * nt)
+    vals = np.empty(int(voff[-1]))
+    for j in range(materials):
+        L = np.log10(rtabs[roff[j]:roff[j + 1]])[:, None]
+        Mv = np.log10(ttabs[toff[j]:toff[j + 1]])[None, :]
+        c = coef[j]
+        g = c[0] + c[1] * L + c[2] * Mv + c[3] * L * Mv + 0.05 * np.sin(7.0 * L)
+        vals[voff[j]:voff[j + 1]] = g.reshape(-1)
+    poff = base.rho.query_off
+    rho = Batch(rtabs, roff, poff,
+                np.array([0.5 * rtabs[roff[t]] for t in range(materials)]),
+                np.array([2.0 * rtabs[roff[t + 1] - 1] for t in range(materials)]))
+    temp = Batch(ttabs, toff, poff.copy(),
+                 np.array([0.5 * ttabs[toff[t]] for t in range(materials)]),
+                 np.array([2.0 * ttabs[toff[t + 1] - 1] for t in range(materials)]))
+    return Interp(Paired(rho, temp), vals, voff)
+
+
 def paired_targets(pairs: Paired, seed: int = 4096, threads: int = 0, out_rho=None, out_t=None):
     r = log_uniform_segments(seed, S_SEGMENTS, pairs.rho.query_off, pairs.rho.lo, pairs.rho.hi,
                              threads=threads, out=out_rho)
