@@ -271,6 +271,30 @@ SS_API int ss_pair_plan_create(const double *rho_tables, const int64_t *rho_off,
 SS_API int ss_pair_search(ss_plan *plan, const double *rho, const double *temp,
                           int32_t *out_rho, int32_t *out_t);
 
+/* Interpolation after the paired search (the step EOSPAC takes after it,
+ * Sec. 1): material j also has a value grid F_j over its two axes, stored
+ * row-major over (density, temperature) -- F_j[a][b] at
+ * values[voff_j + a * nT_j + b], with the grids back to back in material
+ * order (voff_j = sum over k < j of nR_k nT_k).  For pair p of material j:
+ *   i = clamp(idx_rho(rho[p]), 0, nR_j - 2),  k = clamp(idx_T(T[p]), 0, nT_j - 2)
+ *   u = (rho - R[i]) / (R[i+1] - R[i]),       v = (T - T[k]) / (T[k+1] - T[k])
+ *   out_f[p] = (1-u)(1-v) F[i][k] + u(1-v) F[i+1][k] + (1-u) v F[i][k+1] + u v F[i+1][k+1]
+ * with idx the strict index of this header (outside the axes the edge cell
+ * is extended linearly; NaN gives NaN).  Each workgroup stages both axes of
+ * its material and reads the four corner values from the grid (L2).
+ * Requirements beyond ss_pair_plan_create's: every axis has at least 2
+ * finite, strictly increasing entries; values is a device array of
+ * sum nR_j nT_j float64, referenced (must outlive the plan).  The plan
+ * ignores SS_OPT_PLAN_LEARNED and SS_OPT_CONVENTION.  SYNCHRONOUS. */
+SS_API int ss_interp_plan_create(const double *rho_tables, const int64_t *rho_off,
+                                 const double *t_tables, const int64_t *t_off, int32_t M,
+                                 const int64_t *pair_off, const double *values, ss_plan **out);
+
+/* out_f: float64[m] (device); out_rho, out_t: both NULL, or int32[m] each
+ * (device) to receive the two indices as well.  Asynchronous. */
+SS_API int ss_interp_search(ss_plan *plan, const double *rho, const double *temp, double *out_f,
+                            int32_t *out_rho, int32_t *out_t);
+
 SS_API int ss_plan_destroy(ss_plan *plan);
 
 /* Targets of the most recent search of a plan with learned tables that

@@ -97,6 +97,8 @@ def _register_extra(L) -> None:
         "ss_mlp_gradient": [P, I64, P, P, P],
         "ss_learned_destroy": [P],
         "ss_loghash_bins": [P, I64, I64, P, P],
+        "ss_interp_plan_create": [P, P, P, P, I32, P, P, ctypes.POINTER(P)],
+        "ss_interp_search": [P, P, P, P, P, P],
         "ss_learned_save": [P, ctypes.c_char_p],
         "ss_learned_load": [P, I64, ctypes.c_char_p, ctypes.POINTER(P)],
     }
@@ -351,6 +353,53 @@ class PairPlan(_Plan):
 
 TUNER_KEYS = ("stream_gbs", "hash_base_ns", "hash_per_k_ns", "bin_base_ns", "bin_per_step_ns",
               "stage_ns_per_kb", "calibrated", "bins_per_entry")
+
+
+class InterpPlan(PairPlan):
+    """Paired lookups followed by bilinear interpolation of each material's
+    value grid (ss_interp_plan_create / ss_interp_search)."""
+
+    def __init__(self, rho_tables: torch.Tensor, rho_off, t_tables: torch.Tensor, t_off,
+                 pair_off, values: torch.Tensor):
+        _need(rho_tables, torch.float64, "rho_tables")
+        _need(t_tables, torch.float64, "t_tables")
+        _need(values, torch.float64, "values")
+        self._roff = _host_offsets(rho_off, "rho_off")
+        self._toff = _host_offsets(t_off, "t_off")
+        self._poff = _host_offsets(pair_off, "pair_off")
+        M = self._roff.shape[0] - 1
+        if self._toff.shape[0] != M + 1 or self._poff.shape[0] != M + 1:
+            raise ValueError("offset arrays must all have M+1 entries")
+        self.num_materials = M
+        self.num_descriptors = 2 * M
+        self.num_queries = int(self._poff[-1])
+        self._tables = (rho_tables, t_tables, values)
+        h = ctypes.c_void_p()
+        use_current_stream()
+        check(lib().ss_interp_plan_create(_ptr(rho_tables), _off_ptr(self._roff), _ptr(t_tables),
+                                          _off_ptr(self._toff), M, _off_ptr(self._poff),
+                                          _ptr(values), ctypes.byref(h)))
+        self._handle = h
+
+    def interpolate(self, rho: torch.Tensor, temp: torch.Tensor, out: torch.Tensor | None = None,
+                    out_rho: torch.Tensor | None = None, out_t: torch.Tensor | None = None):
+        _need(rho, torch.float64, "rho")
+        _need(temp, torch.float64, "temp")
+        m = self.num_queries
+        if rho.numel() != m or temp.numel() != m:
+            raise ValueError(f"expected {m} pairs")
+        if out is None:
+            out = torch.empty(m, dtype=torch.float64, device=rho.device)
+        _need(out, torch.float64, "out")
+        if (out_rho is None) != (out_t is None):
+            raise ValueError("out_rho and out_t: both or neither")
+        use_current_stream()
+        check(lib().ss_interp_search(self._handle, _ptr(rho), _ptr(temp), _ptr(out),
+                                     _ptr(out_rho), _ptr(out_t)))
+        return out
+
+    def search(self, *a, **k):
+        raise TypeError("interpolation plan: use interpolate()")
 
 
 def tuner_calibrate() -> dict:

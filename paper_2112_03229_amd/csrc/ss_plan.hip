@@ -59,6 +59,8 @@ enum PlanMode {
   kPairJoint = 1,  // paired: a workgroup searches a tile of both axes (both tables staged)
   kPairSplit = 2,  // paired: the density searches and the temperature searches are
                    // 2M segments of one launch, one table staged per workgroup
+  kPairInterp = 3, // paired as kPairJoint, then bilinear interpolation of the
+                   // material's value grid at each pair
 };
 
 struct MultiArgs {
@@ -85,6 +87,13 @@ struct MultiArgs {
                              // are xb[query_off[s] - split ...])
   int lds_bins_a, lds_tab_b, lds_bins_b;  // byte offsets in LDS
   int lds_model_a, lds_model_b;           // learned models' LDS images
+  // kPairInterp: value grids (material j's grid at value_off[j], row-major
+  // over (density, temperature)), the interpolated output and whether the
+  // index outputs oa / ob are written
+  const double* values;
+  const int64_t* value_off;
+  double* of;
+  int store_idx;
 };
 
 // What a workgroup keeps about the table it has staged.
@@ -191,9 +200,47 @@ __device__ __forceinline__ void search_tile(const Staged& st, const double* sa, 
   }
 }
 
+// Bilinear interpolation of one material's grid at Q pairs whose cells the
+// two searches found (ra over the staged density axis sa, rb over the
+// temperature axis sb): the strict index clamped to the edge cells, the
+// fractional positions u and v (linear extension outside the axes), and
+// the four corner values read from the grid in global memory (L2).
+template <int Q>
+__device__ __forceinline__ void interpolate(const double* sa, int na, const double* sb, int nb,
+                                            const double* __restrict__ F, const double (&r)[Q],
+                                            const double (&t)[Q], const int (&ra)[Q],
+                                            const int (&rb)[Q], double (&f)[Q]) {
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = min(max(ra[q], 0), na - 2), k = min(max(rb[q], 0), nb - 2);
+    const double u = (r[q] - sa[i]) / (sa[i + 1] - sa[i]);
+    const double v = (t[q] - sb[k]) / (sb[k + 1] - sb[k]);
+    const double* row0 = F + (int64_t)i * nb + k;
+    const double* row1 = row0 + nb;
+    const double f00 = row0[0], f01 = row0[1], f10 = row1[0], f11 = row1[1];
+    f[q] = (1.0 - u) * (1.0 - v) * f00 + u * (1.0 - v) * f10 + (1.0 - u) * v * f01 + u * v * f11;
+  }
+}
+
+template <int Q>
+__device__ __forceinline__ void store_tile_f64(double* __restrict__ out, int64_t m, int64_t base,
+                                               int nt, bool full, const double (&v)[Q]) {
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q], out + base + (int64_t)q * nt);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t k = base + (int64_t)q * nt;
+      if (k < m) out[k] = v[q];
+    }
+  }
+}
+
 template <int MODE, int Q, int LEARN, int CONV>
 __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) {
-  constexpr bool PAIRED = MODE == kPairJoint;
+  constexpr bool INTERP = MODE == kPairInterp;
+  constexpr bool PAIRED = MODE == kPairJoint || INTERP;
   constexpr bool SPLIT = MODE == kPairSplit;
   extern __shared__ __align__(16) unsigned char lds[];
   double* sa = reinterpret_cast<double*>(lds);
@@ -236,6 +283,8 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
   }
 
   Staged sta, stb{};
+  const double* grid = nullptr;
+  if constexpr (INTERP) grid = a.values + a.value_off[sg.seg];
   sta = stage_desc(a.desc[sg.seg], SPLIT && sg.part ? a.tables_b : a.tables_a, a.bins, a.params,
                    sa, Ca, Ma);
   if constexpr (PAIRED)
@@ -254,13 +303,24 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
     const bool full = cur.q0 + per_tile == cur.q1;
     int r[Q], fell[Q];
     search_tile<Q, LEARN, CONV>(sta, sa, Ca, Ma, ca, r, fell);
-    store_tile<Q>(SPLIT && sg.part ? a.ob : a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
+    if constexpr (!INTERP)
+      store_tile<Q>(SPLIT && sg.part ? a.ob : a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
     if constexpr (LEARN) {
 #pragma unroll
       for (int q = 0; q < Q; ++q)
         fallbacks += (full || cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1) ? fell[q] : 0;
     }
-    if constexpr (PAIRED) {
+    if constexpr (INTERP) {
+      int rt[Q];
+      search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, cb, rt, fell);
+      double f[Q];
+      interpolate<Q>(sa, sta.n, sb, stb.n, grid, ca, cb, r, rt, f);
+      store_tile_f64<Q>(a.of, cur.q1, cur.q0 + threadIdx.x, nt, full, f);
+      if (a.store_idx) {
+        store_tile<Q>(a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
+        store_tile<Q>(a.ob, cur.q1, cur.q0 + threadIdx.x, nt, full, rt);
+      }
+    } else if constexpr (PAIRED) {
       search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, cb, r, fell);
       store_tile<Q>(a.ob, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
       if constexpr (LEARN) {
@@ -274,6 +334,7 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
       __syncthreads();  // every lane is done with the old table
       sta = stage_desc(a.desc[sg1.seg], SPLIT && sg1.part ? a.tables_b : a.tables_a, a.bins,
                        a.params, sa, Ca, Ma);
+      if constexpr (INTERP) grid = a.values + a.value_off[sg1.seg];
       if constexpr (PAIRED)
         stb = stage_desc(a.desc[a.pair_base + sg1.seg], a.tables_b, a.bins, a.params, sb, Cb,
                          Mb);
@@ -332,6 +393,7 @@ struct ss_plan {
   int mode = 0;                  // ss::PlanMode
   int64_t split = 0;             // kPairSplit: offset of the temperature segments' targets
   bool convention = false;       // the paper's convention (SS_OPT_CONVENTION at creation)
+  int64_t* d_value_off = nullptr;  // kPairInterp: first value of each material's grid
   int32_t T = 0;                 // descriptors (batched: tables; paired: 2 * materials)
   int32_t M = 0;                 // materials (paired)
   int32_t S = 0;                 // segments: tables (batched), materials (joint paired) or
@@ -368,7 +430,8 @@ struct ss_plan {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (void* ptr : {(void*)d_desc, (void*)d_bins, (void*)d_tile_off, (void*)d_query_off,
-                      (void*)d_wg_start, (void*)d_k, (void*)d_pool, (void*)d_fallbacks})
+                      (void*)d_wg_start, (void*)d_k, (void*)d_pool, (void*)d_fallbacks,
+                      (void*)d_value_off})
       if (ptr) (void)hipFree(ptr);
   }
 };
@@ -481,6 +544,8 @@ const void* plan_kernel_conv(bool conv) {
 
 const void* plan_kernel(int mode, bool learned, bool conv) {
   switch (mode) {
+    case kPairInterp:
+      return reinterpret_cast<const void*>(&multi_kernel<kPairInterp, kPairQ, 0, 0>);
     case kPairJoint:
       return learned ? plan_kernel_conv<kPairJoint, kLearnedPlanQ, 1>(conv)
                      : plan_kernel_conv<kPairJoint, kPairQ, 0>(conv);
@@ -531,7 +596,8 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
 
   p->block = option(SS_OPT_BLOCK_SIZE) > 0 ? (int)option(SS_OPT_BLOCK_SIZE) : kPlanBlock;
   if (p->learned_tables > 0) p->block = std::min(p->block, kPlanBlock);
-  p->q = p->learned_tables > 0 ? kLearnedPlanQ : (p->mode == kPairJoint ? kPairQ : kPlanQ);
+  p->q = p->learned_tables > 0 ? kLearnedPlanQ
+         : (p->mode == kPairJoint || p->mode == kPairInterp ? kPairQ : kPlanQ);
   const int64_t per_tile = (int64_t)p->block * p->q;
   // tiles of every segment, numbered back to back; a segment's positions are
   // taken relative to the start of its own target array
@@ -551,12 +617,13 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   int model_a = (int)p->lds, model_b = (int)p->lds;
   if (learned) {  // one model image per staged table
     p->lds += kModelBytes;
-    if (p->mode == kPairJoint) {
+    if (p->mode == kPairJoint || p->mode == kPairInterp) {
       model_b = (int)p->lds;
       p->lds += kModelBytes;
     }
   }
-  p->convention = option(SS_OPT_CONVENTION) != 0;
+  // interpolation locates cells with the strict index (its own definition)
+  p->convention = p->mode != kPairInterp && option(SS_OPT_CONVENTION) != 0;
   p->kernel = plan_kernel(p->mode, learned, p->convention);
   DeviceInfo di;
   int rc = device_info(&di);
@@ -645,16 +712,20 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   return SS_OK;
 }
 
-int run_plan(ss_plan* p, const double* xa, int32_t* oa, const double* xb, int32_t* ob) {
+int run_plan(ss_plan* p, const double* xa, int32_t* oa, const double* xb, int32_t* ob,
+             double* of = nullptr) {
   if (p->total_queries == 0 || p->total_tiles == 0) return SS_OK;
   int dev = -1;
   SS_TRY_HIP(hipGetDevice(&dev));
   if (dev != p->device) return fail(SS_ERR_INVALID_ARG, "plan was built on another device");
-  if (xa != p->args.xa || oa != p->args.oa || xb != p->args.xb || ob != p->args.ob) {
+  if (xa != p->args.xa || oa != p->args.oa || xb != p->args.xb || ob != p->args.ob ||
+      of != p->args.of) {
     p->args.xa = xa;
     p->args.oa = oa;
     p->args.xb = xb;
     p->args.ob = ob;
+    p->args.of = of;
+    p->args.store_idx = oa != nullptr && ob != nullptr;
     void* kargs[] = {&p->args};
     hipKernelNodeParams kp = search_node_params(p, kargs);
     SS_TRY_HIP(hipGraphExecKernelNodeSetParams(p->exec, p->search_node, &kp));
@@ -745,9 +816,16 @@ int ss_multi_search(ss_plan* p, const double* targets, int32_t* out_idx) {
   return run_plan(p, targets, out_idx, nullptr, nullptr);
 }
 
-int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const double* t_tables,
-                        const int64_t* t_off, int32_t M, const int64_t* pair_off, ss_plan** out) {
-  clear_error();
+}  // extern "C"
+
+namespace ss {
+namespace {
+
+// Paired plans of every form (mode kPairSplit, kPairJoint or kPairInterp;
+// values: the interpolation form's value grids, else null).
+int create_paired(const double* rho_tables, const int64_t* rho_off, const double* t_tables,
+                  const int64_t* t_off, int32_t M, const int64_t* pair_off, int mode,
+                  const double* values, ss_plan** out) {
   if (!out) return fail(SS_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (M < 1 || M > (1 << 20)) return fail(SS_ERR_INVALID_ARG, "M must be in 1..2^20");
@@ -765,14 +843,36 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
   if (nr > 0) SS_TRY_HIP(hipMemcpyAsync(hr.data(), rho_tables, 8 * nr, hipMemcpyDeviceToHost, st));
   if (ntt > 0) SS_TRY_HIP(hipMemcpyAsync(ht.data(), t_tables, 8 * ntt, hipMemcpyDeviceToHost, st));
   SS_TRY_HIP(hipStreamSynchronize(st));
+  int64_t nvalues = 0;
+  std::vector<int64_t> value_off;
+  if (mode == kPairInterp) {
+    // every axis needs a cell: at least 2 strictly increasing finite entries
+    value_off.assign(M + 1, 0);
+    for (int j = 0; j < M; ++j) {
+      const double* axes[2] = {hr.data() + rho_off[j], ht.data() + t_off[j]};
+      const int64_t len[2] = {rho_off[j + 1] - rho_off[j], t_off[j + 1] - t_off[j]};
+      for (int ax = 0; ax < 2; ++ax) {
+        if (len[ax] < 2)
+          return fail(SS_ERR_INVALID_ARG, "interpolation needs 2 or more entries per axis");
+        for (int64_t i = 0; i < len[ax]; ++i)
+          if (!std::isfinite(axes[ax][i]) || (i > 0 && !(axes[ax][i] > axes[ax][i - 1])))
+            return fail(SS_ERR_INVALID_ARG, "material " + std::to_string(j) +
+                                                ": axes must be finite and strictly increasing");
+      }
+      value_off[j + 1] = value_off[j] + len[0] * len[1];
+    }
+    nvalues = value_off[M];
+    if ((rc = check_span(values, nvalues, 8, 8, "values")) != SS_OK) return rc;
+    if ((rc = check_device_ptr(values, "values")) != SS_OK) return rc;
+  }
   ss_plan* p = new (std::nothrow) ss_plan();
   if (!p) return fail(SS_ERR_OOM, "plan");
   p->paired = 1;
-  p->mode = option(SS_OPT_PAIR_JOINT) ? kPairJoint : kPairSplit;
+  p->mode = mode;
   p->M = M;
   p->T = 2 * M;
   p->total_queries = pair_off[M];
-  if (p->mode == kPairJoint) {
+  if (p->mode == kPairJoint || p->mode == kPairInterp) {
     p->S = M;
     p->query_off.assign(pair_off, pair_off + M + 1);
   } else {
@@ -792,7 +892,7 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
     tab_b = std::max(tab_b, align16((size_t)(t_off[j + 1] - t_off[j] + SS_PAD) * 8));
   }
   size_t budget_a, budget_b;
-  if (p->mode == kPairJoint) {
+  if (p->mode == kPairJoint || p->mode == kPairInterp) {
     if (tab_a + tab_b > kPlanLdsBudget) return fail_delete(p, "tables too large for LDS");
     // the bin budget is split in proportion to the two axes' largest tables
     const size_t bins_total = kPlanLdsBudget - tab_a - tab_b;
@@ -819,7 +919,7 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
     if (p->tuned[M + j].algo == SS_ALGO_EXPHASH)
       bins_b = std::max(bins_b, align16((size_t)(p->tuned[M + j].nb + 1) * 2));
   }
-  if (option(SS_OPT_PLAN_LEARNED)) {
+  if (option(SS_OPT_PLAN_LEARNED) && p->mode != kPairInterp) {
     if ((rc = apply_learned(p, rho_tables, t_tables, hr, ht)) != SS_OK)
       return fail_delete(p, nullptr, rc);
     bins_a = bins_b = 0;
@@ -830,7 +930,14 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
         bins_b = std::max(bins_b, align16((size_t)(p->desc[M + j].nb + 1) * 2));
     }
   }
-  if (p->mode == kPairJoint)
+  if (p->mode == kPairInterp) {
+    SS_TRY_HIP(hipMalloc(&p->d_value_off, sizeof(int64_t) * (M + 1)));
+    SS_TRY_HIP(hipMemcpy(p->d_value_off, value_off.data(), sizeof(int64_t) * (M + 1),
+                         hipMemcpyHostToDevice));
+    p->args.values = values;
+    p->args.value_off = p->d_value_off;
+  }
+  if (p->mode == kPairJoint || p->mode == kPairInterp)
     rc = finish_plan(p, rho_tables, t_tables, pool, tab_a, bins_a, tab_b, bins_b);
   else
     rc = finish_plan(p, rho_tables, t_tables, pool, tab_a, std::max(bins_a, bins_b), 0, 0);
@@ -842,11 +949,64 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
   return SS_OK;
 }
 
+}  // namespace
+}  // namespace ss
+
+extern "C" {
+
+int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const double* t_tables,
+                        const int64_t* t_off, int32_t M, const int64_t* pair_off, ss_plan** out) {
+  clear_error();
+  return create_paired(rho_tables, rho_off, t_tables, t_off, M, pair_off,
+                       option(SS_OPT_PAIR_JOINT) ? kPairJoint : kPairSplit, nullptr, out);
+}
+
+int ss_interp_plan_create(const double* rho_tables, const int64_t* rho_off,
+                          const double* t_tables, const int64_t* t_off, int32_t M,
+                          const int64_t* pair_off, const double* values, ss_plan** out) {
+  clear_error();
+  return create_paired(rho_tables, rho_off, t_tables, t_off, M, pair_off, kPairInterp, values,
+                       out);
+}
+
+int ss_interp_search(ss_plan* p, const double* rho, const double* temp, double* out_f,
+                     int32_t* out_rho, int32_t* out_t) {
+  clear_error();
+  if (!p) return fail(SS_ERR_INVALID_ARG, "plan is null");
+  if (p->mode != kPairInterp) return fail(SS_ERR_INVALID_ARG, "not an interpolation plan");
+  if ((out_rho == nullptr) != (out_t == nullptr))
+    return fail(SS_ERR_INVALID_ARG, "out_rho and out_t: both or neither");
+  const int64_t m = p->total_queries;
+  int rc = check_span(rho, m, 8, 8, "rho");
+  if (rc == SS_OK) rc = check_span(temp, m, 8, 8, "temp");
+  if (rc == SS_OK) rc = check_span(out_f, m, 8, 8, "out_f");
+  if (rc == SS_OK && out_rho) rc = check_span(out_rho, m, 4, 4, "out_rho");
+  if (rc == SS_OK && out_t) rc = check_span(out_t, m, 4, 4, "out_t");
+  if (rc != SS_OK) return rc;
+  if (m > 0) {
+    const size_t ib = (size_t)m * 8, ob = (size_t)m * 4;
+    if (overlaps(out_f, ib, rho, ib) || overlaps(out_f, ib, temp, ib) ||
+        (out_rho && (overlaps(out_rho, ob, rho, ib) || overlaps(out_rho, ob, temp, ib) ||
+                     overlaps(out_rho, ob, out_f, ib) || overlaps(out_t, ob, rho, ib) ||
+                     overlaps(out_t, ob, temp, ib) || overlaps(out_t, ob, out_f, ib) ||
+                     overlaps(out_rho, ob, out_t, ob))))
+      return fail(SS_ERR_INVALID_ARG, "outputs overlap inputs or each other");
+    if ((rc = check_device_ptr(rho, "rho")) != SS_OK ||
+        (rc = check_device_ptr(temp, "temp")) != SS_OK ||
+        (rc = check_device_ptr(out_f, "out_f")) != SS_OK ||
+        (out_rho && (rc = check_device_ptr(out_rho, "out_rho")) != SS_OK) ||
+        (out_t && (rc = check_device_ptr(out_t, "out_t")) != SS_OK))
+      return rc;
+  }
+  return run_plan(p, rho, out_rho, temp, out_t, out_f);
+}
+
 int ss_pair_search(ss_plan* p, const double* rho, const double* temp, int32_t* out_rho,
                    int32_t* out_t) {
   clear_error();
   if (!p) return fail(SS_ERR_INVALID_ARG, "plan is null");
   if (!p->paired) return fail(SS_ERR_INVALID_ARG, "batched plan: use ss_multi_search");
+  if (p->mode == kPairInterp) return fail(SS_ERR_INVALID_ARG, "interpolation plan: use ss_interp_search");
   const int64_t m = p->total_queries;
   int rc = check_span(rho, m, 8, 8, "rho");
   if (rc == SS_OK) rc = check_span(temp, m, 8, 8, "temp");
