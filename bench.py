@@ -384,6 +384,45 @@ def measure_small_m(torch, binding, inputs, dev) -> dict:
     return {"unit": "us per call (graph-replayed)", **res}
 
 
+def measure_interp(torch, binding, inputs, dev) -> dict:
+    """1024 materials with SESAME-sized axes (50..150 x 20..100 points) and
+    value grids; 1e9 (rho, T) pairs searched and interpolated in one launch.
+    Algorithmic bytes: 24 per pair (two float64 targets in, one float64
+    value out); with the two int32 indices also written, 32."""
+    it = inputs.interp_layout()
+    p = it.pairs
+    m = p.num_pairs
+    hr = torch.empty(m, dtype=torch.float64).pin_memory()
+    ht = torch.empty(m, dtype=torch.float64).pin_memory()
+    inputs.paired_targets(p, out_rho=hr.numpy(), out_t=ht.numpy())
+    r, t = hr.to(dev), ht.to(dev)
+    del hr, ht
+    f = torch.empty(m, dtype=torch.float64, device=dev)
+    plan = binding.InterpPlan(torch.from_numpy(p.rho.tables).to(dev), p.rho.table_off,
+                              torch.from_numpy(p.temp.tables).to(dev), p.temp.table_off,
+                              p.rho.query_off, torch.from_numpy(it.values).to(dev))
+    ms = time_call(torch, lambda: plan.interpolate(r, t, f), reps=3)
+    gbs = 24 * m / (ms * 1e-3) / 1e9
+    o_r = torch.empty(m, dtype=torch.int32, device=dev)
+    o_t = torch.empty(m, dtype=torch.int32, device=dev)
+    ms_i = time_call(torch, lambda: plan.interpolate(r, t, f, o_r, o_t), reps=3)
+    gbs_i = 32 * m / (ms_i * 1e-3) / 1e9
+    info = plan.info()
+    plan.close()
+    del r, t, f, o_r, o_t
+    return {"workload": f"1024 materials (axes 50..150 x 20..100), {m} pairs, bilinear "
+                        "interpolation of each material's value grid",
+            "gpairs_per_s": round(m / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
+            "bytes_per_pair": 24, "achieved_gbs": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "with_indices": {"gpairs_per_s": round(m / (ms_i * 1e-3) / 1e9, 2),
+                             "ms": round(ms_i, 4), "bytes_per_pair": 32,
+                             "achieved_gbs": round(gbs_i, 1),
+                             "frac": round(gbs_i / HBM_PEAK_GBS, 4)},
+            "value_grid_mb": round(it.values.nbytes / 1e6, 1),
+            "tiles_per_wg": info["tiles_per_wg"], "lds_bytes": info["lds_bytes"]}
+
+
 # FP32 work of one learned-index query: the MLP's 32 + 1024 + 32 multiply-adds
 # (2 flops each); the window check and bisection are not counted.  The 1024
 # of layer 2 run on the matrix cores (FP32 MFMA), the rest on the vector ALUs;
@@ -572,6 +611,9 @@ def main():
         torch.cuda.empty_cache()
         log("bench: paired plan")
         result["paired"] = measure_paired(torch, binding, inputs, dev)
+        torch.cuda.empty_cache()
+        log("bench: interpolation after the paired search")
+        result["interp"] = measure_interp(torch, binding, inputs, dev)
         torch.cuda.empty_cache()
         log("bench: learned index")
         result["learned"] = measure_learned(torch, binding, inputs, dev)

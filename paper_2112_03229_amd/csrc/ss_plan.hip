@@ -94,6 +94,8 @@ struct MultiArgs {
   const int64_t* value_off;
   double* of;
   int store_idx;
+  int lds_grid;      // byte offset of the staged value grid in LDS
+  int grid_cap;      // grids of at most this many values are staged in LDS
 };
 
 // What a workgroup keeps about the table it has staged.
@@ -222,6 +224,23 @@ __device__ __forceinline__ void interpolate(const double* sa, int na, const doub
   }
 }
 
+// Where a material's value grid is read from: staged in LDS when it fits
+// (each workgroup copies it once; the corner reads then cost LDS bandwidth
+// instead of two L2 lines per pair), else from global memory.
+struct Grid {
+  const double* g;   // global grid
+  const double* l;   // LDS copy, or null
+};
+
+__device__ __forceinline__ Grid stage_grid(const MultiArgs& a, int seg, int nr, int nt,
+                                           double* lds_grid) {
+  const double* g = a.values + a.value_off[seg];
+  const int count = nr * nt;
+  if (count > a.grid_cap) return {g, nullptr};
+  for (int i = threadIdx.x; i < count; i += blockDim.x) lds_grid[i] = g[i];
+  return {g, lds_grid};
+}
+
 template <int Q>
 __device__ __forceinline__ void store_tile_f64(double* __restrict__ out, int64_t m, int64_t base,
                                                int nt, bool full, const double (&v)[Q]) {
@@ -283,12 +302,13 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
   }
 
   Staged sta, stb{};
-  const double* grid = nullptr;
-  if constexpr (INTERP) grid = a.values + a.value_off[sg.seg];
+  Grid grid{nullptr, nullptr};
+  double* lds_grid = reinterpret_cast<double*>(lds + a.lds_grid);
   sta = stage_desc(a.desc[sg.seg], SPLIT && sg.part ? a.tables_b : a.tables_a, a.bins, a.params,
                    sa, Ca, Ma);
   if constexpr (PAIRED)
     stb = stage_desc(a.desc[a.pair_base + sg.seg], a.tables_b, a.bins, a.params, sb, Cb, Mb);
+  if constexpr (INTERP) grid = stage_grid(a, sg.seg, sta.n, stb.n, lds_grid);
   __syncthreads();
   int fallbacks = 0;
   for (int64_t j = j0; j < j1; ++j) {
@@ -314,7 +334,10 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
       int rt[Q];
       search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, cb, rt, fell);
       double f[Q];
-      interpolate<Q>(sa, sta.n, sb, stb.n, grid, ca, cb, r, rt, f);
+      if (grid.l)  // uniform: the grid of the workgroup's current material
+        interpolate<Q>(sa, sta.n, sb, stb.n, grid.l, ca, cb, r, rt, f);
+      else
+        interpolate<Q>(sa, sta.n, sb, stb.n, grid.g, ca, cb, r, rt, f);
       store_tile_f64<Q>(a.of, cur.q1, cur.q0 + threadIdx.x, nt, full, f);
       if (a.store_idx) {
         store_tile<Q>(a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
@@ -334,10 +357,10 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
       __syncthreads();  // every lane is done with the old table
       sta = stage_desc(a.desc[sg1.seg], SPLIT && sg1.part ? a.tables_b : a.tables_a, a.bins,
                        a.params, sa, Ca, Ma);
-      if constexpr (INTERP) grid = a.values + a.value_off[sg1.seg];
       if constexpr (PAIRED)
         stb = stage_desc(a.desc[a.pair_base + sg1.seg], a.tables_b, a.bins, a.params, sb, Cb,
                          Mb);
+      if constexpr (INTERP) grid = stage_grid(a, sg1.seg, sta.n, stb.n, lds_grid);
       __syncthreads();
     }
     sg = sg1;
@@ -394,6 +417,7 @@ struct ss_plan {
   int64_t split = 0;             // kPairSplit: offset of the temperature segments' targets
   bool convention = false;       // the paper's convention (SS_OPT_CONVENTION at creation)
   int64_t* d_value_off = nullptr;  // kPairInterp: first value of each material's grid
+  int grid_cap = 0;                // kPairInterp: largest grid (values) staged in LDS
   int32_t T = 0;                 // descriptors (batched: tables; paired: 2 * materials)
   int32_t M = 0;                 // materials (paired)
   int32_t S = 0;                 // segments: tables (batched), materials (joint paired) or
@@ -449,6 +473,10 @@ constexpr int kXcds = 8;                  // accelerator complex dies of an MI35
 // LDS a plan's workgroup may use (tables + bin tables): three 512-thread
 // workgroups per CU fit in 160 KB.
 constexpr size_t kPlanLdsBudget = 48 * 1024;
+// Interpolation plans stage a material's value grid in LDS when it has at
+// most this many float64 values (72 KB: two 512-thread workgroups per CU
+// with their axes).
+constexpr int64_t kInterpGridLdsValues = 9216;
 
 int check_offsets(const int64_t* off, int32_t T, const char* name, int64_t max_len) {
   if (!off) return fail(SS_ERR_INVALID_ARG, std::string(name) + " is null");
@@ -614,6 +642,13 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
 
   p->lds = lds_tab_a + lds_bins_a + lds_tab_b + lds_bins_b;
   const bool learned = p->learned_tables > 0;
+  if (p->mode == kPairInterp && p->grid_cap > 0) {
+    p->args.lds_grid = (int)p->lds;
+    p->args.grid_cap = p->grid_cap;
+    p->lds += (size_t)p->grid_cap * sizeof(double);
+    SS_TRY_HIP(hipFuncSetAttribute(plan_kernel(p->mode, false, false),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds));
+  }
   int model_a = (int)p->lds, model_b = (int)p->lds;
   if (learned) {  // one model image per staged table
     p->lds += kModelBytes;
@@ -843,7 +878,7 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
   if (nr > 0) SS_TRY_HIP(hipMemcpyAsync(hr.data(), rho_tables, 8 * nr, hipMemcpyDeviceToHost, st));
   if (ntt > 0) SS_TRY_HIP(hipMemcpyAsync(ht.data(), t_tables, 8 * ntt, hipMemcpyDeviceToHost, st));
   SS_TRY_HIP(hipStreamSynchronize(st));
-  int64_t nvalues = 0;
+  int64_t nvalues = 0, grid_cap_needed = 0;
   std::vector<int64_t> value_off;
   if (mode == kPairInterp) {
     // every axis needs a cell: at least 2 strictly increasing finite entries
@@ -862,6 +897,10 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
       value_off[j + 1] = value_off[j] + len[0] * len[1];
     }
     nvalues = value_off[M];
+    for (int j = 0; j < M; ++j) {
+      const int64_t count = value_off[j + 1] - value_off[j];
+      if (count <= kInterpGridLdsValues) grid_cap_needed = std::max(grid_cap_needed, count);
+    }
     if ((rc = check_span(values, nvalues, 8, 8, "values")) != SS_OK) return rc;
     if ((rc = check_device_ptr(values, "values")) != SS_OK) return rc;
   }
@@ -869,6 +908,7 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
   if (!p) return fail(SS_ERR_OOM, "plan");
   p->paired = 1;
   p->mode = mode;
+  p->grid_cap = (int)grid_cap_needed;
   p->M = M;
   p->T = 2 * M;
   p->total_queries = pair_off[M];
