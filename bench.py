@@ -103,8 +103,8 @@ def cpu_baseline(tables, host_targets, budget_s: float = 15.0):
             _, used = oracle.search_lt(table, sample, threads=threads, return_threads=True)
             total_s += time.perf_counter() - t0
             total_q += per_pair
-    # the paper's own setting: one core (a quarter of the time budget)
-    per_pair1 = int(min(M, max(10000, budget_s / 4 / (per_q * threads))))
+    # the paper's own setting: one core (half the time budget)
+    per_pair1 = int(min(M, max(10000, budget_s / 2 / (per_q * threads))))
     q1, s1 = 0, 0.0
     for table in tables:
         for order in ORDERS:
