@@ -5,15 +5,16 @@
 // Every table's targets are cut into tiles at absolute multiples of
 // blockDim.x * Q target positions (so a table's first and last tiles may be
 // short and every other tile is aligned: its loads and stores cover whole
-// cache lines), and the tiles of all tables are numbered back to back.  Workgroup w of the grid searches the k
-// consecutive tiles [w k, (w+1) k) -- k is the tile shape the tuner picks --
-// so the grid is several times the resident workgroup count and the
-// hardware dispatcher balances it, exactly like the single-table launch.  A
-// workgroup stages the table of its first tile (copying the table and its
-// precomputed bin table from global memory into LDS) after requesting that
-// tile's targets, and restages only when its range crosses into the next
-// table.  Tiles are streamed with the next tile prefetched.  No atomics,
-// no work queue: a plan is one kernel node in its graph.
+// cache lines), and the tiles of all tables are numbered back to back.  Each
+// workgroup searches up to k consecutive tiles of one segment (k is the
+// tile shape the tuner picks; a segment's last workgroup may take fewer), so
+// the grid is several times the resident workgroup count and the hardware
+// dispatcher balances it, exactly like the single-table launch.  A
+// workgroup stages its segment's table (copying the table and its
+// precomputed bin table from global memory into LDS) after requesting its
+// first tile's targets, once.  Tiles are streamed with the next two tiles
+// prefetched.  No atomics, no work queue: a plan is one kernel node in its
+// graph.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -42,15 +43,17 @@ struct TableDesc {
 };
 
 // Everything a workgroup needs to issue its first target loads, in one
-// 32-byte record: its first tile's target range, its segment's target end
-// and how many of its tiles lie in that segment.
+// 32-byte record: its segment's target range and tile count, and which of
+// the segment's tiles it searches.  Workgroup ranges are cut at segment
+// boundaries (the last workgroup of a segment may take fewer tiles), so a
+// workgroup stages one table once and never restages mid-range.
 struct WgStart {
   int64_t seg_q0;    // the segment's first target
   int64_t seg_q1;    // end of the segment's targets
-  int32_t seg;       // segment (table or material) of the first tile
-  int32_t first;     // index of the first tile within the segment
+  int32_t seg;       // segment (table or material)
+  int32_t first;     // index of the workgroup's first tile within the segment
   int32_t seg_tiles; // tiles of the segment
-  int32_t pad_;
+  int32_t count;     // tiles of this workgroup
 };
 
 // Launch forms of the plan kernel.
@@ -281,10 +284,10 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
     wid = (blockIdx.x % a.xcd_groups) * per + blockIdx.x / a.xcd_groups;
   }
   if (wid >= a.num_wg) return;
-  const int64_t j0 = (int64_t)wid * a.tiles_per_wg;
-  const int64_t j1 = min(j0 + (int64_t)a.tiles_per_wg, a.total_tiles);
-  if (j0 >= j1) return;
   const WgStart ws = a.wg_start[wid];
+  const int64_t j0 = a.tile_off[ws.seg] + ws.first;
+  const int64_t j1 = j0 + ws.count;
+  if (j0 >= j1) return;
   // Tiles j, j+1 and j+2 are in flight at once: the targets of the two
   // tiles after the one being searched are already being loaded.
   Segment sg{ws.seg, SPLIT && ws.seg >= a.pair_base, j0 - ws.first,
@@ -667,8 +670,26 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   const int resident = blocks_per_cu(p->kernel, p->block, p->lds) * di.num_cus;
   p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident, S);
   if (option(SS_OPT_PLAN_TILES) > 0) p->tiles_per_wg = (int)option(SS_OPT_PLAN_TILES);
-  const int64_t num_wg =
-      std::max<int64_t>(1, (p->total_tiles + p->tiles_per_wg - 1) / p->tiles_per_wg);
+  // workgroup ranges: up to tiles_per_wg tiles, cut at segment boundaries
+  std::vector<WgStart> wg_start;
+  for (int s = 0; s < S; ++s) {
+    const int64_t tiles = tile_off[s + 1] - tile_off[s];
+    for (int64_t f = 0; f < tiles; f += p->tiles_per_wg) {
+      WgStart st;
+      st.seg = s;
+      st.seg_q0 = p->query_off[s] - seg_base(s);
+      st.seg_q1 = p->query_off[s + 1] - seg_base(s);
+      st.first = (int32_t)f;
+      st.seg_tiles = (int32_t)tiles;
+      st.count = (int32_t)std::min<int64_t>(p->tiles_per_wg, tiles - f);
+      wg_start.push_back(st);
+    }
+  }
+  if (wg_start.empty()) {  // no targets: one idle record keeps the launch valid
+    WgStart st{0, 0, 0, 0, 0, 0};
+    wg_start.push_back(st);
+  }
+  const int64_t num_wg = (int64_t)wg_start.size();
   const int xcd = (int)option(SS_OPT_PLAN_XCD);
   const int groups = xcd == 1 ? 1 : kXcds;
   const int64_t grid = (num_wg + groups - 1) / groups * groups;
@@ -676,21 +697,6 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   p->grid = (int)grid;
   p->num_wg = (int)num_wg;
   p->xcd_groups = groups;
-  std::vector<WgStart> wg_start(p->num_wg);
-  {
-    int s = 0;
-    for (int w = 0; w < p->num_wg; ++w) {
-      const int64_t j = (int64_t)w * p->tiles_per_wg;
-      while (s < S - 1 && j >= tile_off[s + 1]) ++s;
-      WgStart& st = wg_start[w];
-      st.seg = s;
-      st.seg_q0 = p->query_off[s] - seg_base(s);
-      st.seg_q1 = p->query_off[s + 1] - seg_base(s);
-      st.first = (int32_t)(j - tile_off[s]);
-      st.seg_tiles = (int32_t)(tile_off[s + 1] - tile_off[s]);
-      st.pad_ = 0;
-    }
-  }
   SS_TRY_HIP(hipMalloc(&p->d_tile_off, sizeof(int64_t) * (S + 1)));
   SS_TRY_HIP(hipMalloc(&p->d_query_off, sizeof(int64_t) * (S + 1)));
   SS_TRY_HIP(hipMalloc(&p->d_wg_start, sizeof(WgStart) * p->num_wg));
