@@ -234,7 +234,12 @@ SS_API int ss_loghash_bins(const double *table, int64_t n, int64_t nb, int32_t *
  * exponent-hash bin tables on the device, and prepares a HIP graph whose
  * one kernel node searches the whole batch.  Plans own device memory; the tables
  * are referenced (not copied) and must stay valid and unchanged while the
- * plan is used.  A plan may be used from one thread at a time.
+ * plan is used.  A plan may be used from one thread at a time, and its
+ * searches run in the order they are issued on the caller's stream; passing
+ * new target or output pointers updates the graph's kernel parameters in
+ * place, so searches of one plan must not be issued on two streams at once.
+ * Destroy a plan only after its last search has completed (synchronise the
+ * stream first).
  * ------------------------------------------------------------------------- */
 typedef struct ss_plan ss_plan;
 

@@ -977,9 +977,14 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
     }
   }
   if (p->mode == kPairInterp) {
-    SS_TRY_HIP(hipMalloc(&p->d_value_off, sizeof(int64_t) * (M + 1)));
-    SS_TRY_HIP(hipMemcpy(p->d_value_off, value_off.data(), sizeof(int64_t) * (M + 1),
-                         hipMemcpyHostToDevice));
+    hipError_t e = hipMalloc(&p->d_value_off, sizeof(int64_t) * (M + 1));
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_value_off, value_off.data(), sizeof(int64_t) * (M + 1),
+                    hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      delete p;
+      return hip_fail(e, "interpolation value offsets");
+    }
     p->args.values = values;
     p->args.value_off = p->d_value_off;
   }
