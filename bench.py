@@ -126,8 +126,25 @@ def cpu_baseline(tables, host_targets, budget_s: float = 15.0):
         "single_core": {"value": q1 / s1 / 1e9, "unit": "Gqueries/s",
                         "sample": f"{per_pair1} targets per (table, order) pair, "
                                   f"{q1} queries, {s1:.1f} s, 1 thread"},
+        "context_library_bisection": library_bisection(tables, host_targets),
         "host_cpu": _cpu_model(),
     }
+
+
+def library_bisection(tables, host_targets, per_pair: int = 4 * 10**6) -> dict:
+    """Context only (not the baseline): numpy.searchsorted, a library
+    bisection, on one core over a sample of every (table, order) pair."""
+    q, sec = 0, 0.0
+    for table in tables:
+        for order in ORDERS:
+            x = host_targets[order]
+            sample = np.ascontiguousarray(x[:per_pair])
+            t0 = time.perf_counter()
+            np.searchsorted(table, sample, side="left")
+            sec += time.perf_counter() - t0
+            q += per_pair
+    return {"value": q / sec / 1e9, "unit": "Gqueries/s", "cores": 1,
+            "kind": "numpy.searchsorted (context)", "sample": f"{q} queries, {sec:.2f} s"}
 
 
 def _cpu_model() -> str:
