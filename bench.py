@@ -4,14 +4,16 @@ Workload (one "step"): three single tables of 100, 300 and 1000 float64
 entries (sorted log-uniform draws on [1e-8, 1e6]), each searched with 1e8
 float64 targets in two orders -- i.i.d. log-uniform on [0.5e-8, 2e6] and a
 smooth sorted random walk in log space -- i.e. six launches of the library's
-automatically chosen kernel, 6e8 queries per step.  Inputs are generated on
-the host, copied to HBM before timing, and stay resident.
+automatically chosen kernel (the staged bisection for these tables), 6e8
+queries per step.  Inputs are generated on the host, copied to HBM before
+timing, and stay resident.
 
 Output: one JSON line with whole-job throughput in Gqueries/s (12 algorithmic
 bytes per query: an 8-byte target read, a 4-byte index written), the HBM
-roofline fraction of the dominant kernel (timed per launch with HIP events on
-the launch stream), per-kernel comparisons on the same data, and the CPU
-oracle timed on the host's cores over a bounded sample.
+roofline fraction of the dominant kernel (its average launch duration from
+HIP events on the launch stream around the timed region), per-kernel
+comparisons on the same data, and the CPU oracle timed on the host's cores
+over a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-kernels]
 """
@@ -172,11 +174,17 @@ def copy_calibration(torch) -> None:
     print(json.dumps({"copy_calibration_bytes": n * 8, "dispatches": 3}), flush=True)
 
 
-def time_call(torch, fn, reps: int = 5, warm: int = 3) -> float:
-    """Average milliseconds of fn() over reps calls on the current stream
-    (after `warm` untimed calls: the first passes over freshly allocated
-    multi-GB buffers run several percent slower)."""
-    for _ in range(warm):
+def time_call(torch, fn, reps: int = 5, warm_ms: float = 50.0) -> float:
+    """Average milliseconds of fn() over reps calls on the current stream,
+    after untimed calls that keep the GPU busy for at least warm_ms: after
+    an idle period (host-side input generation) MI355X takes ~20 ms of load
+    to reach its steady clocks, and first passes over freshly allocated
+    multi-GB buffers run slower."""
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    for _ in range(min(1000, max(2, int(warm_ms / max(first_ms, 1e-3)) + 1))):
         fn()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -482,8 +490,8 @@ def measure_learned(torch, binding, inputs, dev) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-kernels", action="store_true",
                     help="skip the per-kernel comparison after the timed region")
@@ -528,13 +536,9 @@ def main():
     pairs = [(i, o) for i in range(len(TABLE_SIZES)) for o in ORDERS]
     stream = torch.cuda.current_stream()
 
-    def step(events=None):
-        for j, (i, o) in enumerate(pairs):
-            if events is not None:
-                events[j][0].record(stream)
+    def step():
+        for i, o in pairs:
             binding.search_sorted_batch(d_tables[i], d_x[o], d_out[(TABLE_SIZES[i], o)])
-            if events is not None:
-                events[j][1].record(stream)
 
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -542,23 +546,30 @@ def main():
     torch.cuda.synchronize()
 
     log(f"bench: timing {args.steps} steps")
-    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)]
-           for _ in pairs] for _ in range(args.steps)]
+    # One pair of HIP events on the launch stream around the whole timed
+    # region: the launches run back to back, and the average launch
+    # duration is the region's event time over the launch count.  (An event
+    # pair around every launch puts a marker between consecutive kernels,
+    # which idles the GPU for ~10 us each time.)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        step(ev[s])
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launch_ms = [e[0].elapsed_time(e[1]) for st in ev for e in st]
-    avg_launch_ms = float(np.mean(launch_ms))
+    avg_launch_ms = ev0.elapsed_time(ev1) / (args.steps * len(pairs))
     queries_per_step = len(pairs) * M
     ms_per_step = wall * 1e3 / args.steps
     value = queries_per_step * args.steps / wall / 1e9
 
-    kernel = "single_kernel<exphash>"
+    # the automatic choice for these tables (staged bisection)
+    kernel = "single_kernel<binary>"
     achieved = M * BYTES_PER_QUERY / (avg_launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic("single_kernel<exphash>|single-1e8")
+    traffic = measured_traffic("single_kernel<binary>|single-1e8")
     result = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -575,7 +586,7 @@ def main():
         "config": {
             "workload": "single tables n=100,300,1000 (log-uniform on [1e-8,1e6]); "
                         "1e8 float64 targets per table and order; orders: i.i.d. log-uniform "
-                        "and smooth sorted walk; automatically chosen kernel",
+                        "and smooth sorted walk; automatically chosen kernel (staged bisection)",
             "tables": list(TABLE_SIZES),
             "targets_per_launch": M,
             "launches_per_step": len(pairs),
@@ -600,17 +611,9 @@ def main():
         for (i, o) in pairs:
             row = {}
             for algo in ("binary", "ballot", "exphash", "loghash", "skiplist"):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
                 out = d_out[(TABLE_SIZES[i], o)]
-                binding.search_with(d_tables[i], d_x[o], algo, -1, out)
-                e0.record(stream)
-                reps = 3
-                for _ in range(reps):
-                    binding.search_with(d_tables[i], d_x[o], algo, -1, out)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / reps
+                ms = time_call(torch, lambda: binding.search_with(d_tables[i], d_x[o], algo, -1,
+                                                                  out), reps=5, warm_ms=20.0)
                 row[algo] = round(M / (ms * 1e-3) / 1e9, 2)
             comp[f"n={TABLE_SIZES[i]}/{o}"] = row
         result["kernels_gqps"] = comp

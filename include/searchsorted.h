@@ -166,10 +166,11 @@ SS_API int ss_get_option(int option, int64_t *value_out /* host */);
  *   targets : m float64 values, device, 8-byte aligned, any values
  *   m       : m >= 0; m == 0 is a no-op
  *   out_idx : m int32, device, 4-byte aligned, must not overlap the inputs
- * The kernel is chosen from n and m (and SS_OPT_FORCE_ALGO): the exponent
- * hash for non-negative tables that fit in LDS (bin parameters are derived
- * on the device from the table itself) when its per-workgroup bin build is
- * amortised (m >= max(1024 n, 2^22)), bisection otherwise.  Allocates
+ * The kernel is the bisection over the table staged in LDS (or, for
+ * tables over 64 KB, read from global memory) unless SS_OPT_FORCE_ALGO
+ * names another: with one table per call the search is bound by HBM and a
+ * hash's per-workgroup bin build costs more than it saves (plans, which
+ * build each bin table once, choose per table).  Allocates
  * nothing; asynchronous; safe to capture in a HIP graph.  With
  * SS_OPT_CONVENTION = 1 the results follow the paper's convention. */
 SS_API int search_sorted_batch(const double *table, int64_t n, const double *targets, int64_t m,

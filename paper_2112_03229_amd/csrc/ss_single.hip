@@ -3,10 +3,11 @@
 // the global-memory bisection, plus the C ABI entry points search_sorted_batch, ss_search_with,
 // ss_validate_table, ss_exphash_bins and ss_loghash_bins.
 //
-// Launch shape: a persistent grid (enough workgroups to fill every CU at the
-// occupancy the LDS footprint allows).  Each workgroup stages the table once
-// (K3 also builds its bin table in LDS) and then streams tiles of
-// blockDim.x * Q targets: slot q of lane t reads target base + q*blockDim.x + t,
+// Launch shape: at least enough workgroups to fill every CU at the occupancy
+// the LDS footprint allows, and a few tiles per workgroup (more for larger
+// tables and for the hashes, whose setup costs more).  Each workgroup stages
+// the table once (K3 also builds its bin table in LDS) and then streams tiles
+// of blockDim.x * Q targets: slot q of lane t reads target base + q*blockDim.x + t,
 // so every load and store instruction of a wavefront covers one contiguous
 // run (512 B of targets, 256 B of indices).  Targets are read and indices
 // written with non-temporal hints: each byte is touched once.
@@ -22,11 +23,10 @@ namespace ss {
 
 constexpr int kDefaultQ = 8;          // targets per lane per tile
 constexpr int kDefaultBlock = 512;    // threads per workgroup
-// Tiles per workgroup of the default grid.  A grid several times larger
-// than the resident workgroup count lets the dispatcher balance CUs that
-// run at different speeds (a strictly persistent grid loses ~10% to its
-// slowest workgroups); the hashes keep more tiles per workgroup to amortise
-// their per-workgroup bin build.
+// Tiles per workgroup of the default grid (see tiles_per_workgroup).  A
+// grid several times larger than the resident workgroup count lets the
+// dispatcher balance CUs that run at different speeds (a strictly
+// persistent grid loses ~10% to its slowest workgroups).
 constexpr int kTilesPerBlockHash = 6;
 constexpr int kTilesPerBlockOther = 3;
 constexpr size_t kStageLimit = 65536; // LDS bytes a single-table launch may use
@@ -169,23 +169,23 @@ struct SinglePlan {
 
 // Chooses the kernel and its LDS layout.  Returns SS_OK or an error for a
 // forced kernel that cannot run on this table size.
-// The automatic choice hashes only when its per-workgroup setup (staging
-// the bins' gap fill, two barriers and the longest-bin reduction, O(n)) is
-// amortised over several tiles: m >= max(1024 n, 2^22).  Measured per call
-// on MI355X, 64 calls replayed from a graph, m = 1e2..1e4: n = 110,
-// bisection 3.7 us, exponent hash 5.4 us; n = 4000, 5.6 us against 11.3 us.
-// At 1e8 targets the two are within 3%.
-constexpr int64_t kHashMinTargetsPerEntry = 1024;
-constexpr int64_t kHashMinTargets = int64_t(1) << 22;
-
-static int plan_single(int64_t n, int64_t m, int algo, int cap_opt, SinglePlan* p) {
+//
+// The automatic choice is the staged bisection whenever the table fits in
+// LDS.  Measured on MI355X with 1e8 i.i.d. log-uniform targets, each kernel
+// at its best tiles per workgroup: n = 100, bisection 545 Gq/s against 512
+// for the exponent hash; n = 1000, 522 against 500; n = 2000, 497 against
+// 481; n = 4000, 474 against 444.  Small m gives the same order
+// (64 graph-replayed calls of 1e2..1e4 targets: n = 110, 3.7 against 5.4
+// us per call; n = 4000, 5.6 against 11.3 us).  With the table in LDS the
+// search is bound by HBM either way, and each workgroup's bin build (gap
+// fill, two barriers, the longest-bin reduction) costs more than the few
+// LDS probes it saves.  Plans, whose bin tables are built once per table
+// and only copied by each workgroup, are where the hash wins (their tuner
+// chooses per table).
+static int plan_single(int64_t n, int algo, int cap_opt, SinglePlan* p) {
   const size_t tab_bytes = align_up((size_t)(n + SS_PAD) * sizeof(double), 16);
   const bool stageable = tab_bytes <= kStageLimit;
-  if (algo == SS_ALGO_AUTO) {
-    const bool amortised = m >= std::max(kHashMinTargetsPerEntry * n, kHashMinTargets);
-    if (n >= 1 && n <= 65535 && stageable && amortised) algo = SS_ALGO_EXPHASH;
-    else algo = stageable ? SS_ALGO_BINARY : SS_ALGO_BINARY_GLOBAL;
-  }
+  if (algo == SS_ALGO_AUTO) algo = stageable ? SS_ALGO_BINARY : SS_ALGO_BINARY_GLOBAL;
   // an empty table is answered by the staged bisection (its +inf sentinel
   // makes every count 0) so that no kernel reads a zero-length table
   if (n == 0) algo = SS_ALGO_BINARY;
@@ -220,6 +220,18 @@ static int plan_single(int64_t n, int64_t m, int algo, int cap_opt, SinglePlan* 
     }
   }
   return SS_OK;
+}
+
+// Tiles each workgroup of the default grid streams.  The staged bisection
+// pays one table copy per workgroup, so small tables take the finest grid:
+// measured on MI355X (512 x 8 targets per tile, 1e8 targets, Gq/s at 1 / 2
+// / 3 / 4 / 6 tiles): n = 100, 545 / 533 / 517 / 508 / 486; n = 1000, 457 /
+// 522 / 517 / 505 / 482; n = 2000, 415 / 493 / 497 / 495 / 483; n = 4000,
+// 349 / 445 / 471 / 472 / 474.  The hashes also amortise their bin build.
+static int tiles_per_workgroup(int algo, int64_t n) {
+  if (algo == SS_ALGO_BINARY) return n <= 128 ? 1 : n <= 1024 ? 2 : n <= 2048 ? 3 : 4;
+  if (algo == SS_ALGO_EXPHASH || algo == SS_ALGO_LOGHASH) return kTilesPerBlockHash;
+  return kTilesPerBlockOther;
 }
 
 template <int Q, int CONV>
@@ -266,7 +278,7 @@ int launch_single(const double* table, int64_t n, const double* x, int64_t m, in
   DeviceInfo di;
   if ((rc = device_info(&di)) != SS_OK) return rc;
   SinglePlan p;
-  if ((rc = plan_single(n, m, algo, (int)option(SS_OPT_BUCKET_CAP), &p)) != SS_OK) return rc;
+  if ((rc = plan_single(n, algo, (int)option(SS_OPT_BUCKET_CAP), &p)) != SS_OK) return rc;
   int nt = (int)option(SS_OPT_BLOCK_SIZE);
   if (nt == 0) nt = kDefaultBlock;
   int q = (int)option(SS_OPT_TARGETS_PER_LANE);
@@ -279,9 +291,7 @@ int launch_single(const double* table, int64_t n, const double* x, int64_t m, in
   int64_t grid = option(SS_OPT_GRID_BLOCKS);
   if (grid <= 0) {
     const int64_t resident = (int64_t)blocks_per_cu(kern, nt, p.lds) * di.num_cus;
-    const int tpb = (p.algo == SS_ALGO_EXPHASH || p.algo == SS_ALGO_LOGHASH) ? kTilesPerBlockHash
-                                                                             : kTilesPerBlockOther;
-    grid = std::max<int64_t>(resident, ntiles / tpb);
+    grid = std::max<int64_t>(resident, ntiles / tiles_per_workgroup(p.algo, n));
   }
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
   SingleArgs a{table, x, out, m, (int)n, bits, p.cap, p.c_off, p.scr_off};

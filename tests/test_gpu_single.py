@@ -303,15 +303,17 @@ def test_non_default_stream_and_graph_replay(binding, gpu, oracle_mod, inputs_mo
         assert np.array_equal(out2.cpu().numpy(), want), r
 
 
-def test_full_size_loghash(binding, gpu, oracle_mod, inputs_mod):
-    """The log hash forced on the 1000-entry table with 1e8 targets."""
+@pytest.mark.parametrize("algo", ["exphash", "loghash", "skiplist", "ballot"])
+def test_full_size_forced(binding, gpu, oracle_mod, inputs_mod, algo):
+    """Each kernel the automatic choice does not take, forced on the
+    1000-entry table with 1e8 targets in its default launch shape."""
     table = inputs_mod.single_table(1000)
     m = 10**8
     t = torch.from_numpy(table).to(gpu)
     host = torch.empty(m, dtype=torch.float64).pin_memory()
     inputs_mod.table_targets(table, m, seed=11, out=host.numpy())
-    say("case full loghash n=1000")
-    out = binding.search_with(t, host.to(gpu), "loghash")
+    say(f"case full {algo} n=1000")
+    out = binding.search_with(t, host.to(gpu), algo)
     got = out.cpu().numpy()
     x = host.numpy()
     bad, first = oracle_mod.check_bracket(table, x, got)
