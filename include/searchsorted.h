@@ -118,8 +118,13 @@ typedef enum {
     SS_OPT_LEARNED_STEPS = 10,   /* Adam steps of plan models; 0 (default)
                                     = 500 */
     SS_OPT_PLAN_XCD = 11,        /* workgroup-to-XCD mapping of plans built
-                                    afterwards: 0 (default) = contiguous
-                                    tile ranges per XCD, 1 = dispatch order */
+                                    afterwards: the workgroup ranges are
+                                    dealt to the 8 XCDs round robin in
+                                    chunks of C consecutive ranges.  0
+                                    (default): C = 8; 1: dispatch order
+                                    (C = 1); 2..2^24: C = the value (a C of
+                                    at least a 1/8 of the ranges gives each
+                                    XCD one contiguous part) */
     SS_OPT_PAIR_JOINT = 12,      /* paired plans built afterwards: 0
                                     (default) = the density and temperature
                                     searches run as 2M independent segments

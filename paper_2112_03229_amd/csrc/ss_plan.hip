@@ -84,6 +84,7 @@ struct MultiArgs {
   int tiles_per_wg;
   int num_wg;                // workgroups with work (the grid may be padded)
   int xcd_groups;            // > 1: workgroup ids remapped per XCD (see below)
+  int xcd_chunk;             // consecutive workgroups an XCD takes per turn
   int pair_base;             // index of the first temperature descriptor (paired)
   int64_t split;             // kPairSplit: temperature segments' targets start here in
                              // the segment offsets (targets of segment s >= pair_base
@@ -273,15 +274,22 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
   float* Mb = reinterpret_cast<float*>(lds + a.lds_model_b);
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
-  // Workgroup b runs on XCD b mod X (the dispatcher's round robin).  With
-  // X = xcd_groups > 1 the grid is padded to a multiple of X and block b
-  // takes logical range (b mod X) * (grid / X) + b / X, so each XCD sweeps
-  // one contiguous part of the tile space and the tables it stages stay in
-  // its own L2.
+  // Workgroup b runs on XCD b mod X (the dispatcher's round robin) as that
+  // XCD's i-th workgroup, i = b / X.  With X = xcd_groups > 1 (the grid
+  // padded to a multiple of X) the workgroup ranges are dealt to the XCDs in
+  // chunks of C = xcd_chunk consecutive ranges: XCD x takes chunks x, x + X,
+  // x + 2X, ..., so neighbouring ranges, which mostly share a table, run on
+  // one XCD and find it in that XCD's L2, while every XCD still receives an
+  // even mix of the whole plan (large and small tables alike).  The slots
+  // past the last whole chunk keep dispatch order.  A bijection on
+  // [0, grid): chunk slots map onto [0, X * full), the rest onto
+  // [X * full, grid).
   int wid = blockIdx.x;
   if (a.xcd_groups > 1) {
-    const int per = gridDim.x / a.xcd_groups;
-    wid = (blockIdx.x % a.xcd_groups) * per + blockIdx.x / a.xcd_groups;
+    const int X = a.xcd_groups, C = a.xcd_chunk;
+    const int x = blockIdx.x % X, i = blockIdx.x / X;
+    const int full = gridDim.x / X / C * C;
+    wid = i < full ? ((i / C) * X + x) * C + i % C : X * full + (i - full) * X + x;
   }
   if (wid >= a.num_wg) return;
   const WgStart ws = a.wg_start[wid];
@@ -441,7 +449,7 @@ struct ss_plan {
   int learned_tables = 0;
   int64_t total_tiles = 0;
   int tiles_per_wg = 0;
-  int num_wg = 0, xcd_groups = 1;
+  int num_wg = 0, xcd_groups = 1, xcd_chunk = 1;
   int grid = 0, block = 0, q = 0;
   size_t lds = 0;
   int max_k = 0;
@@ -473,6 +481,12 @@ constexpr int kPairQ = 4;
 constexpr int kLearnedPlanQ = 2;          // the model's registers limit Q
 constexpr int kDefaultPlanLearnedSteps = 500;
 constexpr int kXcds = 8;                  // accelerator complex dies of an MI355X
+// Default workgroup ranges per XCD turn.  Measured on MI355X, chunks of 1 /
+// 8 / 64 / one contiguous part per XCD: 512-table batch 5.97 / 6.03 / 5.90 /
+// 5.89 TB/s; 4096-material paired workload 5.71 / 5.70 / 5.66 / 5.47.  A
+// contiguous part per XCD gives the dies unequal work (the paired plan's
+// density segments, with the larger tables, come first).
+constexpr int kXcdChunk = 8;
 // LDS a plan's workgroup may use (tables + bin tables): three 512-thread
 // workgroups per CU fit in 160 KB.
 constexpr size_t kPlanLdsBudget = 48 * 1024;
@@ -690,13 +704,15 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
     wg_start.push_back(st);
   }
   const int64_t num_wg = (int64_t)wg_start.size();
-  const int xcd = (int)option(SS_OPT_PLAN_XCD);
+  const int64_t xcd = option(SS_OPT_PLAN_XCD);
   const int groups = xcd == 1 ? 1 : kXcds;
   const int64_t grid = (num_wg + groups - 1) / groups * groups;
   if (grid > INT32_MAX) return fail(SS_ERR_INVALID_ARG, "too many tiles for one launch");
   p->grid = (int)grid;
   p->num_wg = (int)num_wg;
   p->xcd_groups = groups;
+  p->xcd_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(xcd >= 2 ? xcd : kXcdChunk,
+                                                            grid / groups));
   SS_TRY_HIP(hipMalloc(&p->d_tile_off, sizeof(int64_t) * (S + 1)));
   SS_TRY_HIP(hipMalloc(&p->d_query_off, sizeof(int64_t) * (S + 1)));
   SS_TRY_HIP(hipMalloc(&p->d_wg_start, sizeof(WgStart) * p->num_wg));
@@ -721,6 +737,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   a.tiles_per_wg = p->tiles_per_wg;
   a.num_wg = p->num_wg;
   a.xcd_groups = p->xcd_groups;
+  a.xcd_chunk = p->xcd_chunk;
   a.pair_base = p->paired ? p->M : 0;
   a.split = p->split;
   a.lds_bins_a = (int)lds_tab_a;

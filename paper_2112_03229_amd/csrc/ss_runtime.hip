@@ -211,7 +211,8 @@ int ss_set_option(int opt, int64_t v) {
       ss::g_learned_steps = v;
       return SS_OK;
     case SS_OPT_PLAN_XCD:
-      if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PLAN_XCD: 0 or 1");
+      if (v < 0 || v > (int64_t(1) << 24))
+        return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PLAN_XCD: expected 0..2^24");
       ss::g_plan_xcd = v;
       return SS_OK;
     case SS_OPT_PAIR_JOINT:

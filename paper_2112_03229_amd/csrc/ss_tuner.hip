@@ -175,17 +175,17 @@ TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bi
 int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident,
                                int segments) {
   (void)model;
-  // Every workgroup stages its first tile's table before searching, so the
-  // tile count per workgroup trades staging stalls against load balance.
-  // Measured on MI355X (steady state, tiles aligned to absolute positions,
-  // two tiles prefetched): 512 tables with ~350 tiles each: 3 tiles per
-  // workgroup 5.87 TB/s, 4: 5.88, 6: 5.79, 8: 5.71, 12: 5.55; 8192 density
-  // and temperature segments with ~30 tiles each: 4: 5.36, 6: 5.44, 8: 5.45,
-  // 12: 5.40, 16: 5.33.  Short segments (under 64 tiles on average) take 8,
-  // long ones 4, reduced while that leaves fewer than ~6 waves of
-  // workgroups.
+  // Every workgroup stages its table before searching, so the tile count
+  // per workgroup trades staging stalls against load balance.  Measured on
+  // MI355X (steady clocks, tiles aligned to absolute positions, two tiles
+  // prefetched, workgroup ranges cut at segment boundaries and dealt to the
+  // XCDs in chunks of 8): 512 tables with ~350 tiles each: 3 tiles per
+  // workgroup 5.92 TB/s, 4: 6.03; 8192 density and temperature segments
+  // with ~60 tiles each: 6: 5.70, 8: 5.63.  Short segments (under 64 tiles
+  // on average) take 6, long ones 4, reduced while that leaves fewer than
+  // ~6 waves of workgroups.
   const int64_t avg = total_tiles / std::max(segments, 1);
-  int64_t k = avg < 64 ? 8 : 4;
+  int64_t k = avg < 64 ? 6 : 4;
   while (k > 1 && total_tiles / k < 6LL * std::max(resident, 1)) --k;
   return (int)k;
 }

@@ -49,10 +49,13 @@ def test_version_and_options(L):
     b.set_option(b.OPT_FORCE_ALGO, b.ALGO_LOGHASH)
     b.set_option(b.OPT_FORCE_ALGO, b.ALGO_SKIPLIST)
     b.set_option(b.OPT_FORCE_ALGO, b.ALGO_AUTO)
+    for v in (1, 2, 16, 1 << 24, 0):
+        b.set_option(b.OPT_PLAN_XCD, v)
+        assert b.get_option(b.OPT_PLAN_XCD) == v
     for opt, bad in ((b.OPT_FORCE_ALGO, 9), (b.OPT_FORCE_ALGO, 8), (b.OPT_FORCE_ALGO, b.ALGO_LEARNED),
                      (b.OPT_BUCKET_BITS, 21), (b.OPT_BLOCK_SIZE, 100),
                      (b.OPT_CHECK_POINTERS, 2), (b.OPT_PAIR_JOINT, 2), (b.OPT_CONVENTION, 2),
-                     (999, 0)):
+                     (b.OPT_PLAN_XCD, -1), (b.OPT_PLAN_XCD, (1 << 24) + 1), (999, 0)):
         with pytest.raises(b.SearchSortedError) as e:
             b.set_option(opt, bad)
         assert e.value.code == -1

@@ -98,6 +98,30 @@ def test_batched_composition(binding, gpu, oracle_mod, inputs_mod):
     plan.close()
 
 
+@pytest.mark.parametrize("xcd", [0, 1, 2, 3, 7, 1 << 24])
+def test_xcd_mappings_cover_every_range(binding, gpu, oracle_mod, inputs_mod, xcd):
+    """Every workgroup-to-XCD mapping (dispatch order, chunks of 2, 3, 7, the
+    default, one contiguous part per XCD) searches every tile exactly once,
+    with grids that are and are not multiples of the chunk."""
+    tables, toff, qoff, x = odd_batch(inputs_mod, seed=17)
+    want = oracle_mod.search_lt_segments(tables, toff, x, qoff)
+    for k in (1, 3):
+        try:
+            binding.set_option(binding.OPT_PLAN_XCD, xcd)
+            binding.set_option(binding.OPT_PLAN_TILES, k)
+            say(f"case xcd={xcd} tiles={k}")
+            plan = binding.MultiPlan(torch.from_numpy(tables).to(gpu), toff, qoff)
+        finally:
+            binding.set_option(binding.OPT_PLAN_XCD, 0)
+            binding.set_option(binding.OPT_PLAN_TILES, 0)
+        out = torch.full((x.size,), -9, dtype=torch.int32, device=gpu)
+        plan.search(torch.from_numpy(x).to(gpu), out)
+        got = out.cpu().numpy()
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, (xcd, k, bad[:5], got[bad[:5]], want[bad[:5]])
+        plan.close()
+
+
 def test_batched_rejects_bad_arguments(binding, gpu, inputs_mod):
     t = torch.from_numpy(inputs_mod.single_table(100)).to(gpu)
     with pytest.raises(binding.SearchSortedError):

@@ -12,7 +12,7 @@ import torch
 pytestmark = pytest.mark.gpu
 
 ALGOS = ["auto", "binary", "ballot", "exphash", "binary_global", "loghash", "skiplist"]
-TILE = 256 * 8           # targets per workgroup tile at the default launch shape
+TILE = 512 * 8           # targets per workgroup tile at the default launch shape
 
 
 def say(*a):
@@ -352,3 +352,34 @@ def test_full_size_single64(binding, gpu, oracle_mod, inputs_mod):
     for algo in ALGOS:
         say(f"case single64 algo={algo}")
         assert np.array_equal(run(binding, gpu, table, x, algo), want), algo
+
+
+@pytest.mark.parametrize("algo", ["auto", "exphash"])
+def test_more_than_2_31_targets(binding, gpu, oracle_mod, inputs_mod, algo):
+    """m = 2^31 + 4111 targets in one call (64-bit target positions): target
+    k is a[k mod n] for even k (idx = k mod n - 1) and the next double above
+    it for odd k (idx = k mod n), checked on the device in chunks; positions
+    around 2^31 and a seeded sample are compared with the oracle."""
+    table = inputs_mod.single_table(100)
+    assert np.all(np.diff(table) > 0)
+    n = table.size
+    m = 2**31 + 4111
+    say(f"case m={m} algo={algo}")
+    t = torch.from_numpy(table).to(gpu)
+    x = torch.empty(m, dtype=torch.float64, device=gpu)
+    chunk = 1 << 28
+    for k0 in range(0, m, chunk):
+        k = torch.arange(k0, min(m, k0 + chunk), device=gpu, dtype=torch.int64)
+        v = t[k % n]
+        x[k0:k0 + k.numel()] = torch.where(k % 2 == 1, torch.nextafter(v, torch.full_like(v, np.inf)), v)
+    out = binding.search_with(t, x, algo)
+    for k0 in range(0, m, chunk):
+        k = torch.arange(k0, min(m, k0 + chunk), device=gpu, dtype=torch.int64)
+        want = (k % n) - 1 + (k % 2)
+        bad = int((out[k0:k0 + k.numel()].to(torch.int64) != want).sum())
+        assert bad == 0, (k0, bad)
+    pos = np.concatenate([np.arange(2**31 - 2048, m), (inputs_mod.uniform(77, 5, 4096) * m).astype(np.int64)])
+    pt = torch.from_numpy(pos).to(gpu)
+    xs = x[pt].cpu().numpy()
+    assert np.array_equal(out[pt].cpu().numpy(), oracle_mod.search_lt(table, xs))
+    del x, out
