@@ -210,7 +210,14 @@ __device__ __forceinline__ void search_tile(const Staged& st, const double* sa, 
 // two searches found (ra over the staged density axis sa, rb over the
 // temperature axis sb): the strict index clamped to the edge cells, the
 // fractional positions u and v (linear extension outside the axes), and
-// the four corner values read from the grid in global memory (L2).
+// the four corner values F read from the grid (LDS or global memory).  The
+// value is formed as two interpolations along the density axis followed by
+// one along the temperature axis, g0 = u f10 + (1 - u) f00, g1 = u f11 +
+// (1 - u) f01, f = v g1 + (1 - v) g0, each a product and a fused
+// multiply-add: the same bilinear function as the four-weight form, to a
+// few units of rounding of (1 + |u|)(1 + |v|) sum |F|, in fewer float64
+// operations, and exact at the grid nodes (u and v in {0, 1}; a target
+// equal to a node lands in the cell below it with u = 1).
 template <int Q>
 __device__ __forceinline__ void interpolate(const double* sa, int na, const double* sb, int nb,
                                             const double* __restrict__ F, const double (&r)[Q],
@@ -224,7 +231,9 @@ __device__ __forceinline__ void interpolate(const double* sa, int na, const doub
     const double* row0 = F + (int64_t)i * nb + k;
     const double* row1 = row0 + nb;
     const double f00 = row0[0], f01 = row0[1], f10 = row1[0], f11 = row1[1];
-    f[q] = (1.0 - u) * (1.0 - v) * f00 + u * (1.0 - v) * f10 + (1.0 - u) * v * f01 + u * v * f11;
+    const double u1 = 1.0 - u, v1 = 1.0 - v;
+    const double g0 = fma(u, f10, u1 * f00), g1 = fma(u, f11, u1 * f01);
+    f[q] = fma(v, g1, v1 * g0);
   }
 }
 
