@@ -378,6 +378,45 @@ def measure_small(torch, binding, inputs, dev) -> dict:
                                    "buffers": SMALL_BUFFERS, "matches_eager": replays_ok}}
 
 
+PAPER_M = 5 * 10**6
+PAPER_BUFFERS = 8
+
+
+def measure_paper_shape(torch, binding, inputs, dev) -> dict:
+    """The paper's own measured configuration, for context: a 110-entry
+    table on [3e-6, 5.4e4] (stand-in for the SESAME density axis) and 5e6
+    targets log-uniform on [1e-10, 1e10], about half outside it.  Each
+    kernel: 64 calls replayed from a HIP graph, rotating over 8 target
+    buffers (320 MB, more than the 256 MB last-level cache)."""
+    table = inputs.paper_shape_table()
+    t = torch.from_numpy(table).to(dev)
+    host = torch.empty(PAPER_BUFFERS * PAPER_M, dtype=torch.float64).pin_memory()
+    inputs.paper_shape_targets(host.numel(), out=host.numpy())
+    x = host.to(dev).view(PAPER_BUFFERS, PAPER_M)
+    del host
+    out = torch.empty(PAPER_BUFFERS, PAPER_M, dtype=torch.int32, device=dev)
+    res = {"workload": "one 110-entry table on [3e-6, 5.4e4], 5e6 targets log-uniform on "
+                       "[1e-10, 1e10] per call (about half outside the table), 8 rotating "
+                       "target buffers, 64 graph-replayed calls"}
+    for algo in ("auto", "binary", "ballot", "exphash", "loghash", "skiplist"):
+        def call(b):
+            binding.search_with(t, x[b], algo, -1, out[b])
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            call(0)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, capture_error_mode="relaxed"):
+            for k in range(64):
+                call(k % PAPER_BUFFERS)
+        res[algo] = roof(PAPER_M, time_call(torch, g.replay, reps=5) / 64)
+        del g
+    del x, out
+    return res
+
+
 def measure_small_m(torch, binding, inputs, dev) -> dict:
     """Per-call time in the small-m regime (m = 1e2..1e4 targets per call),
     where the per-workgroup setup decides: 64 calls replayed from a HIP
@@ -625,6 +664,9 @@ def main():
         log("bench: small table, graph-replayed calls")
         result["small"] = measure_small(torch, binding, inputs, dev)
         result["small"]["small_m"] = measure_small_m(torch, binding, inputs, dev)
+        torch.cuda.empty_cache()
+        log("bench: the paper's configuration (n = 110, 5e6 targets)")
+        result["paper_shape"] = measure_paper_shape(torch, binding, inputs, dev)
         torch.cuda.empty_cache()
         log("bench: batched plan")
         result["batched"] = measure_batched(torch, binding, inputs, dev)

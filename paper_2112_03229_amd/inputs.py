@@ -137,6 +137,12 @@ def paper_shape_table(seed: int = 110):
     return t
 
 
+def paper_shape_targets(m: int, seed: int = 5, threads: int = 0, out=None):
+    """The paper's targets for that table: i.i.d. log-uniform on [1e-10, 1e10],
+    so that about half fall outside [3e-6, 5.4e4]."""
+    return log_uniform(seed, S_TARGETS, 1e-10, 1e10, m, threads=threads, out=out)
+
+
 def single64_table(seed: int = 64):
     return jittered_log_table(seed, 64, -6.0, 4.0, 0.1)
 

@@ -178,6 +178,22 @@ def test_launch_shapes(binding, gpu, oracle_mod, inputs_mod, block):
         binding.set_option(binding.OPT_GRID_BLOCKS, 0)
 
 
+def test_paper_shape_every_kernel(binding, gpu, oracle_mod, inputs_mod):
+    """The paper's measured configuration: the 110-entry stand-in for the
+    density axis and 5e6 targets log-uniform on [1e-10, 1e10] (about half
+    outside the table), every kernel bit for bit against the oracle."""
+    table = inputs_mod.paper_shape_table()
+    x = inputs_mod.paper_shape_targets(5 * 10**6)
+    outside = np.mean((x < table[0]) | (x > table[-1]))
+    assert 0.4 < outside < 0.6
+    want = oracle_mod.search_lt(table, x)
+    for algo in ALGOS:
+        say(f"case paper shape algo={algo}")
+        got = run(binding, gpu, table, x, algo)
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, (algo, bad[:5], got[bad[:5]], want[bad[:5]])
+
+
 @pytest.mark.parametrize("s", [0, 3, 5, 8])
 @pytest.mark.parametrize("n", [64, 110, 1000, 4000])
 def test_exphash_bins_match_oracle(binding, gpu, oracle_mod, inputs_mod, n, s):
