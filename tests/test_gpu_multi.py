@@ -237,12 +237,14 @@ def test_full_size_batched(binding, gpu, oracle_mod, inputs_mod):
     bad, first = oracle_mod.check_bracket_segments(batch.tables, batch.table_off, x,
                                                    batch.query_off, got)
     assert bad == 0, first
-    pos = np.sort((inputs_mod.uniform(512, 97, 400000) * m).astype(np.int64))
+    # a seeded sample of 1e7 targets against the definition, every table
+    pos = np.sort((inputs_mod.uniform(512, 97, 10**7) * m).astype(np.int64))
     seg = np.searchsorted(batch.query_off, pos, side="right") - 1
-    for t in np.unique(seg)[:512]:
-        p = pos[seg == t]
-        tab = batch.table(t)
-        assert np.array_equal(got[p], oracle_mod.search_lt_at(tab, x, p)), t
+    bounds = np.searchsorted(seg, np.arange(batch.num_tables + 1))
+    for t in range(batch.num_tables):
+        p = pos[bounds[t]:bounds[t + 1]]
+        if p.size:
+            assert np.array_equal(got[p], oracle_mod.search_lt_at(batch.table(t), x, p)), t
 
 
 def test_full_size_paired(binding, gpu, oracle_mod, inputs_mod, pair_form):
@@ -266,11 +268,16 @@ def test_full_size_paired(binding, gpu, oracle_mod, inputs_mod, pair_form):
         say(f"check {name}")
         bad, first = oracle_mod.check_bracket_segments(b.tables, b.table_off, x, b.query_off, got)
         assert bad == 0, (name, first)
-        pos = np.sort((inputs_mod.uniform(4096, 98, 200000) * m).astype(np.int64))
+        # a seeded sample of 1e7 targets per axis against the definition,
+        # every material
+        pos = np.sort((inputs_mod.uniform(4096, 98, 10**7) * m).astype(np.int64))
         seg = np.searchsorted(b.query_off, pos, side="right") - 1
-        for t in np.unique(seg)[::8]:
-            p = pos[seg == t]
-            assert np.array_equal(got[p], oracle_mod.search_lt_at(b.table(t), x, p)), (name, t)
+        M = b.query_off.size - 1
+        bounds = np.searchsorted(seg, np.arange(M + 1))
+        for t in range(M):
+            p = pos[bounds[t]:bounds[t + 1]]
+            if p.size:
+                assert np.array_equal(got[p], oracle_mod.search_lt_at(b.table(t), x, p)), (name, t)
 
 
 def test_learned_batched_plan_is_exact(binding, gpu, oracle_mod, inputs_mod):
