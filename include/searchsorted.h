@@ -342,6 +342,13 @@ SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
  * entries, `steps` steps at learning rate `lr` (beta1 0.9, beta2 0.999,
  * eps 1e-8, cosine-decayed rate), parameters initialised from `seed`; run by
  * one workgroup with deterministic, fixed-order reductions.
+ * Evaluation (search, E and ss_learned_predict): the trained model is
+ * compiled once, exactly: with one input, layer 1 and layer 2's
+ * pre-activation are one linear function of z between consecutive
+ * breakpoints -b1_j / w1_j of layer 1, so p(z) = b3 + sum_k w3_k
+ * max(P_sk z + Q_sk, 0) with s the segment holding z (P, Q formed in
+ * float64 and rounded to FP32).  This is the same function as the layered
+ * form, up to FP32 rounding.
  * Search: g = floor(p (n-1)) clamped to [-1, n-1]; the window
  * [L, R] = [g - E, g + E] clamped to [-1, n-1] is accepted if
  * (L == -1 or a[L] < x) and (R == n-1 or x <= a[R+1]); the index is then

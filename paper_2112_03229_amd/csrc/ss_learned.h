@@ -10,7 +10,7 @@ namespace ss {
 
 struct LearnedSlot {
   int64_t tab_off;  // first entry in its tables array
-  int64_t p_off;    // first parameter in the pool
+  int64_t i_off;    // first float of its compiled image in the image pool
   int n;            // entries (>= 2, 0 < a[0] < a[n-1] < inf)
   int which;        // 0: first tables array, 1: second (paired plans)
   float u0, inv;    // model input normalisation (computed on the device)
@@ -18,11 +18,12 @@ struct LearnedSlot {
   int pad_;
 };
 
-// Trains one model per slot into d_pool (kNP floats per slot at p_off) with
-// one workgroup per slot, then measures each slot's error bound; fills u0,
-// inv and E of every slot.  SYNCHRONOUS on the current stream.
+// Trains one model per slot (one workgroup per slot), compiles each into
+// d_images (kImageFloats floats per slot at i_off) and measures each slot's
+// error bound with the compiled forward pass; fills u0, inv and E of every
+// slot.  SYNCHRONOUS on the current stream.
 int learned_train_slots(const double* tables_a, const double* tables_b,
-                        std::vector<LearnedSlot>& slots, float* d_pool, int steps, float lr,
+                        std::vector<LearnedSlot>& slots, float* d_images, int steps, float lr,
                         uint64_t seed);
 
 // True if a table (host copy) can have a learned model.

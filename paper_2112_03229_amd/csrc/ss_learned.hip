@@ -10,9 +10,15 @@
 //                  batch in a fixed order (deterministic): the 1024 W2
 //                  gradients as a 32 x 256 x 32 product on the matrix
 //                  cores, the other 129 one thread each.
-//   bound_kernel   E = 1 + max |g(x) - idx(x)| over the probes.
-//   learned_kernel the search: table and model in LDS, the model's middle
-//                  layer on the matrix cores, Q targets per lane.
+//   compile_kernel the trained model as the search evaluates it: layer 1
+//                  and layer 2's pre-activation are piecewise linear in the
+//                  one input, so each of the at most 33 segments between
+//                  layer 1's breakpoints gets its 32 slopes and offsets
+//                  (formed in float64, rounded once).
+//   bound_kernel   E = 1 + max |g(x) - idx(x)| over the probes, with the
+//                  compiled model.
+//   learned_kernel the search: table and compiled model in LDS, Q targets
+//                  per lane.
 //   predict_kernel the model's fractional position for inspection.
 #include <algorithm>
 #include <cstdio>
@@ -254,14 +260,104 @@ __global__ __launch_bounds__(kTrainThreads) void train_kernel(TrainArgs a) {
 
 // One workgroup per slot (table) of a plan: trains every model at once.
 __global__ __launch_bounds__(kTrainThreads) void train_many_kernel(
-    const double* tables_a, const double* tables_b, const LearnedSlot* slots, float* pool,
+    const double* tables_a, const double* tables_b, const LearnedSlot* slots, float* params,
     int steps, float lr, uint64_t seed) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const LearnedSlot sl = slots[blockIdx.x];
   TrainArgs a{(sl.which ? tables_b : tables_a) + sl.tab_off, sl.n, steps, lr,
               seed ^ (0x9e3779b97f4a7c15ULL * (uint64_t)(blockIdx.x + 1)), sl.u0, sl.inv,
-              pool + sl.p_off, 1, nullptr, nullptr};
+              params + (int64_t)blockIdx.x * kNP, 1, nullptr, nullptr};
   train_body(*reinterpret_cast<TrainLds*>(lds_raw), a);
+}
+
+// ---------------------------------------------------------------------------
+// Compilation of a trained model into the image the search evaluates (the
+// layout and the segment form are described with mlp_eval).
+// ---------------------------------------------------------------------------
+
+// One workgroup (at least 33 threads) compiles one model: P holds the kNP
+// parameters in the standard layout, img receives kImageFloats floats.
+// Breakpoints t_j = -b1_j / w1_j are formed in float64; a unit without one
+// (w1_j = 0, or a NaN) sorts last as +inf and is active exactly when
+// b1_j > 0.  The active units of segment s are judged at a point inside it,
+// and P_sk, Q_sk are summed in float64 and rounded once.  Breakpoints beyond
+// the FP32 range round to +-inf, which keeps the segment of every FP32
+// input unchanged.
+__device__ void compile_model(const float* __restrict__ P, float* __restrict__ img) {
+  __shared__ double bp[kH];
+  __shared__ double ts[kH];
+  __shared__ unsigned act[kISegments];
+  __shared__ int nbp;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid < kH) {
+    const double w = P[kOffW1 + tid], b = P[kOffB1 + tid];
+    const double t = -b / w;
+    bp[tid] = (w != 0.0 && t == t) ? t : __builtin_inf();
+  }
+  __syncthreads();
+  if (tid < kH) {  // rank by (breakpoint, unit): a permutation of 0..31
+    const double t = bp[tid];
+    int rank = 0;
+    for (int i = 0; i < kH; ++i) rank += (bp[i] < t || (bp[i] == t && i < tid)) ? 1 : 0;
+    ts[rank] = t;
+  }
+  if (tid == 0) {
+    int c = 0;
+    for (int i = 0; i < kH; ++i) c += bp[i] < __builtin_inf() ? 1 : 0;
+    nbp = c;
+  }
+  __syncthreads();
+  const int m = nbp;
+  if (tid < kISegments) {
+    double z;
+    if (m == 0) z = 0.0;
+    else if (tid == 0) z = ts[0] - fmax(1.0, fabs(ts[0]));
+    else if (tid >= m) z = ts[m - 1] + fmax(1.0, fabs(ts[m - 1]));
+    else z = 0.5 * ts[tid - 1] + 0.5 * ts[tid];
+    // (z may round to +-inf past a breakpoint near the float64 limit; units
+    // without a breakpoint are decided by b1 alone)
+    unsigned mask = 0;
+    for (int j = 0; j < kH; ++j) {
+      const double w = P[kOffW1 + j], b = P[kOffB1 + j];
+      const bool on = bp[j] < __builtin_inf() ? w * z + b > 0.0 : b > 0.0;
+      mask |= on ? 1u << j : 0u;
+    }
+    act[tid] = mask;
+  }
+  __syncthreads();
+  for (int i = tid; i < kISegments * kH; i += nt) {
+    const int seg = i / kH, k = i % kH;
+    const unsigned mask = act[seg];
+    double pk = 0.0, qk = P[kOffB2 + k];
+    for (int j = 0; j < kH; ++j) {
+      if ((mask >> j) & 1u) {
+        const double w2 = P[kOffW2 + k * kH + j];
+        pk += w2 * (double)P[kOffW1 + j];
+        qk += w2 * (double)P[kOffB1 + j];
+      }
+    }
+    img[kIRows + kIRowPitch * seg + 2 * k] = (float)pk;
+    img[kIRows + kIRowPitch * seg + 2 * k + 1] = (float)qk;
+  }
+  for (int i = tid; i < kISegments * (kIRowPitch - 2 * kH); i += nt)
+    img[kIRows + kIRowPitch * (i / (kIRowPitch - 2 * kH)) + 2 * kH + i % (kIRowPitch - 2 * kH)] = 0.0f;
+  for (int i = tid; i < kH; i += nt) {
+    img[kIT + i] = i < m ? (float)ts[i] : __builtin_inff();
+    img[kIW3 + i] = P[kOffW3 + i];
+  }
+  if (tid < kIRows - kIB3) img[kIB3 + tid] = tid == 0 ? P[kOffB3] : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void compile_kernel(const float* __restrict__ P,
+                                                      float* __restrict__ img) {
+  compile_model(P, img);
+}
+
+// One workgroup per slot of a plan.
+__global__ __launch_bounds__(256) void compile_many_kernel(const LearnedSlot* slots,
+                                                           const float* __restrict__ params,
+                                                           float* __restrict__ images) {
+  compile_model(params + (int64_t)blockIdx.x * kNP, images + slots[blockIdx.x].i_off);
 }
 
 // ---------------------------------------------------------------------------
@@ -283,7 +379,8 @@ __device__ __forceinline__ int exact_index(const double* __restrict__ a, int n, 
 // search's own forward pass (so every lane of the wavefront calls it; lanes
 // without an entry pass valid = false and get 0).
 __device__ __forceinline__ int probe_error(const double* __restrict__ a, int n, const float* m,
-                                           float u0, float inv, int i, bool valid) {
+                                           const OutLayer& o, float u0, float inv, int i,
+                                           bool valid) {
   const int e = valid ? i : 0;
   double probe[3];
   probe[0] = a[e];
@@ -292,7 +389,7 @@ __device__ __forceinline__ int probe_error(const double* __restrict__ a, int n, 
   int worst = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const float p = mlp_eval_wave(m, model_input(probe[c], u0, inv));
+    const float p = mlp_eval(m, o, model_input(probe[c], u0, inv));
     const int g = predicted_index(p, n);
     worst = max(worst, abs(g - exact_index(a, n, probe[c])));
   }
@@ -300,18 +397,19 @@ __device__ __forceinline__ int probe_error(const double* __restrict__ a, int n, 
 }
 
 __global__ __launch_bounds__(256) void bound_kernel(const double* __restrict__ a, int n,
-                                                    const float* __restrict__ P, float u0,
+                                                    const float* __restrict__ img, float u0,
                                                     float inv, int* worst) {
-  __shared__ __align__(16) float model[kModelFloats];
-  stage_model(model, P);
+  __shared__ __align__(16) float model[kImageFloats];
+  stage_image(model, img);
   __syncthreads();
+  const OutLayer o = load_out_layer(model);
   int local = 0;
   const int stride = gridDim.x * blockDim.x;
   // the loop bound is uniform across the workgroup: every lane takes part
   // in every forward pass
   for (int base = blockIdx.x * blockDim.x; base < n; base += stride) {
     const int i = base + threadIdx.x;
-    local = max(local, probe_error(a, n, model, u0, inv, i, i < n));
+    local = max(local, probe_error(a, n, model, o, u0, inv, i, i < n));
   }
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(worst, local);
@@ -333,18 +431,20 @@ __global__ void norm_many_kernel(const double* tables_a, const double* tables_b,
 
 __global__ __launch_bounds__(256) void bound_many_kernel(const double* tables_a,
                                                          const double* tables_b,
-                                                         LearnedSlot* slots, const float* pool) {
+                                                         LearnedSlot* slots,
+                                                         const float* images) {
   __shared__ int worst;
-  __shared__ __align__(16) float model[kModelFloats];
+  __shared__ __align__(16) float model[kImageFloats];
   const LearnedSlot sl = slots[blockIdx.x];
   const double* a = (sl.which ? tables_b : tables_a) + sl.tab_off;
-  stage_model(model, pool + sl.p_off);
+  stage_image(model, images + sl.i_off);
   if (threadIdx.x == 0) worst = 0;
   __syncthreads();
+  const OutLayer o = load_out_layer(model);
   int local = 0;
   for (int base = 0; base < sl.n; base += blockDim.x) {
     const int i = base + threadIdx.x;
-    local = max(local, probe_error(a, sl.n, model, sl.u0, sl.inv, i, i < sl.n));
+    local = max(local, probe_error(a, sl.n, model, o, sl.u0, sl.inv, i, i < sl.n));
   }
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(&worst, local);
@@ -358,7 +458,7 @@ __global__ __launch_bounds__(256) void bound_many_kernel(const double* tables_a,
 
 struct LearnedArgs {
   const double* table;
-  const float* P;
+  const float* img;     // compiled model
   const double* x;
   int32_t* out;
   unsigned long long* fallbacks;
@@ -381,8 +481,9 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   double cur[Q];
   if (t < ntiles) load_tile<Q>(a.x, a.m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= a.m, cur);
   stage_table(sa, a.table, a.n);
-  stage_model(model, a.P);
+  stage_image(model, a.img);
   __syncthreads();
+  const OutLayer o = load_out_layer(model);
   int fb = 0;
   for (; t < ntiles; t += gridDim.x) {
     const int64_t tn = t + gridDim.x;
@@ -392,10 +493,10 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
     if constexpr (CONV) {
       double xs[Q];
       convention_in<Q>(cur, xs);
-      search_learned<Q>(sa, a.n, model, a.E, a.u0, a.inv, xs, r, fell);
+      search_learned<Q>(sa, a.n, model, o, a.E, a.u0, a.inv, xs, r, fell);
       convention_out<Q>(a.n, cur, r);
     } else {
-      search_learned<Q>(sa, a.n, model, a.E, a.u0, a.inv, cur, r, fell);
+      search_learned<Q>(sa, a.n, model, o, a.E, a.u0, a.inv, cur, r, fell);
     }
     const int64_t base = t * per_tile + threadIdx.x;
     const bool full = (t + 1) * per_tile <= a.m;
@@ -413,17 +514,18 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
 
 __global__ void clear_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
-__global__ __launch_bounds__(256) void predict_kernel(const float* __restrict__ P,
+__global__ __launch_bounds__(256) void predict_kernel(const float* __restrict__ img,
                                                       const double* __restrict__ x, int64_t m,
                                                       float* __restrict__ out, float u0,
                                                       float inv, int n) {
-  __shared__ __align__(16) float model[kModelFloats];
-  stage_model(model, P);
+  __shared__ __align__(16) float model[kImageFloats];
+  stage_image(model, img);
   __syncthreads();
+  const OutLayer o = load_out_layer(model);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
     const int64_t i = base + threadIdx.x;
-    const float p = mlp_eval_wave(model, model_input(x[i < m ? i : 0], u0, inv));
+    const float p = mlp_eval(model, o, model_input(x[i < m ? i : 0], u0, inv));
     if (i < m) out[i] = p * (float)(n - 1);
   }
 }
@@ -443,10 +545,12 @@ struct ss_learned {
   double loss = 0;
   int device = -1;
   float* d_params = nullptr;
+  float* d_image = nullptr;  // the compiled model the search evaluates
   unsigned long long* d_fallbacks = nullptr;
   std::vector<float> params;
   ~ss_learned() {
     if (d_params) (void)hipFree(d_params);
+    if (d_image) (void)hipFree(d_image);
     if (d_fallbacks) (void)hipFree(d_fallbacks);
   }
 };
@@ -454,7 +558,7 @@ struct ss_learned {
 namespace ss {
 namespace {
 
-constexpr int kLearnedQ = 2;
+constexpr int kLearnedQ = 1;
 constexpr int kLearnedBlock = 256;
 
 int check_learned_table(const double* table, int64_t n, std::vector<double>* host) {
@@ -498,7 +602,7 @@ int measure_bound(ss_learned* h) {
   hipError_t e = hipMemcpyAsync(d_worst, &worst, sizeof(int), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
     const int blocks = std::min(1024, (h->n + 255) / 256);
-    hipLaunchKernelGGL(bound_kernel, dim3(blocks), dim3(256), 0, st, h->table, h->n, h->d_params,
+    hipLaunchKernelGGL(bound_kernel, dim3(blocks), dim3(256), 0, st, h->table, h->n, h->d_image,
                        h->u0, h->inv, d_worst);
     e = hipGetLastError();
   }
@@ -553,6 +657,10 @@ int run_train(const double* table, int n, float u0, float inv, float* d_params, 
 int finish_learned(ss_learned* h) {
   SS_TRY_HIP(hipMalloc(&h->d_fallbacks, sizeof(unsigned long long)));
   SS_TRY_HIP(hipMemset(h->d_fallbacks, 0, sizeof(unsigned long long)));
+  SS_TRY_HIP(hipMalloc(&h->d_image, sizeof(float) * kImageFloats));
+  hipLaunchKernelGGL(compile_kernel, dim3(1), dim3(256), 0, current_stream(), h->d_params,
+                     h->d_image);
+  SS_TRY_HIP(hipGetLastError());
   h->params.resize(kNP);
   SS_TRY_HIP(hipMemcpy(h->params.data(), h->d_params, sizeof(float) * kNP, hipMemcpyDeviceToHost));
   int dev = 0;
@@ -568,16 +676,19 @@ bool learned_eligible(const double* a, int64_t n) {
 }
 
 int learned_train_slots(const double* tables_a, const double* tables_b,
-                        std::vector<LearnedSlot>& slots, float* d_pool, int steps, float lr,
+                        std::vector<LearnedSlot>& slots, float* d_images, int steps, float lr,
                         uint64_t seed) {
   if (slots.empty()) return SS_OK;
   hipStream_t st = current_stream();
   const int count = (int)slots.size();
   LearnedSlot* d_slots = nullptr;
+  float* d_params = nullptr;
   SS_TRY_HIP(hipMalloc(&d_slots, sizeof(LearnedSlot) * count));
   const size_t lds = sizeof(TrainLds);
-  hipError_t e = hipMemcpyAsync(d_slots, slots.data(), sizeof(LearnedSlot) * count,
-                                hipMemcpyHostToDevice, st);
+  hipError_t e = hipMalloc(&d_params, sizeof(float) * kNP * count);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_slots, slots.data(), sizeof(LearnedSlot) * count,
+                       hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(norm_many_kernel, dim3((count + 255) / 256), dim3(256), 0, st, tables_a,
                        tables_b, d_slots, count);
@@ -588,12 +699,17 @@ int learned_train_slots(const double* tables_a, const double* tables_b,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(train_many_kernel, dim3(count), dim3(kTrainThreads), lds, st, tables_a,
-                       tables_b, d_slots, d_pool, steps, lr, seed);
+                       tables_b, d_slots, d_params, steps, lr, seed);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(compile_many_kernel, dim3(count), dim3(256), 0, st, d_slots, d_params,
+                       d_images);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(bound_many_kernel, dim3(count), dim3(256), 0, st, tables_a, tables_b,
-                       d_slots, d_pool);
+                       d_slots, d_images);
     e = hipGetLastError();
   }
   if (e == hipSuccess)
@@ -601,6 +717,7 @@ int learned_train_slots(const double* tables_a, const double* tables_b,
                        hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d_slots);
+  if (d_params) (void)hipFree(d_params);
   if (e != hipSuccess) return hip_fail(e, "training plan models");
   return SS_OK;
 }
@@ -754,7 +871,7 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
   DeviceInfo di;
   if ((rc = device_info(&di)) != SS_OK) return rc;
   const size_t tab = ((size_t)(h->n + SS_PAD) * 8 + 15) / 16 * 16;
-  const size_t lds = tab + kModelBytes;
+  const size_t lds = tab + kImageBytes;
   const void* kern = option(SS_OPT_CONVENTION)
                          ? reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 1>)
                          : reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 0>);
@@ -762,8 +879,8 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
   const int64_t ntiles = (m + per_tile - 1) / per_tile;
   int64_t grid = (int64_t)blocks_per_cu(kern, kLearnedBlock, lds) * di.num_cus * 4;
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
-  LearnedArgs a{h->table, h->d_params, targets, out_idx, h->d_fallbacks, m, h->n, h->E, h->u0, h->inv,
-                (int)tab};
+  LearnedArgs a{h->table, h->d_image, targets, out_idx, h->d_fallbacks, m, h->n, h->E, h->u0,
+                h->inv, (int)tab};
   void* args[] = {&a};
   SS_TRY_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(kLearnedBlock), args, lds, st));
   return SS_OK;
@@ -779,7 +896,7 @@ int ss_learned_predict(ss_learned* h, const double* x, int64_t m, float* out_pos
     return rc;
   const int64_t blocks = std::min<int64_t>((m + 255) / 256, 8192);
   hipLaunchKernelGGL(predict_kernel, dim3((unsigned)blocks), dim3(256), 0, current_stream(),
-                     h->d_params, x, m, out_pos, h->u0, h->inv, h->n);
+                     h->d_image, x, m, out_pos, h->u0, h->inv, h->n);
   SS_TRY_HIP(hipGetLastError());
   return SS_OK;
 }

@@ -1,7 +1,7 @@
 // Device code of the learned index's model, shared by the single-table
 // learned search, the error bound and the plan kernels: parameter layout,
-// model input, the matrix-core forward pass, predicted index and the
-// verified window search.
+// model input, the compiled forward pass, predicted index and the verified
+// window search.
 #pragma once
 
 #include "ss_device.h"
@@ -20,25 +20,38 @@ __device__ __forceinline__ float model_input(double x, float u0, float inv) {
   return (__log2f((float)x) - u0) * inv;
 }
 
-// LDS image of one model for the matrix-core forward pass: the vectors w1,
-// b1, b2, w3, b3, then W2 with its rows padded to 36 floats (16-byte aligned
-// rows that start on different banks).
-constexpr int kMW1 = 0, kMB1 = 32, kMB2 = 64, kMW3 = 96, kMB3 = 128, kMW2 = 132, kW2Pitch = 36;
-constexpr int kModelFloats = kMW2 + kH * kW2Pitch;
-constexpr int kModelBytes = kModelFloats * 4;
+// The forward pass as the search evaluates it.  With one input, layer 1
+// followed by layer 2's pre-activation is piecewise linear in z: unit j of
+// layer 1 switches at its breakpoint t_j = -b1_j / w1_j, and between two
+// consecutive breakpoints the set of active units is fixed, so for z in
+// segment s
+//   g_k(z) = b2_k + sum_{j active in s} W2_kj (w1_j z + b1_j) = P_sk z + Q_sk.
+// The model is compiled once (compile_model) into an image holding the at
+// most 32 breakpoints sorted ascending, one row (P_sk, Q_sk) for k < 32 per
+// segment (33 segments) and the output layer, and a query costs a 6-step
+// bisection over the breakpoints, 32 fused multiply-adds for g, 32 ReLUs and
+// the 32-term output sum: the same function as the 1088 multiply-adds of the
+// layered form, in another order of rounding.
+//
+// Image layout (floats; identical in global memory and LDS):
+//   [0, 32)    breakpoints, ascending, padded with +inf
+//   [32, 64)   w3
+//   64         b3 (65..67 unused)
+//   [68, ...)  33 rows of pitch 68: row s holds P_s0, Q_s0, P_s1, Q_s1, ...
+//              (the pitch puts consecutive rows' 16-byte reads on
+//              different LDS banks)
+constexpr int kIT = 0, kIW3 = 32, kIB3 = 64, kIRows = 68, kIRowPitch = 68, kISegments = kH + 1;
+constexpr int kImageFloats = kIRows + kISegments * kIRowPitch;
+constexpr int kImageBytes = kImageFloats * 4;
+static_assert(kImageBytes % 16 == 0, "16-byte copies");
 
-// Copies the 1153 parameters (standard layout) into the LDS image; called
-// by every thread of the workgroup, followed by a barrier before use.
-__device__ __forceinline__ void stage_model(float* m, const float* __restrict__ P) {
-  for (int i = threadIdx.x; i < kNP; i += blockDim.x) {
-    int d;
-    if (i < kOffW2) d = i;                                        // w1, b1
-    else if (i < kOffB2) d = kMW2 + kW2Pitch * ((i - kOffW2) / kH) + (i - kOffW2) % kH;
-    else if (i < kOffW3) d = kMB2 + (i - kOffB2);
-    else if (i < kOffB3) d = kMW3 + (i - kOffW3);
-    else d = kMB3;
-    m[d] = P[i];
-  }
+// Copies a compiled image into LDS with 16-byte loads; called by every
+// thread of the workgroup, followed by a barrier before use.
+__device__ __forceinline__ void stage_image(float* m, const float* __restrict__ img) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4* src = reinterpret_cast<const f4*>(img);
+  f4* dst = reinterpret_cast<f4*>(m);
+  for (int i = threadIdx.x; i < kImageFloats / 4; i += blockDim.x) dst[i] = src[i];
 }
 
 // max(v, 0) as one integer max on the encoding: non-negative floats are
@@ -49,66 +62,47 @@ __device__ __forceinline__ float relu_bits(float v) {
 }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef float v32f __attribute__((ext_vector_type(32)));
 
-// Forward pass of one input per lane, 64 inputs per call: every lane of the
-// wavefront must call it (uniform control flow).  Layer 1 and the output
-// layer run on the vector ALUs; layer 2 (1024 of the 1088 multiply-adds) is
-// a 32 x 32 x 32 product per 32 inputs on the matrix cores:
-//   H2^T (unit k x input q) = W2 (k x j) . H1^T (j x q)
-// as 32 rank-1 steps of v_mfma_f32_32x32x1f32, whose two 32 x 32 blocks
-// hold the inputs of lanes 0-31 and of lanes 32-63.  At step j lane l gives
-// the A operand W2[l mod 32][j] and the B operand h1_j of its own input.
-// Block b's result column c (input of lane 32b + c) is spread over lanes c
-// and c + 32, 16 units each: accumulator register r of lane l holds unit
-// 8 (r / 4) + 4 (l / 32) + r mod 4.  Each lane sums the output layer over
-// its 16 units for both blocks and swaps the other block's partial sum with
-// lane l xor 32.
-__device__ __forceinline__ float mlp_eval_wave(const float* m0, float z) {
-  // The model is re-read from LDS on every call: an opaque zero offset keeps
-  // the compiler from holding all of it in registers across calls, which
-  // would halve the wavefronts per SIMD that keep the matrix cores fed.
-  int opaque = 0;
-  asm volatile("" : "+s"(opaque));
-  const float* m = m0 + opaque;
-  const int lane = threadIdx.x & 63;
-  const int row = lane & 31, hi = lane >> 5;
-  const v4f* b2v = reinterpret_cast<const v4f*>(m + kMB2);
-  const v4f* w3v = reinterpret_cast<const v4f*>(m + kMW3);
-  const v4f* w1v = reinterpret_cast<const v4f*>(m + kMW1);
-  const v4f* b1v = reinterpret_cast<const v4f*>(m + kMB1);
-  const v4f* w2v = reinterpret_cast<const v4f*>(m + kMW2 + kW2Pitch * row);
-  v32f acc;
+// The output layer of a staged model: the same for every lane, so it is read
+// once per staging and kept in scalar registers (the 32 weights would
+// otherwise take 32 vector registers per lane).  The whole workgroup calls
+// it after the barrier that follows stage_image.
+struct OutLayer {
+  float w3[kH];
+  float b3;
+};
+
+__device__ __forceinline__ float lane0_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ OutLayer load_out_layer(const float* m) {
+  OutLayer o;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {  // start from the bias of the units held
-    const v4f b = b2v[2 * t + hi];
+  for (int k = 0; k < kH; ++k) o.w3[k] = lane0_f(m[kIW3 + k]);
+  o.b3 = lane0_f(m[kIB3]);
+  return o;
+}
+
+// The model's output p(z) from a compiled image in LDS and its output
+// layer.  The segment is s = #{i : t_i < z} (0..32; NaN gives 0).  Lanes
+// are independent: no wavefront-wide operation.
+__device__ __forceinline__ float mlp_eval(const float* m, const OutLayer& o, float z) {
+  int s = 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      acc[4 * t + u] = b[u];
-      acc[16 + 4 * t + u] = b[u];
-    }
+  for (int step = 16; step >= 1; step >>= 1) s = (m[kIT + s + step - 1] < z) ? s + step : s;
+  s += (m[kIT + s] < z) ? 1 : 0;
+  const v4f* row = reinterpret_cast<const v4f*>(m + kIRows + kIRowPitch * s);
+  float acc0 = o.b3, acc1 = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kH / 4; ++c) {
+    const v4f a = row[2 * c], b = row[2 * c + 1];
+    acc0 = fmaf(o.w3[4 * c], relu_bits(fmaf(a[0], z, a[1])), acc0);
+    acc1 = fmaf(o.w3[4 * c + 1], relu_bits(fmaf(a[2], z, a[3])), acc1);
+    acc0 = fmaf(o.w3[4 * c + 2], relu_bits(fmaf(b[0], z, b[1])), acc0);
+    acc1 = fmaf(o.w3[4 * c + 3], relu_bits(fmaf(b[2], z, b[3])), acc1);
   }
-#pragma unroll
-  for (int j4 = 0; j4 < kH / 4; ++j4) {
-    const v4f w2 = w2v[j4], w1 = w1v[j4], b1 = b1v[j4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const float h = fmaxf(fmaf(w1[u], z, b1[u]), 0.0f);
-      acc = __builtin_amdgcn_mfma_f32_32x32x1f32(w2[u], h, acc, 0, 0, 0);
-    }
-  }
-  float s0 = 0.0f, s1 = 0.0f;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const v4f w = w3v[2 * t + hi];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      s0 = fmaf(w[u], relu_bits(acc[4 * t + u]), s0);
-      s1 = fmaf(w[u], relu_bits(acc[16 + 4 * t + u]), s1);
-    }
-  }
-  const float own = hi ? s1 : s0, other = hi ? s0 : s1;
-  return own + __shfl_xor(other, 32) + m[kMB3];
+  return acc0 + acc1;
 }
 
 // Predicted index g = floor(p (n-1)) clamped to [-1, n-1].  Any p, even NaN
@@ -118,16 +112,16 @@ __device__ __forceinline__ int predicted_index(float p, int n) {
   return (int)fminf(fmaxf(g, -1.0f), (float)(n - 1));
 }
 
-// The verified window search for Q targets per lane (every lane of the
-// wavefront calls it).  m is the model's LDS image.
+// The verified window search for Q targets per lane.  m is the model's
+// compiled image in LDS, o its output layer.
 template <int Q>
 __device__ __forceinline__ void search_learned(const double* __restrict__ sa, int n,
-                                               const float* m, int E, float u0, float inv,
-                                               const double (&x)[Q], int (&r)[Q],
-                                               int (&fell_back)[Q]) {
+                                               const float* m, const OutLayer& o, int E,
+                                               float u0, float inv, const double (&x)[Q],
+                                               int (&r)[Q], int (&fell_back)[Q]) {
   float p[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) p[q] = mlp_eval_wave(m, model_input(x[q], u0, inv));
+  for (int q = 0; q < Q; ++q) p[q] = mlp_eval(m, o, model_input(x[q], u0, inv));
   int step = 1;
   while (step * 2 <= 2 * E + 1) step *= 2;  // >= half the window length
 #pragma unroll

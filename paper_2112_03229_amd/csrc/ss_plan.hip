@@ -34,7 +34,7 @@ namespace ss {
 struct TableDesc {
   int64_t tab_off;   // first entry in the tables array
   int64_t bins_off;  // first entry in the bin pool (exponent hash), else 0
-  int64_t p_off;     // first parameter in the model pool (learned), else 0
+  int64_t p_off;     // first float of its compiled model in the image pool (learned), else 0
   int n;
   int algo;          // SS_ALGO_BINARY, SS_ALGO_EXPHASH or SS_ALGO_LEARNED
   int shift, kmin, kmaxc, nb, K;
@@ -122,7 +122,7 @@ __device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* _
   stage_table(sa, tables + d.tab_off, d.n);
   Staged st{{0, d.shift, d.kmin, d.kmaxc, d.nb, d.K}, d.algo == SS_ALGO_LEARNED, d.n, d.E,
             d.u0, d.inv};
-  if (d.algo == SS_ALGO_LEARNED) stage_model(model, params + d.p_off);
+  if (d.algo == SS_ALGO_LEARNED) stage_image(model, params + d.p_off);
   if (d.algo == SS_ALGO_EXPHASH) {
     st.hp.ok = 1;
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -137,12 +137,13 @@ __device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* _
 template <int Q, int LEARN>
 __device__ __forceinline__ void search_staged(const Staged& st, const double* sa,
                                               const uint16_t* C, const float* model,
-                                              const double (&x)[Q], int (&r)[Q], int (&fell)[Q]) {
+                                              const OutLayer& o, const double (&x)[Q],
+                                              int (&r)[Q], int (&fell)[Q]) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) fell[q] = 0;
   if constexpr (LEARN) {
     if (st.learned) {  // uniform across the workgroup
-      search_learned<Q>(sa, st.n, model, st.E, st.u0, st.inv, x, r, fell);
+      search_learned<Q>(sa, st.n, model, o, st.E, st.u0, st.inv, x, r, fell);
       return;
     }
   }
@@ -187,22 +188,19 @@ __device__ __forceinline__ void load_range(const double* __restrict__ x, TileRan
   load_tile<Q>(x, r.q1, r.q0 + threadIdx.x, nt, r.q0 + (int64_t)nt * Q <= r.q1, v);
 }
 
-// Plans with learned tables launch at most 512 threads per workgroup: the
-// model's matrix-core accumulators need more than the 128 registers per
-// lane that 1024-thread workgroups leave.
 // Searches one tile of targets against a staged table, in the strict
 // convention or (CONV = 1) the paper's.
 template <int Q, int LEARN, int CONV>
 __device__ __forceinline__ void search_tile(const Staged& st, const double* sa, const uint16_t* C,
-                                            const float* model, const double (&x)[Q], int (&r)[Q],
-                                            int (&fell)[Q]) {
+                                            const float* model, const OutLayer& o,
+                                            const double (&x)[Q], int (&r)[Q], int (&fell)[Q]) {
   if constexpr (CONV) {
     double xs[Q];
     convention_in<Q>(x, xs);
-    search_staged<Q, LEARN>(st, sa, C, model, xs, r, fell);
+    search_staged<Q, LEARN>(st, sa, C, model, o, xs, r, fell);
     convention_out<Q>(st.n, x, r);
   } else {
-    search_staged<Q, LEARN>(st, sa, C, model, x, r, fell);
+    search_staged<Q, LEARN>(st, sa, C, model, o, x, r, fell);
   }
 }
 
@@ -270,7 +268,7 @@ __device__ __forceinline__ void store_tile_f64(double* __restrict__ out, int64_t
 }
 
 template <int MODE, int Q, int LEARN, int CONV>
-__global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) {
+__global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   constexpr bool INTERP = MODE == kPairInterp;
   constexpr bool PAIRED = MODE == kPairJoint || INTERP;
   constexpr bool SPLIT = MODE == kPairSplit;
@@ -330,6 +328,12 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
     stb = stage_desc(a.desc[a.pair_base + sg.seg], a.tables_b, a.bins, a.params, sb, Cb, Mb);
   if constexpr (INTERP) grid = stage_grid(a, sg.seg, sta.n, stb.n, lds_grid);
   __syncthreads();
+  // output layers of staged learned models (unused for other tables)
+  OutLayer oa{}, ob{};
+  if constexpr (LEARN) {
+    oa = load_out_layer(Ma);
+    if constexpr (PAIRED) ob = load_out_layer(Mb);
+  }
   int fallbacks = 0;
   for (int64_t j = j0; j < j1; ++j) {
     double ca2[Q], cb2[Q];
@@ -342,7 +346,7 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
     }
     const bool full = cur.q0 + per_tile == cur.q1;
     int r[Q], fell[Q];
-    search_tile<Q, LEARN, CONV>(sta, sa, Ca, Ma, ca, r, fell);
+    search_tile<Q, LEARN, CONV>(sta, sa, Ca, Ma, oa, ca, r, fell);
     if constexpr (!INTERP)
       store_tile<Q>(SPLIT && sg.part ? a.ob : a.oa, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
     if constexpr (LEARN) {
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
     }
     if constexpr (INTERP) {
       int rt[Q];
-      search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, cb, rt, fell);
+      search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, ob, cb, rt, fell);
       double f[Q];
       if (grid.l)  // uniform: the grid of the workgroup's current material
         interpolate<Q>(sa, sta.n, sb, stb.n, grid.l, ca, cb, r, rt, f);
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
         store_tile<Q>(a.ob, cur.q1, cur.q0 + threadIdx.x, nt, full, rt);
       }
     } else if constexpr (PAIRED) {
-      search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, cb, r, fell);
+      search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, ob, cb, r, fell);
       store_tile<Q>(a.ob, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
       if constexpr (LEARN) {
 #pragma unroll
@@ -382,6 +386,10 @@ __global__ __launch_bounds__(LEARN ? 512 : 1024) void multi_kernel(MultiArgs a) 
                          Mb);
       if constexpr (INTERP) grid = stage_grid(a, sg1.seg, sta.n, stb.n, lds_grid);
       __syncthreads();
+      if constexpr (LEARN) {
+        oa = load_out_layer(Ma);
+        if constexpr (PAIRED) ob = load_out_layer(Mb);
+      }
     }
     sg = sg1;
     sg1 = sg2;
@@ -453,7 +461,7 @@ struct ss_plan {
   int64_t* d_query_off = nullptr;
   ss::WgStart* d_wg_start = nullptr;
   int* d_k = nullptr;
-  float* d_pool = nullptr;                 // learned models
+  float* d_pool = nullptr;                 // learned models, compiled (kImageFloats each)
   unsigned long long* d_fallbacks = nullptr;
   int learned_tables = 0;
   int64_t total_tiles = 0;
@@ -487,7 +495,7 @@ namespace {
 constexpr int kPlanBlock = 512;
 constexpr int kPlanQ = 8;
 constexpr int kPairQ = 4;
-constexpr int kLearnedPlanQ = 2;          // the model's registers limit Q
+constexpr int kLearnedPlanQ = 1;          // registers: the model rows of each query
 constexpr int kDefaultPlanLearnedSteps = 500;
 constexpr int kXcds = 8;                  // accelerator complex dies of an MI355X
 // Default workgroup ranges per XCD turn.  Measured on MI355X, chunks of 1 /
@@ -559,14 +567,14 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
     if (!learned_eligible(h, d.n)) continue;
     LearnedSlot sl{};
     sl.tab_off = d.tab_off;
-    sl.p_off = (int64_t)slots.size() * kNP;
+    sl.i_off = (int64_t)slots.size() * kImageFloats;
     sl.n = d.n;
     sl.which = which;
     slots.push_back(sl);
     slot_desc.push_back(t);
   }
   if (slots.empty()) return SS_OK;
-  SS_TRY_HIP(hipMalloc(&p->d_pool, sizeof(float) * kNP * slots.size()));
+  SS_TRY_HIP(hipMalloc(&p->d_pool, sizeof(float) * kImageFloats * slots.size()));
   SS_TRY_HIP(hipMalloc(&p->d_fallbacks, sizeof(unsigned long long)));
   SS_TRY_HIP(hipMemset(p->d_fallbacks, 0, sizeof(unsigned long long)));
   int steps = (int)option(SS_OPT_LEARNED_STEPS);
@@ -579,7 +587,7 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
     d.algo = SS_ALGO_LEARNED;
     d.bins_off = 0;
     d.nb = d.K = 0;
-    d.p_off = slots[i].p_off;
+    d.p_off = slots[i].i_off;
     d.E = slots[i].E;
     d.u0 = slots[i].u0;
     d.inv = slots[i].inv;
@@ -649,7 +657,6 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   }
 
   p->block = option(SS_OPT_BLOCK_SIZE) > 0 ? (int)option(SS_OPT_BLOCK_SIZE) : kPlanBlock;
-  if (p->learned_tables > 0) p->block = std::min(p->block, kPlanBlock);
   p->q = p->learned_tables > 0 ? kLearnedPlanQ
          : (p->mode == kPairJoint || p->mode == kPairInterp ? kPairQ : kPlanQ);
   const int64_t per_tile = (int64_t)p->block * p->q;
@@ -677,10 +684,10 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   }
   int model_a = (int)p->lds, model_b = (int)p->lds;
   if (learned) {  // one model image per staged table
-    p->lds += kModelBytes;
+    p->lds += kImageBytes;
     if (p->mode == kPairJoint || p->mode == kPairInterp) {
       model_b = (int)p->lds;
-      p->lds += kModelBytes;
+      p->lds += kImageBytes;
     }
   }
   // interpolation locates cells with the strict index (its own definition)

@@ -80,11 +80,60 @@ def test_forward_matches_oracle(binding, gpu, inputs_mod, trained):
     x = inputs_mod.table_targets(table, 20000, seed=5)
     pos = li.predict(torch.from_numpy(x).to(gpu)).cpu().numpy().astype(np.float64)
     want = OL.forward(w, OL.model_input(x, table)) * (table.size - 1)
-    # FP32 forward (1088 FMAs, FP32 log2 of x rounded to FP32) vs float64:
-    # agreement to a small fraction of one table position
+    # FP32 compiled forward (FP32 log2 of x rounded to FP32) vs the float64
+    # layered forward: agreement to a small fraction of one table position
     err = np.abs(pos - want)
     say(f"forward max abs err (positions): {err.max():.3e}")
     assert err.max() < 0.05
+
+
+def test_compiled_model_matches_layered_oracle(binding, gpu, inputs_mod):
+    """The search evaluates a compiled form of the model (layer 1 and layer
+    2's pre-activation as one linear piece per segment between layer 1's
+    breakpoints).  On weights built to stress it -- units with w1 = 0
+    (always on, always off), three units sharing one breakpoint (one with a
+    negative slope), a breakpoint near 1e30, breakpoints inside and
+    outside [0, 1] -- and inputs on both sides of every breakpoint, its
+    output must equal the float64 layered forward pass to FP32 rounding of
+    the terms' magnitudes."""
+    table = inputs_mod.learned_table()
+    t = torch.from_numpy(table).to(gpu)
+    rng = np.random.default_rng(7)
+    w1 = rng.normal(0, 3, 32)
+    b1 = rng.normal(0, 1, 32)
+    w1[0:3], b1[0:3] = 0.0, [0.5, -0.5, 0.0]
+    w1[3:6], b1[3:6] = [2.0, 4.0, -2.0], [-1.0, -2.0, 1.0]
+    w1[6], b1[6] = 1e-30, 1.0
+    W2 = rng.normal(0, 0.3, (32, 32))
+    b2 = rng.normal(0, 0.1, 32)
+    w3 = rng.normal(0, 0.3, 32)
+    b3 = 0.1
+    w = np.concatenate([w1, b1, W2.reshape(-1), b2, w3, [b3]]).astype(np.float32)
+    li = binding.LearnedIndex(t, weights=w)
+    wd = w.astype(np.float64)
+    w1, b1 = wd[0:32], wd[32:64]
+    W2 = wd[64:64 + 1024].reshape(32, 32)
+    b2, w3, b3 = wd[1088:1120], wd[1120:1152], wd[1152]
+    # inputs: a spread over [-0.2, 1.2] and both sides of every breakpoint
+    # with |z| < 2 (x then stays inside the FP32 range that the model input
+    # is formed in)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        bp = -b1 / w1
+    bp = bp[np.isfinite(bp) & (np.abs(bp) < 2)]
+    z = np.concatenate([np.linspace(-0.2, 1.2, 20001), bp - 1e-6, bp + 1e-6, bp])
+    u0, u1 = np.log2(table[0]), np.log2(table[-1])
+    x = np.exp2(u0 + z * (u1 - u0))
+    p = li.predict(torch.from_numpy(x).to(gpu)).cpu().numpy().astype(np.float64)
+    p /= table.size - 1
+    zr = OL.model_input(x, table)
+    want = OL.forward(wd, zr)
+    mag = np.abs(w3) @ (np.abs(W2) @ (np.outer(np.abs(w1), np.abs(zr)) + np.abs(b1)[:, None])
+                        + np.abs(b2)[:, None]) + abs(b3)
+    slope = np.abs(w3) @ (np.abs(W2) @ np.abs(w1))
+    tol = 4e-6 * mag + 4e-6 * slope * np.maximum(1.0, np.abs(zr))
+    err = np.abs(p - want)
+    say(f"compiled vs layered: worst err / tol {np.max(err / tol):.3f}")
+    assert np.all(err <= tol), (np.argmax(err / tol), err.max())
 
 
 @pytest.mark.parametrize("which", ["init", "trained"])
