@@ -698,7 +698,8 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   if (rc != SS_OK) return rc;
   p->device = di.device;
   const int resident = blocks_per_cu(p->kernel, p->block, p->lds) * di.num_cus;
-  p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident, S);
+  p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident, S,
+                                               per_tile);
   if (option(SS_OPT_PLAN_TILES) > 0) p->tiles_per_wg = (int)option(SS_OPT_PLAN_TILES);
   // workgroup ranges: up to tiles_per_wg tiles, cut at segment boundaries
   std::vector<WgStart> wg_start;

@@ -40,9 +40,10 @@ const TunerModel& tuner_model();
 TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bins_budget);
 
 // Consecutive tiles per workgroup of a plan launch with `total_tiles`
-// tiles in `segments` segments and `resident` workgroups resident at once.
+// tiles of `per_tile` targets in `segments` segments and `resident`
+// workgroups resident at once.
 int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident,
-                               int segments);
+                               int segments, int64_t per_tile);
 
 // Longest run of equal exponent-hash keys (the largest bin) at bits s.
 int host_longest_bin(const double* a, int n, int s);

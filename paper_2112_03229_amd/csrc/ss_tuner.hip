@@ -173,19 +173,24 @@ TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bi
 }
 
 int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident,
-                               int segments) {
+                               int segments, int64_t per_tile) {
   (void)model;
-  // Every workgroup stages its table before searching, so the tile count
-  // per workgroup trades staging stalls against load balance.  Measured on
-  // MI355X (steady clocks, tiles aligned to absolute positions, two tiles
+  // Every workgroup stages its table before searching, so the targets per
+  // workgroup trade staging stalls against load balance.  Measured on MI355X
+  // (steady clocks, tiles aligned to absolute positions, two tiles
   // prefetched, workgroup ranges cut at segment boundaries and dealt to the
-  // XCDs in chunks of 8): 512 tables with ~350 tiles each: 3 tiles per
-  // workgroup 5.92 TB/s, 4: 6.03; 8192 density and temperature segments
-  // with ~60 tiles each: 6: 5.70, 8: 5.63.  Short segments (under 64 tiles
-  // on average) take 6, long ones 4, reduced while that leaves fewer than
-  // ~6 waves of workgroups.
-  const int64_t avg = total_tiles / std::max(segments, 1);
-  int64_t k = avg < 64 ? 6 : 4;
+  // XCDs in chunks of 8), with tiles of 4096 targets: 512 tables with ~350
+  // tiles each: 3 tiles per workgroup 5.92 TB/s, 4: 6.03; 8192 density and
+  // temperature segments with ~60 tiles each: 6: 5.70, 8: 5.63.  Short
+  // segments (under 64 such tiles on average) take 6, long ones 4.  Smaller
+  // tiles (one target per lane in plans with learned models: 512 targets)
+  // take proportionally more, the same targets per workgroup: the 512-table
+  // batch with every table learned ran at 88.8 / 97.9 / 104.3 / 107.1 /
+  // 108.0 Gq/s with 4 / 8 / 16 / 32 / 64 tiles of 512.  The count is then
+  // reduced while it leaves fewer than ~6 waves of workgroups.
+  const int64_t scale = std::max<int64_t>(1, 4096 / std::max<int64_t>(per_tile, 1));
+  const int64_t avg = total_tiles / std::max(segments, 1) / scale;
+  int64_t k = (avg < 64 ? 6 : 4) * scale;
   while (k > 1 && total_tiles / k < 6LL * std::max(resident, 1)) --k;
   return (int)k;
 }
