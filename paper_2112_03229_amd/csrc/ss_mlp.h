@@ -132,13 +132,13 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
     const bool hi_ok = R >= n - 1 || x[q] <= sa[min(R + 1, n - 1)];
     fell_back[q] = !(lo_ok && hi_ok);
     if (lo_ok && hi_ok) {
-      // largest pos in [L+1, R+1] with a[pos-1] < x (all of a[..L] are < x)
+      // pos = #{a < x} lies in [L+1, R+1]: every entry up to a[L] is below
+      // x and every entry from a[R+1] on is not, so the steps need no upper
+      // bound (a read at or past R+1 never advances pos; reads past the
+      // table are clamped to its +inf sentinel a[n]).  2 step - 1 >= 2E
+      // covers the window.
       int pos = L + 1;
-      for (int s = step; s >= 1; s >>= 1) {
-        const int cand = pos + s;
-        const int ridx = max(min(cand, R + 1) - 1, 0);
-        pos = ((cand <= R + 1) & (sa[ridx] < x[q])) ? cand : pos;
-      }
+      for (int s = step; s >= 1; s >>= 1) pos = (sa[min(pos + s - 1, n)] < x[q]) ? pos + s : pos;
       r[q] = pos - 1;
     } else {
       int base = 0, len = n;
