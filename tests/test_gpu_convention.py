@@ -158,3 +158,21 @@ def test_learned_paper_convention(binding, gpu, oracle_mod, inputs_mod, paper_co
     x = targets(inputs_mod, table, 3 * TILE + 5, seed=9)
     got = li.search(torch.from_numpy(x).to(gpu)).cpu().numpy()
     assert np.array_equal(got, oracle_mod.search_le_clamped(table, x))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_random_tables_paper_convention(binding, gpu, oracle_mod, paper_convention, seed):
+    """Seeded fuzzing in the paper's convention: random tables (duplicates,
+    signed entries, zeros, denormals, infinities) and targets at, between
+    and around their entries, every kernel against search_le_clamped."""
+    from test_gpu_single import fuzz_table, fuzz_targets
+    rng = np.random.default_rng(2000 + seed)
+    for case in range(30):
+        n = int(rng.choice([0, 1, 2, 5, 64, 65, 300, 1000, 4000]))
+        table = fuzz_table(rng, n)
+        x = fuzz_targets(rng, table, int(rng.integers(1, 3 * TILE)))
+        want = oracle_mod.search_le_clamped(table, x)
+        for algo in ALGOS:
+            got = run(binding, gpu, table, x, algo)
+            bad = np.nonzero(got != want)[0]
+            assert bad.size == 0, (seed, case, n, algo, bad[:3], got[bad[:3]], want[bad[:3]], x[bad[:3]])

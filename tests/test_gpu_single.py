@@ -399,3 +399,83 @@ def test_more_than_2_31_targets(binding, gpu, oracle_mod, inputs_mod, algo):
     xs = x[pt].cpu().numpy()
     assert np.array_equal(out[pt].cpu().numpy(), oracle_mod.search_lt(table, xs))
     del x, out
+
+
+def fuzz_table(rng, n):
+    """A sorted table of n entries from one of several distributions:
+    log-spaced, with runs of duplicates, signed, with zeros and denormals,
+    with infinities at the end, or clustered."""
+    kind = rng.integers(0, 6)
+    if kind == 0:
+        t = 10.0 ** rng.uniform(-12, 12, n)
+    elif kind == 1:
+        t = np.repeat(10.0 ** rng.uniform(-3, 3, max(1, n // 4 + 1)), 4)[:n]
+    elif kind == 2:
+        t = rng.normal(0, 1e3, n)
+    elif kind == 3:
+        t = np.concatenate([np.zeros(n // 8), np.full(n // 8, 5e-324), 10.0 ** rng.uniform(-310, -300, n // 8),
+                            10.0 ** rng.uniform(-5, 5, n - 3 * (n // 8))])
+    elif kind == 4:
+        t = 10.0 ** rng.uniform(-2, 2, n)
+        t[-min(n, 2):] = np.inf
+    else:
+        t = 1.0 + rng.integers(0, 7, n) * 2.0 ** -52
+    return np.sort(t.astype(np.float64))
+
+
+def fuzz_targets(rng, table, m):
+    n = table.size
+    parts = [10.0 ** rng.uniform(-14, 14, m // 4) * rng.choice([-1.0, 1.0], m // 4)]
+    if n:
+        fin = table[np.isfinite(table)]
+        if fin.size:
+            pick = rng.choice(fin, m // 4)
+            parts += [pick, np.nextafter(pick, np.inf), np.nextafter(pick, -np.inf)]
+    x = np.concatenate(parts + [inputs_special()])
+    rng.shuffle(x)
+    return x
+
+
+def inputs_special():
+    return np.array([np.nan, -0.0, 0.0, 5e-324, -5e-324, np.inf, -np.inf, 1.7976931348623157e308])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_tables_every_kernel(binding, gpu, oracle_mod, seed):
+    """Seeded fuzzing: 40 random tables per seed (0..5000 entries, six
+    distributions) and targets at, between and around their entries, every
+    kernel bit for bit against the oracle."""
+    rng = np.random.default_rng(1000 + seed)
+    for case in range(40):
+        n = int(rng.choice([0, 1, 2, 3, 7, 63, 64, 65, 130, 1000, 4095, 5000]))
+        table = fuzz_table(rng, n)
+        x = fuzz_targets(rng, table, int(rng.integers(1, 3 * TILE)))
+        want = oracle_mod.search_lt(table, x)
+        for algo in ALGOS:
+            got = run(binding, gpu, table, x, algo)
+            bad = np.nonzero(got != want)[0]
+            assert bad.size == 0, (seed, case, n, algo, bad[:3], got[bad[:3]], want[bad[:3]], x[bad[:3]])
+
+
+def test_random_batches(binding, gpu, oracle_mod):
+    """A batched plan over 60 fuzzed tables (empty target slices and empty
+    tables included) against the oracle."""
+    rng = np.random.default_rng(77)
+    tabs, xs, counts = [], [], []
+    for t in range(60):
+        n = int(rng.choice([0, 1, 5, 64, 300, 2000]))
+        tab = fuzz_table(rng, n)
+        m = int(rng.choice([0, 1, 100, 5000, 70000]))
+        x = fuzz_targets(rng, tab, max(m, 1))[:m]
+        tabs.append(tab)
+        xs.append(x)
+        counts.append(x.size)
+    toff = np.concatenate([[0], np.cumsum([t.size for t in tabs])]).astype(np.int64)
+    qoff = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    tables = np.concatenate(tabs)
+    x = np.concatenate(xs)
+    want = oracle_mod.search_lt_segments(tables, toff, x, qoff)
+    plan = binding.MultiPlan(torch.from_numpy(tables).to(gpu), toff, qoff)
+    got = plan.search(torch.from_numpy(x).to(gpu)).cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], want[bad[:5]])
