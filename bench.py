@@ -649,6 +649,23 @@ def main():
         },
     }
 
+    # After the timed region: 20 more steps, each bracketed by its own event
+    # pair (the paper reports trials of a run); their median and minimum
+    # beside the mean above.  Not part of `value`.
+    trial_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(20)]
+    for e0, e1 in trial_ev:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    trial_ms = np.array([e0.elapsed_time(e1) for e0, e1 in trial_ev])
+    result["trials"] = {"steps": len(trial_ms),
+                        "median_ms_per_step": round(float(np.median(trial_ms)), 4),
+                        "min_ms_per_step": round(float(trial_ms.min()), 4),
+                        "median_gqps": round(queries_per_step / (np.median(trial_ms) * 1e-3) / 1e9, 2),
+                        "max_gqps": round(queries_per_step / (trial_ms.min() * 1e-3) / 1e9, 2)}
+
     if not args.no_kernels:
         log("bench: per-kernel comparison")
         comp = {}
