@@ -546,7 +546,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}, "
               f"WORLD_SIZE={world}); the search shards by target ranges with no exchange "
               "step, so per-GPU throughput is the single-GPU figure.", file=sys.stderr)
         sys.exit(2)

@@ -61,7 +61,7 @@ typedef enum {
     SS_ERR_NO_DEVICE = -3,      /* no usable GPU */
     SS_ERR_HIP = -4,            /* a HIP runtime call failed */
     SS_ERR_OOM = -5,            /* device or host allocation failed */
-    SS_ERR_UNSUPPORTED = -6     /* valid request this build cannot serve */
+    SS_ERR_UNSUPPORTED = -6     /* valid request the library cannot serve */
 } ss_status;
 
 /* Search kernels (values of SS_OPT_FORCE_ALGO and of plan choices). */

@@ -279,7 +279,7 @@ __global__ __launch_bounds__(kTrainThreads) void train_many_kernel(
 // parameters in the standard layout, img receives kImageFloats floats.
 // Breakpoints t_j = -b1_j / w1_j are formed in float64; a unit without one
 // (w1_j = 0, or a NaN) sorts last as +inf and is active exactly when
-// b1_j > 0.  The active units of segment s are judged at a point inside it,
+// b1_j > 0.  The active units of segment s are decided at a point inside it,
 // and P_sk, Q_sk are summed in float64 and rounded once.  Breakpoints beyond
 // the FP32 range round to +-inf, which keeps the segment of every FP32
 // input unchanged.
