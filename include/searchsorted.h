@@ -343,12 +343,14 @@ SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
  * eps 1e-8, cosine-decayed rate), parameters initialised from `seed`; run by
  * one workgroup with deterministic, fixed-order reductions.
  * Evaluation (search, E and ss_learned_predict): the trained model is
- * compiled once, exactly: with one input, layer 1 and layer 2's
- * pre-activation are one linear function of z between consecutive
- * breakpoints -b1_j / w1_j of layer 1, so p(z) = b3 + sum_k w3_k
- * max(P_sk z + Q_sk, 0) with s the segment holding z (P, Q formed in
- * float64 and rounded to FP32).  This is the same function as the layered
- * form, up to FP32 rounding.
+ * compiled once, exactly.  With one input z the network is a continuous
+ * piecewise-linear function: its pieces end at layer 1's breakpoints
+ * -b1_j / w1_j and, between those, where a layer-2 unit's pre-activation
+ * changes sign.  The compiled form is the sorted list of piece boundaries
+ * (at most 1088) and one (slope, intercept) per piece (at most 1089), both
+ * formed in float64 and rounded to FP32: p(z) = slope_i z + intercept_i for
+ * the piece i holding z, found by bisection over the boundaries.  This is
+ * the same function as the layered form, up to FP32 rounding.
  * Search: g = floor(p (n-1)) clamped to [-1, n-1]; the window
  * [L, R] = [g - E, g + E] clamped to [-1, n-1] is accepted if
  * (L == -1 or a[L] < x) and (R == n-1 or x <= a[R+1]); the index is then

@@ -275,24 +275,44 @@ __global__ __launch_bounds__(kTrainThreads) void train_many_kernel(
 // layout and the segment form are described with mlp_eval).
 // ---------------------------------------------------------------------------
 
-// One workgroup (at least 33 threads) compiles one model: P holds the kNP
-// parameters in the standard layout, img receives kImageFloats floats.
-// Breakpoints t_j = -b1_j / w1_j are formed in float64; a unit without one
-// (w1_j = 0, or a NaN) sorts last as +inf and is active exactly when
-// b1_j > 0.  The active units of segment s are decided at a point inside it,
-// and P_sk, Q_sk are summed in float64 and rounded once.  Breakpoints beyond
-// the FP32 range round to +-inf, which keeps the segment of every FP32
-// input unchanged.
+// Midpoint of (lo, hi) with infinite ends: a point inside the interval
+// (either end may be +-inf; an interval with both ends infinite gives 0).
+__device__ __forceinline__ double inside(double lo, double hi) {
+  const double inf = __builtin_inf();
+  if (lo == -inf && hi == inf) return 0.0;
+  if (lo == -inf) return hi - fmax(1.0, fabs(hi));
+  if (hi == inf) return lo + fmax(1.0, fabs(lo));
+  return 0.5 * lo + 0.5 * hi;
+}
+
+// One workgroup (at least 64 threads) compiles one model: P holds the kNP
+// parameters in the standard layout, img receives the image described with
+// mlp_eval.  Everything is formed in float64 and rounded once:
+//   1. layer 1's breakpoints t_j = -b1_j / w1_j, sorted; a unit without one
+//      (w1_j = 0, or a NaN) is active exactly when b1_j > 0;
+//   2. per segment s between consecutive breakpoints (at most 33), the
+//      active layer-1 units at a point inside it and layer 2's lines
+//      g_k = P_sk z + Q_sk;
+//   3. per segment, the points -Q_sk / P_sk strictly inside it where a
+//      layer-2 unit switches, sorted;
+//   4. the pieces, segment by segment: boundaries in order (each segment's
+//      switching points, then the segment's right breakpoint), and per
+//      piece the active layer-2 units at a point inside it, giving
+//      slope = sum w3_k P_sk and intercept = b3 + sum w3_k Q_sk.
+// Breakpoints beyond the FP32 range round to +-inf, which leaves the piece
+// of every FP32 input unchanged.
 __device__ void compile_model(const float* __restrict__ P, float* __restrict__ img) {
-  __shared__ double bp[kH];
-  __shared__ double ts[kH];
-  __shared__ unsigned act[kISegments];
-  __shared__ int nbp;
+  constexpr int S = kISegments;
+  __shared__ double bp[kH], ts[kH];
+  __shared__ unsigned act[S];
+  __shared__ double ps[S][kH], qs[S][kH], cr[S][kH], crs[S][kH];
+  __shared__ int ncr[S], poff[S + 1], m_s, nbp_s;
   const int tid = threadIdx.x, nt = blockDim.x;
+  const double inf = __builtin_inf();
   if (tid < kH) {
     const double w = P[kOffW1 + tid], b = P[kOffB1 + tid];
     const double t = -b / w;
-    bp[tid] = (w != 0.0 && t == t) ? t : __builtin_inf();
+    bp[tid] = (w != 0.0 && t == t) ? t : inf;
   }
   __syncthreads();
   if (tid < kH) {  // rank by (breakpoint, unit): a permutation of 0..31
@@ -303,29 +323,25 @@ __device__ void compile_model(const float* __restrict__ P, float* __restrict__ i
   }
   if (tid == 0) {
     int c = 0;
-    for (int i = 0; i < kH; ++i) c += bp[i] < __builtin_inf() ? 1 : 0;
-    nbp = c;
+    for (int i = 0; i < kH; ++i) c += bp[i] < inf ? 1 : 0;
+    m_s = c;
   }
   __syncthreads();
-  const int m = nbp;
-  if (tid < kISegments) {
-    double z;
-    if (m == 0) z = 0.0;
-    else if (tid == 0) z = ts[0] - fmax(1.0, fabs(ts[0]));
-    else if (tid >= m) z = ts[m - 1] + fmax(1.0, fabs(ts[m - 1]));
-    else z = 0.5 * ts[tid - 1] + 0.5 * ts[tid];
-    // (z may round to +-inf past a breakpoint near the float64 limit; units
-    // without a breakpoint are decided by b1 alone)
+  const int m = m_s;
+  // 2. active layer-1 units and layer 2's lines per segment
+  if (tid < S) {
+    const double z = inside(tid == 0 || m == 0 ? -inf : ts[min(tid, m) - 1],
+                            tid >= m ? inf : ts[tid]);
     unsigned mask = 0;
     for (int j = 0; j < kH; ++j) {
       const double w = P[kOffW1 + j], b = P[kOffB1 + j];
-      const bool on = bp[j] < __builtin_inf() ? w * z + b > 0.0 : b > 0.0;
+      const bool on = bp[j] < inf ? w * z + b > 0.0 : b > 0.0;
       mask |= on ? 1u << j : 0u;
     }
     act[tid] = mask;
   }
   __syncthreads();
-  for (int i = tid; i < kISegments * kH; i += nt) {
+  for (int i = tid; i < S * kH; i += nt) {
     const int seg = i / kH, k = i % kH;
     const unsigned mask = act[seg];
     double pk = 0.0, qk = P[kOffB2 + k];
@@ -336,16 +352,71 @@ __device__ void compile_model(const float* __restrict__ P, float* __restrict__ i
         qk += w2 * (double)P[kOffB1 + j];
       }
     }
-    img[kIRows + kIRowPitch * seg + 2 * k] = (float)pk;
-    img[kIRows + kIRowPitch * seg + 2 * k + 1] = (float)qk;
+    ps[seg][k] = pk;
+    qs[seg][k] = qk;
+    // 3. where unit k switches strictly inside the segment (+inf if not)
+    const double lo = seg == 0 || m == 0 ? -inf : ts[min(seg, m) - 1];
+    const double hi = seg >= m ? inf : ts[seg];
+    const double c = -qk / pk;
+    cr[seg][k] = (seg <= m && pk != 0.0 && c > lo && c < hi) ? c : inf;
   }
-  for (int i = tid; i < kISegments * (kIRowPitch - 2 * kH); i += nt)
-    img[kIRows + kIRowPitch * (i / (kIRowPitch - 2 * kH)) + 2 * kH + i % (kIRowPitch - 2 * kH)] = 0.0f;
-  for (int i = tid; i < kH; i += nt) {
-    img[kIT + i] = i < m ? (float)ts[i] : __builtin_inff();
-    img[kIW3 + i] = P[kOffW3 + i];
+  __syncthreads();
+  for (int i = tid; i < S * kH; i += nt) {  // sort each segment's points
+    const int seg = i / kH, k = i % kH;
+    const double c = cr[seg][k];
+    int rank = 0;
+    for (int j = 0; j < kH; ++j) rank += (cr[seg][j] < c || (cr[seg][j] == c && j < k)) ? 1 : 0;
+    crs[seg][rank] = c;
   }
-  if (tid < kIRows - kIB3) img[kIB3 + tid] = tid == 0 ? P[kOffB3] : 0.0f;
+  if (tid < S) {
+    int c = 0;
+    for (int j = 0; j < kH; ++j) c += cr[tid][j] < inf ? 1 : 0;
+    ncr[tid] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {  // pieces of segment s start at poff[s]
+    poff[0] = 0;
+    for (int seg = 0; seg < S; ++seg) poff[seg + 1] = poff[seg] + (seg <= m ? ncr[seg] + 1 : 0);
+    const int nb = poff[S] - 1;
+    int nbp = 2;
+    while (nbp < nb) nbp <<= 1;
+    nbp_s = nbp;
+  }
+  __syncthreads();
+  const int np = poff[S], nbp = nbp_s;
+  // 4. boundaries, padding and pieces
+  for (int i = tid; i < nbp; i += nt) {
+    float v = __builtin_inff();
+    if (i < np - 1) {
+      int seg = 0;
+      while (poff[seg + 1] <= i) ++seg;
+      const int j = i - poff[seg];
+      v = (float)(j < ncr[seg] ? crs[seg][j] : ts[seg]);
+    }
+    img[kIHead + i] = v;
+  }
+  for (int p = tid; p < np; p += nt) {
+    int seg = 0;
+    while (poff[seg + 1] <= p) ++seg;
+    const int j = p - poff[seg];
+    const double slo = seg == 0 ? -inf : ts[seg - 1], shi = seg >= m ? inf : ts[seg];  // seg <= m
+    const double z = inside(j == 0 ? slo : crs[seg][j - 1], j == ncr[seg] ? shi : crs[seg][j]);
+    double slope = 0.0, icpt = P[kOffB3];
+    for (int k = 0; k < kH; ++k) {
+      const double pk = ps[seg][k], qk = qs[seg][k];
+      if (pk != 0.0 ? pk * z + qk > 0.0 : qk > 0.0) {
+        slope += (double)P[kOffW3 + k] * pk;
+        icpt += (double)P[kOffW3 + k] * qk;
+      }
+    }
+    img[kIHead + nbp + 2 * p] = (float)slope;
+    img[kIHead + nbp + 2 * p + 1] = (float)icpt;
+  }
+  if (tid == 0) {
+    img[0] = __int_as_float(nbp);
+    img[1] = __int_as_float(np);
+    img[2] = img[3] = 0.0f;
+  }
 }
 
 __global__ __launch_bounds__(256) void compile_kernel(const float* __restrict__ P,
@@ -379,7 +450,7 @@ __device__ __forceinline__ int exact_index(const double* __restrict__ a, int n, 
 // search's own forward pass (so every lane of the wavefront calls it; lanes
 // without an entry pass valid = false and get 0).
 __device__ __forceinline__ int probe_error(const double* __restrict__ a, int n, const float* m,
-                                           const OutLayer& o, float u0, float inv, int i,
+                                           int nbp, float u0, float inv, int i,
                                            bool valid) {
   const int e = valid ? i : 0;
   double probe[3];
@@ -389,7 +460,7 @@ __device__ __forceinline__ int probe_error(const double* __restrict__ a, int n, 
   int worst = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const float p = mlp_eval(m, o, model_input(probe[c], u0, inv));
+    const float p = mlp_eval(m, nbp, model_input(probe[c], u0, inv));
     const int g = predicted_index(p, n);
     worst = max(worst, abs(g - exact_index(a, n, probe[c])));
   }
@@ -402,14 +473,14 @@ __global__ __launch_bounds__(256) void bound_kernel(const double* __restrict__ a
   __shared__ __align__(16) float model[kImageFloats];
   stage_image(model, img);
   __syncthreads();
-  const OutLayer o = load_out_layer(model);
+  const int nbp = image_bounds(model);
   int local = 0;
   const int stride = gridDim.x * blockDim.x;
   // the loop bound is uniform across the workgroup: every lane takes part
   // in every forward pass
   for (int base = blockIdx.x * blockDim.x; base < n; base += stride) {
     const int i = base + threadIdx.x;
-    local = max(local, probe_error(a, n, model, o, u0, inv, i, i < n));
+    local = max(local, probe_error(a, n, model, nbp, u0, inv, i, i < n));
   }
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(worst, local);
@@ -440,11 +511,11 @@ __global__ __launch_bounds__(256) void bound_many_kernel(const double* tables_a,
   stage_image(model, images + sl.i_off);
   if (threadIdx.x == 0) worst = 0;
   __syncthreads();
-  const OutLayer o = load_out_layer(model);
+  const int nbp = image_bounds(model);
   int local = 0;
   for (int base = 0; base < sl.n; base += blockDim.x) {
     const int i = base + threadIdx.x;
-    local = max(local, probe_error(a, sl.n, model, o, sl.u0, sl.inv, i, i < sl.n));
+    local = max(local, probe_error(a, sl.n, model, nbp, sl.u0, sl.inv, i, i < sl.n));
   }
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(&worst, local);
@@ -483,7 +554,7 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   stage_table(sa, a.table, a.n);
   stage_image(model, a.img);
   __syncthreads();
-  const OutLayer o = load_out_layer(model);
+  const int nbp = image_bounds(model);
   int fb = 0;
   for (; t < ntiles; t += gridDim.x) {
     const int64_t tn = t + gridDim.x;
@@ -493,10 +564,10 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
     if constexpr (CONV) {
       double xs[Q];
       convention_in<Q>(cur, xs);
-      search_learned<Q>(sa, a.n, model, o, a.E, a.u0, a.inv, xs, r, fell);
+      search_learned<Q>(sa, a.n, model, nbp, a.E, a.u0, a.inv, xs, r, fell);
       convention_out<Q>(a.n, cur, r);
     } else {
-      search_learned<Q>(sa, a.n, model, o, a.E, a.u0, a.inv, cur, r, fell);
+      search_learned<Q>(sa, a.n, model, nbp, a.E, a.u0, a.inv, cur, r, fell);
     }
     const int64_t base = t * per_tile + threadIdx.x;
     const bool full = (t + 1) * per_tile <= a.m;
@@ -521,11 +592,11 @@ __global__ __launch_bounds__(256) void predict_kernel(const float* __restrict__ 
   __shared__ __align__(16) float model[kImageFloats];
   stage_image(model, img);
   __syncthreads();
-  const OutLayer o = load_out_layer(model);
+  const int nbp = image_bounds(model);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
     const int64_t i = base + threadIdx.x;
-    const float p = mlp_eval(model, o, model_input(x[i < m ? i : 0], u0, inv));
+    const float p = mlp_eval(model, nbp, model_input(x[i < m ? i : 0], u0, inv));
     if (i < m) out[i] = p * (float)(n - 1);
   }
 }
@@ -546,6 +617,7 @@ struct ss_learned {
   int device = -1;
   float* d_params = nullptr;
   float* d_image = nullptr;  // the compiled model the search evaluates
+  int image_floats = 0;      // its floats in use (a multiple of 4)
   unsigned long long* d_fallbacks = nullptr;
   std::vector<float> params;
   ~ss_learned() {
@@ -558,7 +630,7 @@ struct ss_learned {
 namespace ss {
 namespace {
 
-constexpr int kLearnedQ = 1;
+constexpr int kLearnedQ = 4;  // measured best of 1, 2, 4, 6, 8 on a 2000-entry table
 constexpr int kLearnedBlock = 256;
 
 int check_learned_table(const double* table, int64_t n, std::vector<double>* host) {
@@ -666,7 +738,14 @@ int finish_learned(ss_learned* h) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   h->device = dev;
-  return measure_bound(h);
+  int rc = measure_bound(h);  // (synchronises the stream after the compile)
+  if (rc != SS_OK) return rc;
+  int head[2] = {0, 0};
+  SS_TRY_HIP(hipMemcpy(head, h->d_image, sizeof(head), hipMemcpyDeviceToHost));
+  if (head[0] < 2 || head[0] > kIMaxBounds || head[1] < 1 || head[1] > kIMaxPieces)
+    return fail(SS_ERR_UNSUPPORTED, "compiled model is malformed");
+  h->image_floats = image_used_floats(head[0], head[1]);
+  return SS_OK;
 }
 
 }  // namespace
@@ -871,7 +950,7 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
   DeviceInfo di;
   if ((rc = device_info(&di)) != SS_OK) return rc;
   const size_t tab = ((size_t)(h->n + SS_PAD) * 8 + 15) / 16 * 16;
-  const size_t lds = tab + kImageBytes;
+  const size_t lds = tab + (size_t)h->image_floats * 4;
   const void* kern = option(SS_OPT_CONVENTION)
                          ? reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 1>)
                          : reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 0>);

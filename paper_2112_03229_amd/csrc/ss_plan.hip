@@ -137,13 +137,13 @@ __device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* _
 template <int Q, int LEARN>
 __device__ __forceinline__ void search_staged(const Staged& st, const double* sa,
                                               const uint16_t* C, const float* model,
-                                              const OutLayer& o, const double (&x)[Q],
+                                              int nbp, const double (&x)[Q],
                                               int (&r)[Q], int (&fell)[Q]) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) fell[q] = 0;
   if constexpr (LEARN) {
     if (st.learned) {  // uniform across the workgroup
-      search_learned<Q>(sa, st.n, model, o, st.E, st.u0, st.inv, x, r, fell);
+      search_learned<Q>(sa, st.n, model, nbp, st.E, st.u0, st.inv, x, r, fell);
       return;
     }
   }
@@ -192,15 +192,15 @@ __device__ __forceinline__ void load_range(const double* __restrict__ x, TileRan
 // convention or (CONV = 1) the paper's.
 template <int Q, int LEARN, int CONV>
 __device__ __forceinline__ void search_tile(const Staged& st, const double* sa, const uint16_t* C,
-                                            const float* model, const OutLayer& o,
+                                            const float* model, int nbp,
                                             const double (&x)[Q], int (&r)[Q], int (&fell)[Q]) {
   if constexpr (CONV) {
     double xs[Q];
     convention_in<Q>(x, xs);
-    search_staged<Q, LEARN>(st, sa, C, model, o, xs, r, fell);
+    search_staged<Q, LEARN>(st, sa, C, model, nbp, xs, r, fell);
     convention_out<Q>(st.n, x, r);
   } else {
-    search_staged<Q, LEARN>(st, sa, C, model, o, x, r, fell);
+    search_staged<Q, LEARN>(st, sa, C, model, nbp, x, r, fell);
   }
 }
 
@@ -328,11 +328,11 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     stb = stage_desc(a.desc[a.pair_base + sg.seg], a.tables_b, a.bins, a.params, sb, Cb, Mb);
   if constexpr (INTERP) grid = stage_grid(a, sg.seg, sta.n, stb.n, lds_grid);
   __syncthreads();
-  // output layers of staged learned models (unused for other tables)
-  OutLayer oa{}, ob{};
+  // padded boundary counts of staged learned models (unused for other tables)
+  int oa = 0, ob = 0;
   if constexpr (LEARN) {
-    oa = load_out_layer(Ma);
-    if constexpr (PAIRED) ob = load_out_layer(Mb);
+    oa = image_bounds(Ma);
+    if constexpr (PAIRED) ob = image_bounds(Mb);
   }
   int fallbacks = 0;
   for (int64_t j = j0; j < j1; ++j) {
@@ -387,8 +387,8 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
       if constexpr (INTERP) grid = stage_grid(a, sg1.seg, sta.n, stb.n, lds_grid);
       __syncthreads();
       if constexpr (LEARN) {
-        oa = load_out_layer(Ma);
-        if constexpr (PAIRED) ob = load_out_layer(Mb);
+        oa = image_bounds(Ma);
+        if constexpr (PAIRED) ob = image_bounds(Mb);
       }
     }
     sg = sg1;
@@ -462,6 +462,7 @@ struct ss_plan {
   ss::WgStart* d_wg_start = nullptr;
   int* d_k = nullptr;
   float* d_pool = nullptr;                 // learned models, compiled (kImageFloats each)
+  size_t image_bytes = 0;                  // largest compiled model in use (16-byte multiple)
   unsigned long long* d_fallbacks = nullptr;
   int learned_tables = 0;
   int64_t total_tiles = 0;
@@ -495,7 +496,7 @@ namespace {
 constexpr int kPlanBlock = 512;
 constexpr int kPlanQ = 8;
 constexpr int kPairQ = 4;
-constexpr int kLearnedPlanQ = 1;          // registers: the model rows of each query
+constexpr int kLearnedPlanQ = 1;  // measured: 2 and 4 lengthen each tile and lose ~5%
 constexpr int kDefaultPlanLearnedSteps = 500;
 constexpr int kXcds = 8;                  // accelerator complex dies of an MI355X
 // Default workgroup ranges per XCD turn.  Measured on MI355X, chunks of 1 /
@@ -581,6 +582,17 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
   if (steps <= 0) steps = kDefaultPlanLearnedSteps;
   int rc = learned_train_slots(tables_a, tables_b, slots, p->d_pool, steps, 0.01f, 1);
   if (rc != SS_OK) return rc;
+  // every image's (boundaries, pieces) header: LDS is reserved for the largest
+  std::vector<int> head(2 * slots.size());
+  SS_TRY_HIP(hipMemcpy2D(head.data(), 2 * sizeof(int), p->d_pool, kImageBytes, 2 * sizeof(int),
+                         slots.size(), hipMemcpyDeviceToHost));
+  p->image_bytes = 0;
+  for (size_t i = 0; i < slots.size(); ++i) {
+    const int nbp = head[2 * i], np = head[2 * i + 1];
+    if (nbp < 2 || nbp > kIMaxBounds || np < 1 || np > kIMaxPieces)
+      return fail(SS_ERR_UNSUPPORTED, "compiled model " + std::to_string(i) + " is malformed");
+    p->image_bytes = std::max(p->image_bytes, (size_t)image_used_floats(nbp, np) * 4);
+  }
   for (size_t i = 0; i < slots.size(); ++i) {
     const int t = slot_desc[i];
     TableDesc& d = p->desc[t];
@@ -684,10 +696,10 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   }
   int model_a = (int)p->lds, model_b = (int)p->lds;
   if (learned) {  // one model image per staged table
-    p->lds += kImageBytes;
+    p->lds += p->image_bytes;
     if (p->mode == kPairJoint || p->mode == kPairInterp) {
       model_b = (int)p->lds;
-      p->lds += kImageBytes;
+      p->lds += p->image_bytes;
     }
   }
   // interpolation locates cells with the strict index (its own definition)

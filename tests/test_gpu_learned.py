@@ -88,11 +88,12 @@ def test_forward_matches_oracle(binding, gpu, inputs_mod, trained):
 
 
 def test_compiled_model_matches_layered_oracle(binding, gpu, inputs_mod):
-    """The search evaluates a compiled form of the model (layer 1 and layer
-    2's pre-activation as one linear piece per segment between layer 1's
-    breakpoints).  On weights built to stress it -- units with w1 = 0
-    (always on, always off), three units sharing one breakpoint (one with a
-    negative slope), a breakpoint near 1e30, breakpoints inside and
+    """The search evaluates a compiled form of the model: its pieces as a
+    continuous piecewise-linear function of z (bounded by layer 1's
+    breakpoints and by the sign changes of layer 2's pre-activations), each
+    one (slope, intercept).  On weights built to stress it -- units with
+    w1 = 0 (always on, always off), three units sharing one breakpoint (one
+    with a negative slope), a breakpoint near 1e30, breakpoints inside and
     outside [0, 1] -- and inputs on both sides of every breakpoint, its
     output must equal the float64 layered forward pass to FP32 rounding of
     the terms' magnitudes."""
