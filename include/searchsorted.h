@@ -401,8 +401,10 @@ SS_API int ss_learned_search(ss_learned *h, const double *targets, int64_t m,
  * target (device in, device out); asynchronous. */
 SS_API int ss_learned_predict(ss_learned *h, const double *x, int64_t m, float *out_pos);
 
-/* info (host, 6 doubles): {E, n, steps, final training loss, log2 a[0],
- * 1 / (log2 a[n-1] - log2 a[0])}.  SYNCHRONOUS only in that it reads the
+/* info (host, count >= 6 doubles): {E, n, steps, final training loss,
+ * log2 a[0], 1 / (log2 a[n-1] - log2 a[0])}; with count >= 8 also the
+ * compiled model's piece count and its padded boundary slots (a power of two,
+ * at least 2 and at least pieces - 1).  SYNCHRONOUS only in that it reads the
  * handle's host copy. */
 SS_API int ss_learned_info(const ss_learned *h, double *info, int count);
 

@@ -618,6 +618,7 @@ struct ss_learned {
   float* d_params = nullptr;
   float* d_image = nullptr;  // the compiled model the search evaluates
   int image_floats = 0;      // its floats in use (a multiple of 4)
+  int pieces = 0, bound_slots = 0;  // its pieces and padded boundary slots
   unsigned long long* d_fallbacks = nullptr;
   std::vector<float> params;
   ~ss_learned() {
@@ -745,6 +746,8 @@ int finish_learned(ss_learned* h) {
   if (head[0] < 2 || head[0] > kIMaxBounds || head[1] < 1 || head[1] > kIMaxPieces)
     return fail(SS_ERR_UNSUPPORTED, "compiled model is malformed");
   h->image_floats = image_used_floats(head[0], head[1]);
+  h->bound_slots = head[0];
+  h->pieces = head[1];
   return SS_OK;
 }
 
@@ -989,6 +992,10 @@ int ss_learned_info(const ss_learned* h, double* info, int count) {
   info[3] = h->loss;
   info[4] = h->u0;
   info[5] = h->inv;
+  if (count >= 8) {
+    info[6] = h->pieces;
+    info[7] = h->bound_slots;
+  }
   return SS_OK;
 }
 

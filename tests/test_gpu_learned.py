@@ -87,6 +87,31 @@ def test_forward_matches_oracle(binding, gpu, inputs_mod, trained):
     assert err.max() < 0.05
 
 
+def compiled_vs_layered(li, gpu, table, w, extra_z):
+    """Largest |compiled - layered| / tolerance over inputs spread on
+    [-0.2, 1.2] plus extra_z (model inputs; |z| < 2 keeps x inside the FP32
+    range the model input is formed in): the compiled FP32 output against
+    the float64 layered forward pass, to FP32 rounding of the terms'
+    magnitudes and of the input."""
+    wd = w.astype(np.float64)
+    w1, b1 = wd[0:32], wd[32:64]
+    W2 = wd[64:64 + 1024].reshape(32, 32)
+    b2, w3, b3 = wd[1088:1120], wd[1120:1152], wd[1152]
+    extra_z = np.asarray(extra_z, dtype=np.float64)
+    z = np.concatenate([np.linspace(-0.2, 1.2, 20001), extra_z[np.abs(extra_z) < 2]])
+    u0, u1 = np.log2(table[0]), np.log2(table[-1])
+    x = np.exp2(u0 + z * (u1 - u0))
+    p = li.predict(torch.from_numpy(x).to(gpu)).cpu().numpy().astype(np.float64)
+    p /= table.size - 1
+    zr = OL.model_input(x, table)
+    want = OL.forward(wd, zr)
+    mag = np.abs(w3) @ (np.abs(W2) @ (np.outer(np.abs(w1), np.abs(zr)) + np.abs(b1)[:, None])
+                        + np.abs(b2)[:, None]) + abs(b3)
+    slope = np.abs(w3) @ (np.abs(W2) @ np.abs(w1))
+    tol = 4e-6 * mag + 4e-6 * slope * np.maximum(1.0, np.abs(zr))
+    return np.abs(p - want) / tol
+
+
 def test_compiled_model_matches_layered_oracle(binding, gpu, inputs_mod):
     """The search evaluates a compiled form of the model: its pieces as a
     continuous piecewise-linear function of z (bounded by layer 1's
@@ -112,29 +137,59 @@ def test_compiled_model_matches_layered_oracle(binding, gpu, inputs_mod):
     w = np.concatenate([w1, b1, W2.reshape(-1), b2, w3, [b3]]).astype(np.float32)
     li = binding.LearnedIndex(t, weights=w)
     wd = w.astype(np.float64)
-    w1, b1 = wd[0:32], wd[32:64]
-    W2 = wd[64:64 + 1024].reshape(32, 32)
-    b2, w3, b3 = wd[1088:1120], wd[1120:1152], wd[1152]
-    # inputs: a spread over [-0.2, 1.2] and both sides of every breakpoint
-    # with |z| < 2 (x then stays inside the FP32 range that the model input
-    # is formed in)
     with np.errstate(divide="ignore", invalid="ignore"):
-        bp = -b1 / w1
-    bp = bp[np.isfinite(bp) & (np.abs(bp) < 2)]
-    z = np.concatenate([np.linspace(-0.2, 1.2, 20001), bp - 1e-6, bp + 1e-6, bp])
-    u0, u1 = np.log2(table[0]), np.log2(table[-1])
-    x = np.exp2(u0 + z * (u1 - u0))
-    p = li.predict(torch.from_numpy(x).to(gpu)).cpu().numpy().astype(np.float64)
-    p /= table.size - 1
-    zr = OL.model_input(x, table)
-    want = OL.forward(wd, zr)
-    mag = np.abs(w3) @ (np.abs(W2) @ (np.outer(np.abs(w1), np.abs(zr)) + np.abs(b1)[:, None])
-                        + np.abs(b2)[:, None]) + abs(b3)
-    slope = np.abs(w3) @ (np.abs(W2) @ np.abs(w1))
-    tol = 4e-6 * mag + 4e-6 * slope * np.maximum(1.0, np.abs(zr))
-    err = np.abs(p - want)
-    say(f"compiled vs layered: worst err / tol {np.max(err / tol):.3f}")
-    assert np.all(err <= tol), (np.argmax(err / tol), err.max())
+        bp = -wd[32:64] / wd[0:32]
+    bp = bp[np.isfinite(bp)]
+    r = compiled_vs_layered(li, gpu, table, w, np.concatenate([bp - 1e-6, bp + 1e-6, bp]))
+    say(f"compiled vs layered: worst err / tol {r.max():.2e}, pieces {li.info()['pieces']}")
+    assert np.all(r <= 1.0), (np.argmax(r), r.max())
+
+
+def test_compiled_model_with_the_most_pieces(binding, gpu, oracle_mod, inputs_mod):
+    """A model with as many pieces as the compiled form holds.  Layer 1's
+    breakpoints are j / 32 (w1 = 1, b1 = -j / 32).  Every layer-2 unit's
+    pre-activation is a zigzag between -1 + d_k and 1 + d_k (slope +-64 on
+    alternate segments, |d_k| < 0.4 distinct), so it changes sign once in
+    each of the 32 segments right of z = 0 and never left of it.  That gives
+    32 + 32 * 32 = 1056 piece boundaries: 1057 pieces and 2048 boundary
+    slots, the largest padding.  The compiled output must match the layered
+    forward pass on both sides of every boundary, and the search, whose
+    model is useless for this table, must still return exact indices."""
+    table = inputs_mod.learned_table()
+    t = torch.from_numpy(table).to(gpu)
+    j = np.arange(32)
+    w1 = np.ones(32)
+    b1 = -j / 32.0
+    row = np.where(j == 0, 64.0, 128.0 * (-1.0) ** j)
+    W2 = np.tile(row, (32, 1))
+    d = (j - 15.5) / 40.0
+    b2 = -1.0 + d
+    w3 = np.random.default_rng(11).normal(0, 0.3, 32)
+    w = np.concatenate([w1, b1, W2.reshape(-1), b2, w3, [0.05]]).astype(np.float32)
+    li = binding.LearnedIndex(t, weights=w)
+    info = li.info()
+    say(f"most pieces: {info}")
+    assert info["pieces"] == 1057 and info["bound_slots"] == 2048
+    # probes around every boundary, located from the layered weights: layer
+    # 1's breakpoints and, in each segment s (units 0..s-1 active), where
+    # unit k's line P z + Q crosses zero
+    wd = w.astype(np.float64)
+    w1d, b1d = wd[0:32], wd[32:64]
+    W2d, b2d = wd[64:1088].reshape(32, 32), wd[1088:1120]
+    probes = [-b1d / w1d]
+    for s_ in range(1, 33):
+        P = W2d[:, :s_] @ w1d[:s_]
+        Q = b2d + W2d[:, :s_] @ b1d[:s_]
+        probes.append(-Q / P)
+    bz = np.concatenate(probes)
+    r = compiled_vs_layered(li, gpu, table, w, np.concatenate([bz - 2e-6, bz + 2e-6, bz]))
+    say(f"most pieces: worst err / tol {r.max():.2e}")
+    assert np.all(r <= 1.0), (np.argmax(r), r.max())
+    x = targets_for(inputs_mod, table, 100003, seed=17)
+    want = oracle_mod.search_lt(table, x)
+    got = li.search(torch.from_numpy(x).to(gpu)).cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], want[bad[:5]])
 
 
 @pytest.mark.parametrize("which", ["init", "trained"])
