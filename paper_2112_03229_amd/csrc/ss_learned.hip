@@ -10,11 +10,10 @@
 //                  batch in a fixed order (deterministic): the 1024 W2
 //                  gradients as a 32 x 256 x 32 product on the matrix
 //                  cores, the other 129 one thread each.
-//   compile_kernel the trained model as the search evaluates it: layer 1
-//                  and layer 2's pre-activation are piecewise linear in the
-//                  one input, so each of the at most 33 segments between
-//                  layer 1's breakpoints gets its 32 slopes and offsets
-//                  (formed in float64, rounded once).
+//   compile_kernel the trained model as the search evaluates it: the
+//                  network is piecewise linear in its one input, so it is
+//                  listed as its pieces (sorted boundaries and one slope
+//                  and intercept each, formed in float64, rounded once).
 //   bound_kernel   E = 1 + max |g(x) - idx(x)| over the probes, with the
 //                  compiled model.
 //   learned_kernel the search: table and compiled model in LDS, Q targets

@@ -51,7 +51,6 @@ constexpr int kImageFloats = kIHead + kIMaxBounds + 2 * kIMaxPieces + 2;  // 16-
 constexpr int kImageBytes = kImageFloats * 4;
 static_assert(kImageBytes % 16 == 0, "16-byte copies");
 
-// Floats of an image in use (header, padded boundaries, pieces).
 // Floats in use of an image with nbp padded boundaries and np pieces (a
 // multiple of 4, for 16-byte staging).
 __host__ __device__ constexpr int image_used_floats(int nbp, int np) {
