@@ -77,19 +77,36 @@ __device__ __forceinline__ int image_bounds(const float* m) {
   return __builtin_amdgcn_readfirstlane(__float_as_int(m[0]));
 }
 
-// The model's output p(z) from a compiled image in LDS with nbp padded
-// boundaries: piece i = #{boundaries < z} (0 for NaN), then one fused
-// multiply-add.  Lanes are independent.
-__device__ __forceinline__ float mlp_eval(const float* m, int nbp, float z) {
+// The model's outputs p(z) for Q inputs per lane from a compiled image in
+// LDS with nbp padded boundaries: piece i = #{boundaries < z} (0 for NaN),
+// then one fused multiply-add.  The bisection's trip count, log2(nbp), is
+// uniform, and each step issues the Q lanes' reads together.  Lanes are
+// independent.
+template <int Q>
+__device__ __forceinline__ void mlp_eval_q(const float* m, int nbp, const float (&z)[Q],
+                                           float (&p)[Q]) {
   const float* b = m + kIHead;
-  int i = 0;
+  int i[Q];
 #pragma unroll
-  for (int step = kIMaxBounds / 2; step >= 1; step >>= 1)
-    if (step < nbp) i = (b[i + step - 1] < z) ? i + step : i;  // uniform guard
-  i += (b[i] < z) ? 1 : 0;
+  for (int q = 0; q < Q; ++q) i[q] = 0;
+  for (int step = nbp >> 1; step >= 1; step >>= 1) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) i[q] = (b[i[q] + step - 1] < z[q]) ? i[q] + step : i[q];
+  }
   typedef float f2 __attribute__((ext_vector_type(2)));
-  const f2 sq = *reinterpret_cast<const f2*>(m + kIHead + nbp + 2 * i);
-  return fmaf(sq.x, z, sq.y);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    i[q] += (b[i[q]] < z[q]) ? 1 : 0;
+    const f2 sq = *reinterpret_cast<const f2*>(m + kIHead + nbp + 2 * i[q]);
+    p[q] = fmaf(sq.x, z[q], sq.y);
+  }
+}
+
+__device__ __forceinline__ float mlp_eval(const float* m, int nbp, float z) {
+  const float zq[1] = {z};
+  float p[1];
+  mlp_eval_q<1>(m, nbp, zq, p);
+  return p[0];
 }
 
 // Predicted index g = floor(p (n-1)) clamped to [-1, n-1].  Any p, even NaN
@@ -106,28 +123,39 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
                                                const float* m, int nbp, int E, float u0,
                                                float inv, const double (&x)[Q], int (&r)[Q],
                                                int (&fell_back)[Q]) {
-  float p[Q];
+  float z[Q], p[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) p[q] = mlp_eval(m, nbp, model_input(x[q], u0, inv));
+  for (int q = 0; q < Q; ++q) z[q] = model_input(x[q], u0, inv);
+  mlp_eval_q<Q>(m, nbp, z, p);
   int step = 1;
   while (step * 2 <= 2 * E + 1) step *= 2;  // >= half the window length
+  int pos[Q];
+  unsigned ok = 0;  // bit q: target q's window was verified
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int g = predicted_index(p[q], n);
     const int L = max(g - E, -1), R = min(g + E, n - 1);
     const bool lo_ok = L < 0 || sa[max(L, 0)] < x[q];
     const bool hi_ok = R >= n - 1 || x[q] <= sa[min(R + 1, n - 1)];
-    fell_back[q] = !(lo_ok && hi_ok);
-    if (lo_ok && hi_ok) {
-      // pos = #{a < x} lies in [L+1, R+1]: every entry up to a[L] is below
-      // x and every entry from a[R+1] on is not, so the steps need no upper
-      // bound (a read at or past R+1 never advances pos; reads past the
-      // table are clamped to its +inf sentinel a[n]).  2 step - 1 >= 2E
-      // covers the window.
-      int pos = L + 1;
-      for (int s = step; s >= 1; s >>= 1) pos = (sa[min(pos + s - 1, n)] < x[q]) ? pos + s : pos;
-      r[q] = pos - 1;
-    } else {
+    ok |= (lo_ok && hi_ok) ? 1u << q : 0u;
+    fell_back[q] = (lo_ok && hi_ok) ? 0 : 1;
+    pos[q] = L + 1;
+  }
+  // Window search, all Q together.  If the window is verified, pos = #{a <
+  // x} lies in [L+1, R+1]: every entry up to a[L] is below x and every
+  // entry from a[R+1] on is not, so the steps need no upper bound (a read
+  // at or past R+1 never advances pos; reads past the table are clamped to
+  // its +inf sentinel a[n]).  2 step - 1 >= 2E covers the window.  Lanes
+  // whose window failed run the same steps harmlessly and are redone below.
+  for (int s = step; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      pos[q] = (sa[min(pos[q] + s - 1, n)] < x[q]) ? pos[q] + s : pos[q];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    r[q] = pos[q] - 1;
+    if (!((ok >> q) & 1u)) {  // fallback: bisection over the whole table
       int base = 0, len = n;
       while (len > 1) {
         const int half = len >> 1;

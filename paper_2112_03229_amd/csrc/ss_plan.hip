@@ -496,7 +496,6 @@ namespace {
 constexpr int kPlanBlock = 512;
 constexpr int kPlanQ = 8;
 constexpr int kPairQ = 4;
-constexpr int kLearnedPlanQ = 1;  // measured: 2 and 4 lengthen each tile and lose ~5%
 constexpr int kDefaultPlanLearnedSteps = 500;
 constexpr int kXcds = 8;                  // accelerator complex dies of an MI355X
 // Default workgroup ranges per XCD turn.  Measured on MI355X, chunks of 1 /
@@ -621,13 +620,13 @@ const void* plan_kernel(int mode, bool learned, bool conv) {
     case kPairInterp:
       return reinterpret_cast<const void*>(&multi_kernel<kPairInterp, kPairQ, 0, 0>);
     case kPairJoint:
-      return learned ? plan_kernel_conv<kPairJoint, kLearnedPlanQ, 1>(conv)
+      return learned ? plan_kernel_conv<kPairJoint, kPairQ, 1>(conv)
                      : plan_kernel_conv<kPairJoint, kPairQ, 0>(conv);
     case kPairSplit:
-      return learned ? plan_kernel_conv<kPairSplit, kLearnedPlanQ, 1>(conv)
+      return learned ? plan_kernel_conv<kPairSplit, kPlanQ, 1>(conv)
                      : plan_kernel_conv<kPairSplit, kPlanQ, 0>(conv);
     default:
-      return learned ? plan_kernel_conv<kBatched, kLearnedPlanQ, 1>(conv)
+      return learned ? plan_kernel_conv<kBatched, kPlanQ, 1>(conv)
                      : plan_kernel_conv<kBatched, kPlanQ, 0>(conv);
   }
 }
@@ -669,8 +668,9 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   }
 
   p->block = option(SS_OPT_BLOCK_SIZE) > 0 ? (int)option(SS_OPT_BLOCK_SIZE) : kPlanBlock;
-  p->q = p->learned_tables > 0 ? kLearnedPlanQ
-         : (p->mode == kPairJoint || p->mode == kPairInterp ? kPairQ : kPlanQ);
+  // learned plans take the same targets per lane as plain ones (measured
+  // on the batched and split forms: 8 beat 4, 2 and 1)
+  p->q = p->mode == kPairJoint || p->mode == kPairInterp ? kPairQ : kPlanQ;
   const int64_t per_tile = (int64_t)p->block * p->q;
   // tiles of every segment, numbered back to back; a segment's positions are
   // taken relative to the start of its own target array
