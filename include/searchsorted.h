@@ -393,7 +393,10 @@ SS_API int ss_learned_save(const ss_learned *h, const char *path);
  * malformed file or a size mismatch.  SYNCHRONOUS. */
 SS_API int ss_learned_load(const double *table, int64_t n, const char *path, ss_learned **out);
 
-/* out_idx[k] = idx(targets[k]) through the learned index; asynchronous. */
+/* out_idx[k] = idx(targets[k]) through the learned index; asynchronous.
+ * The table is staged in LDS with the compiled model when both fit in
+ * 64 KB (n up to about 8000); larger tables are read in place from global
+ * memory, with the same results. */
 SS_API int ss_learned_search(ss_learned *h, const double *targets, int64_t m,
                              int32_t *out_idx);
 

@@ -536,13 +536,16 @@ struct LearnedArgs {
   int n;
   int E;
   float u0, inv;
-  int model_off;  // byte offset of the model's LDS image (after the table)
+  int model_off;  // byte offset of the model's LDS image (after the table; 0 if not staged)
 };
 
-template <int Q, int CONV>
+// GLOBAL = 1: the table is too large to stage and is read in place from
+// global memory (L2-resident after the first reads); only the model is
+// staged.
+template <int Q, int CONV, int GLOBAL>
 __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
-  double* sa = reinterpret_cast<double*>(lds);
+  const double* sa = GLOBAL ? a.table : reinterpret_cast<const double*>(lds);
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
   const int64_t ntiles = (a.m + per_tile - 1) / per_tile;
@@ -550,7 +553,7 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   int64_t t = blockIdx.x;
   double cur[Q];
   if (t < ntiles) load_tile<Q>(a.x, a.m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= a.m, cur);
-  stage_table(sa, a.table, a.n);
+  if constexpr (!GLOBAL) stage_table(reinterpret_cast<double*>(lds), a.table, a.n);
   stage_image(model, a.img);
   __syncthreads();
   const int nbp = image_bounds(model);
@@ -563,10 +566,10 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
     if constexpr (CONV) {
       double xs[Q];
       convention_in<Q>(cur, xs);
-      search_learned<Q>(sa, a.n, model, nbp, a.E, a.u0, a.inv, xs, r, fell);
+      search_learned<Q, !GLOBAL>(sa, a.n, model, nbp, a.E, a.u0, a.inv, xs, r, fell);
       convention_out<Q>(a.n, cur, r);
     } else {
-      search_learned<Q>(sa, a.n, model, nbp, a.E, a.u0, a.inv, cur, r, fell);
+      search_learned<Q, !GLOBAL>(sa, a.n, model, nbp, a.E, a.u0, a.inv, cur, r, fell);
     }
     const int64_t base = t * per_tile + threadIdx.x;
     const bool full = (t + 1) * per_tile <= a.m;
@@ -632,6 +635,7 @@ namespace {
 
 constexpr int kLearnedQ = 4;  // measured best of 1, 2, 4, 6, 8 on a 2000-entry table
 constexpr int kLearnedBlock = 256;
+constexpr size_t kLearnedStageLimit = 65536;  // LDS bytes: table + model, if staged
 
 int check_learned_table(const double* table, int64_t n, std::vector<double>* host) {
   if (n < 2 || n > 65535) return fail(SS_ERR_INVALID_ARG, "n must be in 2..65535");
@@ -951,11 +955,17 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
     return rc;
   DeviceInfo di;
   if ((rc = device_info(&di)) != SS_OK) return rc;
-  const size_t tab = ((size_t)(h->n + SS_PAD) * 8 + 15) / 16 * 16;
+  // the table is staged with the model when both fit, else read in place
+  size_t tab = ((size_t)(h->n + SS_PAD) * 8 + 15) / 16 * 16;
+  const bool staged = tab + (size_t)h->image_floats * 4 <= kLearnedStageLimit;
+  if (!staged) tab = 0;
   const size_t lds = tab + (size_t)h->image_floats * 4;
-  const void* kern = option(SS_OPT_CONVENTION)
-                         ? reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 1>)
-                         : reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 0>);
+  const bool conv = option(SS_OPT_CONVENTION) != 0;
+  const void* kern =
+      staged ? (conv ? reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 1, 0>)
+                     : reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 0, 0>))
+             : (conv ? reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 1, 1>)
+                     : reinterpret_cast<const void*>(&learned_kernel<kLearnedQ, 0, 1>));
   const int64_t per_tile = (int64_t)kLearnedBlock * kLearnedQ;
   const int64_t ntiles = (m + per_tile - 1) / per_tile;
   int64_t grid = (int64_t)blocks_per_cu(kern, kLearnedBlock, lds) * di.num_cus * 4;

@@ -117,8 +117,10 @@ __device__ __forceinline__ int predicted_index(float p, int n) {
 }
 
 // The verified window search for Q targets per lane.  m is the model's
-// compiled image in LDS, nbp its padded boundary count.
-template <int Q>
+// compiled image in LDS, nbp its padded boundary count.  sa is the table:
+// staged in LDS with +inf sentinels from a[n] on (SENTINEL), or read in
+// place from global memory (no sentinel; reads stay inside [0, n)).
+template <int Q, bool SENTINEL = true>
 __device__ __forceinline__ void search_learned(const double* __restrict__ sa, int n,
                                                const float* m, int nbp, int E, float u0,
                                                float inv, const double (&x)[Q], int (&r)[Q],
@@ -144,13 +146,21 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
   // Window search, all Q together.  If the window is verified, pos = #{a <
   // x} lies in [L+1, R+1]: every entry up to a[L] is below x and every
   // entry from a[R+1] on is not, so the steps need no upper bound (a read
-  // at or past R+1 never advances pos; reads past the table are clamped to
-  // its +inf sentinel a[n]).  2 step - 1 >= 2E covers the window.  Lanes
-  // whose window failed run the same steps harmlessly and are redone below.
+  // at or past R+1 never advances pos; a read past the table counts as
+  // +inf: the sentinel a[n], or an explicit test without one).
+  // 2 step - 1 >= 2E covers the window.  Lanes whose window failed run the
+  // same steps harmlessly and are redone below.
   for (int s = step; s >= 1; s >>= 1) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-      pos[q] = (sa[min(pos[q] + s - 1, n)] < x[q]) ? pos[q] + s : pos[q];
+    for (int q = 0; q < Q; ++q) {
+      const int k = pos[q] + s - 1;
+      bool lt;
+      if constexpr (SENTINEL)
+        lt = sa[min(k, n)] < x[q];
+      else
+        lt = k < n && sa[min(k, n - 1)] < x[q];
+      pos[q] = lt ? pos[q] + s : pos[q];
+    }
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {

@@ -253,6 +253,39 @@ def test_small_tables_and_ragged_sizes(binding, gpu, oracle_mod, inputs_mod):
             assert np.array_equal(li.search(torch.from_numpy(x).to(gpu)).cpu().numpy(), want)
 
 
+@pytest.mark.parametrize("n", [8200, 65535])
+def test_tables_too_large_to_stage(binding, gpu, oracle_mod, inputs_mod, n):
+    """Tables whose staged copy and model exceed the 64 KB staging limit are
+    read in place from global memory: exact in both conventions, with a
+    trained model (n = 8200) and with one that is useless for the table (the
+    largest n, from given weights, so every window is wide or fails)."""
+    rng = np.random.default_rng(n)
+    table = np.sort(np.exp(rng.uniform(np.log(1e-8), np.log(1e6), n)))
+    table[0], table[-1] = 1e-8, 1e6
+    t = torch.from_numpy(table).to(gpu)
+    say(f"case learned global table n={n}")
+    if n <= 10000:
+        li = binding.LearnedIndex(t, steps=300, seed=3)
+    else:
+        w = np.random.default_rng(5).normal(0, 0.5, 1153).astype(np.float32)
+        li = binding.LearnedIndex(t, weights=w)
+    x = targets_for(inputs_mod, table, 200003, seed=n)
+    xd = torch.from_numpy(x).to(gpu)
+    got = li.search(xd).cpu().numpy()
+    want = oracle_mod.search_lt(table, x)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], want[bad[:5]])
+    say(f"E {li.info()['E']} fallbacks {li.fallbacks()}")
+    binding.set_option(binding.OPT_CONVENTION, 1)
+    try:
+        got = li.search(xd).cpu().numpy()
+    finally:
+        binding.set_option(binding.OPT_CONVENTION, 0)
+    want = oracle_mod.search_le_clamped(table, x)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:5], got[bad[:5]], want[bad[:5]])
+
+
 def test_rejects_bad_tables(binding, gpu):
     neg = torch.tensor([-1.0, 2.0, 3.0], dtype=torch.float64, device=gpu)
     with pytest.raises(binding.SearchSortedError):
