@@ -252,7 +252,9 @@ typedef struct ss_plan ss_plan;
 /* Plan for T tables stored back to back (CSR):
  *   tables    : device, float64; table t is tables[table_off[t] .. table_off[t+1])
  *   table_off : host, T+1 non-decreasing int64 offsets, table_off[0] == 0;
- *               each table holds at most 65535 entries and must be sorted
+ *               each table must be sorted and is staged whole in LDS: at
+ *               most 6136 entries (48 KB with its +inf padding), else
+ *               SS_ERR_UNSUPPORTED (single-table calls take any size)
  *   T         : 1 <= T <= 2^20
  *   query_off : host, T+1 non-decreasing int64 offsets, query_off[0] == 0;
  *               the targets (and indices) of table t are positions
@@ -272,7 +274,12 @@ SS_API int ss_multi_search(ss_plan *plan, const double *targets, int32_t *out_id
 
 /* Paired lookup (the density and temperature axes of EOS tables, Sec. 1):
  * M materials, each with a density table and a temperature table (CSR as
- * above, each <= 65535 entries), and pair_off (host, M+1) grouping the
+ * above, each at most 6136 entries; in the joint form, SS_OPT_PAIR_JOINT,
+ * and in interpolation plans, which stage both axes at once, the largest
+ * density table and the largest temperature table together at most 6128:
+ * their two staged copies, each with 8 +inf entries and rounded up to 16
+ * bytes, within 48 KB),
+ * and pair_off (host, M+1) grouping the
  * query pairs by material.  ss_pair_search writes, for every pair k of
  * material j, out_rho[k] = idx over density table j of rho[k] and
  * out_t[k] = idx over temperature table j of temp[k], in one launch. */

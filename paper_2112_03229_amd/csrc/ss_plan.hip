@@ -862,7 +862,9 @@ int ss_multi_plan_create(const double* tables, const int64_t* table_off, int32_t
   size_t max_tab = 16, max_bins = 0;
   for (int t = 0; t < T; ++t)
     max_tab = std::max(max_tab, align16((size_t)(table_off[t + 1] - table_off[t] + SS_PAD) * 8));
-  if (max_tab > kPlanLdsBudget) return fail_delete(p, "tables too large for LDS");
+  if (max_tab > kPlanLdsBudget)
+    return fail_delete(p, "a table exceeds the 48 KB LDS staging budget (6136 entries)",
+                       SS_ERR_UNSUPPORTED);
   int64_t pool = 0;
   for (int t = 0; t < T; ++t) {
     const int n = (int)(table_off[t + 1] - table_off[t]);
@@ -985,7 +987,11 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
   }
   size_t budget_a, budget_b;
   if (p->mode == kPairJoint || p->mode == kPairInterp) {
-    if (tab_a + tab_b > kPlanLdsBudget) return fail_delete(p, "tables too large for LDS");
+    if (tab_a + tab_b > kPlanLdsBudget)
+      return fail_delete(p,
+                         "the largest density and temperature tables together exceed the "
+                         "48 KB LDS staging budget (6128 entries)",
+                         SS_ERR_UNSUPPORTED);
     // the bin budget is split in proportion to the two axes' largest tables
     const size_t bins_total = kPlanLdsBudget - tab_a - tab_b;
     budget_a = bins_total * tab_a / (tab_a + tab_b);
@@ -993,7 +999,9 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
   } else {
     // one table at a time: either axis may use what the largest table leaves
     tab_a = tab_b = std::max(tab_a, tab_b);
-    if (tab_a > kPlanLdsBudget) return fail_delete(p, "tables too large for LDS");
+    if (tab_a > kPlanLdsBudget)
+      return fail_delete(p, "a table exceeds the 48 KB LDS staging budget (6136 entries)",
+                         SS_ERR_UNSUPPORTED);
     budget_a = budget_b = kPlanLdsBudget - tab_a;
   }
   int64_t pool = 0;

@@ -136,6 +136,43 @@ def test_batched_rejects_bad_arguments(binding, gpu, inputs_mod):
         plan.search(torch.zeros(11, dtype=torch.float64, device=gpu))
 
 
+def test_largest_stageable_tables(binding, gpu, oracle_mod, inputs_mod, pair_form):
+    """A table of 6136 entries (48 KB staged with its padding) is the
+    largest a plan takes: exact at that size; one entry more is refused
+    with SS_ERR_UNSUPPORTED.  Paired plans: each table up to 6136 in the
+    split form; in the joint form the two axes together up to 6128."""
+    rng = np.random.default_rng(61)
+    def table(n):
+        return np.sort(np.exp(rng.uniform(np.log(1e-6), np.log(1e6), n)))
+    big, small = table(6136), table(40)
+    x = inputs_mod.table_targets(big, 50000, seed=3)
+    tb = torch.from_numpy(np.concatenate([small, big])).to(gpu)
+    plan = binding.MultiPlan(tb, [0, 40, 6176], [0, 1000, 51000])
+    xs = np.concatenate([inputs_mod.table_targets(small, 1000, seed=4), x])
+    got = plan.search(torch.from_numpy(xs).to(gpu)).cpu().numpy()
+    want = np.concatenate([oracle_mod.search_lt(small, xs[:1000]), oracle_mod.search_lt(big, x)])
+    assert np.array_equal(got, want)
+    plan.close()
+    over = torch.from_numpy(table(6137)).to(gpu)
+    with pytest.raises(binding.SearchSortedError) as e:
+        binding.MultiPlan(over, [0, 6137], [0, 10])
+    assert e.value.code == -6
+    rho, tt = table(6136) if pair_form == 0 else table(6000), table(128)
+    r = inputs_mod.table_targets(rho, 20000, seed=5)
+    tq = inputs_mod.table_targets(tt, 20000, seed=6)
+    pp = binding.PairPlan(torch.from_numpy(rho).to(gpu), [0, rho.size],
+                          torch.from_numpy(tt).to(gpu), [0, tt.size], [0, 20000])
+    out_r, out_t = pp.search(torch.from_numpy(r).to(gpu), torch.from_numpy(tq).to(gpu))
+    assert np.array_equal(out_r.cpu().numpy(), oracle_mod.search_lt(rho, r))
+    assert np.array_equal(out_t.cpu().numpy(), oracle_mod.search_lt(tt, tq))
+    pp.close()
+    if pair_form == 1:
+        with pytest.raises(binding.SearchSortedError) as e:
+            binding.PairPlan(torch.from_numpy(rho).to(gpu), [0, rho.size],
+                             torch.from_numpy(table(129)).to(gpu), [0, 129], [0, 10])
+        assert e.value.code == -6
+
+
 @pytest.fixture(params=[0, 1], ids=["split", "joint"])
 def pair_form(request, binding):
     """Both launch forms of paired plans: the density and temperature
