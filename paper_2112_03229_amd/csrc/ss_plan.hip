@@ -691,8 +691,6 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
     p->args.lds_grid = (int)p->lds;
     p->args.grid_cap = p->grid_cap;
     p->lds += (size_t)p->grid_cap * sizeof(double);
-    SS_TRY_HIP(hipFuncSetAttribute(plan_kernel(p->mode, false, false),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)p->lds));
   }
   int model_a = (int)p->lds, model_b = (int)p->lds;
   if (learned) {  // one model image per staged table
@@ -709,6 +707,15 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   int rc = device_info(&di);
   if (rc != SS_OK) return rc;
   p->device = di.device;
+  // staged grids and learned models can take a workgroup past the 64 KB a
+  // launch gets without asking
+  if (p->lds > di.lds_per_block)
+    return fail(SS_ERR_UNSUPPORTED, "plan needs " + std::to_string(p->lds) +
+                                        " bytes of LDS per workgroup; the device has " +
+                                        std::to_string(di.lds_per_block));
+  if (p->lds > 65536)
+    SS_TRY_HIP(hipFuncSetAttribute(p->kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)p->lds));
   const int resident = blocks_per_cu(p->kernel, p->block, p->lds) * di.num_cus;
   p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident, S,
                                                per_tile);
