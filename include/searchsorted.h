@@ -356,8 +356,10 @@ SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
  * changes sign.  The compiled form is the sorted list of piece boundaries
  * (at most 1088) and one (slope, intercept) per piece (at most 1089), both
  * formed in float64 and rounded to FP32: p(z) = slope_i z + intercept_i for
- * the piece i holding z, found by bisection over the boundaries.  This is
- * the same function as the layered form, up to FP32 rounding.
+ * the piece i holding z, i = #{boundaries < z}.  i is found through a table
+ * of equal cells over the boundaries' range (prefix counts plus a scan of
+ * at most 8 boundaries), or by bisection when some cell would hold more.
+ * This is the same function as the layered form, up to FP32 rounding.
  * Search: g = floor(p (n-1)) clamped to [-1, n-1]; the window
  * [L, R] = [g - E, g + E] clamped to [-1, n-1] is accepted if
  * (L == -1 or a[L] < x) and (R == n-1 or x <= a[R+1]); the index is then
@@ -414,8 +416,9 @@ SS_API int ss_learned_predict(ss_learned *h, const double *x, int64_t m, float *
 /* info (host, count >= 6 doubles): {E, n, steps, final training loss,
  * log2 a[0], 1 / (log2 a[n-1] - log2 a[0])}; with count >= 8 also the
  * compiled model's piece count and its padded boundary slots (a power of two,
- * at least 2 and at least pieces - 1).  SYNCHRONOUS only in that it reads the
- * handle's host copy. */
+ * at least pieces + 7); with count >= 10 also its cell count (0: the piece
+ * is found by bisection) and the most boundaries in one cell.  SYNCHRONOUS
+ * only in that it reads the handle's host copy. */
 SS_API int ss_learned_info(const ss_learned *h, double *info, int count);
 
 /* Targets of the most recent ss_learned_search that failed the window

@@ -509,11 +509,11 @@ class LearnedIndex:
         return out
 
     def info(self) -> dict:
-        buf = (ctypes.c_double * 8)()
-        check(lib().ss_learned_info(self._handle, buf, 8))
+        buf = (ctypes.c_double * 10)()
+        check(lib().ss_learned_info(self._handle, buf, 10))
         return {"E": int(buf[0]), "n": int(buf[1]), "steps": int(buf[2]), "loss": buf[3],
                 "u0": buf[4], "inv": buf[5], "pieces": int(buf[6]),
-                "bound_slots": int(buf[7])}
+                "bound_slots": int(buf[7]), "cells": int(buf[8]), "cell_scan": int(buf[9])}
 
     def fallbacks(self) -> int:
         v = ctypes.c_int64()

@@ -271,7 +271,8 @@ __global__ __launch_bounds__(kTrainThreads) void train_many_kernel(
 
 // ---------------------------------------------------------------------------
 // Compilation of a trained model into the image the search evaluates (the
-// layout and the segment form are described with mlp_eval).
+// piecewise-linear form, the cell table and the layout are described with
+// mlp_eval_q).
 // ---------------------------------------------------------------------------
 
 // Midpoint of (lo, hi) with infinite ends: a point inside the interval
@@ -297,7 +298,12 @@ __device__ __forceinline__ double inside(double lo, double hi) {
 //   4. the pieces, segment by segment: boundaries in order (each segment's
 //      switching points, then the segment's right breakpoint), and per
 //      piece the active layer-2 units at a point inside it, giving
-//      slope = sum w3_k P_sk and intercept = b3 + sum w3_k Q_sk.
+//      slope = sum w3_k P_sk and intercept = b3 + sum w3_k Q_sk;
+//   5. the cell table: G (a power of two >= 2 nb, at most kIMaxCells)
+//      equal cells over the boundaries' range less its outermost few, each
+//      boundary's cell from the FP32 expression the search uses, the prefix
+//      counts by gap filling, and K, the fullest cell (no table if
+//      K > kCellScan).
 // Breakpoints beyond the FP32 range round to +-inf, which leaves the piece
 // of every FP32 input unchanged.
 __device__ void compile_model(const float* __restrict__ P, float* __restrict__ img) {
@@ -306,6 +312,10 @@ __device__ void compile_model(const float* __restrict__ P, float* __restrict__ i
   __shared__ unsigned act[S];
   __shared__ double ps[S][kH], qs[S][kH], cr[S][kH], crs[S][kH];
   __shared__ int ncr[S], poff[S + 1], m_s, nbp_s;
+  __shared__ float bnd[kIMaxBounds];
+  __shared__ int cells[kIMaxCells + 1];
+  __shared__ int G_s, K_s;
+  __shared__ float z0_s, cinv_s;
   const int tid = threadIdx.x, nt = blockDim.x;
   const double inf = __builtin_inf();
   if (tid < kH) {
@@ -378,7 +388,7 @@ __device__ void compile_model(const float* __restrict__ P, float* __restrict__ i
     for (int seg = 0; seg < S; ++seg) poff[seg + 1] = poff[seg] + (seg <= m ? ncr[seg] + 1 : 0);
     const int nb = poff[S] - 1;
     int nbp = 2;
-    while (nbp < nb) nbp <<= 1;
+    while (nbp < nb + kCellScan) nbp <<= 1;  // the cell scan may read kCellScan - 1 past
     nbp_s = nbp;
   }
   __syncthreads();
@@ -393,6 +403,7 @@ __device__ void compile_model(const float* __restrict__ P, float* __restrict__ i
       v = (float)(j < ncr[seg] ? crs[seg][j] : ts[seg]);
     }
     img[kIHead + i] = v;
+    bnd[i] = v;
   }
   for (int p = tid; p < np; p += nt) {
     int seg = 0;
@@ -411,10 +422,76 @@ __device__ void compile_model(const float* __restrict__ P, float* __restrict__ i
     img[kIHead + nbp + 2 * p] = (float)slope;
     img[kIHead + nbp + 2 * p + 1] = (float)icpt;
   }
+  // 5. the cell table.  Cells span [bnd[s], bnd[nb-1-s]]: trimming the s
+  // outermost boundaries on each side (layer-1 breakpoints far outside the
+  // table's range) keeps them from stretching the cells; they then share
+  // the end cells.  Thread 0 tries s = 0..kCellScan and keeps the fullest
+  // cell's smallest count K (the longest run of equal cells along the
+  // sorted boundaries).
+  __syncthreads();
+  const int nb = np - 1;
+  if (tid == 0) {
+    const float inff = __builtin_inff();
+    int bestK = kIMaxBounds + 1, bestG = 0;
+    float bz0 = 0.0f, bcinv = 0.0f;
+    if (nb > 0) {
+      int G = 2;
+      while (G < 2 * nb && G < kIMaxCells) G <<= 1;
+      const int smax = min(kCellScan, (nb - 1) / 2);
+      for (int t = 0; t <= smax; ++t) {
+        const float lo = bnd[t], span = bnd[nb - 1 - t] - lo;
+        if (!(lo > -inff) || !(span > 0.0f && span < inff)) continue;
+        const float cinv = (float)G / span;
+        int K = 0, run = 0, prev = -1;
+        for (int k = 0; k < nb; ++k) {
+          const int c = cell_of(bnd[k], lo, cinv, G);
+          run = c == prev ? run + 1 : 1;
+          prev = c;
+          K = max(K, run);
+        }
+        if (K < bestK) {
+          bestK = K;
+          bestG = G;
+          bz0 = lo;
+          bcinv = cinv;
+        }
+      }
+    }
+    const bool use = bestG > 0 && bestK <= kCellScan;
+    G_s = use ? bestG : 0;
+    K_s = use ? bestK : 0;
+    z0_s = use ? bz0 : 0.0f;
+    cinv_s = use ? bcinv : 0.0f;
+  }
+  __syncthreads();
+  const int G = G_s, K = K_s;
+  const float z0 = z0_s, cinv = cinv_s;
+  if (G > 0) {
+    // boundary k opens the cells after its predecessor's, up to its own
+    for (int k = tid; k < nb; k += nt) {
+      const int ck = cell_of(bnd[k], z0, cinv, G);
+      const int cp = k == 0 ? -1 : cell_of(bnd[k - 1], z0, cinv, G);
+      for (int c = cp + 1; c <= ck; ++c) cells[c] = k;
+    }
+    const int clast = cell_of(bnd[nb - 1], z0, cinv, G);
+    for (int c = clast + 1 + tid; c <= G; c += nt) cells[c] = nb;
+  }
+  __syncthreads();
+  const int Gw = G;
+  const int coff = kIHead + nbp + 2 * np;
+  if (Gw > 0) {
+    uint16_t* C = reinterpret_cast<uint16_t*>(img + coff);
+    for (int c = tid; c <= Gw; c += nt) C[c] = (uint16_t)cells[c];
+  }
   if (tid == 0) {
     img[0] = __int_as_float(nbp);
     img[1] = __int_as_float(np);
-    img[2] = img[3] = 0.0f;
+    img[2] = __int_as_float(Gw);
+    img[3] = __int_as_float(K);
+    img[4] = z0;
+    img[5] = cinv;
+    img[6] = __int_as_float(coff);
+    img[7] = 0.0f;
   }
 }
 
@@ -449,7 +526,7 @@ __device__ __forceinline__ int exact_index(const double* __restrict__ a, int n, 
 // search's own forward pass (so every lane of the wavefront calls it; lanes
 // without an entry pass valid = false and get 0).
 __device__ __forceinline__ int probe_error(const double* __restrict__ a, int n, const float* m,
-                                           int nbp, float u0, float inv, int i,
+                                           const ImageHead& hd, float u0, float inv, int i,
                                            bool valid) {
   const int e = valid ? i : 0;
   double probe[3];
@@ -459,7 +536,7 @@ __device__ __forceinline__ int probe_error(const double* __restrict__ a, int n, 
   int worst = 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const float p = mlp_eval(m, nbp, model_input(probe[c], u0, inv));
+    const float p = mlp_eval(m, hd, model_input(probe[c], u0, inv));
     const int g = predicted_index(p, n);
     worst = max(worst, abs(g - exact_index(a, n, probe[c])));
   }
@@ -472,14 +549,14 @@ __global__ __launch_bounds__(256) void bound_kernel(const double* __restrict__ a
   __shared__ __align__(16) float model[kImageFloats];
   stage_image(model, img);
   __syncthreads();
-  const int nbp = image_bounds(model);
+  const ImageHead hd = image_head(model);
   int local = 0;
   const int stride = gridDim.x * blockDim.x;
   // the loop bound is uniform across the workgroup: every lane takes part
   // in every forward pass
   for (int base = blockIdx.x * blockDim.x; base < n; base += stride) {
     const int i = base + threadIdx.x;
-    local = max(local, probe_error(a, n, model, nbp, u0, inv, i, i < n));
+    local = max(local, probe_error(a, n, model, hd, u0, inv, i, i < n));
   }
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(worst, local);
@@ -510,11 +587,11 @@ __global__ __launch_bounds__(256) void bound_many_kernel(const double* tables_a,
   stage_image(model, images + sl.i_off);
   if (threadIdx.x == 0) worst = 0;
   __syncthreads();
-  const int nbp = image_bounds(model);
+  const ImageHead hd = image_head(model);
   int local = 0;
   for (int base = 0; base < sl.n; base += blockDim.x) {
     const int i = base + threadIdx.x;
-    local = max(local, probe_error(a, sl.n, model, nbp, sl.u0, sl.inv, i, i < sl.n));
+    local = max(local, probe_error(a, sl.n, model, hd, sl.u0, sl.inv, i, i < sl.n));
   }
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(&worst, local);
@@ -556,7 +633,7 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   if constexpr (!GLOBAL) stage_table(reinterpret_cast<double*>(lds), a.table, a.n);
   stage_image(model, a.img);
   __syncthreads();
-  const int nbp = image_bounds(model);
+  const ImageHead hd = image_head(model);
   int fb = 0;
   for (; t < ntiles; t += gridDim.x) {
     const int64_t tn = t + gridDim.x;
@@ -566,10 +643,10 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
     if constexpr (CONV) {
       double xs[Q];
       convention_in<Q>(cur, xs);
-      search_learned<Q, !GLOBAL>(sa, a.n, model, nbp, a.E, a.u0, a.inv, xs, r, fell);
+      search_learned<Q, !GLOBAL>(sa, a.n, model, hd, a.E, a.u0, a.inv, xs, r, fell);
       convention_out<Q>(a.n, cur, r);
     } else {
-      search_learned<Q, !GLOBAL>(sa, a.n, model, nbp, a.E, a.u0, a.inv, cur, r, fell);
+      search_learned<Q, !GLOBAL>(sa, a.n, model, hd, a.E, a.u0, a.inv, cur, r, fell);
     }
     const int64_t base = t * per_tile + threadIdx.x;
     const bool full = (t + 1) * per_tile <= a.m;
@@ -594,11 +671,11 @@ __global__ __launch_bounds__(256) void predict_kernel(const float* __restrict__ 
   __shared__ __align__(16) float model[kImageFloats];
   stage_image(model, img);
   __syncthreads();
-  const int nbp = image_bounds(model);
+  const ImageHead hd = image_head(model);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
     const int64_t i = base + threadIdx.x;
-    const float p = mlp_eval(model, nbp, model_input(x[i < m ? i : 0], u0, inv));
+    const float p = mlp_eval(model, hd, model_input(x[i < m ? i : 0], u0, inv));
     if (i < m) out[i] = p * (float)(n - 1);
   }
 }
@@ -621,6 +698,7 @@ struct ss_learned {
   float* d_image = nullptr;  // the compiled model the search evaluates
   int image_floats = 0;      // its floats in use (a multiple of 4)
   int pieces = 0, bound_slots = 0;  // its pieces and padded boundary slots
+  int cells = 0, cell_scan = 0;     // its cell table (0: none) and fullest cell
   unsigned long long* d_fallbacks = nullptr;
   std::vector<float> params;
   ~ss_learned() {
@@ -744,13 +822,14 @@ int finish_learned(ss_learned* h) {
   h->device = dev;
   int rc = measure_bound(h);  // (synchronises the stream after the compile)
   if (rc != SS_OK) return rc;
-  int head[2] = {0, 0};
+  int head[4] = {0, 0, 0, 0};
   SS_TRY_HIP(hipMemcpy(head, h->d_image, sizeof(head), hipMemcpyDeviceToHost));
-  if (head[0] < 2 || head[0] > kIMaxBounds || head[1] < 1 || head[1] > kIMaxPieces)
-    return fail(SS_ERR_UNSUPPORTED, "compiled model is malformed");
-  h->image_floats = image_used_floats(head[0], head[1]);
+  if (!image_header_valid(head)) return fail(SS_ERR_UNSUPPORTED, "compiled model is malformed");
+  h->image_floats = image_used_floats(head[0], head[1], head[2]);
   h->bound_slots = head[0];
   h->pieces = head[1];
+  h->cells = head[2];
+  h->cell_scan = head[3];
   return SS_OK;
 }
 
@@ -1004,6 +1083,10 @@ int ss_learned_info(const ss_learned* h, double* info, int count) {
   if (count >= 8) {
     info[6] = h->pieces;
     info[7] = h->bound_slots;
+  }
+  if (count >= 10) {
+    info[8] = h->cells;
+    info[9] = h->cell_scan;
   }
   return SS_OK;
 }

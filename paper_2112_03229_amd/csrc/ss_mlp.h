@@ -33,32 +33,58 @@ __device__ __forceinline__ float model_input(double x, float u0, float inv) {
 //   p(z) = b3 + sum_{k active} w3_k (P_k z + Q_k) = slope z + intercept.
 // compile_model lists these pieces once per model (at most 33 segments of
 // at most 33 pieces): the sorted boundaries and one (slope, intercept) per
-// piece, formed in float64 and rounded once.  A query then costs a
-// bisection over the boundaries and one fused multiply-add: the same
+// piece, formed in float64 and rounded once.  A query then finds its piece,
+// i = #{boundaries < z}, and costs one fused multiply-add: the same
 // function as the 1088 multiply-adds of the layered form, up to FP32
-// rounding.
+// rounding.  The piece is found through a table of G equal cells over the
+// boundaries' range (the idea of the logarithm hash, applied to z):
+// C[c] counts the boundaries in cells before c, so i = C[cell(z)] plus a
+// scan of at most K boundaries from there.  cell() is monotone and the
+// same FP32 expression for boundaries and queries, so every boundary in an
+// earlier cell is below z and every one in a later cell is not.  A model
+// whose fullest cell holds more than kCellScan boundaries has no table
+// (G = 0) and is searched by bisection over the boundaries.
 //
 // Image layout (floats; identical in global memory and LDS):
-//   [0]            nbp: boundaries after padding (a power of two), as int bits
-//   [1]            np: pieces (np - 1 real boundaries), as int bits
-//   [4, 4 + nbp)   boundaries, ascending, padded with +inf
-//   [4 + nbp, ...) np pairs (slope, intercept)
-constexpr int kIHead = 4;
+//   [0] nbp   boundary slots: a power of two >= nb + kCellScan (int bits)
+//   [1] np    pieces; nb = np - 1 real boundaries (int bits)
+//   [2] G     cells (0: none) (int bits)
+//   [3] K     most boundaries in one cell, <= kCellScan (int bits)
+//   [4] z0, [5] cinv   cell(z) = clamp((z - z0) * cinv, 0, G - 1), truncated
+//   [6] coff  first float of the cell table (int bits)
+//   [8, 8 + nbp)          boundaries, ascending, padded with +inf
+//   [8 + nbp, + 2 np)     np pairs (slope, intercept)
+//   [coff, ...)           G + 1 uint16 prefix counts C[0..G]
+constexpr int kIHead = 8;
 constexpr int kISegments = kH + 1;  // layer-1 segments: at most 32 breakpoints
 constexpr int kIMaxPieces = (kH + 1) * (kH + 1);
-constexpr int kIMaxBounds = 2048;  // a power of two >= kIMaxPieces - 1
-constexpr int kImageFloats = kIHead + kIMaxBounds + 2 * kIMaxPieces + 2;  // 16-byte multiple
+constexpr int kCellScan = 8;        // longest in-cell scan; fuller tables bisect
+constexpr int kIMaxBounds = 2048;   // a power of two >= kIMaxPieces - 1 + kCellScan
+constexpr int kIMaxCells = 2048;
+constexpr int kImageFloats =
+    (kIHead + kIMaxBounds + 2 * kIMaxPieces + (kIMaxCells + 2) / 2 + 3) / 4 * 4;
 constexpr int kImageBytes = kImageFloats * 4;
 static_assert(kImageBytes % 16 == 0, "16-byte copies");
+static_assert(kIMaxPieces - 1 + kCellScan <= kIMaxBounds, "boundary slots");
 
-// Floats in use of an image with nbp padded boundaries and np pieces (a
-// multiple of 4, for 16-byte staging).
-__host__ __device__ constexpr int image_used_floats(int nbp, int np) {
-  return (kIHead + nbp + 2 * np + 3) / 4 * 4;
+// Floats in use of an image (a multiple of 4, for 16-byte staging).
+__host__ __device__ constexpr int image_used_floats(int nbp, int np, int G) {
+  return (kIHead + nbp + 2 * np + (G > 0 ? (G + 2) / 2 : 0) + 3) / 4 * 4;
+}
+
+// The first four header words (nbp, np, G, K) of a compiled image, as the
+// host reads them back: true if they describe an image that fits the slot.
+inline bool image_header_valid(const int* head) {
+  const int nbp = head[0], np = head[1], G = head[2], K = head[3];
+  const bool pow2_nbp = nbp >= 2 && nbp <= kIMaxBounds && (nbp & (nbp - 1)) == 0;
+  const bool cells_ok = G == 0 ? K == 0 : (G >= 2 && G <= kIMaxCells && (G & (G - 1)) == 0 &&
+                                           K >= 1 && K <= kCellScan);
+  return pow2_nbp && np >= 1 && np <= kIMaxPieces && np - 1 + kCellScan <= nbp && cells_ok;
 }
 
 __device__ __forceinline__ int image_floats(const float* img) {
-  return image_used_floats(__float_as_int(img[0]), __float_as_int(img[1]));
+  return image_used_floats(__float_as_int(img[0]), __float_as_int(img[1]),
+                           __float_as_int(img[2]));
 }
 
 // Copies the used part of a compiled image into LDS with 16-byte loads;
@@ -71,41 +97,78 @@ __device__ __forceinline__ void stage_image(float* m, const float* __restrict__ 
   for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src[i];
 }
 
-// Padded boundary count of a staged image, uniform across the workgroup
-// (read after the barrier that follows stage_image).
-__device__ __forceinline__ int image_bounds(const float* m) {
-  return __builtin_amdgcn_readfirstlane(__float_as_int(m[0]));
+// The header of a staged image, uniform across the workgroup (read after
+// the barrier that follows stage_image).
+struct ImageHead {
+  int nbp, G, K, coff;
+  float z0, cinv;
+};
+
+__device__ __forceinline__ ImageHead image_head(const float* m) {
+  ImageHead h;
+  h.nbp = __builtin_amdgcn_readfirstlane(__float_as_int(m[0]));
+  h.G = __builtin_amdgcn_readfirstlane(__float_as_int(m[2]));
+  h.K = __builtin_amdgcn_readfirstlane(__float_as_int(m[3]));
+  h.z0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m[4])));
+  h.cinv = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m[5])));
+  h.coff = __builtin_amdgcn_readfirstlane(__float_as_int(m[6]));
+  return h;
+}
+
+// Cell of a boundary or an input (G > 0): monotone non-decreasing in v, NaN
+// to cell 0.  Compilation and search must evaluate exactly this expression.
+__device__ __forceinline__ int cell_of(float v, float z0, float cinv, int G) {
+  float t = (v - z0) * cinv;
+  t = fminf(fmaxf(t, 0.0f), (float)(G - 1));
+  return (int)t;
 }
 
 // The model's outputs p(z) for Q inputs per lane from a compiled image in
-// LDS with nbp padded boundaries: piece i = #{boundaries < z} (0 for NaN),
-// then one fused multiply-add.  The bisection's trip count, log2(nbp), is
-// uniform, and each step issues the Q lanes' reads together.  Lanes are
-// independent.
+// LDS: piece i = #{boundaries < z} (0 for NaN), then one fused
+// multiply-add.  Both lookups (the cell scan, or the bisection over the
+// nbp slots) have uniform trip counts and issue the Q lanes' reads of each
+// step together.  Lanes are independent.
 template <int Q>
-__device__ __forceinline__ void mlp_eval_q(const float* m, int nbp, const float (&z)[Q],
-                                           float (&p)[Q]) {
+__device__ __forceinline__ void mlp_eval_q(const float* m, const ImageHead& h,
+                                           const float (&z)[Q], float (&p)[Q]) {
   const float* b = m + kIHead;
   int i[Q];
+  if (h.G > 0) {
+    const uint16_t* C = reinterpret_cast<const uint16_t*>(m + h.coff);
+    int base[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) i[q] = 0;
-  for (int step = nbp >> 1; step >= 1; step >>= 1) {
+    for (int q = 0; q < Q; ++q) {
+      base[q] = C[cell_of(z[q], h.z0, h.cinv, h.G)];
+      i[q] = base[q];
+    }
+    // base + k < nb + kCellScan <= nbp: reads past the cell's boundaries
+    // meet later cells' boundaries (not below z) or the +inf padding
+    for (int k = 0; k < h.K; ++k) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) i[q] = (b[i[q] + step - 1] < z[q]) ? i[q] + step : i[q];
+      for (int q = 0; q < Q; ++q) i[q] += (b[base[q] + k] < z[q]) ? 1 : 0;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) i[q] = 0;
+    for (int step = h.nbp >> 1; step >= 1; step >>= 1) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) i[q] = (b[i[q] + step - 1] < z[q]) ? i[q] + step : i[q];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) i[q] += (b[i[q]] < z[q]) ? 1 : 0;
   }
   typedef float f2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    i[q] += (b[i[q]] < z[q]) ? 1 : 0;
-    const f2 sq = *reinterpret_cast<const f2*>(m + kIHead + nbp + 2 * i[q]);
+    const f2 sq = *reinterpret_cast<const f2*>(m + kIHead + h.nbp + 2 * i[q]);
     p[q] = fmaf(sq.x, z[q], sq.y);
   }
 }
 
-__device__ __forceinline__ float mlp_eval(const float* m, int nbp, float z) {
+__device__ __forceinline__ float mlp_eval(const float* m, const ImageHead& h, float z) {
   const float zq[1] = {z};
   float p[1];
-  mlp_eval_q<1>(m, nbp, zq, p);
+  mlp_eval_q<1>(m, h, zq, p);
   return p[0];
 }
 
@@ -117,18 +180,18 @@ __device__ __forceinline__ int predicted_index(float p, int n) {
 }
 
 // The verified window search for Q targets per lane.  m is the model's
-// compiled image in LDS, nbp its padded boundary count.  sa is the table:
+// compiled image in LDS, h its header.  sa is the table:
 // staged in LDS with +inf sentinels from a[n] on (SENTINEL), or read in
 // place from global memory (no sentinel; reads stay inside [0, n)).
 template <int Q, bool SENTINEL = true>
 __device__ __forceinline__ void search_learned(const double* __restrict__ sa, int n,
-                                               const float* m, int nbp, int E, float u0,
-                                               float inv, const double (&x)[Q], int (&r)[Q],
-                                               int (&fell_back)[Q]) {
+                                               const float* m, const ImageHead& h, int E,
+                                               float u0, float inv, const double (&x)[Q],
+                                               int (&r)[Q], int (&fell_back)[Q]) {
   float z[Q], p[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) z[q] = model_input(x[q], u0, inv);
-  mlp_eval_q<Q>(m, nbp, z, p);
+  mlp_eval_q<Q>(m, h, z, p);
   int step = 1;
   while (step * 2 <= 2 * E + 1) step *= 2;  // >= half the window length
   int pos[Q];

@@ -137,13 +137,13 @@ __device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* _
 template <int Q, int LEARN>
 __device__ __forceinline__ void search_staged(const Staged& st, const double* sa,
                                               const uint16_t* C, const float* model,
-                                              int nbp, const double (&x)[Q],
+                                              const ImageHead& hd, const double (&x)[Q],
                                               int (&r)[Q], int (&fell)[Q]) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) fell[q] = 0;
   if constexpr (LEARN) {
     if (st.learned) {  // uniform across the workgroup
-      search_learned<Q>(sa, st.n, model, nbp, st.E, st.u0, st.inv, x, r, fell);
+      search_learned<Q>(sa, st.n, model, hd, st.E, st.u0, st.inv, x, r, fell);
       return;
     }
   }
@@ -192,15 +192,15 @@ __device__ __forceinline__ void load_range(const double* __restrict__ x, TileRan
 // convention or (CONV = 1) the paper's.
 template <int Q, int LEARN, int CONV>
 __device__ __forceinline__ void search_tile(const Staged& st, const double* sa, const uint16_t* C,
-                                            const float* model, int nbp,
+                                            const float* model, const ImageHead& hd,
                                             const double (&x)[Q], int (&r)[Q], int (&fell)[Q]) {
   if constexpr (CONV) {
     double xs[Q];
     convention_in<Q>(x, xs);
-    search_staged<Q, LEARN>(st, sa, C, model, nbp, xs, r, fell);
+    search_staged<Q, LEARN>(st, sa, C, model, hd, xs, r, fell);
     convention_out<Q>(st.n, x, r);
   } else {
-    search_staged<Q, LEARN>(st, sa, C, model, nbp, x, r, fell);
+    search_staged<Q, LEARN>(st, sa, C, model, hd, x, r, fell);
   }
 }
 
@@ -328,11 +328,11 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     stb = stage_desc(a.desc[a.pair_base + sg.seg], a.tables_b, a.bins, a.params, sb, Cb, Mb);
   if constexpr (INTERP) grid = stage_grid(a, sg.seg, sta.n, stb.n, lds_grid);
   __syncthreads();
-  // padded boundary counts of staged learned models (unused for other tables)
-  int oa = 0, ob = 0;
+  // headers of staged learned models (unused for other tables)
+  ImageHead oa{}, ob{};
   if constexpr (LEARN) {
-    oa = image_bounds(Ma);
-    if constexpr (PAIRED) ob = image_bounds(Mb);
+    oa = image_head(Ma);
+    if constexpr (PAIRED) ob = image_head(Mb);
   }
   int fallbacks = 0;
   for (int64_t j = j0; j < j1; ++j) {
@@ -387,8 +387,8 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
       if constexpr (INTERP) grid = stage_grid(a, sg1.seg, sta.n, stb.n, lds_grid);
       __syncthreads();
       if constexpr (LEARN) {
-        oa = image_bounds(Ma);
-        if constexpr (PAIRED) ob = image_bounds(Mb);
+        oa = image_head(Ma);
+        if constexpr (PAIRED) ob = image_head(Mb);
       }
     }
     sg = sg1;
@@ -582,15 +582,16 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
   int rc = learned_train_slots(tables_a, tables_b, slots, p->d_pool, steps, 0.01f, 1);
   if (rc != SS_OK) return rc;
   // every image's (boundaries, pieces) header: LDS is reserved for the largest
-  std::vector<int> head(2 * slots.size());
-  SS_TRY_HIP(hipMemcpy2D(head.data(), 2 * sizeof(int), p->d_pool, kImageBytes, 2 * sizeof(int),
+  std::vector<int> head(4 * slots.size());
+  SS_TRY_HIP(hipMemcpy2D(head.data(), 4 * sizeof(int), p->d_pool, kImageBytes, 4 * sizeof(int),
                          slots.size(), hipMemcpyDeviceToHost));
   p->image_bytes = 0;
   for (size_t i = 0; i < slots.size(); ++i) {
-    const int nbp = head[2 * i], np = head[2 * i + 1];
-    if (nbp < 2 || nbp > kIMaxBounds || np < 1 || np > kIMaxPieces)
+    const int* hd = head.data() + 4 * i;
+    if (!image_header_valid(hd))
       return fail(SS_ERR_UNSUPPORTED, "compiled model " + std::to_string(i) + " is malformed");
-    p->image_bytes = std::max(p->image_bytes, (size_t)image_used_floats(nbp, np) * 4);
+    p->image_bytes =
+        std::max(p->image_bytes, (size_t)image_used_floats(hd[0], hd[1], hd[2]) * 4);
   }
   for (size_t i = 0; i < slots.size(); ++i) {
     const int t = slot_desc[i];

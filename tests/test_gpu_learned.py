@@ -54,6 +54,7 @@ def test_trained_model_is_exact(binding, gpu, oracle_mod, inputs_mod, trained):
     info = li.info()
     say(f"learned: {info}")
     assert info["n"] == 2000 and info["E"] >= 1 and info["loss"] < 1e-3
+    assert info["cells"] > 0  # a trained model's pieces are found through cells
     x = targets_for(inputs_mod, table, 300001, seed=3)
     want = oracle_mod.search_lt(table, x)
     got = li.search(torch.from_numpy(x).to(gpu)).cpu().numpy()
@@ -112,7 +113,8 @@ def compiled_vs_layered(li, gpu, table, w, extra_z):
     return np.abs(p - want) / tol
 
 
-def test_compiled_model_matches_layered_oracle(binding, gpu, inputs_mod):
+@pytest.mark.parametrize("crowded", [False, True], ids=["cells", "bisection"])
+def test_compiled_model_matches_layered_oracle(binding, gpu, inputs_mod, crowded):
     """The search evaluates a compiled form of the model: its pieces as a
     continuous piecewise-linear function of z (bounded by layer 1's
     breakpoints and by the sign changes of layer 2's pre-activations), each
@@ -121,7 +123,9 @@ def test_compiled_model_matches_layered_oracle(binding, gpu, inputs_mod):
     with a negative slope), a breakpoint near 1e30, breakpoints inside and
     outside [0, 1] -- and inputs on both sides of every breakpoint, its
     output must equal the float64 layered forward pass to FP32 rounding of
-    the terms' magnitudes."""
+    the terms' magnitudes.  The piece is found through the cell table; with
+    twelve more units sharing one breakpoint (crowded) no cell table can
+    hold them within the scan length, and it is found by bisection."""
     table = inputs_mod.learned_table()
     t = torch.from_numpy(table).to(gpu)
     rng = np.random.default_rng(7)
@@ -130,6 +134,9 @@ def test_compiled_model_matches_layered_oracle(binding, gpu, inputs_mod):
     w1[0:3], b1[0:3] = 0.0, [0.5, -0.5, 0.0]
     w1[3:6], b1[3:6] = [2.0, 4.0, -2.0], [-1.0, -2.0, 1.0]
     w1[6], b1[6] = 1e-30, 1.0
+    if crowded:
+        w1[7:19] = 1.0 + 0.25 * np.arange(12)
+        b1[7:19] = -0.375 * w1[7:19]  # breakpoint exactly 0.375 for all twelve
     W2 = rng.normal(0, 0.3, (32, 32))
     b2 = rng.normal(0, 0.1, 32)
     w3 = rng.normal(0, 0.3, 32)
@@ -141,8 +148,13 @@ def test_compiled_model_matches_layered_oracle(binding, gpu, inputs_mod):
         bp = -wd[32:64] / wd[0:32]
     bp = bp[np.isfinite(bp)]
     r = compiled_vs_layered(li, gpu, table, w, np.concatenate([bp - 1e-6, bp + 1e-6, bp]))
-    say(f"compiled vs layered: worst err / tol {r.max():.2e}, pieces {li.info()['pieces']}")
+    info = li.info()
+    say(f"compiled vs layered: worst err / tol {r.max():.2e}, pieces {info['pieces']}, "
+        f"cells {info['cells']}")
     assert np.all(r <= 1.0), (np.argmax(r), r.max())
+    # the breakpoint near -1e30 is trimmed from the cells' range; twelve
+    # equal boundaries always share a cell
+    assert (info["cells"] == 0) == crowded
 
 
 def test_compiled_model_with_the_most_pieces(binding, gpu, oracle_mod, inputs_mod):
@@ -170,6 +182,8 @@ def test_compiled_model_with_the_most_pieces(binding, gpu, oracle_mod, inputs_mo
     info = li.info()
     say(f"most pieces: {info}")
     assert info["pieces"] == 1057 and info["bound_slots"] == 2048
+    # 1056 boundaries over [0, 1.03): 2048 cells, a few boundaries each
+    assert info["cells"] == 2048 and 1 <= info["cell_scan"] <= 8
     # probes around every boundary, located from the layered weights: layer
     # 1's breakpoints and, in each segment s (units 0..s-1 active), where
     # unit k's line P z + Q crosses zero
