@@ -183,11 +183,12 @@ int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int
   // tiles each: 3 tiles per workgroup 5.92 TB/s, 4: 6.03; 8192 density and
   // temperature segments with ~60 tiles each: 6: 5.70, 8: 5.63.  Short
   // segments (under 64 such tiles on average) take 6, long ones 4.  Smaller
-  // tiles (one target per lane in plans with learned models: 512 targets)
-  // take proportionally more, the same targets per workgroup: the 512-table
-  // batch with every table learned ran at 88.8 / 97.9 / 104.3 / 107.1 /
-  // 108.0 Gq/s with 4 / 8 / 16 / 32 / 64 tiles of 512.  The count is then
-  // reduced while it leaves fewer than ~6 waves of workgroups.
+  // tiles (the joint and interpolation forms' 2048 targets) take
+  // proportionally more, the same targets per workgroup.  Scaling held when
+  // measured with 512-target tiles (an earlier learned-plan launch shape):
+  // the 512-table batch with every table learned ran at 88.8 / 97.9 /
+  // 104.3 / 107.1 / 108.0 Gq/s with 4 / 8 / 16 / 32 / 64 tiles of 512.  The
+  // count is then reduced while it leaves fewer than ~6 waves of workgroups.
   const int64_t scale = std::max<int64_t>(1, 4096 / std::max<int64_t>(per_tile, 1));
   const int64_t avg = total_tiles / std::max(segments, 1) / scale;
   int64_t k = (avg < 64 ? 6 : 4) * scale;
