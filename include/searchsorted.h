@@ -248,6 +248,7 @@ SS_API int ss_loghash_bins(const double *table, int64_t n, int64_t nb, int32_t *
  * stream first).
  * ------------------------------------------------------------------------- */
 typedef struct ss_plan ss_plan;
+typedef struct ss_learned ss_learned; /* learned index handle (below) */
 
 /* Plan for T tables stored back to back (CSR):
  *   tables    : device, float64; table t is tables[table_off[t] .. table_off[t+1])
@@ -264,6 +265,19 @@ typedef struct ss_plan ss_plan;
  * SYNCHRONOUS (device work on the current stream, then waits). */
 SS_API int ss_multi_plan_create(const double *tables, const int64_t *table_off, int32_t T,
                                 const int64_t *query_off, ss_plan **out);
+
+/* As ss_multi_plan_create, with learned models attached to chosen tables:
+ * models (host, T handles) holds for table t either NULL (the tuner chooses
+ * its kernel) or a handle built on exactly that table -- on the device
+ * memory tables + table_off[t], with its entry count, on the current
+ * device -- which then searches it (verified window, bisection fallback;
+ * the plan counts fallbacks as with SS_OPT_PLAN_LEARNED).  The plan copies
+ * each model's compiled form at creation, so the handles may be destroyed
+ * afterwards.  SS_OPT_PLAN_LEARNED is ignored.  Returns SS_ERR_INVALID_ARG
+ * for a handle built on other memory or another size.  SYNCHRONOUS. */
+SS_API int ss_multi_plan_create_learned(const double *tables, const int64_t *table_off,
+                                        int32_t T, const int64_t *query_off,
+                                        ss_learned *const *models, ss_plan **out);
 
 /* out_idx[k] = idx_t(targets[k]) for every k in [query_off[t], query_off[t+1]),
  * where idx_t is the operation defined at the top of this header applied to
@@ -368,7 +382,6 @@ SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
  * neighbours and the log-midpoints between entries, measured on the device
  * with the search's own prediction code.
  * ------------------------------------------------------------------------- */
-typedef struct ss_learned ss_learned;
 
 typedef struct {
     int32_t steps;     /* Adam steps; 0 keeps the initial parameters */
@@ -425,6 +438,14 @@ SS_API int ss_learned_info(const ss_learned *h, double *info, int count);
  * check and were answered by the fallback.  SYNCHRONOUS (waits for the
  * current stream). */
 SS_API int ss_learned_fallbacks(ss_learned *h, int64_t *count);
+
+/* The model's error bound E (host out), as measured at build or load time:
+ * every table entry's predicted index lies within E - 1 of its index. */
+SS_API int ss_learned_error_bound(const ss_learned *h, int32_t *E);
+
+/* Statistics of the most recent ss_learned_search: the targets answered by
+ * the fallback (the same count as ss_learned_fallbacks).  SYNCHRONOUS. */
+SS_API int ss_learned_stats(ss_learned *h, int64_t *fallbacks);
 
 /* Copies the 1153 parameters (host out, cap >= 1153). */
 SS_API int ss_learned_weights(const ss_learned *h, float *out, int64_t cap);

@@ -76,6 +76,7 @@ def _register_extra(L) -> None:
     P, I64, I32, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
     sigs = {
         "ss_multi_plan_create": [P, P, I32, P, ctypes.POINTER(P)],
+        "ss_multi_plan_create_learned": [P, P, I32, P, P, ctypes.POINTER(P)],
         "ss_multi_search": [P, P, P],
         "ss_plan_destroy": [P],
         "ss_plan_info": [P, I, P, I64],
@@ -92,6 +93,8 @@ def _register_extra(L) -> None:
         "ss_learned_search": [P, P, I64, P],
         "ss_learned_info": [P, P, I],
         "ss_learned_fallbacks": [P, ctypes.POINTER(I64)],
+        "ss_learned_error_bound": [P, ctypes.POINTER(I32)],
+        "ss_learned_stats": [P, ctypes.POINTER(I64)],
         "ss_learned_predict": [P, P, I64, P],
         "ss_learned_weights": [P, P, I64],
         "ss_mlp_gradient": [P, I64, P, P, P],
@@ -273,9 +276,11 @@ class _Plan:
 
 
 class MultiPlan(_Plan):
-    """Many tables searched in one launch (see ss_multi_plan_create)."""
+    """Many tables searched in one launch (see ss_multi_plan_create).  With
+    models (a list of T LearnedIndex or None), each given model searches its
+    table (ss_multi_plan_create_learned); the plan copies the models."""
 
-    def __init__(self, tables: torch.Tensor, table_off, query_off):
+    def __init__(self, tables: torch.Tensor, table_off, query_off, models=None):
         _need(tables, torch.float64, "tables")
         self._toff = _host_offsets(table_off, "table_off")
         self._qoff = _host_offsets(query_off, "query_off")
@@ -286,8 +291,18 @@ class MultiPlan(_Plan):
         self._tables = tables  # referenced by the plan: keep alive
         h = ctypes.c_void_p()
         use_current_stream()
-        check(lib().ss_multi_plan_create(_ptr(tables), _off_ptr(self._toff), self.num_descriptors,
-                                         _off_ptr(self._qoff), ctypes.byref(h)))
+        if models is None:
+            check(lib().ss_multi_plan_create(_ptr(tables), _off_ptr(self._toff),
+                                             self.num_descriptors, _off_ptr(self._qoff),
+                                             ctypes.byref(h)))
+        else:
+            if len(models) != self.num_descriptors:
+                raise ValueError(f"expected {self.num_descriptors} models (or None entries)")
+            arr = (ctypes.c_void_p * len(models))(
+                *[None if mdl is None else mdl._handle.value for mdl in models])
+            check(lib().ss_multi_plan_create_learned(_ptr(tables), _off_ptr(self._toff),
+                                                     self.num_descriptors, _off_ptr(self._qoff),
+                                                     arr, ctypes.byref(h)))
         self._handle = h
 
     def search(self, targets: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
@@ -519,6 +534,18 @@ class LearnedIndex:
         v = ctypes.c_int64()
         use_current_stream()
         check(lib().ss_learned_fallbacks(self._handle, ctypes.byref(v)))
+        return v.value
+
+    def error_bound(self) -> int:
+        v = ctypes.c_int32()
+        check(lib().ss_learned_error_bound(self._handle, ctypes.byref(v)))
+        return v.value
+
+    def stats(self) -> int:
+        """Fallbacks of the most recent search (ss_learned_stats)."""
+        v = ctypes.c_int64()
+        use_current_stream()
+        check(lib().ss_learned_stats(self._handle, ctypes.byref(v)))
         return v.value
 
     def weights(self):

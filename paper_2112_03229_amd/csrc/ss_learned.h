@@ -6,6 +6,8 @@
 
 #include <vector>
 
+#include "../../include/searchsorted.h"
+
 namespace ss {
 
 struct LearnedSlot {
@@ -28,5 +30,17 @@ int learned_train_slots(const double* tables_a, const double* tables_b,
 
 // True if a table (host copy) can have a learned model.
 bool learned_eligible(const double* a, int64_t n);
+
+// What a plan needs of a learned handle to search its table with it.
+struct LearnedExport {
+  const double* table;   // the device table the model was built on
+  int n;
+  int device;
+  int E;
+  float u0, inv;
+  const float* image;    // compiled model (device)
+  int image_floats;      // its floats in use
+};
+int learned_export(const ss_learned* h, LearnedExport* out);
 
 }  // namespace ss

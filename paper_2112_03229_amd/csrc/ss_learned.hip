@@ -1102,6 +1102,17 @@ int ss_learned_fallbacks(ss_learned* h, int64_t* count) {
   return SS_OK;
 }
 
+int ss_learned_error_bound(const ss_learned* h, int32_t* E) {
+  clear_error();
+  if (!h || !E) return fail(SS_ERR_INVALID_ARG, "null argument");
+  *E = h->E;
+  return SS_OK;
+}
+
+int ss_learned_stats(ss_learned* h, int64_t* fallbacks) {
+  return ss_learned_fallbacks(h, fallbacks);
+}
+
 int ss_learned_weights(const ss_learned* h, float* out, int64_t cap) {
   clear_error();
   if (!h || !out || cap < kNP) return fail(SS_ERR_INVALID_ARG, "need a handle and 1153 slots");
@@ -1144,3 +1155,18 @@ int ss_learned_destroy(ss_learned* h) {
 }
 
 }  // extern "C"
+
+namespace ss {
+int learned_export(const ss_learned* h, LearnedExport* out) {
+  if (!h || !out || !h->d_image) return fail(SS_ERR_INVALID_ARG, "learned handle is null");
+  out->table = h->table;
+  out->n = h->n;
+  out->device = h->device;
+  out->E = h->E;
+  out->u0 = h->u0;
+  out->inv = h->inv;
+  out->image = h->d_image;
+  out->image_floats = h->image_floats;
+  return SS_OK;
+}
+}  // namespace ss

@@ -610,6 +610,54 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
   return SS_OK;
 }
 
+// Attaches given learned handles to a batched plan (models[t], or null for
+// the tuner's choice): each handle must have been built on table t's own
+// memory.  Its compiled model is copied into the plan's pool, so the plan
+// does not depend on the handle afterwards.
+int attach_learned(ss_plan* p, const double* tables, const int64_t* table_off,
+                   ss_learned* const* models) {
+  int dev = 0;
+  SS_TRY_HIP(hipGetDevice(&dev));
+  std::vector<int> with;
+  std::vector<LearnedExport> ex;
+  for (int t = 0; t < p->T; ++t) {
+    if (!models[t]) continue;
+    LearnedExport e{};
+    const int rc = learned_export(models[t], &e);
+    if (rc != SS_OK) return rc;
+    if (e.table != tables + table_off[t] || e.n != table_off[t + 1] - table_off[t])
+      return fail(SS_ERR_INVALID_ARG,
+                  "model " + std::to_string(t) + " was not built on table " + std::to_string(t));
+    if (e.device != dev)
+      return fail(SS_ERR_INVALID_ARG, "model " + std::to_string(t) + " is on another device");
+    with.push_back(t);
+    ex.push_back(e);
+  }
+  if (ex.empty()) return SS_OK;
+  SS_TRY_HIP(hipMalloc(&p->d_pool, sizeof(float) * kImageFloats * ex.size()));
+  SS_TRY_HIP(hipMalloc(&p->d_fallbacks, sizeof(unsigned long long)));
+  SS_TRY_HIP(hipMemset(p->d_fallbacks, 0, sizeof(unsigned long long)));
+  p->image_bytes = 0;
+  for (size_t i = 0; i < ex.size(); ++i) {
+    SS_TRY_HIP(hipMemcpy(p->d_pool + i * kImageFloats, ex[i].image,
+                         sizeof(float) * ex[i].image_floats, hipMemcpyDeviceToDevice));
+    p->image_bytes = std::max(p->image_bytes, (size_t)ex[i].image_floats * 4);
+    const int t = with[i];
+    TableDesc& d = p->desc[t];
+    d.algo = SS_ALGO_LEARNED;
+    d.bins_off = 0;
+    d.nb = d.K = 0;
+    d.p_off = (int64_t)i * kImageFloats;
+    d.E = ex[i].E;
+    d.u0 = ex[i].u0;
+    d.inv = ex[i].inv;
+    p->tuned[t].algo = SS_ALGO_LEARNED;
+    p->tuned[t].bits = -1;
+  }
+  p->learned_tables = (int)ex.size();
+  return SS_OK;
+}
+
 template <int MODE, int Q, int LEARN>
 const void* plan_kernel_conv(bool conv) {
   return conv ? reinterpret_cast<const void*>(&multi_kernel<MODE, Q, LEARN, 1>)
@@ -838,8 +886,10 @@ using namespace ss;
 
 extern "C" {
 
-int ss_multi_plan_create(const double* tables, const int64_t* table_off, int32_t T,
-                         const int64_t* query_off, ss_plan** out) {
+// Batched plan creation; models (T handles, entries may be null) attaches
+// learned models, else SS_OPT_PLAN_LEARNED may train them.
+static int create_batched(const double* tables, const int64_t* table_off, int32_t T,
+                          const int64_t* query_off, ss_learned* const* models, ss_plan** out) {
   clear_error();
   if (!out) return fail(SS_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
@@ -881,8 +931,10 @@ int ss_multi_plan_create(const double* tables, const int64_t* table_off, int32_t
     if (p->tuned[t].algo == SS_ALGO_EXPHASH)
       max_bins = std::max(max_bins, align16((size_t)(p->tuned[t].nb + 1) * 2));
   }
-  if (option(SS_OPT_PLAN_LEARNED)) {
-    if ((rc = apply_learned(p, tables, nullptr, host, host)) != SS_OK) return fail_delete(p, nullptr, rc);
+  if (models || option(SS_OPT_PLAN_LEARNED)) {
+    rc = models ? attach_learned(p, tables, table_off, models)
+                : apply_learned(p, tables, nullptr, host, host);
+    if (rc != SS_OK) return fail_delete(p, nullptr, rc);
     max_bins = 0;
     for (int t = 0; t < T; ++t)
       if (p->desc[t].algo == SS_ALGO_EXPHASH)
@@ -895,6 +947,21 @@ int ss_multi_plan_create(const double* tables, const int64_t* table_off, int32_t
   }
   *out = p;
   return SS_OK;
+}
+
+int ss_multi_plan_create(const double* tables, const int64_t* table_off, int32_t T,
+                         const int64_t* query_off, ss_plan** out) {
+  return create_batched(tables, table_off, T, query_off, nullptr, out);
+}
+
+int ss_multi_plan_create_learned(const double* tables, const int64_t* table_off, int32_t T,
+                                 const int64_t* query_off, ss_learned* const* models,
+                                 ss_plan** out) {
+  if (!models) {
+    clear_error();
+    return fail(SS_ERR_INVALID_ARG, "models is null");
+  }
+  return create_batched(tables, table_off, T, query_off, models, out);
 }
 
 int ss_multi_search(ss_plan* p, const double* targets, int32_t* out_idx) {

@@ -351,3 +351,36 @@ def test_save_and_load(binding, gpu, oracle_mod, inputs_mod, trained, tmp_path):
     bad.write_text('{"format": "searchsorted-learned-1", "n": 2000, "weights": [1, 2]}')
     with pytest.raises(binding.SearchSortedError):
         binding.LearnedIndex.load(t, str(bad))
+
+
+def test_plan_with_attached_models(binding, gpu, oracle_mod, inputs_mod):
+    """Learned handles built on tables of a batch are attached to a batched
+    plan (ss_multi_plan_create_learned): those tables are searched through
+    the copied models (the plan reports them learned) and every index is
+    exact; the plan keeps working after the handles are destroyed; a handle
+    built on a copy of a table, not on the table's own memory, is refused."""
+    batch = inputs_mod.batched_layout(seed=31, num_tables=6, query_scale=1e-3)
+    tt = torch.from_numpy(batch.tables).to(gpu)
+    off = batch.table_off
+    say("case attached models T=6")
+    models = [None] * 6
+    for t in (0, 2, 5):
+        models[t] = binding.LearnedIndex(tt[off[t]:off[t + 1]], steps=300, seed=t)
+    assert all(models[t].error_bound() >= 1 for t in (0, 2, 5))
+    plan = binding.MultiPlan(tt, off, batch.query_off, models=models)
+    algos = plan.info()["algos"]
+    assert [int(a) == binding.ALGO_LEARNED for a in algos] == [True, False, True, False, False,
+                                                                True]
+    x = np.empty(batch.num_queries)
+    inputs_mod.batched_targets(batch, out=x)
+    want = oracle_mod.search_lt_segments(batch.tables, off, x, batch.query_off)
+    xd = torch.from_numpy(x).to(gpu)
+    assert np.array_equal(plan.search(xd).cpu().numpy(), want)
+    for t in (0, 2, 5):
+        models[t].close()
+    assert np.array_equal(plan.search(xd).cpu().numpy(), want)
+    plan.close()
+    copy = binding.LearnedIndex(tt[off[1]:off[2]].clone(), steps=50, seed=1)
+    with pytest.raises(binding.SearchSortedError):
+        binding.MultiPlan(tt, off, batch.query_off, models=[None, copy, None, None, None, None])
+    copy.close()
