@@ -176,3 +176,49 @@ def test_random_tables_paper_convention(binding, gpu, oracle_mod, paper_conventi
             got = run(binding, gpu, table, x, algo)
             bad = np.nonzero(got != want)[0]
             assert bad.size == 0, (seed, case, n, algo, bad[:3], got[bad[:3]], want[bad[:3]], x[bad[:3]])
+
+
+@pytest.mark.parametrize("form", ["batched", "split", "joint"])
+def test_learned_plans_paper_convention(binding, gpu, oracle_mod, inputs_mod, form):
+    """Plans whose tables all have learned models, created in the paper's
+    convention: the learned plan kernels' convention variants, against the
+    oracle's clamped count."""
+    say(f"case learned plan convention form={form}")
+    opts = {binding.OPT_CONVENTION: 1, binding.OPT_PLAN_LEARNED: 1,
+            binding.OPT_LEARNED_STEPS: 100, binding.OPT_PAIR_JOINT: int(form == "joint")}
+    try:
+        for k, v in opts.items():
+            binding.set_option(k, v)
+        if form == "batched":
+            batch = inputs_mod.batched_layout(seed=35, num_tables=12, query_scale=1e-3)
+            x = inputs_mod.batched_targets(batch, seed=35)
+            x[::6] = batch.tables[np.arange(0, x.size, 6) % batch.tables.size]
+            x[:14] = inputs_mod.special_values()
+            plan = binding.MultiPlan(torch.from_numpy(batch.tables).to(gpu), batch.table_off,
+                                     batch.query_off)
+        else:
+            pairs = inputs_mod.paired_layout(seed=37, materials=12, total_pairs=200001)
+            rho, temp = inputs_mod.paired_targets(pairs, seed=37)
+            rho[::5] = pairs.rho.tables[np.arange(0, rho.size, 5) % pairs.rho.tables.size]
+            temp[:14] = inputs_mod.special_values()
+            plan = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(gpu),
+                                    pairs.rho.table_off,
+                                    torch.from_numpy(pairs.temp.tables).to(gpu),
+                                    pairs.temp.table_off, pairs.rho.query_off)
+    finally:
+        for k in opts:
+            binding.set_option(k, 0)
+    assert (plan.info()["algos"] == binding.ALGO_LEARNED).all()
+    if form == "batched":
+        got = plan.search(torch.from_numpy(x).to(gpu)).cpu().numpy()
+        assert np.array_equal(got, segments_le(oracle_mod, batch.tables, batch.table_off, x,
+                                               batch.query_off))
+    else:
+        o_r, o_t = plan.search(torch.from_numpy(rho).to(gpu), torch.from_numpy(temp).to(gpu))
+        assert np.array_equal(o_r.cpu().numpy(),
+                              segments_le(oracle_mod, pairs.rho.tables, pairs.rho.table_off, rho,
+                                          pairs.rho.query_off))
+        assert np.array_equal(o_t.cpu().numpy(),
+                              segments_le(oracle_mod, pairs.temp.tables, pairs.temp.table_off,
+                                          temp, pairs.temp.query_off))
+    plan.close()
