@@ -76,11 +76,17 @@ def test_single_table_paper_convention(binding, gpu, oracle_mod, inputs_mod, pap
     table = table.astype(np.float64)
     x = targets(inputs_mod, table, 5 * TILE + 37, seed=len(name))
     want = oracle_mod.search_le_clamped(table, x)
-    for algo in ALGOS:
-        say(f"case convention table={name} algo={algo}")
-        got = run(binding, gpu, table, x, algo)
-        bad = np.nonzero(got != want)[0]
-        assert bad.size == 0, (algo, name, bad[:5], got[bad[:5]], want[bad[:5]], x[bad[:5]])
+    try:
+        for q in (8, 4):  # both targets-per-lane variants of every kernel
+            binding.set_option(binding.OPT_TARGETS_PER_LANE, q)
+            for algo in ALGOS:
+                say(f"case convention table={name} q={q} algo={algo}")
+                got = run(binding, gpu, table, x, algo)
+                bad = np.nonzero(got != want)[0]
+                assert bad.size == 0, (algo, q, name, bad[:5], got[bad[:5]], want[bad[:5]],
+                                       x[bad[:5]])
+    finally:
+        binding.set_option(binding.OPT_TARGETS_PER_LANE, 0)
 
 
 def test_convention_is_read_per_call(binding, gpu, oracle_mod, inputs_mod):

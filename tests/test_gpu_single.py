@@ -162,19 +162,25 @@ def test_exphash_small_caps_force_bin_bisection(binding, gpu, oracle_mod, inputs
 
 
 @pytest.mark.parametrize("block", [256, 512, 1024])
-def test_launch_shapes(binding, gpu, oracle_mod, inputs_mod, block):
+@pytest.mark.parametrize("q", [4, 8])
+def test_launch_shapes(binding, gpu, oracle_mod, inputs_mod, block, q):
+    """Every kernel at every workgroup size and both target counts per lane
+    (SS_OPT_TARGETS_PER_LANE), with the default grid, one workgroup and
+    seven (grid-stride loops over many tiles), on a ragged target count."""
     table = inputs_mod.single_table(300)
     x = mixed_targets(inputs_mod, table, 40 * 1024 + 9, seed=block)
     want = oracle_mod.search_lt(table, x)
     try:
         binding.set_option(binding.OPT_BLOCK_SIZE, block)
+        binding.set_option(binding.OPT_TARGETS_PER_LANE, q)
         for grid in (0, 1, 7):
             binding.set_option(binding.OPT_GRID_BLOCKS, grid)
             for algo in ALGOS:
-                say(f"case block={block} grid={grid} algo={algo}")
+                say(f"case block={block} q={q} grid={grid} algo={algo}")
                 assert np.array_equal(run(binding, gpu, table, x, algo), want)
     finally:
         binding.set_option(binding.OPT_BLOCK_SIZE, 0)
+        binding.set_option(binding.OPT_TARGETS_PER_LANE, 0)
         binding.set_option(binding.OPT_GRID_BLOCKS, 0)
 
 
