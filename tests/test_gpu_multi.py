@@ -98,6 +98,40 @@ def test_batched_composition(binding, gpu, oracle_mod, inputs_mod):
     plan.close()
 
 
+@pytest.mark.parametrize("block", [256, 1024])
+def test_plan_workgroup_sizes(binding, gpu, oracle_mod, inputs_mod, block):
+    """Plans created with another workgroup size (SS_OPT_BLOCK_SIZE): the
+    tile size, the tile cut and the tiles per workgroup all follow it.  The
+    edge batch and a ragged paired layout in both forms, every index."""
+    tables, toff, qoff, x = odd_batch(inputs_mod, seed=11)
+    want = oracle_mod.search_lt_segments(tables, toff, x, qoff)
+    pairs = ragged_pairs(inputs_mod, 23, 40, 300007)
+    rho, temp = inputs_mod.paired_targets(pairs, seed=23)
+    want_r = oracle_mod.search_lt_segments(pairs.rho.tables, pairs.rho.table_off, rho,
+                                           pairs.rho.query_off)
+    want_t = oracle_mod.search_lt_segments(pairs.temp.tables, pairs.temp.table_off, temp,
+                                           pairs.temp.query_off)
+    try:
+        binding.set_option(binding.OPT_BLOCK_SIZE, block)
+        say(f"case plan block={block} batched")
+        plan = binding.MultiPlan(torch.from_numpy(tables).to(gpu), toff, qoff)
+        assert np.array_equal(plan.search(torch.from_numpy(x).to(gpu)).cpu().numpy(), want)
+        plan.close()
+        for joint in (0, 1):
+            binding.set_option(binding.OPT_PAIR_JOINT, joint)
+            say(f"case plan block={block} paired joint={joint}")
+            pp = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(gpu),
+                                  pairs.rho.table_off, torch.from_numpy(pairs.temp.tables).to(gpu),
+                                  pairs.temp.table_off, pairs.rho.query_off)
+            o_r, o_t = pp.search(torch.from_numpy(rho).to(gpu), torch.from_numpy(temp).to(gpu))
+            assert np.array_equal(o_r.cpu().numpy(), want_r)
+            assert np.array_equal(o_t.cpu().numpy(), want_t)
+            pp.close()
+    finally:
+        binding.set_option(binding.OPT_BLOCK_SIZE, 0)
+        binding.set_option(binding.OPT_PAIR_JOINT, 0)
+
+
 @pytest.mark.parametrize("xcd", [0, 1, 2, 3, 7, 1 << 24])
 def test_xcd_mappings_cover_every_range(binding, gpu, oracle_mod, inputs_mod, xcd):
     """Every workgroup-to-XCD mapping (dispatch order, chunks of 2, 3, 7, the
