@@ -282,16 +282,32 @@ int launch_single(const double* table, int64_t n, const double* x, int64_t m, in
   int nt = (int)option(SS_OPT_BLOCK_SIZE);
   if (nt == 0) nt = kDefaultBlock;
   int q = (int)option(SS_OPT_TARGETS_PER_LANE);
-  if (q == 0) q = kDefaultQ;
+  int64_t grid = option(SS_OPT_GRID_BLOCKS);
   const bool conv = option(SS_OPT_CONVENTION) != 0;
-  const void* kern = q == 4 ? (conv ? single_kernel_ptr<4, 1>(p.algo) : single_kernel_ptr<4, 0>(p.algo))
-                            : (conv ? single_kernel_ptr<8, 1>(p.algo) : single_kernel_ptr<8, 0>(p.algo));
+  auto kernel_for = [&](int qq) {
+    return qq == 4 ? (conv ? single_kernel_ptr<4, 1>(p.algo) : single_kernel_ptr<4, 0>(p.algo))
+                   : (conv ? single_kernel_ptr<8, 1>(p.algo) : single_kernel_ptr<8, 0>(p.algo));
+  };
+  // A small call (at most three passes of the resident workgroups at the
+  // default shape) takes four targets per lane and a grid of one pass, each
+  // workgroup looping over its tiles: no partly filled last pass.  Measured
+  // per call on a 110-entry table: 1e6 targets 5.07 -> 4.76 us, 5e6
+  // 13.65 -> 12.26, 1e7 22.4 -> 21.8; at 2e7 (4.8 passes) the default shape
+  // was faster, 40.0 against 42.0.
+  bool small = false;
+  if (q == 0 && grid <= 0) {
+    const int64_t tiles8 = (m + (int64_t)nt * kDefaultQ - 1) / ((int64_t)nt * kDefaultQ);
+    const int64_t resident8 =
+        (int64_t)blocks_per_cu(kernel_for(kDefaultQ), nt, p.lds) * di.num_cus;
+    small = tiles8 <= 3 * resident8;
+  }
+  if (q == 0) q = small ? 4 : kDefaultQ;
+  const void* kern = kernel_for(q);
   const int64_t per_tile = (int64_t)nt * q;
   const int64_t ntiles = (m + per_tile - 1) / per_tile;
-  int64_t grid = option(SS_OPT_GRID_BLOCKS);
   if (grid <= 0) {
     const int64_t resident = (int64_t)blocks_per_cu(kern, nt, p.lds) * di.num_cus;
-    grid = std::max<int64_t>(resident, ntiles / tiles_per_workgroup(p.algo, n));
+    grid = small ? resident : std::max<int64_t>(resident, ntiles / tiles_per_workgroup(p.algo, n));
   }
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
   SingleArgs a{table, x, out, m, (int)n, bits, p.cap, p.c_off, p.scr_off};
