@@ -318,6 +318,40 @@ def test_full_size_batched(binding, gpu, oracle_mod, inputs_mod):
             assert np.array_equal(got[p], oracle_mod.search_lt_at(batch.table(t), x, p)), t
 
 
+def test_full_size_learned_batched(binding, gpu, oracle_mod, inputs_mod):
+    """The 512-table batch with every table learned (500 Adam steps each,
+    the configuration bench.py times): every index bracket-checked, a seeded
+    2e6-target sample against the definition over every table."""
+    batch = inputs_mod.batched_layout()
+    m = batch.num_queries
+    say(f"case full learned batched T=512 m={m}")
+    host = torch.empty(m, dtype=torch.float64).pin_memory()
+    x = inputs_mod.batched_targets(batch, out=host.numpy())
+    try:
+        binding.set_option(binding.OPT_PLAN_LEARNED, 1)
+        plan = binding.MultiPlan(torch.from_numpy(batch.tables).to(gpu), batch.table_off,
+                                 batch.query_off)
+    finally:
+        binding.set_option(binding.OPT_PLAN_LEARNED, 0)
+    assert np.all(plan.info()["algos"] == binding.ALGO_LEARNED)
+    xt = host.to(gpu, non_blocking=True)
+    out = plan.search(xt)
+    got = out.cpu().numpy()
+    say(f"fallbacks {plan.fallbacks()} of {m}")
+    del xt, out
+    plan.close()
+    bad, first = oracle_mod.check_bracket_segments(batch.tables, batch.table_off, x,
+                                                   batch.query_off, got)
+    assert bad == 0, first
+    pos = np.sort((inputs_mod.uniform(512, 98, 2 * 10**6) * m).astype(np.int64))
+    seg = np.searchsorted(batch.query_off, pos, side="right") - 1
+    bounds = np.searchsorted(seg, np.arange(batch.num_tables + 1))
+    for t in range(batch.num_tables):
+        p = pos[bounds[t]:bounds[t + 1]]
+        if p.size:
+            assert np.array_equal(got[p], oracle_mod.search_lt_at(batch.table(t), x, p)), t
+
+
 def test_full_size_paired(binding, gpu, oracle_mod, inputs_mod, pair_form):
     """4096 materials (density 50..4000 entries, temperature 20..1000), 1e9
     pairs, both searches in one launch."""
