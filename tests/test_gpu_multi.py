@@ -385,6 +385,44 @@ def test_full_size_paired(binding, gpu, oracle_mod, inputs_mod, pair_form):
                 assert np.array_equal(got[p], oracle_mod.search_lt_at(b.table(t), x, p)), (name, t)
 
 
+def test_full_size_learned_paired(binding, gpu, oracle_mod, inputs_mod):
+    """The 1e9-pair workload with all 8192 tables learned (500 Adam steps
+    each), split form as bench.py times it: every index bracket-checked on
+    both axes, a seeded 2e6-target sample per axis against the definition."""
+    pairs = inputs_mod.paired_layout()
+    m = pairs.num_pairs
+    say(f"case full learned paired M=4096 pairs={m}")
+    hr = torch.empty(m, dtype=torch.float64).pin_memory()
+    ht = torch.empty(m, dtype=torch.float64).pin_memory()
+    rho, temp = inputs_mod.paired_targets(pairs, out_rho=hr.numpy(), out_t=ht.numpy())
+    try:
+        binding.set_option(binding.OPT_PLAN_LEARNED, 1)
+        plan = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(gpu), pairs.rho.table_off,
+                                torch.from_numpy(pairs.temp.tables).to(gpu),
+                                pairs.temp.table_off, pairs.rho.query_off)
+    finally:
+        binding.set_option(binding.OPT_PLAN_LEARNED, 0)
+    assert np.all(plan.info()["algos"] == binding.ALGO_LEARNED)
+    dr, dt = hr.to(gpu, non_blocking=True), ht.to(gpu, non_blocking=True)
+    out_r, out_t = plan.search(dr, dt)
+    got_r = out_r.cpu().numpy()
+    got_t = out_t.cpu().numpy()
+    say(f"fallbacks {plan.fallbacks()} of {2 * m}")
+    del dr, dt, out_r, out_t
+    plan.close()
+    for name, b, x, got in (("rho", pairs.rho, rho, got_r), ("temp", pairs.temp, temp, got_t)):
+        bad, first = oracle_mod.check_bracket_segments(b.tables, b.table_off, x, b.query_off, got)
+        assert bad == 0, (name, first)
+        pos = np.sort((inputs_mod.uniform(4096, 99, 2 * 10**6) * m).astype(np.int64))
+        seg = np.searchsorted(b.query_off, pos, side="right") - 1
+        M = b.query_off.size - 1
+        bounds = np.searchsorted(seg, np.arange(M + 1))
+        for t in range(M):
+            p = pos[bounds[t]:bounds[t + 1]]
+            if p.size:
+                assert np.array_equal(got[p], oracle_mod.search_lt_at(b.table(t), x, p)), (name, t)
+
+
 def test_learned_batched_plan_is_exact(binding, gpu, oracle_mod, inputs_mod):
     """Every eligible table gets a device-trained model; ineligible ones
     (negative entries, a single entry, empty) keep the tuner's kernel."""
