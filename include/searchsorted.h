@@ -102,16 +102,18 @@ typedef enum {
     SS_OPT_BLOCK_SIZE = 4,       /* threads per workgroup of single-table
                                     launches and of plans built afterwards:
                                     256, 512 or 1024; 0 (default) = auto */
-    SS_OPT_GRID_BLOCKS = 5,      /* workgroups per launch; 0 (default) =
-                                    a few tiles per workgroup, or for a
-                                    small call one pass of the resident
-                                    workgroups */
+    SS_OPT_GRID_BLOCKS = 5,      /* workgroups per single-table launch; 0
+                                    (default) = a few tiles per workgroup,
+                                    or for a small call one pass of the
+                                    resident workgroups */
     SS_OPT_CHECK_POINTERS = 6,   /* 1 (default): verify that buffers are
                                     device memory before launching; 0: skip */
-    SS_OPT_TARGETS_PER_LANE = 7, /* targets each lane keeps in flight per
-                                    tile: 4 or 8; 0 (default) = 8, or 4 for
-                                    a small call (at most three passes of
-                                    the resident workgroups at 8) */
+    SS_OPT_TARGETS_PER_LANE = 7, /* targets each lane of a single-table
+                                    launch keeps in flight per tile: 4 or
+                                    8; 0 (default) = 8, or 4 for a small
+                                    call (at most three passes of the
+                                    resident workgroups at 8).  Plans and
+                                    learned searches use their own */
     SS_OPT_PLAN_TILES = 8,       /* tiles per workgroup of plans built
                                     afterwards; 0 (default) = tuner */
     SS_OPT_PLAN_LEARNED = 9,     /* 1: plans built afterwards give every
