@@ -213,21 +213,28 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
   // +inf: the sentinel a[n], or an explicit test without one).
   // 2 step - 1 >= 2E covers the window.  Lanes whose window failed run the
   // same steps harmlessly and are redone below.
-  for (int s = step; s >= 1; s >>= 1) {
+  // The steps track r = pos - 1 as a byte offset into the table, which
+  // saves the index arithmetic of each step (the kernel is vector-bound).
+  const char* sb = reinterpret_cast<const char*>(sa);
+  const int n8 = n * 8;
+  int rb[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) rb[q] = (pos[q] - 1) * 8;
+  for (int s8 = step * 8; s8 >= 8; s8 >>= 1) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int k = pos[q] + s - 1;
+      const int kb = rb[q] + s8;  // a[k], k = pos + s - 1 >= 0
       bool lt;
       if constexpr (SENTINEL)
-        lt = sa[min(k, n)] < x[q];
+        lt = *reinterpret_cast<const double*>(sb + min(kb, n8)) < x[q];
       else
-        lt = k < n && sa[min(k, n - 1)] < x[q];
-      pos[q] = lt ? pos[q] + s : pos[q];
+        lt = kb < n8 && *reinterpret_cast<const double*>(sb + min(kb, n8 - 8)) < x[q];
+      rb[q] = lt ? kb : rb[q];
     }
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    r[q] = pos[q] - 1;
+    r[q] = rb[q] >> 3;
     if (!((ok >> q) & 1u)) {  // fallback: bisection over the whole table
       int base = 0, len = n;
       while (len > 1) {
