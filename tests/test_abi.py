@@ -137,3 +137,21 @@ def test_plan_argument_errors(L):
     assert L.ss_multi_search(None, P(0x10000), P(0x20000)) == -1
     assert L.ss_pair_search(None, P(0x10000), P(0x20000), P(0x30000), P(0x40000)) == -1
     assert L.ss_plan_destroy(None) == 0
+
+
+def test_learned_accessors_reject_null_handles(L):
+    """The learned accessors and the plan attachment refuse null arguments
+    with SS_ERR_INVALID_ARG before touching the device."""
+    P = ctypes.c_void_p
+    E = ctypes.c_int32(-7)
+    assert L.ss_learned_error_bound(P(0), ctypes.byref(E)) == -1
+    assert E.value == -7
+    cnt = ctypes.c_int64(-7)
+    assert L.ss_learned_stats(P(0), ctypes.byref(cnt)) == -1
+    assert L.ss_learned_fallbacks(P(0), ctypes.byref(cnt)) == -1
+    off = (ctypes.c_int64 * 2)(0, 4)
+    qoff = (ctypes.c_int64 * 2)(0, 8)
+    out = P(0)
+    assert L.ss_multi_plan_create_learned(P(0x10000), off, 1, qoff, P(0), ctypes.byref(out)) == -1
+    assert b"models" in L.ss_last_error()
+    assert out.value is None
