@@ -666,6 +666,22 @@ def main():
                         "median_gqps": round(queries_per_step / (np.median(trial_ms) * 1e-3) / 1e9, 2),
                         "max_gqps": round(queries_per_step / (trial_ms.min() * 1e-3) / 1e9, 2)}
 
+    # The same kernel over the same 1e8-target arrays with a one-entry table
+    # (its search reduces to one compare): the rate this access pattern
+    # reaches on this GPU, a practical ceiling beside the 8 TB/s peak.
+    log("bench: stream ceiling (one-entry table)")
+    one = torch.ones(1, dtype=torch.float64, device=dev)
+    ceil_ms = min(time_call(torch, lambda: binding.search_sorted_batch(one, d_x[o],
+                                                                       d_out[(TABLE_SIZES[0], o)]),
+                            reps=10)
+                  for o in ORDERS)
+    ceiling = M * BYTES_PER_QUERY / (ceil_ms * 1e-3) / 1e9
+    result["roofline"]["stream_ceiling"] = {
+        "achieved": round(ceiling, 1), "unit": "GB/s",
+        "frac_of_peak": round(ceiling / HBM_PEAK_GBS, 4),
+        "kernel_frac_of_ceiling": round(achieved / ceiling, 4),
+        "how": "the same kernel and targets with a one-entry table"}
+
     if not args.no_kernels:
         log("bench: per-kernel comparison")
         comp = {}
