@@ -356,10 +356,13 @@ int oracle_search_le_clamped(const double *a, int64_t n, const double *x, int64_
  *   u = (r - R[i]) / (R[i+1] - R[i]),        v = (t - T[k]) / (T[k+1] - T[k])
  *   f = (1-u)(1-v) F[i][k] + u(1-v) F[i+1][k] + (1-u) v F[i][k+1] + u v F[i+1][k+1]
  * (outside the axes the edge cell is extended linearly; NaN gives NaN).
- * scale = (1 + |u|)(1 + |v|)(|F[i][k]| + |F[i+1][k]| + |F[i][k+1]| +
- * |F[i+1][k+1]|) bounds every term and every partial sum of f, including
- * the factors 1-u and 1-v, so a few units of rounding times scale bound
- * the difference between two evaluation orders. */
+ * scale = |w00 F[i][k]| + |w10 F[i+1][k]| + |w01 F[i][k+1]| + |w11 F[i+1][k+1]|,
+ * the four terms' magnitudes with the weights formed from the rounded u,
+ * 1-u, v and 1-v.  Any evaluation order of the same four terms from the
+ * same rounded factors (products, sums, fused multiply-adds) stays within a
+ * few units of rounding of scale of the exact sum of those terms, however
+ * much they cancel, so a small multiple of eps * scale bounds the
+ * difference between two such orders. */
 static int64_t count_lt(const double *a, int64_t n, double x) {
     int64_t c = 0;
     for (int64_t i = 0; i < n; ++i) c += a[i] < x;
@@ -390,8 +393,7 @@ void oracle_interp_pairs(const double *rho_tables, const int64_t *rho_off, const
                          f01 = F[i * nt + k + 1], f11 = F[(i + 1) * nt + k + 1];
             out[p] = w00 * f00 + w10 * f10 + w01 * f01 + w11 * f11;
             if (scale)
-                scale[p] = (1 + fabs(u)) * (1 + fabs(v)) *
-                           (fabs(f00) + fabs(f10) + fabs(f01) + fabs(f11));
+                scale[p] = fabs(w00 * f00) + fabs(w10 * f10) + fabs(w01 * f01) + fabs(w11 * f11);
         }
         voff += nr * nt;
     }

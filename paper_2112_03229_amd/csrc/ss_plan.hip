@@ -212,10 +212,11 @@ __device__ __forceinline__ void search_tile(const Staged& st, const double* sa, 
 // value is formed as two interpolations along the density axis followed by
 // one along the temperature axis, g0 = u f10 + (1 - u) f00, g1 = u f11 +
 // (1 - u) f01, f = v g1 + (1 - v) g0, each a product and a fused
-// multiply-add: the same bilinear function as the four-weight form, to a
-// few units of rounding of (1 + |u|)(1 + |v|) sum |F|, in fewer float64
-// operations, and exact at the grid nodes (u and v in {0, 1}; a target
-// equal to a node lands in the cell below it with u = 1).
+// multiply-add: the same four terms w_ij F_ij as the four-weight form
+// (weights from the same rounded u, 1 - u, v, 1 - v), summed in another
+// order, so within a few units of rounding of sum |w_ij F_ij| of it, in
+// fewer float64 operations, and exact at the grid nodes (u and v in {0, 1};
+// a target equal to a node lands in the cell below it with u = 1).
 template <int Q>
 __device__ __forceinline__ void interpolate(const double* sa, int na, const double* sb, int nb,
                                             const double* __restrict__ F, const double (&r)[Q],

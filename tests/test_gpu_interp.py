@@ -5,8 +5,9 @@ The cell indices are integer decisions made by exact comparisons, so they
 must equal the oracle's (and the optional index outputs equal
 ``oracle.search_lt`` per axis).  The interpolated values are float64
 arithmetic in another order (and with fused multiply-adds): they must agree
-within 16 units of rounding of the oracle's bound ``scale`` =
-(1+|u|)(1+|v|) sum |F corners|, and equal the grid exactly at grid nodes.
+within 16 units of rounding of the oracle's bound ``scale`` = sum of the
+four terms' magnitudes |w_ij F_ij| (weights from the rounded u, 1-u, v and
+1-v), and equal the grid exactly at grid nodes.
 """
 import numpy as np
 import pytest

@@ -70,3 +70,64 @@ def test_nan_and_segments(oracle_mod, inputs_mod):
         F = it.values[it.value_off[j]:it.value_off[j + 1]].reshape(R.size, T.size)
         g, _ = run(oracle_mod, R, T, F, rho[q0:q1], temp[q0:q1])
         assert np.array_equal(g, f[q0:q1], equal_nan=True)
+
+
+# ---------------------------------------------------------------------------
+# The rounding bound `scale` (the tolerance of the GPU parity test): the sum
+# of the four terms' magnitudes |w_ij F_ij|, pinned on hand-computed cells in
+# exact rational arithmetic.
+
+EPS = np.finfo(np.float64).eps
+
+
+def _exact_cell(R, T, F, r, t):
+    """Exact (f, scale) for one pair in rational arithmetic.  The inputs are
+    chosen so that u, 1-u, v and 1-v are exact in float64."""
+    from fractions import Fraction as Q
+    u = (Q(r) - Q(R[0])) / (Q(R[1]) - Q(R[0]))
+    v = (Q(t) - Q(T[0])) / (Q(T[1]) - Q(T[0]))
+    terms = [(1 - u) * (1 - v) * Q(F[0][0]), u * (1 - v) * Q(F[1][0]),
+             (1 - u) * v * Q(F[0][1]), u * v * Q(F[1][1])]
+    return sum(terms), sum(abs(x) for x in terms)
+
+
+@pytest.mark.parametrize("case", ["large_corner_tiny_weight", "extrapolated_cancelling"])
+def test_scale_is_the_termwise_magnitude(oracle_mod, case):
+    R, T = np.array([1.0, 2.0]), np.array([10.0, 20.0])
+    if case == "large_corner_tiny_weight":
+        # u = 1 - 2^-30 and v = 1 - 2^-20 (both exact): the 1e18 corner
+        # carries the weight (1-u)(1-v) = 2^-50, so its term is about 888
+        F = np.array([[1e18, 1.0], [3.0, -2.0]])
+        r, t = 2.0 - 2.0**-30, 20.0 - 10.0 * 2.0**-20
+    else:
+        # u = -3 (outside the axis), v = 1/2: terms 10, -16.5, 14, -19.5
+        F = np.array([[5.0, 7.0], [11.0, 13.0]])
+        r, t = -2.0, 15.0
+    f, scale = run(oracle_mod, R, T, F, np.array([r]), np.array([t]))
+    want_f, want_scale = _exact_cell(R, T, F, r, t)
+    assert abs(scale[0] - float(want_scale)) <= 4 * EPS * float(want_scale)
+    assert abs(f[0] - float(want_f)) <= 8 * EPS * float(want_scale)
+    if case == "large_corner_tiny_weight":
+        # the bound follows the terms, not the corners: (1+|u|)(1+|v|) sum |F|
+        # would be about 4e18 here
+        assert 880.0 < scale[0] < 900.0
+    else:
+        assert scale[0] == 60.0 and f[0] == -12.0
+
+
+def test_scale_bounds_another_evaluation_order(oracle_mod, inputs_mod):
+    """Three one-dimensional interpolations with fused multiply-adds (another
+    order of the same terms) stay within a few eps * scale of the oracle,
+    also outside the axes where the terms cancel."""
+    R, T, F = one_material(inputs_mod, nr=30, nt=20, seed=11)
+    rho = inputs_mod.log_uniform(8, 1, 1e-5, 1e5, 20000)
+    temp = inputs_mod.log_uniform(8, 2, 1.0, 1e6, 20000)
+    f, scale = run(oracle_mod, R, T, F, rho, temp)
+    i = np.clip(np.searchsorted(R, rho, side="left") - 1, 0, R.size - 2)
+    k = np.clip(np.searchsorted(T, temp, side="left") - 1, 0, T.size - 2)
+    u = (rho - R[i]) / (R[i + 1] - R[i])
+    v = (temp - T[k]) / (T[k + 1] - T[k])
+    g0 = u * F[i + 1, k] + (1 - u) * F[i, k]
+    g1 = u * F[i + 1, k + 1] + (1 - u) * F[i, k + 1]
+    other = v * g1 + (1 - v) * g0
+    assert np.all(np.abs(other - f) <= 16 * EPS * scale)

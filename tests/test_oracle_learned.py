@@ -49,3 +49,55 @@ def test_input_normalisation(inputs_mod):
     table = inputs_mod.single_table(1000)
     z = L.model_input(table, table)
     assert z[0] == 0.0 and abs(z[-1] - 1.0) < 1e-15 and np.all(np.diff(z) >= 0)
+
+
+# ---------------------------------------------------------------------------
+# grad_scale (the tolerance of the device-gradient parity test): the size of
+# each gradient's terms without cancellation.
+
+def test_grad_scale_equals_gradient_without_cancellation(inputs_mod):
+    """All weights and biases non-negative and the output above every target
+    (b3 = 2 > 1 >= i/(n-1)): every term of every gradient sum is
+    non-negative, so the terms' magnitudes sum to the gradient itself."""
+    table = inputs_mod.single_table(300)
+    rng = np.random.default_rng(4)
+    p = np.abs(rng.normal(0.0, 0.5, L.NPARAM))
+    p[L.OFF_B3] = 2.0
+    _, grad = L.loss_and_grad(p, table)
+    assert np.all(grad >= 0.0)
+    assert np.array_equal(L.grad_scale(p, table), grad)
+
+
+def test_grad_scale_hand_computed():
+    """n = 3, table [1, 2, 4] (z = 0, 1/2, 1; targets 0, 1/2, 1), one active
+    unit per layer: w1_0 = 1, b1_0 = 1/2, W2[0][0] = -2, b2_0 = 3,
+    w3_0 = -1, b3 = 3/2.  Outputs -1/2, 1/2, 3/2; residuals -1/2, 0, 1/2;
+    the second layer's unit is off at z = 1.  The b3 gradient cancels to 0;
+    its scale is 2/3."""
+    table = np.array([1.0, 2.0, 4.0])
+    p = np.zeros(L.NPARAM)
+    p[L.OFF_W1] = 1.0
+    p[L.OFF_B1] = 0.5
+    p[L.OFF_W2] = -2.0
+    p[L.OFF_B2] = 3.0
+    p[L.OFF_W3] = -1.0
+    p[L.OFF_B3] = 1.5
+    want = np.zeros(L.NPARAM)
+    want[L.OFF_B1] = 2.0 / 3.0
+    want[L.OFF_W2] = 1.0 / 6.0
+    want[L.OFF_B2] = 1.0 / 3.0
+    want[L.OFF_W3] = 2.0 / 3.0
+    want[L.OFF_B3] = 2.0 / 3.0
+    s = L.grad_scale(p, table)
+    assert np.allclose(s, want, rtol=4 * np.finfo(float).eps, atol=0.0)
+    _, grad = L.loss_and_grad(p, table)
+    assert grad[L.OFF_B3] == 0.0 and abs(grad[L.OFF_W3] + 2.0 / 3.0) < 1e-15
+
+
+def test_grad_scale_bounds_the_gradient(inputs_mod):
+    table = inputs_mod.single_table(300)
+    for seed in (1, 2, 3):
+        p = random_params(seed)
+        _, grad = L.loss_and_grad(p, table)
+        s = L.grad_scale(p, table)
+        assert np.all(np.abs(grad) <= s * (1 + 1e-12) + 1e-300)
