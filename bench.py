@@ -1,21 +1,23 @@
 """Benchmark of the batched sorted search on one MI355X.
 
-Workload (one "step"): three single tables of 100, 300 and 1000 float64
-entries (sorted log-uniform draws on [1e-8, 1e6]), each searched with 1e8
-float64 targets in two orders -- i.i.d. log-uniform on [0.5e-8, 2e6] and a
-smooth sorted random walk in log space -- i.e. six launches of the library's
-automatically chosen kernel (the staged bisection for these tables), 6e8
-queries per step.  Inputs are generated on the host, copied to HBM before
-timing, and stay resident.
+Headline workload (one "step"): the paired lookup of 4096 materials.  Each
+material has a density table (50..4000 float64 entries) and a temperature
+table (20..1000 entries), log-distributed within seeded ranges; 1e9 (rho, T)
+float64 pairs, unevenly spread over the materials, are searched in both
+tables -- 2e9 searches -- in one plan launch with the autotuner's per-table
+choice of kernel (exponent hash, bisection or learned index).  Inputs are
+generated on the host, copied to HBM before timing, and stay resident.
 
-Output: one JSON line with whole-job throughput in Gqueries/s (12 algorithmic
-bytes per query: an 8-byte target read, a 4-byte index written), the HBM
-roofline fraction of the dominant kernel (its average launch duration from
-HIP events on the launch stream around the timed region), per-kernel
-comparisons on the same data, and the CPU oracle timed on the host's cores
-over a bounded sample.
+Output: one JSON line with whole-job throughput in Gqueries/s (one query is
+one search: 12 algorithmic bytes, an 8-byte target read and a 4-byte index
+written), the HBM roofline fraction of the plan kernel (its average launch
+duration from HIP events on the launch stream around the timed region), the
+metric's comparison of learned+batched against plain search on the same
+pairs, the other workloads measured after the timed region, and the CPU
+oracle timed on the host's cores over a bounded sample of the same pairs.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-kernels]
+                       [--no-systems]
 """
 from __future__ import annotations
 
@@ -38,6 +40,11 @@ BYTES_PER_QUERY = 12
 TABLE_SIZES = (100, 300, 1000)
 ORDERS = ("random", "smooth")
 M = 10**8
+# Untimed load before any timed region, whatever the warm-up step count:
+# after an idle period (host-side input generation) MI355X takes about 20 ms
+# of load to reach steady clocks.
+WARM_FLOOR_MS = 200.0
+TRIALS = 20  # the paper reports the mean of 20 trials (Sec. 4)
 
 
 def log(*a):
@@ -80,73 +87,82 @@ def measured_traffic(key: str):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(tables, host_targets, budget_s: float = 15.0):
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle on the headline's own pairs, and the paper's numbers
+# ---------------------------------------------------------------------------
+
+def paper_cpu_speedups() -> list:
+    """The paper's CPU results, quoted with their hardware (none is re-run here;
+    its figures are not in the text, so only the numbers it states are given)."""
+    cpus = "one core of an AMD EPYC 7551 (AVX2, 256-bit), an Intel Xeon Phi 7250 (AVX-512) " \
+           "or an Intel Xeon Gold 6152 (AVX-512) (Table 1); which CPU gave the best case is " \
+           "not stated"
+    work = "the 110-entry density axis of SESAME table 301, material 3720; 5e6 targets on " \
+           "1e-10..1e10; mean of 20 trials (Sec. 4, Sec. 5)"
+    return [
+        {"what": "vectorised (OpenMP SIMD) exponent hash search vs EOSPAC's hunt-and-locate",
+         "speedup": "up to 8x (the conclusion words it as 800%)",
+         "hardware": cpus, "compiler": "Intel 20.0.2 (gcc 9.3.0 showed no significant "
+                                       "vectorisation gain)", "workload": work,
+         "source": "Abstract; Sec. 6"},
+        {"what": "unvectorised exponent hash search vs hunt-and-locate",
+         "speedup": "more than 2x (over 100% faster)", "hardware": cpus,
+         "compiler": "gcc 9.3.0 / Intel 20.0.2, vectorisation disabled", "workload": work,
+         "source": "Sec. 6"},
+        {"what": "explicit OpenMP SIMD plus auto-vectorisation flags vs auto-vectorisation alone",
+         "speedup": "up to 4.8x (worded as 480%)", "hardware": cpus,
+         "compiler": "Intel 20.0.2", "workload": work, "source": "Sec. 6"},
+    ]
+
+
+def _pair_sample(pairs, host_r, host_t, frac: float):
+    """The first ceil(frac * count) pairs of every material (both axes)."""
+    po = pairs.rho.query_off
+    counts = np.diff(po)
+    k = np.minimum(counts, np.ceil(counts * frac).astype(np.int64))
+    off = np.zeros(counts.shape[0] + 1, dtype=np.int64)
+    off[1:] = np.cumsum(k)
+    idx = np.concatenate([np.arange(po[j], po[j] + k[j]) for j in range(counts.shape[0])])
+    return off, np.ascontiguousarray(host_r[idx]), np.ascontiguousarray(host_t[idx])
+
+
+def cpu_baseline(pairs, host_r, host_t, budget_s: float = 15.0) -> dict:
     """The CPU oracle (plain linear count) on all host cores, on a bounded
-    sample of every (table, order) pair of the workload."""
+    sample of the headline workload: the first pairs of every material,
+    both axes."""
     import oracle
+
+    def run(frac, threads):
+        off, xr, xt = _pair_sample(pairs, host_r, host_t, frac)
+        t0 = time.perf_counter()
+        _, u1 = oracle.search_lt_segments(pairs.rho.tables, pairs.rho.table_off, xr, off,
+                                          threads=threads, return_threads=True)
+        _, u2 = oracle.search_lt_segments(pairs.temp.tables, pairs.temp.table_off, xt, off,
+                                          threads=threads, return_threads=True)
+        return int(off[-1]), time.perf_counter() - t0, max(u1, u2)
+
+    total = pairs.num_pairs
     threads = oracle.default_threads()
-    # calibrate every (table, order) pair on a small slice, then size one
-    # common sample so that the whole measurement takes about budget_s
-    per_q = 0.0
-    for table in tables:
-        for order in ORDERS:
-            cal = np.ascontiguousarray(host_targets[order][:400000])
-            t0 = time.perf_counter()
-            oracle.search_lt(table, cal, threads=threads)
-            per_q += (time.perf_counter() - t0) / cal.shape[0]
-    per_pair = int(min(M, max(100000, budget_s / per_q)))
-    total_q, total_s = 0, 0.0
-    for table in tables:
-        for order in ORDERS:
-            x = host_targets[order]
-            start = (x.shape[0] - per_pair) // 2
-            sample = np.ascontiguousarray(x[start:start + per_pair])
-            t0 = time.perf_counter()
-            _, used = oracle.search_lt(table, sample, threads=threads, return_threads=True)
-            total_s += time.perf_counter() - t0
-            total_q += per_pair
-    # the paper's own setting: one core (half the time budget)
-    per_pair1 = int(min(M, max(10000, budget_s / 2 / (per_q * threads))))
-    q1, s1 = 0, 0.0
-    for table in tables:
-        for order in ORDERS:
-            x = host_targets[order]
-            start = (x.shape[0] - per_pair1) // 2
-            sample = np.ascontiguousarray(x[start:start + per_pair1])
-            t0 = time.perf_counter()
-            oracle.search_lt(table, sample, threads=1)
-            s1 += time.perf_counter() - t0
-            q1 += per_pair1
+    n_cal, s_cal, _ = run(2e-3, threads)
+    frac = min(1.0, max(1e7 / total, budget_s / (s_cal / n_cal) / total))
+    n, sec, used = run(frac, threads)
+    # the paper's own setting: one core (a third of the time budget)
+    frac1 = min(1.0, max(1e5 / total, budget_s / 3 / (s_cal * threads / n_cal) / total))
+    n1, sec1, _ = run(frac1, 1)
     return {
-        "value": total_q / total_s / 1e9,
+        "value": 2 * n / sec / 1e9,
         "unit": "Gqueries/s",
         "cores": int(used),
         "kind": "oracle",
-        "sample": f"{per_pair} contiguous targets from the middle of each of the 6 "
-                  f"(table, order) target arrays ({total_q} queries, {total_s:.1f} s); "
-                  f"plain linear count scan, {used} threads",
-        "single_core": {"value": q1 / s1 / 1e9, "unit": "Gqueries/s",
-                        "sample": f"{per_pair1} targets per (table, order) pair, "
-                                  f"{q1} queries, {s1:.1f} s, 1 thread"},
-        "context_library_bisection": library_bisection(tables, host_targets),
+        "sample": f"the first {frac:.2%} of every material's pairs of the headline workload "
+                  f"({n} pairs = {2 * n} searches, both axes, {sec:.1f} s); plain linear "
+                  f"count scan, {used} threads",
+        "single_core": {"value": 2 * n1 / sec1 / 1e9, "unit": "Gqueries/s",
+                        "sample": f"the first {frac1:.3%} of every material's pairs ({n1} "
+                                  f"pairs), {sec1:.1f} s, 1 thread"},
         "host_cpu": _cpu_model(),
+        "paper_cpu_speedups": paper_cpu_speedups(),
     }
-
-
-def library_bisection(tables, host_targets, per_pair: int = 4 * 10**6) -> dict:
-    """Context only (not the baseline): numpy.searchsorted, a library
-    bisection, on one core over a sample of every (table, order) pair."""
-    q, sec = 0, 0.0
-    for table in tables:
-        for order in ORDERS:
-            x = host_targets[order]
-            sample = np.ascontiguousarray(x[:per_pair])
-            t0 = time.perf_counter()
-            np.searchsorted(table, sample, side="left")
-            sec += time.perf_counter() - t0
-            q += per_pair
-    return {"value": q / sec / 1e9, "unit": "Gqueries/s", "cores": 1,
-            "kind": "numpy.searchsorted (context)", "sample": f"{q} queries, {sec:.2f} s"}
 
 
 def _cpu_model() -> str:
@@ -159,6 +175,10 @@ def _cpu_model() -> str:
         pass
     return "unknown"
 
+
+# ---------------------------------------------------------------------------
+# Timing helpers
+# ---------------------------------------------------------------------------
 
 def copy_calibration(torch) -> None:
     """A plain 1 GiB device-to-device copy, launched 3 times: under rocprofv3
@@ -174,18 +194,28 @@ def copy_calibration(torch) -> None:
     print(json.dumps({"copy_calibration_bytes": n * 8, "dispatches": 3}), flush=True)
 
 
+def warm(torch, fn, steps: int, floor_ms: float) -> dict:
+    """Runs fn `steps` times, then keeps running it until at least floor_ms of
+    wall time has passed since the first call (synchronised)."""
+    t0 = time.perf_counter()
+    done = 0
+    for _ in range(steps):
+        fn()
+        done += 1
+    torch.cuda.synchronize()
+    while (time.perf_counter() - t0) * 1e3 < floor_ms:
+        for _ in range(4):
+            fn()
+            done += 1
+        torch.cuda.synchronize()
+    return {"steps_run": done, "ms": round((time.perf_counter() - t0) * 1e3, 1)}
+
+
 def time_call(torch, fn, reps: int = 5, warm_ms: float = 50.0) -> float:
     """Average milliseconds of fn() over reps calls on the current stream,
-    after untimed calls that keep the GPU busy for at least warm_ms: after
-    an idle period (host-side input generation) MI355X takes ~20 ms of load
-    to reach its steady clocks, and first passes over freshly allocated
-    multi-GB buffers run slower."""
-    t0 = time.perf_counter()
-    fn()
-    torch.cuda.synchronize()
-    first_ms = (time.perf_counter() - t0) * 1e3
-    for _ in range(min(1000, max(2, int(warm_ms / max(first_ms, 1e-3)) + 1))):
-        fn()
+    after untimed calls that keep the GPU busy for at least warm_ms (first
+    passes over freshly allocated multi-GB buffers also run slower)."""
+    warm(torch, fn, 1, warm_ms)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -196,10 +226,296 @@ def time_call(torch, fn, reps: int = 5, warm_ms: float = 50.0) -> float:
     return e0.elapsed_time(e1) / reps
 
 
+def trials(torch, fn, queries: int, stream, count: int = TRIALS) -> dict:
+    """count more calls, each bracketed by its own event pair."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(count)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    return {"count": count, "mean_ms": round(float(ms.mean()), 4),
+            "median_ms": round(float(np.median(ms)), 4), "min_ms": round(float(ms.min()), 4),
+            "mean_gqps": round(queries / (ms.mean() * 1e-3) / 1e9, 2),
+            "median_gqps": round(queries / (np.median(ms) * 1e-3) / 1e9, 2),
+            "max_gqps": round(queries / (ms.min() * 1e-3) / 1e9, 2)}
+
+
 def roof(queries: int, ms: float) -> dict:
     gbs = queries * BYTES_PER_QUERY / (ms * 1e-3) / 1e9
     return {"gqps": round(queries / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
             "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def plan_counts(binding, info) -> dict:
+    algos = info["algos"]
+    return {"learned_tables": int((algos == binding.ALGO_LEARNED).sum()),
+            "exphash_tables": int((algos == binding.ALGO_EXPHASH).sum()),
+            "bisection_tables": int((algos == binding.ALGO_BINARY).sum())}
+
+
+def with_options(binding, opts: dict, make):
+    """make() with the given library options set, restoring them afterwards."""
+    old = {k: binding.get_option(k) for k in opts}
+    for k, v in opts.items():
+        binding.set_option(k, v)
+    try:
+        return make()
+    finally:
+        for k, v in old.items():
+            binding.set_option(k, v)
+
+
+def compare_plans(torch, binding, make, run, queries: int, tuned_counts: dict,
+                  reps: int = 3) -> dict:
+    """The metric's comparison on one workload: plans with the tuner's choice
+    excluding learned models ("plain"), with every eligible table learned,
+    with every table forced to bisection and to the exponent hash."""
+    res = {}
+    variants = (
+        ("plain", {binding.OPT_PLAN_LEARNED: binding.PLAN_LEARNED_NONE}),
+        ("learned_forced", {binding.OPT_PLAN_LEARNED: binding.PLAN_LEARNED_ALL}),
+        ("bisection_forced", {binding.OPT_PLAN_ALGO: binding.ALGO_BINARY}),
+        ("exphash_forced", {binding.OPT_PLAN_ALGO: binding.ALGO_EXPHASH}),
+    )
+    for name, opts in variants:
+        if name == "plain" and tuned_counts["learned_tables"] == 0:
+            res[name] = {"same_plan_as": "tuned",
+                         "note": "the tuner chose no learned table, so the tuned plan is "
+                                 "the plain one"}
+            continue
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = with_options(binding, opts, make)
+        build_s = time.perf_counter() - t0
+        ms = time_call(torch, lambda: run(plan), reps=reps)
+        row = {**roof(queries, ms), **plan_counts(binding, plan.info()),
+               "build_s": round(build_s, 2)}
+        if name == "learned_forced":
+            row["fallbacks"] = plan.fallbacks()
+        plan.close()
+        res[name] = row
+    return res
+
+
+# ---------------------------------------------------------------------------
+# The headline: paired lookup, 4096 materials, 1e9 pairs
+# ---------------------------------------------------------------------------
+
+def paired_headline(torch, binding, inputs, dev, args) -> tuple:
+    pairs = inputs.paired_layout()
+    m = pairs.num_pairs
+    log(f"bench: generating {m} pairs")
+    hr = torch.empty(m, dtype=torch.float64).pin_memory()
+    ht = torch.empty(m, dtype=torch.float64).pin_memory()
+    inputs.paired_targets(pairs, out_rho=hr.numpy(), out_t=ht.numpy())
+    r, t = hr.to(dev), ht.to(dev)
+    o_r = torch.empty(m, dtype=torch.int32, device=dev)
+    o_t = torch.empty(m, dtype=torch.int32, device=dev)
+    d_rt = torch.from_numpy(pairs.rho.tables).to(dev)
+    d_tt = torch.from_numpy(pairs.temp.tables).to(dev)
+
+    def make():
+        return binding.PairPlan(d_rt, pairs.rho.table_off, d_tt, pairs.temp.table_off,
+                                pairs.rho.query_off)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = make()
+    build_s = time.perf_counter() - t0
+    info = plan.info()
+    counts = plan_counts(binding, info)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.search(r, t, o_r, o_t)
+
+    log(f"bench: warmup {args.warmup} (+ a {WARM_FLOOR_MS:.0f} ms floor)")
+    warmed = warm(torch, step, args.warmup, WARM_FLOOR_MS)
+    log(f"bench: timing {args.steps} steps")
+    # One pair of HIP events on the launch stream around the whole timed
+    # region: the launches (one graph launch holding the plan's kernel per
+    # step) run back to back, so the average launch duration is the region's
+    # event time over the step count.
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avg_launch_ms = ev0.elapsed_time(ev1) / args.steps
+    searches = 2 * m
+    value = searches * args.steps / wall / 1e9
+    achieved = searches * BYTES_PER_QUERY / (avg_launch_ms * 1e-3) / 1e9
+    learned = counts["learned_tables"] > 0
+    kernel = f"ss::multi_kernel<2, 8, {int(learned)}, 0> (split paired plan)"
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gqueries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "paired lookup: 4096 materials, density tables of 50..4000 and "
+                        "temperature tables of 20..1000 float64 entries (sorted log-uniform "
+                        "draws within seeded ranges in [1e-10,1e8]); 1e9 (rho,T) float64 "
+                        "pairs = 2e9 searches per step, pair counts per material "
+                        "proportional to 10^U(0,3); one plan launch with the autotuner's "
+                        "per-table kernel (learned index, exponent hash or bisection)",
+            "materials": pairs.num_materials,
+            "pairs_per_step": m,
+            "searches_per_step": searches,
+            "bytes_per_query": BYTES_PER_QUERY,
+            "plan_form": "split (density and temperature searches as 2M segments)",
+            **counts,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("multi_kernel<paired>|paired-4096"),
+            "kernel": kernel,
+            "algorithmic_bytes_per_launch": searches * BYTES_PER_QUERY,
+            "avg_launch_ms": round(avg_launch_ms, 4),
+        },
+        "warmup_run": warmed,
+        "plan": {"build_s": round(build_s, 2), "tiles": info["tiles"],
+                 "tiles_per_wg": info["tiles_per_wg"], "grid": info["grid"],
+                 "lds_bytes": info["lds_bytes"]},
+    }
+    # the paper reports the mean of 20 trials; each trial here is one step
+    # bracketed by its own event pair (context beside `value`, not part of it)
+    result["trials"] = trials(torch, step, searches, stream)
+
+    # The same plan kernel and targets with one-entry tables (every search
+    # reduces to one compare): the rate this access pattern reaches here, a
+    # practical ceiling beside the 8 TB/s peak.
+    log("bench: stream ceiling (one-entry tables)")
+    M_ = pairs.num_materials
+    one = torch.ones(M_, dtype=torch.float64, device=dev)
+    off1 = np.arange(M_ + 1, dtype=np.int64)
+    ceil_plan = binding.PairPlan(one, off1, one, off1, pairs.rho.query_off)
+    ceil_ms = time_call(torch, lambda: ceil_plan.search(r, t, o_r, o_t), reps=5)
+    ceil_plan.close()
+    ceiling = searches * BYTES_PER_QUERY / (ceil_ms * 1e-3) / 1e9
+    result["roofline"]["stream_ceiling"] = {
+        "achieved": round(ceiling, 1), "unit": "GB/s",
+        "frac_of_peak": round(ceiling / HBM_PEAK_GBS, 4),
+        "kernel_frac_of_ceiling": round(achieved / ceiling, 4),
+        "how": "the same plan kernel, targets and pair counts with one-entry tables"}
+
+    if not args.no_systems:
+        log("bench: learned+batched vs plain on the headline pairs")
+        comp = {"tuned": {**roof(searches, avg_launch_ms), **counts,
+                          "build_s": round(build_s, 2)}}
+        comp.update(compare_plans(torch, binding, make,
+                                  lambda pl: pl.search(r, t, o_r, o_t), searches, counts))
+        # the other launch form: both axes of a tile of pairs in one workgroup
+        joint = with_options(binding, {binding.OPT_PAIR_JOINT: 1}, make)
+        comp["joint_form"] = {**roof(searches, time_call(
+            torch, lambda: joint.search(r, t, o_r, o_t), reps=3)), **plan_counts(binding,
+                                                                              joint.info())}
+        joint.close()
+        # plain search without batching: one single-table launch per table
+        po = pairs.rho.query_off
+        tr = [d_rt[pairs.rho.table_off[j]:pairs.rho.table_off[j + 1]] for j in range(M_)]
+        tt = [d_tt[pairs.temp.table_off[j]:pairs.temp.table_off[j + 1]] for j in range(M_)]
+
+        def per_table():
+            for j in range(M_):
+                a, b = int(po[j]), int(po[j + 1])
+                if b > a:
+                    binding.search_sorted_batch(tr[j], r[a:b], o_r[a:b])
+                    binding.search_sorted_batch(tt[j], t[a:b], o_t[a:b])
+        comp["per_table_launches"] = roof(searches, time_call(torch, per_table, reps=1))
+        result["comparison"] = comp
+    plan.close()
+    del r, t, o_r, o_t, d_rt, d_tt
+    return result, pairs, hr.numpy(), ht.numpy()
+
+
+# ---------------------------------------------------------------------------
+# Other workloads, measured after the timed region
+# ---------------------------------------------------------------------------
+
+def measure_single_tables(torch, binding, inputs, dev, no_kernels: bool) -> dict:
+    """Single tables of 100, 300 and 1000 entries, 1e8 targets per launch in
+    two orders (i.i.d. log-uniform and a smooth sorted walk): six launches of
+    the library's automatic kernel choice (the staged bisection)."""
+    tables = [inputs.single_table(n) for n in TABLE_SIZES]
+    host = {}
+    for order in ORDERS:
+        buf = torch.empty(M, dtype=torch.float64).pin_memory()
+        # the three tables share the range [1e-8, 1e6], hence one target array per order
+        inputs.table_targets(tables[0], M, seed=2112, kind=order, out=buf.numpy())
+        host[order] = buf
+    d_tables = [torch.from_numpy(t).to(dev) for t in tables]
+    d_x = {o: host[o].to(dev) for o in ORDERS}
+    d_out = {(n, o): torch.empty(M, dtype=torch.int32, device=dev)
+             for n in TABLE_SIZES for o in ORDERS}
+    pairs = [(i, o) for i in range(len(TABLE_SIZES)) for o in ORDERS]
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for i, o in pairs:
+            binding.search_sorted_batch(d_tables[i], d_x[o], d_out[(TABLE_SIZES[i], o)])
+
+    warm(torch, step, 5, 50.0)
+    reps = 30
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = ev0.elapsed_time(ev1) / reps
+    avg_launch_ms = step_ms / len(pairs)
+    achieved = M * BYTES_PER_QUERY / (avg_launch_ms * 1e-3) / 1e9
+    one = torch.ones(1, dtype=torch.float64, device=dev)
+    ceil_ms = min(time_call(torch, lambda: binding.search_sorted_batch(
+        one, d_x[o], d_out[(TABLE_SIZES[0], o)]), reps=10) for o in ORDERS)
+    ceiling = M * BYTES_PER_QUERY / (ceil_ms * 1e-3) / 1e9
+    res = {"workload": "single tables n=100,300,1000 (log-uniform on [1e-8,1e6]); 1e8 "
+                       "float64 targets per table and order (i.i.d. log-uniform and smooth "
+                       "sorted walk); six launches of the automatic kernel (staged bisection)",
+           **roof(len(pairs) * M, step_ms),
+           "roofline": {"kernel": "ss::single_kernel<1, 8, 0>", "avg_launch_ms":
+                        round(avg_launch_ms, 4), "achieved": round(achieved, 1),
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic("single_kernel<binary>|single-1e8"),
+                        "stream_ceiling_gbs": round(ceiling, 1),
+                        "kernel_frac_of_ceiling": round(achieved / ceiling, 4)},
+           "trials": trials(torch, step, len(pairs) * M, stream)}
+    if not no_kernels:
+        log("bench: per-kernel comparison")
+        comp = {}
+        for (i, o) in pairs:
+            row = {}
+            for algo in ("binary", "ballot", "exphash", "loghash", "skiplist"):
+                out = d_out[(TABLE_SIZES[i], o)]
+                ms = time_call(torch, lambda: binding.search_with(d_tables[i], d_x[o], algo, -1,
+                                                                  out), reps=5, warm_ms=20.0)
+                row[algo] = round(M / (ms * 1e-3) / 1e9, 2)
+            comp[f"n={TABLE_SIZES[i]}/{o}"] = row
+        res["kernels_gqps"] = comp
+    del d_x, d_out, host
+    return res
 
 
 def measure_batched(torch, binding, inputs, dev) -> dict:
@@ -210,97 +526,34 @@ def measure_batched(torch, binding, inputs, dev) -> dict:
     inputs.batched_targets(batch, out=host.numpy())
     x = host.to(dev)
     out = torch.empty(m, dtype=torch.int32, device=dev)
-    plan = binding.MultiPlan(torch.from_numpy(batch.tables).to(dev), batch.table_off,
-                             batch.query_off)
+    d_tab = torch.from_numpy(batch.tables).to(dev)
+
+    def make():
+        return binding.MultiPlan(d_tab, batch.table_off, batch.query_off)
+
+    t0 = time.perf_counter()
+    plan = make()
+    build_s = time.perf_counter() - t0
     ms = time_call(torch, lambda: plan.search(x, out))
     info = plan.info()
+    counts = plan_counts(binding, info)
     res = {"workload": "512 tables, n uniform on 20..2000, ranges within [1e-10,1e8], "
                        f"{m} targets (query counts log-uniform on 1e4..1e7)",
-           **roof(m, ms),
-           "exphash_tables": int((info["algos"] == binding.ALGO_EXPHASH).sum()),
+           "tuned": {**roof(m, ms), **counts, "build_s": round(build_s, 2)},
            "tiles": info["tiles"], "tiles_per_wg": info["tiles_per_wg"],
            "grid": info["grid"], "lds_bytes": info["lds_bytes"],
            "traffic": measured_traffic("multi_kernel<batched>|batched-512")}
-    # plain search: the same tables one single-table launch at a time
-    tabs = [torch.from_numpy(batch.table(t)).to(dev) for t in range(batch.num_tables)]
+    plan.close()
+    res.update(compare_plans(torch, binding, make, lambda pl: pl.search(x, out), m, counts))
+    # plain search without batching: one single-table launch per table
+    tabs = [d_tab[batch.table_off[t]:batch.table_off[t + 1]] for t in range(batch.num_tables)]
     qo = batch.query_off
 
-    def plain():
+    def per_table():
         for t in range(batch.num_tables):
             binding.search_sorted_batch(tabs[t], x[qo[t]:qo[t + 1]], out[qo[t]:qo[t + 1]])
-    res["plain_per_table_launches"] = roof(m, time_call(torch, plain, reps=2))
-    res["learned"] = measure_learned_plan(
-        torch, binding, lambda: binding.MultiPlan(torch.from_numpy(batch.tables).to(dev),
-                                                  batch.table_off, batch.query_off),
-        lambda pl: pl.search(x, out), m)
+    res["per_table_launches"] = roof(m, time_call(torch, per_table, reps=2))
     del x, out, host
-    return res
-
-
-def measure_learned_plan(torch, binding, make, run, queries: int) -> dict:
-    """Same plan with every eligible table given a learned model (trained on
-    the device when the plan is built)."""
-    binding.set_option(binding.OPT_PLAN_LEARNED, 1)
-    try:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan = make()
-        build_s = time.perf_counter() - t0
-    finally:
-        binding.set_option(binding.OPT_PLAN_LEARNED, 0)
-    ms = time_call(torch, lambda: run(plan), reps=2)
-    info = plan.info()
-    res = {**roof(queries, ms), "build_s": round(build_s, 2),
-           "learned_tables": int((info["algos"] == binding.ALGO_LEARNED).sum()),
-           "fallbacks": plan.fallbacks(),
-           "layered_equivalent_tflops":
-               round(LAYERED_FLOPS_PER_QUERY * queries / (ms * 1e-3) / 1e12, 1)}
-    plan.close()
-    return res
-
-
-def measure_paired(torch, binding, inputs, dev) -> dict:
-    """4096 materials, density (50..4000) and temperature (20..1000) tables,
-    1e9 pairs = 2e9 searches in one launch."""
-    pairs = inputs.paired_layout()
-    m = pairs.num_pairs
-    hr = torch.empty(m, dtype=torch.float64).pin_memory()
-    ht = torch.empty(m, dtype=torch.float64).pin_memory()
-    inputs.paired_targets(pairs, out_rho=hr.numpy(), out_t=ht.numpy())
-    r, t = hr.to(dev), ht.to(dev)
-    del hr, ht
-    o_r = torch.empty(m, dtype=torch.int32, device=dev)
-    o_t = torch.empty(m, dtype=torch.int32, device=dev)
-    plan = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(dev), pairs.rho.table_off,
-                            torch.from_numpy(pairs.temp.tables).to(dev), pairs.temp.table_off,
-                            pairs.rho.query_off)
-    ms = time_call(torch, lambda: plan.search(r, t, o_r, o_t), reps=3)
-    info = plan.info()
-    res = {"workload": f"4096 materials, {m} (rho, T) pairs, 2 searches per pair",
-           **roof(2 * m, ms),
-           "exphash_tables": int((info["algos"] == binding.ALGO_EXPHASH).sum()),
-           "tables": info["tables"], "tiles": info["tiles"],
-           "tiles_per_wg": info["tiles_per_wg"], "grid": info["grid"],
-           "lds_bytes": info["lds_bytes"],
-           "traffic": measured_traffic("multi_kernel<paired>|paired-4096")}
-    plan.close()
-    # the other launch form: both axes of a tile of pairs in one workgroup
-    binding.set_option(binding.OPT_PAIR_JOINT, 1)
-    try:
-        joint = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(dev), pairs.rho.table_off,
-                                 torch.from_numpy(pairs.temp.tables).to(dev),
-                                 pairs.temp.table_off, pairs.rho.query_off)
-    finally:
-        binding.set_option(binding.OPT_PAIR_JOINT, 0)
-    res["joint_form"] = roof(2 * m, time_call(torch, lambda: joint.search(r, t, o_r, o_t), reps=3))
-    joint.close()
-    res["learned"] = measure_learned_plan(
-        torch, binding,
-        lambda: binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(dev), pairs.rho.table_off,
-                                 torch.from_numpy(pairs.temp.tables).to(dev),
-                                 pairs.temp.table_off, pairs.rho.query_off),
-        lambda pl: pl.search(r, t, o_r, o_t), 2 * m)
-    del r, t, o_r, o_t
     return res
 
 
@@ -488,20 +741,12 @@ def measure_interp(torch, binding, inputs, dev) -> dict:
             "tiles_per_wg": info["tiles_per_wg"], "lds_bytes": info["lds_bytes"]}
 
 
-# FP32 work of one learned-index query as the search evaluates the model
-# (compiled to its pieces: one fused multiply-add of the piece holding the
-# input, found by an 11-step bisection over at most 2048 padded boundaries,
-# not counted) against the layered form it replaces, 2 * (32 + 32 * 32 + 32)
-# flops per query.  The kernel is bound by neither: the bisections over the
-# boundaries and the table are latency-bound LDS reads.
-MLP_FLOPS_PER_QUERY = 2
-LAYERED_FLOPS_PER_QUERY = 2 * (32 + 32 * 32 + 32)
-FP32_PEAK_TFLOPS = 157.3
-
-
 def measure_learned(torch, binding, inputs, dev) -> dict:
     """One 2000-entry table, 1e8 log-uniform targets: the learned index
-    (trained on the device) against the plain search on the same data."""
+    (trained on the device) against the plain search on the same data.  The
+    search evaluates the model in its compiled piecewise-linear form: one
+    fused multiply-add per query, after the lookup of the piece holding the
+    input; the window search that follows is LDS reads and compares."""
     table = inputs.learned_table()
     t = torch.from_numpy(table).to(dev)
     host = torch.empty(M, dtype=torch.float64).pin_memory()
@@ -516,15 +761,11 @@ def measure_learned(torch, binding, inputs, dev) -> dict:
     fallbacks = li.fallbacks()
     ms_p = time_call(torch, lambda: binding.search_sorted_batch(t, x, out), reps=5)
     info = li.info()
-    # what the layered network would have to sustain to match the search
-    layered_tflops = LAYERED_FLOPS_PER_QUERY * M / (ms_l * 1e-3) / 1e12
     res = {"workload": "one 2000-entry table (log-uniform on [1e-8,1e6]), 1e8 targets",
            "learned": {**roof(M, ms_l), "E": info["E"], "fallbacks": fallbacks,
                        "train_loss": info["loss"], "build_s": round(build_s, 3),
-                       "model": {"flops_per_query": MLP_FLOPS_PER_QUERY,
-                                 "layered_flops_per_query": LAYERED_FLOPS_PER_QUERY,
-                                 "layered_equivalent_tflops": round(layered_tflops, 1),
-                                 "fp32_peak_tflops": FP32_PEAK_TFLOPS}},
+                       "pieces": info.get("pieces"), "cells": info.get("cells"),
+                       "executed_model_flops_per_query": 2},
            "plain": roof(M, ms_p)}
     li.close()
     del x, out, host
@@ -538,9 +779,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-kernels", action="store_true",
-                    help="skip the per-kernel comparison after the timed region")
+                    help="skip the single-table per-kernel comparison")
     ap.add_argument("--no-systems", action="store_true",
-                    help="skip the batched, paired and learned measurements")
+                    help="skip the comparisons and every workload after the headline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -563,141 +804,13 @@ def main():
     torch.cuda.set_device(dev)
     binding.lib()
 
-    log("bench: generating inputs")
-    tables = [inputs.single_table(n) for n in TABLE_SIZES]
-    host = {}
-    for order in ORDERS:
-        buf = torch.empty(M, dtype=torch.float64).pin_memory()
-        # the three tables share the range [1e-8, 1e6], hence one target array per order
-        inputs.table_targets(tables[0], M, seed=2112, kind=order, out=buf.numpy())
-        host[order] = buf
-    d_tables = [torch.from_numpy(t).to(dev) for t in tables]
-    d_x = {o: host[o].to(dev, non_blocking=True) for o in ORDERS}
-    d_out = {(n, o): torch.empty(M, dtype=torch.int32, device=dev)
-             for n in TABLE_SIZES for o in ORDERS}
-    torch.cuda.synchronize()
-
-    pairs = [(i, o) for i in range(len(TABLE_SIZES)) for o in ORDERS]
-    stream = torch.cuda.current_stream()
-
-    def step():
-        for i, o in pairs:
-            binding.search_sorted_batch(d_tables[i], d_x[o], d_out[(TABLE_SIZES[i], o)])
-
-    log(f"bench: warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    log(f"bench: timing {args.steps} steps")
-    # One pair of HIP events on the launch stream around the whole timed
-    # region: the launches run back to back, and the average launch
-    # duration is the region's event time over the launch count.  (An event
-    # pair around every launch puts a marker between consecutive kernels,
-    # which idles the GPU for ~10 us each time.)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    avg_launch_ms = ev0.elapsed_time(ev1) / (args.steps * len(pairs))
-    queries_per_step = len(pairs) * M
-    ms_per_step = wall * 1e3 / args.steps
-    value = queries_per_step * args.steps / wall / 1e9
-
-    # the automatic choice for these tables (staged bisection)
-    kernel = "single_kernel<binary>"
-    achieved = M * BYTES_PER_QUERY / (avg_launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic("single_kernel<binary>|single-1e8")
-    result = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "Gqueries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "single tables n=100,300,1000 (log-uniform on [1e-8,1e6]); "
-                        "1e8 float64 targets per table and order; orders: i.i.d. log-uniform "
-                        "and smooth sorted walk; automatically chosen kernel (staged bisection)",
-            "tables": list(TABLE_SIZES),
-            "targets_per_launch": M,
-            "launches_per_step": len(pairs),
-            "bytes_per_query": BYTES_PER_QUERY,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": kernel,
-            "algorithmic_bytes_per_launch": M * BYTES_PER_QUERY,
-            "avg_launch_ms": round(avg_launch_ms, 4),
-        },
-    }
-
-    # After the timed region: 20 more steps, each bracketed by its own event
-    # pair (the paper reports trials of a run); their median and minimum
-    # beside the mean above.  Not part of `value`.
-    trial_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                for _ in range(20)]
-    for e0, e1 in trial_ev:
-        e0.record(stream)
-        step()
-        e1.record(stream)
-    torch.cuda.synchronize()
-    trial_ms = np.array([e0.elapsed_time(e1) for e0, e1 in trial_ev])
-    result["trials"] = {"steps": len(trial_ms),
-                        "median_ms_per_step": round(float(np.median(trial_ms)), 4),
-                        "min_ms_per_step": round(float(trial_ms.min()), 4),
-                        "median_gqps": round(queries_per_step / (np.median(trial_ms) * 1e-3) / 1e9, 2),
-                        "max_gqps": round(queries_per_step / (trial_ms.min() * 1e-3) / 1e9, 2)}
-
-    # The same kernel over the same 1e8-target arrays with a one-entry table
-    # (its search reduces to one compare): the rate this access pattern
-    # reaches on this GPU, a practical ceiling beside the 8 TB/s peak.
-    log("bench: stream ceiling (one-entry table)")
-    one = torch.ones(1, dtype=torch.float64, device=dev)
-    ceil_ms = min(time_call(torch, lambda: binding.search_sorted_batch(one, d_x[o],
-                                                                       d_out[(TABLE_SIZES[0], o)]),
-                            reps=10)
-                  for o in ORDERS)
-    ceiling = M * BYTES_PER_QUERY / (ceil_ms * 1e-3) / 1e9
-    result["roofline"]["stream_ceiling"] = {
-        "achieved": round(ceiling, 1), "unit": "GB/s",
-        "frac_of_peak": round(ceiling / HBM_PEAK_GBS, 4),
-        "kernel_frac_of_ceiling": round(achieved / ceiling, 4),
-        "how": "the same kernel and targets with a one-entry table"}
-
-    if not args.no_kernels:
-        log("bench: per-kernel comparison")
-        comp = {}
-        for (i, o) in pairs:
-            row = {}
-            for algo in ("binary", "ballot", "exphash", "loghash", "skiplist"):
-                out = d_out[(TABLE_SIZES[i], o)]
-                ms = time_call(torch, lambda: binding.search_with(d_tables[i], d_x[o], algo, -1,
-                                                                  out), reps=5, warm_ms=20.0)
-                row[algo] = round(M / (ms * 1e-3) / 1e9, 2)
-            comp[f"n={TABLE_SIZES[i]}/{o}"] = row
-        result["kernels_gqps"] = comp
+    result, pairs, host_r, host_t = paired_headline(torch, binding, inputs, dev, args)
+    torch.cuda.empty_cache()
 
     if not args.no_systems:
-        # free the single-table workload before the larger ones
-        del d_x, d_out
+        log("bench: single tables (n = 100, 300, 1000; 1e8 targets)")
+        result["single_tables"] = measure_single_tables(torch, binding, inputs, dev,
+                                                        args.no_kernels)
         torch.cuda.empty_cache()
         log("bench: small table, graph-replayed calls")
         result["small"] = measure_small(torch, binding, inputs, dev)
@@ -709,9 +822,6 @@ def main():
         log("bench: batched plan")
         result["batched"] = measure_batched(torch, binding, inputs, dev)
         torch.cuda.empty_cache()
-        log("bench: paired plan")
-        result["paired"] = measure_paired(torch, binding, inputs, dev)
-        torch.cuda.empty_cache()
         log("bench: interpolation after the paired search")
         result["interp"] = measure_interp(torch, binding, inputs, dev)
         torch.cuda.empty_cache()
@@ -721,7 +831,7 @@ def main():
 
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
-        result["cpu_baseline"] = cpu_baseline(tables, {o: host[o].numpy() for o in ORDERS})
+        result["cpu_baseline"] = cpu_baseline(pairs, host_r, host_t)
     print(json.dumps(result), flush=True)
 
 

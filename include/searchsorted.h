@@ -116,11 +116,13 @@ typedef enum {
                                     learned searches use their own */
     SS_OPT_PLAN_TILES = 8,       /* tiles per workgroup of plans built
                                     afterwards; 0 (default) = tuner */
-    SS_OPT_PLAN_LEARNED = 9,     /* 1: plans built afterwards give every
-                                    eligible table (2 <= n, 0 < a[0] <
-                                    a[n-1] < inf) a learned model trained on
-                                    the device at plan creation; 0 (default):
-                                    exponent hash / bisection per the tuner */
+    SS_OPT_PLAN_LEARNED = 9,     /* learned models in plans built
+                                    afterwards.  0 (default): the tuner
+                                    decides per table (see the autotuner
+                                    section); 1: every eligible table (2 <=
+                                    n, 0 < a[0] < a[n-1] < inf) gets a model
+                                    trained on the device at plan creation;
+                                    2: none (exponent hash / bisection) */
     SS_OPT_LEARNED_STEPS = 10,   /* Adam steps of plan models; 0 (default)
                                     = 500 */
     SS_OPT_PLAN_XCD = 11,        /* workgroup-to-XCD mapping of plans built
@@ -138,7 +140,7 @@ typedef enum {
                                     workgroup; 1 = each workgroup searches
                                     both axes of its pairs with both of the
                                     material's tables staged */
-    SS_OPT_CONVENTION = 13       /* 0 (default): idx(x) = #{a < x} - 1, -1
+    SS_OPT_CONVENTION = 13,      /* 0 (default): idx(x) = #{a < x} - 1, -1
                                     when no entry is below x.  1: the
                                     paper's convention (Sec. 3), the last
                                     index with a[i] <= x clamped to [0,
@@ -146,6 +148,16 @@ typedef enum {
                                     Read by single-table and learned
                                     searches at each call and by plans at
                                     creation */
+    SS_OPT_PLAN_ALGO = 14        /* kernel of every table of plans built
+                                    afterwards: SS_ALGO_AUTO (default) = the
+                                    tuner's choice; SS_ALGO_BINARY = the
+                                    bisection; SS_ALGO_EXPHASH = the
+                                    exponent hash at the tuner's best bin
+                                    bits wherever it applies (bisection
+                                    elsewhere).  Learned models follow
+                                    SS_OPT_PLAN_LEARNED unless this is
+                                    SS_ALGO_BINARY or SS_ALGO_EXPHASH, which
+                                    imply none */
 } ss_option;
 
 /* Human-readable message for the calling thread's most recent error

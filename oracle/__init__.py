@@ -154,7 +154,8 @@ def search_lt_at(table, targets, positions, threads: int = 0):
     return out
 
 
-def search_lt_segments(tables, table_off, targets, query_off, threads: int = 0):
+def search_lt_segments(tables, table_off, targets, query_off, threads: int = 0,
+                       return_threads: bool = False):
     """Segment s searches tables[table_off[s]:table_off[s+1]] with its targets."""
     lib = _load()
     t = _f64(tables)
@@ -164,9 +165,9 @@ def search_lt_segments(tables, table_off, targets, query_off, threads: int = 0):
     nseg = toff.shape[0] - 1
     assert qoff.shape[0] == nseg + 1 and qoff[-1] == x.shape[0] and toff[-1] <= t.shape[0]
     out = np.empty(x.shape[0], dtype=np.int32)
-    lib.oracle_search_lt_segments(_ptr(t), _ptr(toff), _ptr(x), _ptr(qoff), nseg, _ptr(out),
-                                  threads)
-    return out
+    used = lib.oracle_search_lt_segments(_ptr(t), _ptr(toff), _ptr(x), _ptr(qoff), nseg,
+                                         _ptr(out), threads)
+    return (out, used) if return_threads else out
 
 
 def check_bracket(table, targets, idx, threads: int = 0):

@@ -549,6 +549,14 @@ void describe(const TunedTable& tt, int64_t tab_off, TableDesc* d, int64_t* pool
 
 size_t align16(size_t v) { return (v + 15) / 16 * 16; }
 
+// Learned models of plans built now (SS_OPT_PLAN_LEARNED, overridden by a
+// forced plan kernel).
+enum LearnedMode { kLearnedTuner = 0, kLearnedAll = 1, kLearnedNone = 2 };
+int learned_mode() {
+  if (option(SS_OPT_PLAN_ALGO) != SS_ALGO_AUTO) return kLearnedNone;
+  return (int)option(SS_OPT_PLAN_LEARNED);
+}
+
 int fail_delete(ss_plan* p, const char* msg, int code = SS_ERR_INVALID_ARG) {
   delete p;
   return msg ? fail(code, msg) : code;
@@ -927,12 +935,13 @@ static int create_batched(const double* tables, const int64_t* table_off, int32_
   int64_t pool = 0;
   for (int t = 0; t < T; ++t) {
     const int n = (int)(table_off[t + 1] - table_off[t]);
-    p->tuned[t] = tune_table(model, host.data() + table_off[t], n, kPlanLdsBudget - max_tab);
+    p->tuned[t] = tune_table(model, host.data() + table_off[t], n, kPlanLdsBudget - max_tab,
+                             (int)option(SS_OPT_PLAN_ALGO));
     describe(p->tuned[t], table_off[t], &p->desc[t], &pool);
     if (p->tuned[t].algo == SS_ALGO_EXPHASH)
       max_bins = std::max(max_bins, align16((size_t)(p->tuned[t].nb + 1) * 2));
   }
-  if (models || option(SS_OPT_PLAN_LEARNED)) {
+  if (models || learned_mode() == kLearnedAll) {
     rc = models ? attach_learned(p, tables, table_off, models)
                 : apply_learned(p, tables, nullptr, host, host);
     if (rc != SS_OK) return fail_delete(p, nullptr, rc);
@@ -1081,21 +1090,22 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
     budget_a = budget_b = kPlanLdsBudget - tab_a;
   }
   int64_t pool = 0;
+  const int force = (int)option(SS_OPT_PLAN_ALGO);
   for (int j = 0; j < M; ++j) {
     const int n = (int)(rho_off[j + 1] - rho_off[j]);
-    p->tuned[j] = tune_table(model, hr.data() + rho_off[j], n, budget_a);
+    p->tuned[j] = tune_table(model, hr.data() + rho_off[j], n, budget_a, force);
     describe(p->tuned[j], rho_off[j], &p->desc[j], &pool);
     if (p->tuned[j].algo == SS_ALGO_EXPHASH)
       bins_a = std::max(bins_a, align16((size_t)(p->tuned[j].nb + 1) * 2));
   }
   for (int j = 0; j < M; ++j) {
     const int n = (int)(t_off[j + 1] - t_off[j]);
-    p->tuned[M + j] = tune_table(model, ht.data() + t_off[j], n, budget_b);
+    p->tuned[M + j] = tune_table(model, ht.data() + t_off[j], n, budget_b, force);
     describe(p->tuned[M + j], t_off[j], &p->desc[M + j], &pool);
     if (p->tuned[M + j].algo == SS_ALGO_EXPHASH)
       bins_b = std::max(bins_b, align16((size_t)(p->tuned[M + j].nb + 1) * 2));
   }
-  if (option(SS_OPT_PLAN_LEARNED) && p->mode != kPairInterp) {
+  if (learned_mode() == kLearnedAll && p->mode != kPairInterp) {
     if ((rc = apply_learned(p, rho_tables, t_tables, hr, ht)) != SS_OK)
       return fail_delete(p, nullptr, rc);
     bins_a = bins_b = 0;

@@ -27,6 +27,7 @@ std::atomic<int64_t> g_learned_steps{0};
 std::atomic<int64_t> g_plan_xcd{0};
 std::atomic<int64_t> g_pair_joint{0};
 std::atomic<int64_t> g_convention{0};
+std::atomic<int64_t> g_plan_algo{SS_ALGO_AUTO};
 
 std::mutex g_dev_mu;
 std::map<int, DeviceInfo> g_dev_cache;
@@ -65,6 +66,7 @@ int64_t option(int opt) {
     case SS_OPT_PLAN_XCD: return g_plan_xcd.load();
     case SS_OPT_PAIR_JOINT: return g_pair_joint.load();
     case SS_OPT_CONVENTION: return g_convention.load();
+    case SS_OPT_PLAN_ALGO: return g_plan_algo.load();
     default: return 0;
   }
 }
@@ -202,7 +204,7 @@ int ss_set_option(int opt, int64_t v) {
       ss::g_plan_tiles = v;
       return SS_OK;
     case SS_OPT_PLAN_LEARNED:
-      if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PLAN_LEARNED: 0 or 1");
+      if (v < 0 || v > 2) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PLAN_LEARNED: 0, 1 or 2");
       ss::g_plan_learned = v;
       return SS_OK;
     case SS_OPT_LEARNED_STEPS:
@@ -222,6 +224,12 @@ int ss_set_option(int opt, int64_t v) {
     case SS_OPT_CONVENTION:
       if (v != 0 && v != 1) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_CONVENTION: 0 or 1");
       ss::g_convention = v;
+      return SS_OK;
+    case SS_OPT_PLAN_ALGO:
+      if (v != SS_ALGO_AUTO && v != SS_ALGO_BINARY && v != SS_ALGO_EXPHASH)
+        return ss::fail(SS_ERR_INVALID_ARG,
+                        "SS_OPT_PLAN_ALGO: SS_ALGO_AUTO, SS_ALGO_BINARY or SS_ALGO_EXPHASH");
+      ss::g_plan_algo = v;
       return SS_OK;
     default:
       return ss::fail(SS_ERR_INVALID_ARG, "unknown option");
@@ -244,6 +252,7 @@ int ss_get_option(int opt, int64_t* value_out) {
     case SS_OPT_PLAN_XCD:
     case SS_OPT_PAIR_JOINT:
     case SS_OPT_CONVENTION:
+    case SS_OPT_PLAN_ALGO:
       *value_out = ss::option(opt);
       return SS_OK;
     default:

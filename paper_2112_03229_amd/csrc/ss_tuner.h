@@ -36,8 +36,11 @@ struct TunedTable {
 const TunerModel& tuner_model();
 
 // Chooses the kernel and bin bits for one table of n entries; the bin table
-// may take at most `bins_budget` bytes of LDS.
-TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bins_budget);
+// may take at most `bins_budget` bytes of LDS.  force = SS_ALGO_AUTO picks
+// the cheapest; SS_ALGO_BINARY the bisection; SS_ALGO_EXPHASH the cheapest
+// bin bits of the exponent hash wherever it applies (else the bisection).
+TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bins_budget,
+                      int force = 0);
 
 // Consecutive tiles per workgroup of a plan launch with `total_tiles`
 // tiles of `per_tile` targets in `segments` segments and `resident`

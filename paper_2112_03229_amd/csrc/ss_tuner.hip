@@ -138,12 +138,15 @@ int host_longest_bin(const double* a, int n, int s) {
   return best;
 }
 
-TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bins_budget) {
+TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bins_budget,
+                      int force) {
   TunedTable best;
   best.n = n;
   best.algo = SS_ALGO_BINARY;
   best.est_ns = model.bin_base_ns + model.bin_per_step_ns * bisect_steps(n);
-  if (n < 1 || n > 65535) return best;
+  if (n < 1 || n > 65535 || force == SS_ALGO_BINARY) return best;
+  // a forced exponent hash takes its cheapest bin bits whatever the bisection costs
+  if (force == SS_ALGO_EXPHASH) best.est_ns = INFINITY;
   const int h0 = hi_word_host(a[0]), h1 = hi_word_host(a[n - 1]);
   if (h0 < 0 || h1 < h0) return best;
   for (int s = 0; s <= SS_MAX_BITS; ++s) {
@@ -169,6 +172,8 @@ TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bi
       best.est_ns = cost;
     }
   }
+  if (std::isinf(best.est_ns))  // forced hash not applicable: bisection
+    best.est_ns = model.bin_base_ns + model.bin_per_step_ns * bisect_steps(n);
   return best;
 }
 

@@ -52,10 +52,19 @@ def test_version_and_options(L):
     for v in (1, 2, 16, 1 << 24, 0):
         b.set_option(b.OPT_PLAN_XCD, v)
         assert b.get_option(b.OPT_PLAN_XCD) == v
+    for v in (b.PLAN_LEARNED_ALL, b.PLAN_LEARNED_NONE, b.PLAN_LEARNED_TUNER):
+        b.set_option(b.OPT_PLAN_LEARNED, v)
+        assert b.get_option(b.OPT_PLAN_LEARNED) == v
+    for v in (b.ALGO_BINARY, b.ALGO_EXPHASH, b.ALGO_AUTO):
+        b.set_option(b.OPT_PLAN_ALGO, v)
+        assert b.get_option(b.OPT_PLAN_ALGO) == v
     for opt, bad in ((b.OPT_FORCE_ALGO, 9), (b.OPT_FORCE_ALGO, 8), (b.OPT_FORCE_ALGO, b.ALGO_LEARNED),
                      (b.OPT_BUCKET_BITS, 21), (b.OPT_BLOCK_SIZE, 100),
                      (b.OPT_CHECK_POINTERS, 2), (b.OPT_PAIR_JOINT, 2), (b.OPT_CONVENTION, 2),
-                     (b.OPT_PLAN_XCD, -1), (b.OPT_PLAN_XCD, (1 << 24) + 1), (999, 0)):
+                     (b.OPT_PLAN_XCD, -1), (b.OPT_PLAN_XCD, (1 << 24) + 1),
+                     (b.OPT_PLAN_LEARNED, 3), (b.OPT_PLAN_LEARNED, -1),
+                     (b.OPT_PLAN_ALGO, b.ALGO_LEARNED), (b.OPT_PLAN_ALGO, b.ALGO_BALLOT),
+                     (b.OPT_PLAN_ALGO, 8), (999, 0)):
         with pytest.raises(b.SearchSortedError) as e:
             b.set_option(opt, bad)
         assert e.value.code == -1
