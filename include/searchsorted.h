@@ -304,6 +304,40 @@ SS_API int ss_multi_plan_create_learned(const double *tables, const int64_t *tab
  * graph launch). */
 SS_API int ss_multi_search(ss_plan *plan, const double *targets, int32_t *out_idx);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc -- the batched
+ * search of ss_multi_search without a plan:
+ *   out_idx[k] = idx_t(targets[k]) for k in [query_off[t], query_off[t+1])
+ * with idx_t the operation at the top of this header over table t.
+ *   tables    : device, float64, total_n entries; table t is
+ *               tables[table_off[t] .. table_off[t+1]) (sorted, any length up
+ *               to INT32_MAX; up to 6136 entries are staged in LDS, longer
+ *               tables are searched in place)
+ *   table_off : DEVICE, T+1 int64, non-decreasing, within [0, total_n]
+ *   T         : 1 <= T <= 65536 (the limit of the device scratch below;
+ *               larger T returns SS_ERR_INVALID_ARG)
+ *   query_off : DEVICE, T+1 int64, non-decreasing, query_off[0] == 0 and
+ *               query_off[T] == m
+ *   targets   : device, m float64; out_idx: device, m int32, not overlapping
+ *               any input
+ * Every table is searched by bisection (no tuner, no bin tables); results
+ * are those of ss_multi_search on the same tables, and follow
+ * SS_OPT_CONVENTION as read at the call.  Offsets are read on the device and
+ * not validated: offsets outside [0, total_n] / [0, m] are clamped into them
+ * and decreasing ones are raised to the running maximum, so a violation
+ * gives unspecified indices (or leaves targets outside every segment
+ * unwritten) but no out-of-bounds access.
+ * Allocates nothing and never synchronises: two kernels on the current
+ * stream.  Working memory is a 1 MiB array of static device memory that each
+ * GPU the library runs on holds until the process ends; every call on one GPU
+ * shares it, so calls that overlap on one GPU (from two streams or two
+ * threads) race and must be ordered by the caller.  Each call rewrites every
+ * entry it reads.  Asynchronous. */
+SS_API int ss_multi_search_noalloc(const double *tables, int64_t total_n,
+                                   const int64_t *table_off, int32_t T,
+                                   const int64_t *query_off, const double *targets, int64_t m,
+                                   int32_t *out_idx);
+
 /* Paired lookup (the density and temperature axes of EOS tables, Sec. 1):
  * M materials, each with a density table and a temperature table (CSR as
  * above, each at most 6136 entries; in the joint form, SS_OPT_PAIR_JOINT,

@@ -21,7 +21,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 REPO = os.path.dirname(HERE)
 ARCH = os.environ.get("SS_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["ss_runtime.hip", "ss_single.hip", "ss_plan.hip", "ss_tuner.hip",
+HIP_SOURCES = ["ss_runtime.hip", "ss_single.hip", "ss_plan.hip", "ss_tuner.hip", "ss_noalloc.hip",
                "ss_learned.hip"]
 
 

@@ -104,6 +104,7 @@ def _register_extra(L) -> None:
         "ss_loghash_bins": [P, I64, I64, P, P],
         "ss_interp_plan_create": [P, P, P, P, I32, P, P, ctypes.POINTER(P)],
         "ss_interp_search": [P, P, P, P, P, P],
+        "ss_multi_search_noalloc": [P, I64, P, I32, P, P, I64, P],
         "ss_learned_save": [P, ctypes.c_char_p],
         "ss_learned_load": [P, I64, ctypes.c_char_p, ctypes.POINTER(P)],
     }
@@ -319,6 +320,29 @@ class MultiPlan(_Plan):
         use_current_stream()
         check(lib().ss_multi_search(self._handle, _ptr(targets), _ptr(out)))
         return out
+
+
+def multi_search_noalloc(tables: torch.Tensor, table_off: torch.Tensor, query_off: torch.Tensor,
+                         targets: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Batched search without a plan (ss_multi_search_noalloc): table_off and
+    query_off are device int64 tensors of T+1 offsets."""
+    _need(tables, torch.float64, "tables")
+    _need(table_off, torch.int64, "table_off")
+    _need(query_off, torch.int64, "query_off")
+    _need(targets, torch.float64, "targets")
+    T = table_off.numel() - 1
+    if query_off.numel() != T + 1:
+        raise ValueError("table_off and query_off must have the same length")
+    if out is None:
+        out = torch.empty(targets.numel(), dtype=torch.int32, device=targets.device)
+    _need(out, torch.int32, "out")
+    if out.numel() != targets.numel():
+        raise ValueError("out must have one entry per target")
+    use_current_stream()
+    check(lib().ss_multi_search_noalloc(_ptr(tables), tables.numel(), _ptr(table_off), T,
+                                        _ptr(query_off), _ptr(targets), targets.numel(),
+                                        _ptr(out)))
+    return out
 
 
 class PairPlan(_Plan):
