@@ -126,7 +126,7 @@ def _pair_sample(pairs, host_r, host_t, frac: float):
     return off, np.ascontiguousarray(host_r[idx]), np.ascontiguousarray(host_t[idx])
 
 
-def cpu_baseline(pairs, host_r, host_t, budget_s: float = 15.0) -> dict:
+def cpu_baseline(pairs, host_r, host_t, budget_s: float = 20.0) -> dict:
     """The CPU oracle (plain linear count) on all host cores, on a bounded
     sample of the headline workload: the first pairs of every material,
     both axes."""
@@ -143,7 +143,8 @@ def cpu_baseline(pairs, host_r, host_t, budget_s: float = 15.0) -> dict:
 
     total = pairs.num_pairs
     threads = oracle.default_threads()
-    n_cal, s_cal, _ = run(2e-3, threads)
+    # calibration on 1% of the pairs (per-material thread start-up included)
+    n_cal, s_cal, _ = run(1e-2, threads)
     frac = min(1.0, max(1e7 / total, budget_s / (s_cal / n_cal) / total))
     n, sec, used = run(frac, threads)
     # the paper's own setting: one core (a third of the time budget)
@@ -772,6 +773,17 @@ def measure_learned(torch, binding, inputs, dev) -> dict:
     return res
 
 
+ONLY = {
+    "single_tables": lambda torch, b, i, d: measure_single_tables(torch, b, i, d, True),
+    "small": measure_small,
+    "small_m": measure_small_m,
+    "paper_shape": measure_paper_shape,
+    "batched": measure_batched,
+    "interp": measure_interp,
+    "learned": measure_learned,
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -784,6 +796,9 @@ def main():
                     help="skip the comparisons and every workload after the headline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (HBM counter calibration)")
+    ap.add_argument("--only", choices=sorted(ONLY),
+                    help="run one of the other workloads alone and print its record (for "
+                         "profiling); no headline")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -803,6 +818,12 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     binding.lib()
+
+    if args.only:
+        log(f"bench: {args.only} alone")
+        rec = ONLY[args.only](torch, binding, inputs, dev)
+        print(json.dumps({"only": args.only, **rec}), flush=True)
+        return
 
     result, pairs, host_r, host_t = paired_headline(torch, binding, inputs, dev, args)
     torch.cuda.empty_cache()

@@ -394,8 +394,18 @@ SS_API int ss_plan_fallbacks(ss_plan *plan, int64_t *count);
  *   SS_PLAN_SUMMARY: 8 int64 {tables, tiles, tiles per workgroup, grid,
  *                    block, lds_bytes, longest bin (9 = 9 or more),
  *                    graph launches so far}
+ *   SS_PLAN_COSTS  : 2 doubles per table (cap >= 2 T): the autotuner's
+ *                    modelled ns per query of its best plain kernel, and of
+ *                    the table's trained learned model (-1 if none was
+ *                    trained); in tuner mode a trained table is learned
+ *                    exactly when the second is the smaller
  * `cap` is the number of elements `out` can hold. */
-typedef enum { SS_PLAN_ALGOS = 1, SS_PLAN_BITS = 2, SS_PLAN_SUMMARY = 3 } ss_plan_query;
+typedef enum {
+    SS_PLAN_ALGOS = 1,
+    SS_PLAN_BITS = 2,
+    SS_PLAN_SUMMARY = 3,
+    SS_PLAN_COSTS = 4
+} ss_plan_query;
 SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
 
 /* ---------------------------------------------------------------------------
@@ -512,30 +522,50 @@ SS_API int ss_mlp_gradient(const double *table, int64_t n, const float *weights,
 SS_API int ss_learned_destroy(ss_learned *h);
 
 /* ---------------------------------------------------------------------------
- * Autotuner.  Plans choose each table's kernel, exponent-hash bin bits and
- * the work-queue chunk size from a cost model (device-wide nanoseconds per
- * query: memory = 12 B / stream bandwidth; compute = fixed + per-step terms
- * of bisection and of the in-bin scan).  The model starts from built-in
- * coefficients; ss_tuner_calibrate measures them on the current device, and
- * the model can be saved to / loaded from a small JSON file (the library
- * also loads the file named by the environment variable SS_TUNER_CACHE, if
- * set, on first use).  Plans built earlier keep their choices.
+ * Autotuner (paper Sec. 5.1-5.2: the best method depends on the array sizes
+ * and on the distribution of the data).  Plans choose each table's kernel
+ * (exponent hash at some bin bits, bisection, or -- with SS_OPT_PLAN_LEARNED
+ * 0 -- the learned index) and the number of consecutive target tiles a
+ * workgroup takes, from a cost model in device-wide nanoseconds per query:
+ * every kernel moves the same 12 bytes per query, so the choice minimises
+ * compute:
+ *   bisection      bin_base + bin_per_step * ceil(log2 n)
+ *   exponent hash  hash_base + hash_per_k * K(s)   (K: the longest bin)
+ *   learned index  learned_base + learned_per_step * (lookup + window(E)),
+ *                  lookup = the model's piece lookup in LDS steps, window(E)
+ *                  = floor(log2(2E + 1)) + 3 (bisection and its two checks)
+ * In tuner mode a table is trained only when the learned cost at the best
+ * possible bound (E = 1) undercuts its best plain kernel; after training the
+ * measured E and lookup decide.  The model starts from built-in coefficients;
+ * ss_tuner_calibrate measures them on the current device.  A model is saved
+ * as JSON with the device architecture and HIP runtime version it was
+ * measured with, and a file from another architecture or runtime is refused.
+ * If the environment variable SS_TUNER_CACHE names a file, the first plan
+ * (or tuner call) loads it; when it is missing or refused, the model is
+ * calibrated on the current device once and written there (messages on
+ * stderr).  Plans built earlier keep their choices.
  * ------------------------------------------------------------------------- */
 
 /* Runs the calibration microbenchmarks on the current device and stream
- * (about 1.5 GiB of temporary device memory, well under a second).
- * SYNCHRONOUS. */
+ * (about 1.5 GiB of temporary device memory and a 300-step model training,
+ * about a second).  SYNCHRONOUS. */
 SS_API int ss_tuner_calibrate(void);
 
-/* coeffs (host) receives 8 doubles: {stream GB/s, hash fixed ns, hash ns per
- * scanned entry, bisection fixed ns, bisection ns per step, ns per KB
- * restaged, calibrated flag, most bins per table entry}.  count must be
- * >= 8.  ss_tuner_set replaces the model with such 8 values (all finite and
- * non-negative; bandwidth and bins per entry positive). */
+/* coeffs (host) receives, with count >= 8: {stream GB/s, hash fixed ns, hash
+ * ns per scanned entry, bisection fixed ns, bisection ns per step, learned
+ * index fixed ns, calibrated flag, most bins per table entry}; with count >=
+ * 10 also {tiles per workgroup for segments averaging under 64 tiles of 4096
+ * targets, for longer segments}; with count >= 11 also {learned index ns per
+ * LDS step}.  ss_tuner_set replaces the model with 8, 10 or 11 such values
+ * (all finite and non-negative; bandwidth and bins per entry positive; tiles
+ * in 1..4096). */
 SS_API int ss_tuner_get(double *coeffs, int count);
 SS_API int ss_tuner_set(const double *coeffs, int count);
 
-/* Saves / loads the model as JSON at a host file path. */
+/* Saves / loads the model as JSON at a host file path.  Loading refuses
+ * (SS_ERR_INVALID_ARG, model unchanged) a malformed file, or one measured on
+ * another architecture than the current device (or, without a device, than
+ * gfx950) or under another HIP runtime version. */
 SS_API int ss_tuner_save(const char *path);
 SS_API int ss_tuner_load(const char *path);
 

@@ -34,7 +34,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# SS_ORACLE_LIB selects another build of oracle.c (the sanitizer build).
+_LIB_PATH = os.environ.get("SS_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
@@ -47,6 +48,20 @@ def build(force: bool = True) -> str:
              "-pthread", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized(outdir: str) -> str:
+    """``oracle.c`` with AddressSanitizer and UndefinedBehaviorSanitizer
+    (clang, so that one sanitizer runtime serves every instrumented
+    library); load it by setting SS_ORACLE_LIB to the returned path."""
+    os.makedirs(outdir, exist_ok=True)
+    out = os.path.join(outdir, "liboracle.so")
+    subprocess.check_call(
+        ["/opt/rocm/llvm/bin/clang", "-O1", "-fsanitize=address,undefined",
+         "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g", "-std=c11",
+         "-D_GNU_SOURCE", "-fno-fast-math", "-shared", "-fPIC", "-pthread", "-o", out, _SRC,
+         "-lm"])
+    return out
 
 
 def _load():

@@ -3,6 +3,8 @@
 * ``_lib/libsearchsorted.so``: the HIP library behind ``include/searchsorted.h``
   (hipcc, gfx950 only).
 * ``_lib/libssinputs.so``: the host-only seeded input generators (gcc).
+* ``build_sanitized(dir)``: both again with the host code instrumented by
+  AddressSanitizer and UndefinedBehaviorSanitizer (clang), for the CPU suite.
 
 Every call recompiles.  Flags: -O3; no fast-math (the search is exact IEEE
 comparison work); packed FP32 instructions disabled for device code.
@@ -84,6 +86,51 @@ def build_hip(verbose: bool = False, jobs: int = 4) -> str:
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, out)
     return out
+
+
+CLANG = "/opt/rocm/llvm/bin/clang"
+# host-side AddressSanitizer + UndefinedBehaviorSanitizer (device code is not
+# instrumented; on a hipcc line each flag goes to the host pass only)
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+            "-fno-omit-frame-pointer", "-g"]
+
+
+def asan_runtime() -> str:
+    """The sanitizer runtime the instrumented libraries need preloaded."""
+    return subprocess.check_output([CLANG, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                                   text=True).strip()
+
+
+def build_sanitized(outdir: str, verbose: bool = False) -> dict:
+    """Builds the library (host code instrumented) and the input generators
+    with AddressSanitizer and UndefinedBehaviorSanitizer into outdir; returns
+    the environment that makes the package load them (SS_LIBRARY,
+    SS_INPUTS_LIB) plus the preload of the sanitizer runtime."""
+    os.makedirs(outdir, exist_ok=True)
+    inputs = os.path.join(outdir, "libssinputs.so")
+    _run([CLANG, "-O1", *SANITIZE, "-std=c11", "-D_GNU_SOURCE", "-shared", "-fPIC", "-pthread",
+          "-o", inputs, os.path.join(CSRC, "inputs.c"), "-lm"], verbose)
+    host_san = []
+    for f in SANITIZE:
+        host_san += ["-Xarch_host", f]
+    hipcc = _hipcc()
+    objs, procs = [], []
+    for src in HIP_SOURCES:
+        obj = os.path.join(outdir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc, *hip_flags(), *host_san, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), src))
+        objs.append(obj)
+    for p, s in procs:
+        if p.wait() != 0:
+            raise RuntimeError(f"hipcc failed on {s}")
+    lib = os.path.join(outdir, "libsearchsorted.so")
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host",
+          "-fsanitize=address,undefined", "-o", lib, *objs], verbose)
+    return {"SS_LIBRARY": lib, "SS_INPUTS_LIB": inputs, "LD_PRELOAD": asan_runtime(),
+            "ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
+            "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1"}
 
 
 def build_all(verbose: bool = False) -> None:

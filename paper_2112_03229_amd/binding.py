@@ -13,7 +13,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libsearchsorted.so")
+# SS_LIBRARY selects another build of the library (the sanitizer build).
+LIB_PATH = os.environ.get("SS_LIBRARY") or os.path.join(_HERE, "_lib", "libsearchsorted.so")
 
 SS_OK = 0
 STATUS_NAMES = {
@@ -226,7 +227,7 @@ def loghash_bins(table: torch.Tensor, nb: int):
 # plans: many tables (batched) and paired lookups
 # ---------------------------------------------------------------------------
 
-PLAN_ALGOS, PLAN_BITS, PLAN_SUMMARY = 1, 2, 3
+PLAN_ALGOS, PLAN_BITS, PLAN_SUMMARY, PLAN_COSTS = 1, 2, 3, 4
 SUMMARY_KEYS = ("tables", "tiles", "tiles_per_wg", "grid", "block", "lds_bytes",
                 "max_bin", "graph_uses")
 
@@ -272,9 +273,13 @@ class _Plan:
         check(lib().ss_plan_info(self._handle, PLAN_ALGOS, _off_ptr(algos), T))
         check(lib().ss_plan_info(self._handle, PLAN_BITS, _off_ptr(bits), T))
         check(lib().ss_plan_info(self._handle, PLAN_SUMMARY, _off_ptr(summ), 8))
+        costs = np.zeros(2 * T, dtype=np.float64)
+        check(lib().ss_plan_info(self._handle, PLAN_COSTS, _off_ptr(costs), 2 * T))
         out = dict(zip(SUMMARY_KEYS, (int(v) for v in summ)))
         out["algos"] = algos
         out["bits"] = bits
+        out["plain_ns"] = costs[0::2].copy()
+        out["learned_ns"] = costs[1::2].copy()
         return out
 
 
@@ -393,7 +398,8 @@ class PairPlan(_Plan):
 # ---------------------------------------------------------------------------
 
 TUNER_KEYS = ("stream_gbs", "hash_base_ns", "hash_per_k_ns", "bin_base_ns", "bin_per_step_ns",
-              "stage_ns_per_kb", "calibrated", "bins_per_entry")
+              "learned_base_ns", "calibrated", "bins_per_entry", "tiles_short", "tiles_long",
+              "learned_per_step_ns")
 
 
 class InterpPlan(PairPlan):
@@ -450,8 +456,8 @@ def tuner_calibrate() -> dict:
 
 
 def tuner_get() -> dict:
-    buf = (ctypes.c_double * 8)()
-    check(lib().ss_tuner_get(buf, 8))
+    buf = (ctypes.c_double * len(TUNER_KEYS))()
+    check(lib().ss_tuner_get(buf, len(TUNER_KEYS)))
     return dict(zip(TUNER_KEYS, list(buf)))
 
 
@@ -462,8 +468,8 @@ def tuner_set(**changes) -> dict:
     if unknown:
         raise KeyError(sorted(unknown))
     cur.update(changes)
-    buf = (ctypes.c_double * 8)(*[float(cur[k]) for k in TUNER_KEYS])
-    check(lib().ss_tuner_set(buf, 8))
+    buf = (ctypes.c_double * len(TUNER_KEYS))(*[float(cur[k]) for k in TUNER_KEYS])
+    check(lib().ss_tuner_set(buf, len(TUNER_KEYS)))
     return tuner_get()
 
 

@@ -188,6 +188,21 @@ __device__ __forceinline__ void load_range(const double* __restrict__ x, TileRan
   load_tile<Q>(x, r.q1, r.q0 + threadIdx.x, nt, r.q0 + (int64_t)nt * Q <= r.q1, v);
 }
 
+template <int Q>
+__device__ __forceinline__ void store_tile_f64(double* __restrict__ out, int64_t m, int64_t base,
+                                               int nt, bool full, const double (&v)[Q]) {
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q], out + base + (int64_t)q * nt);
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t k = base + (int64_t)q * nt;
+      if (k < m) out[k] = v[q];
+    }
+  }
+}
+
 // Searches one tile of targets against a staged table, in the strict
 // convention or (CONV = 1) the paper's.
 template <int Q, int LEARN, int CONV>
@@ -251,21 +266,6 @@ __device__ __forceinline__ Grid stage_grid(const MultiArgs& a, int seg, int nr, 
   if (count > a.grid_cap) return {g, nullptr};
   for (int i = threadIdx.x; i < count; i += blockDim.x) lds_grid[i] = g[i];
   return {g, lds_grid};
-}
-
-template <int Q>
-__device__ __forceinline__ void store_tile_f64(double* __restrict__ out, int64_t m, int64_t base,
-                                               int nt, bool full, const double (&v)[Q]) {
-  if (full) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(v[q], out + base + (int64_t)q * nt);
-  } else {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int64_t k = base + (int64_t)q * nt;
-      if (k < m) out[k] = v[q];
-    }
-  }
 }
 
 template <int MODE, int Q, int LEARN, int CONV>
@@ -562,11 +562,17 @@ int fail_delete(ss_plan* p, const char* msg, int code = SS_ERR_INVALID_ARG) {
   return msg ? fail(code, msg) : code;
 }
 
-// Gives every eligible table a learned model (SS_OPT_PLAN_LEARNED): trains
-// them all in one launch and records each model's normalisation and bound.
+// Learned models for a plan's tables, trained on the device in one launch.
+// kLearnedAll: every eligible table gets one.  kLearnedTuner: only tables
+// whose modelled learned cost at the best possible bound (E = 1, a one-step
+// cell lookup) undercuts their tuned plain kernel are trained, and a model
+// is kept where its cost with the measured E and lookup still does.
 // host_a / host_b are host copies of the two tables arrays.
 int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
-                  const std::vector<double>& host_a, const std::vector<double>& host_b) {
+                  const std::vector<double>& host_a, const std::vector<double>& host_b,
+                  int mode) {
+  const TunerModel model = tuner_model();
+  constexpr int kBestLookup = 3;  // cell read, one boundary, piece read
   std::vector<LearnedSlot> slots;
   std::vector<int> slot_desc;
   for (int t = 0; t < p->T; ++t) {
@@ -574,6 +580,9 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
     const int which = (p->paired && t >= p->M) ? 1 : 0;
     const double* h = (which ? host_b.data() : host_a.data()) + d.tab_off;
     if (!learned_eligible(h, d.n)) continue;
+    if (mode == kLearnedTuner &&
+        !(learned_cost_ns(model, 1, kBestLookup) < p->tuned[t].est_ns))
+      continue;
     LearnedSlot sl{};
     sl.tab_off = d.tab_off;
     sl.i_off = (int64_t)slots.size() * kImageFloats;
@@ -590,20 +599,35 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
   if (steps <= 0) steps = kDefaultPlanLearnedSteps;
   int rc = learned_train_slots(tables_a, tables_b, slots, p->d_pool, steps, 0.01f, 1);
   if (rc != SS_OK) return rc;
-  // every image's (boundaries, pieces) header: LDS is reserved for the largest
+  // every image's (boundaries, pieces, cells, fullest cell) header: LDS is
+  // reserved for the largest kept image
   std::vector<int> head(4 * slots.size());
   SS_TRY_HIP(hipMemcpy2D(head.data(), 4 * sizeof(int), p->d_pool, kImageBytes, 4 * sizeof(int),
                          slots.size(), hipMemcpyDeviceToHost));
   p->image_bytes = 0;
+  int kept = 0;
   for (size_t i = 0; i < slots.size(); ++i) {
     const int* hd = head.data() + 4 * i;
     if (!image_header_valid(hd))
       return fail(SS_ERR_UNSUPPORTED, "compiled model " + std::to_string(i) + " is malformed");
+    const int t = slot_desc[i];
+    int lookup = 2 + hd[3];  // cell read, scan of the fullest cell, piece read
+    if (hd[2] == 0) {        // no cell table: bisection over the boundary slots
+      lookup = 2;
+      for (int v = 1; v < hd[0]; v <<= 1) ++lookup;
+    }
+    p->tuned[t].learned_ns = learned_cost_ns(model, slots[i].E, lookup);
+    if (mode == kLearnedTuner && !(p->tuned[t].learned_ns < p->tuned[t].est_ns)) {
+      slot_desc[i] = -1;  // trained, but its plain kernel is cheaper
+      continue;
+    }
+    ++kept;
     p->image_bytes =
         std::max(p->image_bytes, (size_t)image_used_floats(hd[0], hd[1], hd[2]) * 4);
   }
   for (size_t i = 0; i < slots.size(); ++i) {
     const int t = slot_desc[i];
+    if (t < 0) continue;
     TableDesc& d = p->desc[t];
     d.algo = SS_ALGO_LEARNED;
     d.bins_off = 0;
@@ -615,7 +639,7 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
     p->tuned[t].algo = SS_ALGO_LEARNED;
     p->tuned[t].bits = -1;
   }
-  p->learned_tables = (int)slots.size();
+  p->learned_tables = kept;
   return SS_OK;
 }
 
@@ -941,9 +965,9 @@ static int create_batched(const double* tables, const int64_t* table_off, int32_
     if (p->tuned[t].algo == SS_ALGO_EXPHASH)
       max_bins = std::max(max_bins, align16((size_t)(p->tuned[t].nb + 1) * 2));
   }
-  if (models || learned_mode() == kLearnedAll) {
+  if (models || learned_mode() != kLearnedNone) {
     rc = models ? attach_learned(p, tables, table_off, models)
-                : apply_learned(p, tables, nullptr, host, host);
+                : apply_learned(p, tables, nullptr, host, host, learned_mode());
     if (rc != SS_OK) return fail_delete(p, nullptr, rc);
     max_bins = 0;
     for (int t = 0; t < T; ++t)
@@ -1105,8 +1129,8 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
     if (p->tuned[M + j].algo == SS_ALGO_EXPHASH)
       bins_b = std::max(bins_b, align16((size_t)(p->tuned[M + j].nb + 1) * 2));
   }
-  if (learned_mode() == kLearnedAll && p->mode != kPairInterp) {
-    if ((rc = apply_learned(p, rho_tables, t_tables, hr, ht)) != SS_OK)
+  if (learned_mode() != kLearnedNone && p->mode != kPairInterp) {
+    if ((rc = apply_learned(p, rho_tables, t_tables, hr, ht, learned_mode())) != SS_OK)
       return fail_delete(p, nullptr, rc);
     bins_a = bins_b = 0;
     for (int j = 0; j < M; ++j) {
@@ -1249,6 +1273,15 @@ int ss_plan_info(const ss_plan* p, int what, void* out, int64_t cap) {
       for (int t = 0; t < p->T; ++t)
         o[t] = what == SS_PLAN_ALGOS ? p->tuned[t].algo
                                      : (p->tuned[t].algo == SS_ALGO_EXPHASH ? p->tuned[t].bits : -1);
+      return SS_OK;
+    }
+    case SS_PLAN_COSTS: {
+      if (cap < 2 * (int64_t)p->T) return fail(SS_ERR_INVALID_ARG, "cap smaller than 2 T");
+      double* o = static_cast<double*>(out);
+      for (int t = 0; t < p->T; ++t) {
+        o[2 * t] = p->tuned[t].est_ns;
+        o[2 * t + 1] = p->tuned[t].learned_ns;
+      }
       return SS_OK;
     }
     case SS_PLAN_SUMMARY: {

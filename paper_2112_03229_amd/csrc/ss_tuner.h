@@ -17,23 +17,38 @@ struct TunerModel {
   double hash_per_k_ns = 0.15e-3;    // per entry of the fixed in-bin scan
   double bin_base_ns = 0.5e-3;       // bisection: final compare and select
   double bin_per_step_ns = 0.10e-3;  // per bisection step
-  double stage_ns_per_kb = 50.0;     // one workgroup restaging 1 KB of LDS
+  double learned_base_ns = 1.6e-3;   // learned index: input, prediction and
+                                     // the window's verification
+  double learned_per_step_ns = 0.10e-3;  // per LDS step of its model lookup and
+                                         // window bisection
   double bins_per_entry = 4.0;       // most exponent-hash bins per table entry
                                      // (each workgroup copies its bins)
+  double tiles_short = 6;            // target tiles (of 4096) per plan workgroup
+  double tiles_long = 4;             // for segments averaging under / over 64 tiles
   int calibrated = 0;                // 1 once measured on this device
 };
 
+// Modelled compute cost (ns per query) of the learned index with error bound
+// E and a model whose piece lookup takes `lookup_steps` LDS steps.
+double learned_cost_ns(const TunerModel& model, int E, int lookup_steps);
+
+// Window steps of the learned search for error bound E (the bisection over
+// 2E + 1 candidate positions plus the two checks of its ends).
+int learned_window_steps(int E);
+
 struct TunedTable {
   int n = 0;
-  int algo = 1;        // SS_ALGO_BINARY or SS_ALGO_EXPHASH
+  int algo = 1;        // SS_ALGO_BINARY or SS_ALGO_EXPHASH (or SS_ALGO_LEARNED)
   int bits = -1;       // s for the exponent hash
   int kmin = 0, kmaxc = 0, nb = 0;
   int K = 0;           // longest bin (exact)
-  double est_ns = 0;   // modelled ns per query (compute part)
+  double est_ns = 0;   // modelled ns per query of the plain choice (compute part)
+  double learned_ns = -1;  // modelled ns per query of its trained learned model
+                           // (-1: none trained)
 };
 
 // The process-wide model (defaults until calibrated or loaded).
-const TunerModel& tuner_model();
+TunerModel tuner_model();
 
 // Chooses the kernel and bin bits for one table of n entries; the bin table
 // may take at most `bins_budget` bytes of LDS.  force = SS_ALGO_AUTO picks

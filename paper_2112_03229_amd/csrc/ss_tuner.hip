@@ -11,7 +11,9 @@
 // ss_tuner_calibrate on the current device: a long HBM stream for the
 // bandwidth, then bisection over tables of 64..4096 entries and the
 // exponent hash at several K on cache-resident targets, fitted by least
-// squares.
+// squares, and a learned index's fixed cost.  The model is cached as JSON
+// with the device architecture and the HIP runtime version it was measured
+// with; a cache from another architecture or runtime is refused.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -31,8 +33,29 @@ int launch_single(const double* table, int64_t n, const double* x, int64_t m, in
 namespace {
 std::mutex g_tuner_mu;
 TunerModel g_model;
-bool g_model_init = false;
-std::string g_model_arch;
+std::once_flag g_env_once;
+std::string g_model_arch;     // device architecture the model was measured on
+
+// The architecture's base name ("gfx950" of "gfx950:sramecc+:xnack-").
+std::string arch_base(const std::string& a) { return a.substr(0, a.find(':')); }
+
+int runtime_version() {
+  int v = 0;
+  if (hipRuntimeGetVersion(&v) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return v;
+}
+
+// Where a model is measured: the current device's architecture, or the
+// library's own target when no device is present.
+std::string current_arch() {
+  DeviceInfo di;
+  if (device_info(&di) == SS_OK) return arch_base(di.arch);
+  clear_error();
+  return "gfx950";
+}
 
 int hi_word_host(double v) {
   uint64_t u;
@@ -75,51 +98,123 @@ int load_file(const char* path, TunerModel* m, std::string* arch) {
   while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
   std::fclose(f);
   TunerModel t;
-  double cal = 0;
+  double cal = 0, runtime = 0;
   if (!parse_key(text, "stream_gbs", &t.stream_gbs) ||
       !parse_key(text, "hash_base_ns", &t.hash_base_ns) ||
       !parse_key(text, "hash_per_k_ns", &t.hash_per_k_ns) ||
       !parse_key(text, "bin_base_ns", &t.bin_base_ns) ||
       !parse_key(text, "bin_per_step_ns", &t.bin_per_step_ns) ||
-      !parse_key(text, "stage_ns_per_kb", &t.stage_ns_per_kb) ||
+      !parse_key(text, "learned_base_ns", &t.learned_base_ns) ||
+      !parse_key(text, "learned_per_step_ns", &t.learned_per_step_ns) ||
       !parse_key(text, "bins_per_entry", &t.bins_per_entry) ||
-      !parse_key(text, "calibrated", &cal))
+      !parse_key(text, "tiles_short", &t.tiles_short) ||
+      !parse_key(text, "tiles_long", &t.tiles_long) ||
+      !parse_key(text, "hip_runtime", &runtime) || !parse_key(text, "calibrated", &cal))
     return fail(SS_ERR_INVALID_ARG, std::string("malformed tuner cache ") + path);
   if (!(t.stream_gbs > 0) || !(t.hash_base_ns >= 0) || !(t.bin_per_step_ns >= 0) ||
-      !(t.bins_per_entry > 0))
+      !(t.learned_base_ns >= 0) || !(t.learned_per_step_ns >= 0) || !(t.bins_per_entry > 0) || !(t.tiles_short >= 1) ||
+      !(t.tiles_long >= 1) || t.tiles_short > 4096 || t.tiles_long > 4096)
     return fail(SS_ERR_INVALID_ARG, std::string("implausible tuner cache ") + path);
   t.calibrated = cal != 0;
-  const size_t a = text.find("\"arch\"");
-  if (a != std::string::npos) {
-    const size_t q0 = text.find('"', text.find(':', a) + 1);
+  std::string a;
+  const size_t k = text.find("\"arch\"");
+  if (k != std::string::npos) {
+    const size_t q0 = text.find('"', text.find(':', k) + 1);
     const size_t q1 = q0 == std::string::npos ? q0 : text.find('"', q0 + 1);
-    if (q1 != std::string::npos) *arch = text.substr(q0 + 1, q1 - q0 - 1);
+    if (q1 != std::string::npos) a = text.substr(q0 + 1, q1 - q0 - 1);
   }
+  // the coefficients are measurements of this library's kernels on one
+  // architecture under one runtime: refuse them anywhere else
+  if (a.empty()) return fail(SS_ERR_INVALID_ARG, std::string("tuner cache ") + path + " names no arch");
+  const std::string here = current_arch();
+  if (arch_base(a) != here)
+    return fail(SS_ERR_INVALID_ARG, std::string("tuner cache ") + path + " was measured on " + a +
+                                        ", this device is " + here);
+  if ((int)runtime != runtime_version())
+    return fail(SS_ERR_INVALID_ARG, std::string("tuner cache ") + path +
+                                        " was measured with HIP runtime " +
+                                        std::to_string((long long)runtime) + ", this process uses " +
+                                        std::to_string(runtime_version()));
   *m = t;
+  *arch = a;
   return SS_OK;
 }
 
-void init_model_locked() {
-  if (g_model_init) return;
-  g_model_init = true;
-  const char* path = std::getenv("SS_TUNER_CACHE");
-  if (path && *path) {
-    TunerModel m;
-    std::string arch;
-    if (load_file(path, &m, &arch) == SS_OK) {
-      g_model = m;
-      g_model_arch = arch;
-    }
-    clear_error();
+TunerModel model_copy() {
+  std::lock_guard<std::mutex> lk(g_tuner_mu);
+  return g_model;
+}
+
+int save_model(const char* path) {
+  TunerModel m;
+  std::string arch;
+  {
+    std::lock_guard<std::mutex> lk(g_tuner_mu);
+    m = g_model;
+    arch = g_model_arch.empty() ? current_arch() : g_model_arch;
   }
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  std::fprintf(f,
+               "{\n  \"arch\": \"%s\",\n  \"hip_runtime\": %d,\n  \"stream_gbs\": %.17g,\n"
+               "  \"hash_base_ns\": %.17g,\n  \"hash_per_k_ns\": %.17g,\n"
+               "  \"bin_base_ns\": %.17g,\n  \"bin_per_step_ns\": %.17g,\n"
+               "  \"learned_base_ns\": %.17g,\n  \"learned_per_step_ns\": %.17g,\n"
+               "  \"bins_per_entry\": %.17g,\n"
+               "  \"tiles_short\": %.17g,\n  \"tiles_long\": %.17g,\n  \"calibrated\": %d\n}\n",
+               arch.c_str(), runtime_version(), m.stream_gbs, m.hash_base_ns, m.hash_per_k_ns,
+               m.bin_base_ns, m.bin_per_step_ns, m.learned_base_ns, m.learned_per_step_ns,
+               m.bins_per_entry,
+               m.tiles_short, m.tiles_long, m.calibrated);
+  const bool ok = std::fclose(f) == 0;
+  return ok ? SS_OK : fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+}
+
+int calibrate();
+
+// SS_TUNER_CACHE names a model file: it is loaded on first use; when it is
+// missing or refused (another architecture or runtime, malformed), the model
+// is calibrated on the current device and written there.  Problems are
+// reported on stderr (the caller's error state is left clean).
+void env_init() {
+  const char* path = std::getenv("SS_TUNER_CACHE");
+  if (!path || !*path) return;
+  TunerModel m;
+  std::string arch;
+  if (load_file(path, &m, &arch) == SS_OK) {
+    std::lock_guard<std::mutex> lk(g_tuner_mu);
+    g_model = m;
+    g_model_arch = arch;
+    clear_error();
+    return;
+  }
+  if (FILE* f = std::fopen(path, "rb")) {
+    std::fclose(f);
+    std::fprintf(stderr, "libsearchsorted: SS_TUNER_CACHE refused (%s); calibrating\n",
+                 ss_last_error());
+  }
+  if (calibrate() != SS_OK || save_model(path) != SS_OK)
+    std::fprintf(stderr, "libsearchsorted: tuner calibration for SS_TUNER_CACHE failed: %s\n",
+                 ss_last_error());
+  clear_error();
 }
 
 }  // namespace
 
-const TunerModel& tuner_model() {
-  std::lock_guard<std::mutex> lk(g_tuner_mu);
-  init_model_locked();
-  return g_model;
+TunerModel tuner_model() {
+  std::call_once(g_env_once, env_init);
+  return model_copy();
+}
+
+double learned_cost_ns(const TunerModel& model, int E, int lookup_steps) {
+  return model.learned_base_ns +
+         model.learned_per_step_ns * (learned_window_steps(E) + lookup_steps);
+}
+
+int learned_window_steps(int E) {
+  int steps = 1;
+  for (int step = 1; step * 2 <= 2 * E + 1; step *= 2) ++steps;
+  return steps + 2;  // the two window-end checks
 }
 
 int host_longest_bin(const double* a, int n, int s) {
@@ -179,7 +274,6 @@ TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bi
 
 int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident,
                                int segments, int64_t per_tile) {
-  (void)model;
   // Every workgroup stages its table before searching, so the targets per
   // workgroup trade staging stalls against load balance.  Measured on MI355X
   // (steady clocks, tiles aligned to absolute positions, two tiles
@@ -192,11 +286,13 @@ int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int
   // proportionally more, the same targets per workgroup.  Scaling held when
   // measured with 512-target tiles (an earlier learned-plan launch shape):
   // the 512-table batch with every table learned ran at 88.8 / 97.9 /
-  // 104.3 / 107.1 / 108.0 Gq/s with 4 / 8 / 16 / 32 / 64 tiles of 512.  The
+  // 104.3 / 107.1 / 108.0 Gq/s with 4 / 8 / 16 / 32 / 64 tiles of 512.
+  // Those sweeps set the model's defaults (tiles_short, tiles_long).  The
   // count is then reduced while it leaves fewer than ~6 waves of workgroups.
   const int64_t scale = std::max<int64_t>(1, 4096 / std::max<int64_t>(per_tile, 1));
   const int64_t avg = total_tiles / std::max(segments, 1) / scale;
-  int64_t k = (avg < 64 ? 6 : 4) * scale;
+  int64_t k = (int64_t)std::lround(avg < 64 ? model.tiles_short : model.tiles_long) * scale;
+  k = std::max<int64_t>(1, std::min<int64_t>(k, 4096));
   while (k > 1 && total_tiles / k < 6LL * std::max(resident, 1)) --k;
   return (int)k;
 }
@@ -267,12 +363,11 @@ void fit_line(const std::vector<double>& x, const std::vector<double>& y, double
 
 }  // namespace ss
 
-using namespace ss;
+namespace ss {
+namespace {
 
-extern "C" {
-
-int ss_tuner_calibrate(void) {
-  clear_error();
+// Runs the calibration microbenchmarks and installs the measured model.
+int calibrate() {
   DeviceInfo di;
   int rc = device_info(&di);
   if (rc != SS_OK) return rc;
@@ -297,7 +392,7 @@ int ss_tuner_calibrate(void) {
     return SS_OK;
   };
 
-  TunerModel m = tuner_model();
+  TunerModel m = model_copy();
   // 1. streaming bandwidth: a one-entry table makes the search trivial
   double ns = 0;
   if ((rc = put_table(1)) != SS_OK) return rc;
@@ -325,12 +420,59 @@ int ss_tuner_calibrate(void) {
     ky.push_back(ns);
   }
   if (kx.size() >= 2) fit_line(kx, ky, &m.hash_base_ns, &m.hash_per_k_ns);
+  // 4. learned index: a model trained on the same 1024-entry table, searched
+  // on the cache-resident targets; its fixed cost is what remains after
+  // its lookup and window steps at the bisection's per-step cost
+  {
+    ss_mlp_opts o{300, 0.01f, 1};
+    ss_learned* lh = nullptr;
+    if ((rc = ss_learned_build(tab, 1024, &o, &lh)) != SS_OK) return rc;
+    double info[10];
+    rc = ss_learned_info(lh, info, 10);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == SS_OK && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+      rc = ss_learned_search(lh, x, small, out);  // warm-up
+      if (rc == SS_OK) (void)hipEventRecord(e0, st);
+      for (int r = 0; r < 10 && rc == SS_OK; ++r) rc = ss_learned_search(lh, x, small, out);
+      if (rc == SS_OK) {
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ns = (double)ms * 1e6 / 10 / (double)small;
+        const int cells = (int)info[8], scan = (int)info[9], slots = (int)info[7];
+        const int lookup = cells > 0 ? 2 + scan : ceil_log2(slots) + 2;
+        // its steps are LDS steps like the bisection's: same per-step cost
+        m.learned_per_step_ns = m.bin_per_step_ns;
+        m.learned_base_ns = std::max(
+            0.0, ns - m.learned_per_step_ns * (learned_window_steps((int)info[0]) + lookup));
+      }
+    } else if (rc == SS_OK) {
+      rc = fail(SS_ERR_HIP, "hipEventCreate");
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)ss_learned_destroy(lh);
+    if (rc != SS_OK) return rc;
+  }
   m.calibrated = 1;
   std::lock_guard<std::mutex> lk(g_tuner_mu);
   g_model = m;
-  g_model_init = true;
-  g_model_arch = di.arch;
+  g_model_arch = arch_base(di.arch);
   return SS_OK;
+}
+
+}  // namespace
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" {
+
+int ss_tuner_calibrate(void) {
+  clear_error();
+  std::call_once(g_env_once, env_init);  // a later first use must not replace this model
+  return calibrate();
 }
 
 int ss_tuner_get(double* coeffs, int count) {
@@ -342,69 +484,65 @@ int ss_tuner_get(double* coeffs, int count) {
   coeffs[2] = m.hash_per_k_ns;
   coeffs[3] = m.bin_base_ns;
   coeffs[4] = m.bin_per_step_ns;
-  coeffs[5] = m.stage_ns_per_kb;
+  coeffs[5] = m.learned_base_ns;
   coeffs[6] = m.calibrated;
   coeffs[7] = m.bins_per_entry;
+  if (count >= 10) {
+    coeffs[8] = m.tiles_short;
+    coeffs[9] = m.tiles_long;
+  }
+  if (count >= 11) coeffs[10] = m.learned_per_step_ns;
   return SS_OK;
 }
 
 int ss_tuner_set(const double* coeffs, int count) {
   clear_error();
   if (!coeffs || count < 8) return fail(SS_ERR_INVALID_ARG, "need 8 coefficients");
-  TunerModel m;
+  std::call_once(g_env_once, env_init);
+  TunerModel m = model_copy();
   m.stream_gbs = coeffs[0];
   m.hash_base_ns = coeffs[1];
   m.hash_per_k_ns = coeffs[2];
   m.bin_base_ns = coeffs[3];
   m.bin_per_step_ns = coeffs[4];
-  m.stage_ns_per_kb = coeffs[5];
+  m.learned_base_ns = coeffs[5];
   m.calibrated = coeffs[6] != 0;
   m.bins_per_entry = coeffs[7];
-  for (int i = 0; i < 8; ++i)
+  const int used = count >= 11 ? 11 : count >= 10 ? 10 : 8;
+  if (count >= 10) {
+    m.tiles_short = coeffs[8];
+    m.tiles_long = coeffs[9];
+  }
+  if (count >= 11) m.learned_per_step_ns = coeffs[10];
+  for (int i = 0; i < used; ++i)
     if (!(coeffs[i] >= 0) || !std::isfinite(coeffs[i]))
       return fail(SS_ERR_INVALID_ARG, "coefficients must be finite and non-negative");
   if (!(m.stream_gbs > 0) || !(m.bins_per_entry > 0))
     return fail(SS_ERR_INVALID_ARG, "stream bandwidth and bins per entry must be positive");
+  if (!(m.tiles_short >= 1 && m.tiles_short <= 4096 && m.tiles_long >= 1 && m.tiles_long <= 4096))
+    return fail(SS_ERR_INVALID_ARG, "tiles per workgroup must be in 1..4096");
   std::lock_guard<std::mutex> lk(g_tuner_mu);
   g_model = m;
-  g_model_init = true;
   return SS_OK;
 }
 
 int ss_tuner_save(const char* path) {
   clear_error();
   if (!path) return fail(SS_ERR_INVALID_ARG, "path is null");
-  TunerModel m;
-  std::string arch;
-  {
-    std::lock_guard<std::mutex> lk(g_tuner_mu);
-    init_model_locked();
-    m = g_model;
-    arch = g_model_arch;
-  }
-  FILE* f = std::fopen(path, "wb");
-  if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
-  std::fprintf(f,
-               "{\n  \"arch\": \"%s\",\n  \"stream_gbs\": %.17g,\n  \"hash_base_ns\": %.17g,\n"
-               "  \"hash_per_k_ns\": %.17g,\n  \"bin_base_ns\": %.17g,\n"
-               "  \"bin_per_step_ns\": %.17g,\n  \"stage_ns_per_kb\": %.17g,\n"
-               "  \"bins_per_entry\": %.17g,\n  \"calibrated\": %d\n}\n",
-               arch.c_str(), m.stream_gbs, m.hash_base_ns, m.hash_per_k_ns, m.bin_base_ns,
-               m.bin_per_step_ns, m.stage_ns_per_kb, m.bins_per_entry, m.calibrated);
-  const bool ok = std::fclose(f) == 0;
-  return ok ? SS_OK : fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  std::call_once(g_env_once, env_init);
+  return save_model(path);
 }
 
 int ss_tuner_load(const char* path) {
   clear_error();
   if (!path) return fail(SS_ERR_INVALID_ARG, "path is null");
+  std::call_once(g_env_once, env_init);
   TunerModel m;
   std::string arch;
   int rc = load_file(path, &m, &arch);
   if (rc != SS_OK) return rc;
   std::lock_guard<std::mutex> lk(g_tuner_mu);
   g_model = m;
-  g_model_init = true;
   g_model_arch = arch;
   return SS_OK;
 }

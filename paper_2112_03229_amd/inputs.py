@@ -36,7 +36,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "_lib", "libssinputs.so")
+# SS_INPUTS_LIB selects another build of the generators (the sanitizer build).
+_LIB_PATH = os.environ.get("SS_INPUTS_LIB") or os.path.join(_HERE, "_lib", "libssinputs.so")
 _lib = None
 
 # stream ids (one independent counter stream per use)

@@ -128,6 +128,35 @@ def test_tuner_model_save_load_roundtrip(L, tmp_path):
     assert b.tuner_get() == before
 
 
+def test_tuner_cache_from_elsewhere_is_refused(L, tmp_path):
+    """A cache measured on another architecture or under another HIP runtime
+    is refused (the model is left as it was); the saved file names both."""
+    import json
+    from paper_2112_03229_amd import binding as b
+    before = b.tuner_get()
+    path = tmp_path / "model.json"
+    b.tuner_save(str(path))
+    rec = json.loads(path.read_text())
+    assert rec["arch"].split(":")[0] == "gfx950" and rec["hip_runtime"] > 0
+    for field, value, words in (("arch", "gfx942", b"gfx942"),
+                                ("arch", "gfx90a:sramecc+:xnack-", b"gfx90a"),
+                                ("arch", "", b"no arch"),
+                                ("hip_runtime", rec["hip_runtime"] + 1, b"runtime")):
+        doctored = dict(rec, **{field: value, "stream_gbs": 1234.5})
+        other = tmp_path / "other.json"
+        other.write_text(json.dumps(doctored))
+        with pytest.raises(b.SearchSortedError) as e:
+            b.tuner_load(str(other))
+        assert e.value.code == -1 and words in L.ss_last_error()
+        assert b.tuner_get() == before
+    # the same record with its own arch and runtime loads
+    other.write_text(json.dumps(dict(rec, stream_gbs=1234.5)))
+    b.tuner_load(str(other))
+    assert b.tuner_get()["stream_gbs"] == 1234.5
+    b.tuner_load(str(path))
+    assert b.tuner_get() == before
+
+
 def test_plan_argument_errors(L):
     import numpy as np
     P = ctypes.c_void_p
