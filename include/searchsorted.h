@@ -148,7 +148,7 @@ typedef enum {
                                     Read by single-table and learned
                                     searches at each call and by plans at
                                     creation */
-    SS_OPT_PLAN_ALGO = 14        /* kernel of every table of plans built
+    SS_OPT_PLAN_ALGO = 14,       /* kernel of every table of plans built
                                     afterwards: SS_ALGO_AUTO (default) = the
                                     tuner's choice; SS_ALGO_BINARY = the
                                     bisection; SS_ALGO_EXPHASH = the
@@ -158,6 +158,13 @@ typedef enum {
                                     SS_OPT_PLAN_LEARNED unless this is
                                     SS_ALGO_BINARY or SS_ALGO_EXPHASH, which
                                     imply none */
+    SS_OPT_PLAN_ORDER = 15       /* tile order of plans built afterwards:
+                                    each segment's tiles go to workgroups of
+                                    at most k tiles; 1 = contiguous ranges
+                                    of k tiles; 2 = strided (workgroup i of
+                                    W takes tiles i, i + W, ..., so a
+                                    segment's workgroups sweep it side by
+                                    side); 0 (default) = 2 */
 } ss_option;
 
 /* Human-readable message for the calling thread's most recent error

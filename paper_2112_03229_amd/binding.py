@@ -35,6 +35,7 @@ OPT_TARGETS_PER_LANE = 7
 OPT_PLAN_TILES, OPT_PLAN_LEARNED, OPT_LEARNED_STEPS, OPT_PLAN_XCD, OPT_PAIR_JOINT = 8, 9, 10, 11, 12
 OPT_CONVENTION = 13
 OPT_PLAN_ALGO = 14
+OPT_PLAN_ORDER = 15
 PLAN_LEARNED_TUNER, PLAN_LEARNED_ALL, PLAN_LEARNED_NONE = 0, 1, 2
 
 

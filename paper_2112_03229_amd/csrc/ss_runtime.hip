@@ -28,6 +28,7 @@ std::atomic<int64_t> g_plan_xcd{0};
 std::atomic<int64_t> g_pair_joint{0};
 std::atomic<int64_t> g_convention{0};
 std::atomic<int64_t> g_plan_algo{SS_ALGO_AUTO};
+std::atomic<int64_t> g_plan_order{0};
 
 std::mutex g_dev_mu;
 std::map<int, DeviceInfo> g_dev_cache;
@@ -67,6 +68,7 @@ int64_t option(int opt) {
     case SS_OPT_PAIR_JOINT: return g_pair_joint.load();
     case SS_OPT_CONVENTION: return g_convention.load();
     case SS_OPT_PLAN_ALGO: return g_plan_algo.load();
+    case SS_OPT_PLAN_ORDER: return g_plan_order.load();
     default: return 0;
   }
 }
@@ -231,6 +233,10 @@ int ss_set_option(int opt, int64_t v) {
                         "SS_OPT_PLAN_ALGO: SS_ALGO_AUTO, SS_ALGO_BINARY or SS_ALGO_EXPHASH");
       ss::g_plan_algo = v;
       return SS_OK;
+    case SS_OPT_PLAN_ORDER:
+      if (v < 0 || v > 2) return ss::fail(SS_ERR_INVALID_ARG, "SS_OPT_PLAN_ORDER: 0, 1 or 2");
+      ss::g_plan_order = v;
+      return SS_OK;
     default:
       return ss::fail(SS_ERR_INVALID_ARG, "unknown option");
   }
@@ -253,6 +259,7 @@ int ss_get_option(int opt, int64_t* value_out) {
     case SS_OPT_PAIR_JOINT:
     case SS_OPT_CONVENTION:
     case SS_OPT_PLAN_ALGO:
+    case SS_OPT_PLAN_ORDER:
       *value_out = ss::option(opt);
       return SS_OK;
     default:

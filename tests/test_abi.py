@@ -58,13 +58,17 @@ def test_version_and_options(L):
     for v in (b.ALGO_BINARY, b.ALGO_EXPHASH, b.ALGO_AUTO):
         b.set_option(b.OPT_PLAN_ALGO, v)
         assert b.get_option(b.OPT_PLAN_ALGO) == v
+    for v in (1, 2, 0):
+        b.set_option(b.OPT_PLAN_ORDER, v)
+        assert b.get_option(b.OPT_PLAN_ORDER) == v
     for opt, bad in ((b.OPT_FORCE_ALGO, 9), (b.OPT_FORCE_ALGO, 8), (b.OPT_FORCE_ALGO, b.ALGO_LEARNED),
                      (b.OPT_BUCKET_BITS, 21), (b.OPT_BLOCK_SIZE, 100),
                      (b.OPT_CHECK_POINTERS, 2), (b.OPT_PAIR_JOINT, 2), (b.OPT_CONVENTION, 2),
                      (b.OPT_PLAN_XCD, -1), (b.OPT_PLAN_XCD, (1 << 24) + 1),
                      (b.OPT_PLAN_LEARNED, 3), (b.OPT_PLAN_LEARNED, -1),
                      (b.OPT_PLAN_ALGO, b.ALGO_LEARNED), (b.OPT_PLAN_ALGO, b.ALGO_BALLOT),
-                     (b.OPT_PLAN_ALGO, 8), (999, 0)):
+                     (b.OPT_PLAN_ALGO, 8), (b.OPT_PLAN_ORDER, 3), (b.OPT_PLAN_ORDER, -1),
+                     (999, 0)):
         with pytest.raises(b.SearchSortedError) as e:
             b.set_option(opt, bad)
         assert e.value.code == -1

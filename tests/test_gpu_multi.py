@@ -156,6 +156,71 @@ def test_xcd_mappings_cover_every_range(binding, gpu, oracle_mod, inputs_mod, xc
         plan.close()
 
 
+@pytest.mark.parametrize("order", [1, 2], ids=["contiguous", "strided"])
+def test_tile_orders_cover_every_tile(binding, gpu, oracle_mod, inputs_mod, order):
+    """Both tile orders (SS_OPT_PLAN_ORDER) at several tiles per workgroup,
+    in every plan form (batched, learned batched, split and joint paired,
+    interpolation): every index equal to the oracle's."""
+    tables, toff, qoff, x = odd_batch(inputs_mod, seed=29)
+    want = oracle_mod.search_lt_segments(tables, toff, x, qoff)
+    pairs = ragged_pairs(inputs_mod, 31, 40, 400009)
+    rho, temp = inputs_mod.paired_targets(pairs, seed=31)
+    want_r = oracle_mod.search_lt_segments(pairs.rho.tables, pairs.rho.table_off, rho,
+                                           pairs.rho.query_off)
+    want_t = oracle_mod.search_lt_segments(pairs.temp.tables, pairs.temp.table_off, temp,
+                                           pairs.temp.query_off)
+    it = inputs_mod.interp_layout(seed=31, materials=24, total_pairs=300011)
+    ri, ti = inputs_mod.paired_targets(it.pairs, seed=31)
+    want_f, scale = oracle_mod.interp_pairs(it.pairs.rho.tables, it.pairs.rho.table_off,
+                                            it.pairs.temp.tables, it.pairs.temp.table_off,
+                                            it.pairs.rho.query_off, it.values, ri, ti)
+    xt = torch.from_numpy(x).to(gpu)
+    dr, dt = torch.from_numpy(rho).to(gpu), torch.from_numpy(temp).to(gpu)
+    for k in (1, 3, 7):
+        try:
+            binding.set_option(binding.OPT_PLAN_ORDER, order)
+            binding.set_option(binding.OPT_PLAN_TILES, k)
+            for learned in (binding.PLAN_LEARNED_NONE, binding.PLAN_LEARNED_ALL):
+                binding.set_option(binding.OPT_PLAN_LEARNED, learned)
+                say(f"case order={order} tiles={k} batched learned={learned}")
+                plan = binding.MultiPlan(torch.from_numpy(tables).to(gpu), toff, qoff)
+                out = torch.full((x.size,), -9, dtype=torch.int32, device=gpu)
+                got = plan.search(xt, out).cpu().numpy()
+                bad = np.nonzero(got != want)[0]
+                assert bad.size == 0, (order, k, learned, bad[:5], got[bad[:5]], want[bad[:5]])
+                plan.close()
+            binding.set_option(binding.OPT_PLAN_LEARNED, 0)
+            for joint in (0, 1):
+                binding.set_option(binding.OPT_PAIR_JOINT, joint)
+                say(f"case order={order} tiles={k} paired joint={joint}")
+                pp = binding.PairPlan(torch.from_numpy(pairs.rho.tables).to(gpu),
+                                      pairs.rho.table_off,
+                                      torch.from_numpy(pairs.temp.tables).to(gpu),
+                                      pairs.temp.table_off, pairs.rho.query_off)
+                o_r, o_t = pp.search(dr, dt)
+                assert np.array_equal(o_r.cpu().numpy(), want_r)
+                assert np.array_equal(o_t.cpu().numpy(), want_t)
+                pp.close()
+            binding.set_option(binding.OPT_PAIR_JOINT, 0)
+            say(f"case order={order} tiles={k} interpolation")
+            ip = binding.InterpPlan(torch.from_numpy(it.pairs.rho.tables).to(gpu),
+                                    it.pairs.rho.table_off,
+                                    torch.from_numpy(it.pairs.temp.tables).to(gpu),
+                                    it.pairs.temp.table_off, it.pairs.rho.query_off,
+                                    torch.from_numpy(it.values).to(gpu))
+            f = ip.interpolate(torch.from_numpy(ri).to(gpu), torch.from_numpy(ti).to(gpu))
+            f = f.cpu().numpy()
+            ok = ~np.isnan(want_f)
+            assert np.array_equal(np.isnan(f), ~ok)
+            assert np.all(np.abs(f[ok] - want_f[ok]) <= 16 * np.finfo(np.float64).eps * scale[ok])
+            ip.close()
+        finally:
+            binding.set_option(binding.OPT_PLAN_ORDER, 0)
+            binding.set_option(binding.OPT_PLAN_TILES, 0)
+            binding.set_option(binding.OPT_PLAN_LEARNED, 0)
+            binding.set_option(binding.OPT_PAIR_JOINT, 0)
+
+
 def test_batched_rejects_bad_arguments(binding, gpu, inputs_mod):
     t = torch.from_numpy(inputs_mod.single_table(100)).to(gpu)
     with pytest.raises(binding.SearchSortedError):
