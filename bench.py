@@ -796,6 +796,9 @@ def main():
                     help="skip the comparisons and every workload after the headline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of known size (HBM counter calibration)")
+    ap.add_argument("--no-calibrate", action="store_true",
+                    help="plan with the tuner's built-in coefficients instead of calibrating "
+                         "them on this device first")
     ap.add_argument("--only", choices=sorted(ONLY),
                     help="run one of the other workloads alone and print its record (for "
                          "profiling); no headline")
@@ -825,7 +828,15 @@ def main():
         print(json.dumps({"only": args.only, **rec}), flush=True)
         return
 
+    tuner = {"calibrated": False, "model": binding.tuner_get()}
+    if not args.no_calibrate:
+        # the autotuner's cost model measured on this device before any plan
+        log("bench: tuner calibration")
+        t0 = time.perf_counter()
+        tuner = {"calibrated": True, "model": binding.tuner_calibrate(),
+                 "seconds": round(time.perf_counter() - t0, 2)}
     result, pairs, host_r, host_t = paired_headline(torch, binding, inputs, dev, args)
+    result["tuner"] = tuner
     torch.cuda.empty_cache()
 
     if not args.no_systems:
