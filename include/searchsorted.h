@@ -388,6 +388,29 @@ SS_API int ss_interp_search(ss_plan *plan, const double *rho, const double *temp
 
 SS_API int ss_plan_destroy(ss_plan *plan);
 
+/* Saves a plan's choices -- per table its kernel and exponent-hash bin
+ * bits, and a learned table's 1153 model parameters -- with its form, tiles
+ * per workgroup, tile order and convention, as a text file: the setup the
+ * paper pays once per table load (Sec. 5.3), kept across runs.
+ * Interpolation plans return SS_ERR_UNSUPPORTED.  Host file I/O only. */
+SS_API int ss_plan_save(const ss_plan *plan, const char *path);
+
+/* Rebuild a saved batched or paired plan (arguments as ss_multi_plan_create
+ * and ss_pair_plan_create; the paired form comes from the file) for tables of
+ * the same sizes, without tuning or training: each table takes its saved
+ * kernel (an exponent hash's bin parameters are recomputed from the table;
+ * a table whose saved bits no longer apply gets the tuner's choice), learned
+ * tables get their saved models, and every model's error bound is measured
+ * again on the device, so the plan is exact for any tables of these sizes.
+ * The saved tiles per workgroup, tile order and convention replace the
+ * options in force.  SS_ERR_INVALID_ARG for a missing or malformed file, a
+ * plan of another form, or tables of other sizes.  SYNCHRONOUS. */
+SS_API int ss_multi_plan_load(const char *path, const double *tables, const int64_t *table_off,
+                              int32_t T, const int64_t *query_off, ss_plan **out);
+SS_API int ss_pair_plan_load(const char *path, const double *rho_tables, const int64_t *rho_off,
+                             const double *t_tables, const int64_t *t_off, int32_t M,
+                             const int64_t *pair_off, ss_plan **out);
+
 /* Targets of the most recent search of a plan with learned tables that
  * failed the window check and were answered by bisection (0 for plans
  * without learned tables).  SYNCHRONOUS (waits for the current stream). */

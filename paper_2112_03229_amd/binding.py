@@ -107,6 +107,9 @@ def _register_extra(L) -> None:
         "ss_interp_plan_create": [P, P, P, P, I32, P, P, ctypes.POINTER(P)],
         "ss_interp_search": [P, P, P, P, P, P],
         "ss_multi_search_noalloc": [P, I64, P, I32, P, P, I64, P],
+        "ss_plan_save": [P, ctypes.c_char_p],
+        "ss_multi_plan_load": [ctypes.c_char_p, P, P, I32, P, ctypes.POINTER(P)],
+        "ss_pair_plan_load": [ctypes.c_char_p, P, P, P, P, I32, P, ctypes.POINTER(P)],
         "ss_learned_save": [P, ctypes.c_char_p],
         "ss_learned_load": [P, I64, ctypes.c_char_p, ctypes.POINTER(P)],
     }
@@ -265,6 +268,10 @@ class _Plan:
         check(lib().ss_plan_fallbacks(self._handle, ctypes.byref(v)))
         return v.value
 
+    def save(self, path: str) -> None:
+        """Writes the plan's choices (ss_plan_save); reload with saved=path."""
+        check(lib().ss_plan_save(self._handle, os.fsencode(path)))
+
     def info(self) -> dict:
         import numpy as np
         T = self.num_descriptors
@@ -289,7 +296,8 @@ class MultiPlan(_Plan):
     models (a list of T LearnedIndex or None), each given model searches its
     table (ss_multi_plan_create_learned); the plan copies the models."""
 
-    def __init__(self, tables: torch.Tensor, table_off, query_off, models=None):
+    def __init__(self, tables: torch.Tensor, table_off, query_off, models=None,
+                 saved: str | None = None):
         _need(tables, torch.float64, "tables")
         self._toff = _host_offsets(table_off, "table_off")
         self._qoff = _host_offsets(query_off, "query_off")
@@ -300,7 +308,11 @@ class MultiPlan(_Plan):
         self._tables = tables  # referenced by the plan: keep alive
         h = ctypes.c_void_p()
         use_current_stream()
-        if models is None:
+        if saved is not None:  # a plan saved with save(): no tuning or training
+            check(lib().ss_multi_plan_load(os.fsencode(saved), _ptr(tables), _off_ptr(self._toff),
+                                           self.num_descriptors, _off_ptr(self._qoff),
+                                           ctypes.byref(h)))
+        elif models is None:
             check(lib().ss_multi_plan_create(_ptr(tables), _off_ptr(self._toff),
                                              self.num_descriptors, _off_ptr(self._qoff),
                                              ctypes.byref(h)))
@@ -355,7 +367,7 @@ class PairPlan(_Plan):
     """Paired density/temperature lookups per material (ss_pair_plan_create)."""
 
     def __init__(self, rho_tables: torch.Tensor, rho_off, t_tables: torch.Tensor, t_off,
-                 pair_off):
+                 pair_off, saved: str | None = None):
         _need(rho_tables, torch.float64, "rho_tables")
         _need(t_tables, torch.float64, "t_tables")
         self._roff = _host_offsets(rho_off, "rho_off")
@@ -370,9 +382,15 @@ class PairPlan(_Plan):
         self._tables = (rho_tables, t_tables)
         h = ctypes.c_void_p()
         use_current_stream()
-        check(lib().ss_pair_plan_create(_ptr(rho_tables), _off_ptr(self._roff), _ptr(t_tables),
-                                        _off_ptr(self._toff), M, _off_ptr(self._poff),
-                                        ctypes.byref(h)))
+        if saved is not None:  # a plan saved with save(): no tuning or training
+            check(lib().ss_pair_plan_load(os.fsencode(saved), _ptr(rho_tables),
+                                          _off_ptr(self._roff), _ptr(t_tables),
+                                          _off_ptr(self._toff), M, _off_ptr(self._poff),
+                                          ctypes.byref(h)))
+        else:
+            check(lib().ss_pair_plan_create(_ptr(rho_tables), _off_ptr(self._roff),
+                                            _ptr(t_tables), _off_ptr(self._toff), M,
+                                            _off_ptr(self._poff), ctypes.byref(h)))
         self._handle = h
 
     def search(self, rho: torch.Tensor, temp: torch.Tensor, out_rho: torch.Tensor | None = None,

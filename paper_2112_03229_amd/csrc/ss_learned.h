@@ -23,10 +23,13 @@ struct LearnedSlot {
 // Trains one model per slot (one workgroup per slot), compiles each into
 // d_images (kImageFloats floats per slot at i_off) and measures each slot's
 // error bound with the compiled forward pass; fills u0, inv and E of every
-// slot.  SYNCHRONOUS on the current stream.
+// slot.  With weights_in (host, SS_MLP_PARAMS floats per slot) the given
+// parameters replace training; weights_out (if not null) receives every
+// slot's parameters.  SYNCHRONOUS on the current stream.
 int learned_train_slots(const double* tables_a, const double* tables_b,
                         std::vector<LearnedSlot>& slots, float* d_images, int steps, float lr,
-                        uint64_t seed);
+                        uint64_t seed, const float* weights_in = nullptr,
+                        std::vector<float>* weights_out = nullptr);
 
 // True if a table (host copy) can have a learned model.
 bool learned_eligible(const double* a, int64_t n);
@@ -40,6 +43,7 @@ struct LearnedExport {
   float u0, inv;
   const float* image;    // compiled model (device)
   int image_floats;      // its floats in use
+  const float* params;   // its SS_MLP_PARAMS parameters (host)
 };
 int learned_export(const ss_learned* h, LearnedExport* out);
 

@@ -841,7 +841,7 @@ bool learned_eligible(const double* a, int64_t n) {
 
 int learned_train_slots(const double* tables_a, const double* tables_b,
                         std::vector<LearnedSlot>& slots, float* d_images, int steps, float lr,
-                        uint64_t seed) {
+                        uint64_t seed, const float* weights_in, std::vector<float>* weights_out) {
   if (slots.empty()) return SS_OK;
   hipStream_t st = current_stream();
   const int count = (int)slots.size();
@@ -861,7 +861,10 @@ int learned_train_slots(const double* tables_a, const double* tables_b,
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&train_many_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e == hipSuccess) {
+  if (e == hipSuccess && weights_in) {
+    e = hipMemcpyAsync(d_params, weights_in, sizeof(float) * kNP * count,
+                       hipMemcpyHostToDevice, st);
+  } else if (e == hipSuccess) {
     hipLaunchKernelGGL(train_many_kernel, dim3(count), dim3(kTrainThreads), lds, st, tables_a,
                        tables_b, d_slots, d_params, steps, lr, seed);
     e = hipGetLastError();
@@ -879,6 +882,11 @@ int learned_train_slots(const double* tables_a, const double* tables_b,
   if (e == hipSuccess)
     e = hipMemcpyAsync(slots.data(), d_slots, sizeof(LearnedSlot) * count,
                        hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && weights_out) {
+    weights_out->resize((size_t)kNP * count);
+    e = hipMemcpyAsync(weights_out->data(), d_params, sizeof(float) * kNP * count,
+                       hipMemcpyDeviceToHost, st);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(d_slots);
   if (d_params) (void)hipFree(d_params);
@@ -1167,6 +1175,7 @@ int learned_export(const ss_learned* h, LearnedExport* out) {
   out->inv = h->inv;
   out->image = h->d_image;
   out->image_floats = h->image_floats;
+  out->params = h->params.data();
   return SS_OK;
 }
 }  // namespace ss

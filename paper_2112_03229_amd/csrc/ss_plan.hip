@@ -21,6 +21,8 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <cstdio>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -439,6 +441,10 @@ struct ss_plan {
   int64_t total_tiles = 0;
   int tiles_per_wg = 0;
   bool strided = false;
+  std::vector<std::vector<float>> weights;  // per descriptor: a learned table's parameters
+  int preset_tiles = 0;                     // from a saved plan: tiles per workgroup,
+  int preset_order = -1;                    // tile order (SS_OPT_PLAN_ORDER value) and
+  int preset_conv = -1;                     // convention, else -1 / 0 (options decide)
   int num_wg = 0, xcd_groups = 1, xcd_chunk = 1;
   int grid = 0, block = 0, q = 0;
   size_t lds = 0;
@@ -525,6 +531,48 @@ size_t align16(size_t v) { return (v + 15) / 16 * 16; }
 enum LearnedMode { kLearnedTuner = 0, kLearnedAll = 1, kLearnedNone = 2 };
 // Tile order of a segment's workgroups (SS_OPT_PLAN_ORDER).
 enum TileOrder { kOrderDefault = 0, kOrderContiguous = 1, kOrderStrided = 2 };
+
+// A saved plan's choices (ss_plan_save / ss_*_plan_load): per descriptor its
+// size, kernel, bin bits and, for a learned table, the model's parameters.
+struct PlanPreset {
+  int mode = 0;
+  int descriptors = 0, materials = 0;
+  int tiles_per_wg = 0, strided = 1, convention = 0;
+  std::vector<int> n, algo, bits;
+  std::vector<std::vector<float>> weights;
+};
+
+// The saved choice for one table, re-derived from the table as it is now:
+// the exponent hash at the saved bits if it still applies within the LDS
+// budget (its bin parameters and longest bin recomputed from the entries),
+// else the tuner's choice; a learned table keeps its plain fallback choice
+// here and gets its model afterwards.
+TunedTable preset_table(const TunerModel& model, const double* a, int n, size_t budget,
+                        int algo, int bits) {
+  if (algo == SS_ALGO_BINARY) return tune_table(model, a, n, budget, SS_ALGO_BINARY);
+  if (algo == SS_ALGO_EXPHASH && bits >= 0 && bits <= SS_MAX_BITS && n >= 1 && n <= 65535) {
+    TunedTable t = tune_table(model, a, n, budget, SS_ALGO_EXPHASH);
+    if (t.algo == SS_ALGO_EXPHASH && t.bits == bits) return t;
+    uint64_t u0, u1;
+    std::memcpy(&u0, &a[0], 8);
+    std::memcpy(&u1, &a[n - 1], 8);
+    const int h0 = (int)(int32_t)(uint32_t)(u0 >> 32), h1 = (int)(int32_t)(uint32_t)(u1 >> 32);
+    const int sh = SS_MAX_BITS - bits;
+    const int64_t nb = (int64_t)(h1 >> sh) - (h0 >> sh) + 1;
+    if (h0 >= 0 && h1 >= h0 && nb <= 65535 && (size_t)(nb + 1) * 2 + 16 <= budget) {
+      t.algo = SS_ALGO_EXPHASH;
+      t.bits = bits;
+      t.kmin = h0 >> sh;
+      t.kmaxc = h1 >> sh;
+      t.nb = (int)nb;
+      t.K = host_longest_bin(a, n, bits);
+      t.est_ns = t.K <= SS_SCAN_MAX ? model.hash_base_ns + model.hash_per_k_ns * t.K
+                                    : model.hash_base_ns + model.bin_per_step_ns * 17;
+      return t;
+    }
+  }
+  return tune_table(model, a, n, budget);
+}
 int learned_mode() {
   if (option(SS_OPT_PLAN_ALGO) != SS_ALGO_AUTO) return kLearnedNone;
   return (int)option(SS_OPT_PLAN_LEARNED);
@@ -543,19 +591,24 @@ int fail_delete(ss_plan* p, const char* msg, int code = SS_ERR_INVALID_ARG) {
 // host_a / host_b are host copies of the two tables arrays.
 int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
                   const std::vector<double>& host_a, const std::vector<double>& host_b,
-                  int mode) {
+                  int mode, const PlanPreset* preset = nullptr) {
   const TunerModel model = tuner_model();
   constexpr int kBestLookup = 3;  // cell read, one boundary, piece read
   std::vector<LearnedSlot> slots;
   std::vector<int> slot_desc;
+  std::vector<float> given;  // a saved plan's parameters, one model per slot
   for (int t = 0; t < p->T; ++t) {
     TableDesc& d = p->desc[t];
     const int which = (p->paired && t >= p->M) ? 1 : 0;
     const double* h = (which ? host_b.data() : host_a.data()) + d.tab_off;
     if (!learned_eligible(h, d.n)) continue;
-    if (mode == kLearnedTuner &&
-        !(learned_cost_ns(model, 1, kBestLookup) < p->tuned[t].est_ns))
+    if (preset) {
+      if (preset->weights[t].empty()) continue;
+      given.insert(given.end(), preset->weights[t].begin(), preset->weights[t].end());
+    } else if (mode == kLearnedTuner &&
+               !(learned_cost_ns(model, 1, kBestLookup) < p->tuned[t].est_ns)) {
       continue;
+    }
     LearnedSlot sl{};
     sl.tab_off = d.tab_off;
     sl.i_off = (int64_t)slots.size() * kImageFloats;
@@ -570,7 +623,9 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
   SS_TRY_HIP(hipMemset(p->d_fallbacks, 0, sizeof(unsigned long long)));
   int steps = (int)option(SS_OPT_LEARNED_STEPS);
   if (steps <= 0) steps = kDefaultPlanLearnedSteps;
-  int rc = learned_train_slots(tables_a, tables_b, slots, p->d_pool, steps, 0.01f, 1);
+  std::vector<float> trained;
+  int rc = learned_train_slots(tables_a, tables_b, slots, p->d_pool, steps, 0.01f, 1,
+                               preset ? given.data() : nullptr, &trained);
   if (rc != SS_OK) return rc;
   // every image's (boundaries, pieces, cells, fullest cell) header: LDS is
   // reserved for the largest kept image
@@ -590,7 +645,7 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
       for (int v = 1; v < hd[0]; v <<= 1) ++lookup;
     }
     p->tuned[t].learned_ns = learned_cost_ns(model, slots[i].E, lookup);
-    if (mode == kLearnedTuner && !(p->tuned[t].learned_ns < p->tuned[t].est_ns)) {
+    if (!preset && mode == kLearnedTuner && !(p->tuned[t].learned_ns < p->tuned[t].est_ns)) {
       slot_desc[i] = -1;  // trained, but its plain kernel is cheaper
       continue;
     }
@@ -611,6 +666,8 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
     d.inv = slots[i].inv;
     p->tuned[t].algo = SS_ALGO_LEARNED;
     p->tuned[t].bits = -1;
+    p->weights[t].assign(trained.begin() + (int64_t)i * SS_MLP_PARAMS,
+                         trained.begin() + (int64_t)(i + 1) * SS_MLP_PARAMS);
   }
   p->learned_tables = kept;
   return SS_OK;
@@ -649,6 +706,7 @@ int attach_learned(ss_plan* p, const double* tables, const int64_t* table_off,
                          sizeof(float) * ex[i].image_floats, hipMemcpyDeviceToDevice));
     p->image_bytes = std::max(p->image_bytes, (size_t)ex[i].image_floats * 4);
     const int t = with[i];
+    if (ex[i].params) p->weights[t].assign(ex[i].params, ex[i].params + SS_MLP_PARAMS);
     TableDesc& d = p->desc[t];
     d.algo = SS_ALGO_LEARNED;
     d.bins_off = 0;
@@ -756,7 +814,8 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
     }
   }
   // interpolation locates cells with the strict index (its own definition)
-  p->convention = p->mode != kPairInterp && option(SS_OPT_CONVENTION) != 0;
+  p->convention = p->mode != kPairInterp &&
+                  (p->preset_conv >= 0 ? p->preset_conv : option(SS_OPT_CONVENTION)) != 0;
   p->kernel = plan_kernel(p->mode, learned, p->convention);
   DeviceInfo di;
   int rc = device_info(&di);
@@ -775,6 +834,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident, S,
                                                per_tile);
   if (option(SS_OPT_PLAN_TILES) > 0) p->tiles_per_wg = (int)option(SS_OPT_PLAN_TILES);
+  if (p->preset_tiles > 0) p->tiles_per_wg = p->preset_tiles;
   // Each segment's tiles go to ceil(tiles / k) workgroups of at most k
   // tiles each (k = tiles_per_wg), never across a segment boundary: either
   // as contiguous ranges (workgroup i takes tiles i k .. i k + k - 1) or
@@ -785,7 +845,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   // 1.459 / 1.464 ms.  A segment's workgroups are dispatched together, and
   // strided they read one advancing window of the segment's targets rather
   // than W separate streams.
-  const int64_t order = option(SS_OPT_PLAN_ORDER);
+  const int64_t order = p->preset_order >= 0 ? p->preset_order : option(SS_OPT_PLAN_ORDER);
   p->strided = order != kOrderContiguous;
   std::vector<WgStart> wg_start;
   for (int s = 0; s < S; ++s) {
@@ -913,7 +973,8 @@ extern "C" {
 // Batched plan creation; models (T handles, entries may be null) attaches
 // learned models, else SS_OPT_PLAN_LEARNED may train them.
 static int create_batched(const double* tables, const int64_t* table_off, int32_t T,
-                          const int64_t* query_off, ss_learned* const* models, ss_plan** out) {
+                          const int64_t* query_off, ss_learned* const* models, ss_plan** out,
+                          const PlanPreset* preset = nullptr) {
   clear_error();
   if (!out) return fail(SS_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
@@ -941,6 +1002,18 @@ static int create_batched(const double* tables, const int64_t* table_off, int32_
   const TunerModel& model = tuner_model();
   p->desc.resize(T);
   p->tuned.resize(T);
+  p->weights.resize(T);
+  if (preset) {
+    if (preset->mode != kBatched || preset->descriptors != T)
+      return fail_delete(p, "the saved plan is not a batched plan of this many tables");
+    for (int t = 0; t < T; ++t)
+      if (preset->n[t] != table_off[t + 1] - table_off[t])
+        return fail_delete(p, ("table " + std::to_string(t) + " differs in size from the saved "
+                               "plan's").c_str());
+    p->preset_tiles = preset->tiles_per_wg;
+    p->preset_order = preset->strided ? kOrderStrided : kOrderContiguous;
+    p->preset_conv = preset->convention;
+  }
   size_t max_tab = 16, max_bins = 0;
   for (int t = 0; t < T; ++t)
     max_tab = std::max(max_tab, align16((size_t)(table_off[t + 1] - table_off[t] + SS_PAD) * 8));
@@ -950,15 +1023,17 @@ static int create_batched(const double* tables, const int64_t* table_off, int32_
   int64_t pool = 0;
   for (int t = 0; t < T; ++t) {
     const int n = (int)(table_off[t + 1] - table_off[t]);
-    p->tuned[t] = tune_table(model, host.data() + table_off[t], n, kPlanLdsBudget - max_tab,
-                             (int)option(SS_OPT_PLAN_ALGO));
+    p->tuned[t] = preset ? preset_table(model, host.data() + table_off[t], n,
+                                        kPlanLdsBudget - max_tab, preset->algo[t], preset->bits[t])
+                         : tune_table(model, host.data() + table_off[t], n,
+                                      kPlanLdsBudget - max_tab, (int)option(SS_OPT_PLAN_ALGO));
     describe(p->tuned[t], table_off[t], &p->desc[t], &pool);
     if (p->tuned[t].algo == SS_ALGO_EXPHASH)
       max_bins = std::max(max_bins, align16((size_t)(p->tuned[t].nb + 1) * 2));
   }
-  if (models || learned_mode() != kLearnedNone) {
+  if (models || preset || learned_mode() != kLearnedNone) {
     rc = models ? attach_learned(p, tables, table_off, models)
-                : apply_learned(p, tables, nullptr, host, host, learned_mode());
+                : apply_learned(p, tables, nullptr, host, host, learned_mode(), preset);
     if (rc != SS_OK) return fail_delete(p, nullptr, rc);
     max_bins = 0;
     for (int t = 0; t < T; ++t)
@@ -1014,7 +1089,7 @@ namespace {
 // values: the interpolation form's value grids, else null).
 int create_paired(const double* rho_tables, const int64_t* rho_off, const double* t_tables,
                   const int64_t* t_off, int32_t M, const int64_t* pair_off, int mode,
-                  const double* values, ss_plan** out) {
+                  const double* values, ss_plan** out, const PlanPreset* preset = nullptr) {
   if (!out) return fail(SS_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (M < 1 || M > (1 << 20)) return fail(SS_ERR_INVALID_ARG, "M must be in 1..2^20");
@@ -1080,6 +1155,19 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
   const TunerModel& model = tuner_model();
   p->desc.resize(2 * M);
   p->tuned.resize(2 * M);
+  p->weights.resize(2 * M);
+  if (preset) {
+    if (preset->mode != mode || preset->descriptors != 2 * M)
+      return fail_delete(p, "the saved plan is not a paired plan of this form and size");
+    for (int j = 0; j < M; ++j)
+      if (preset->n[j] != rho_off[j + 1] - rho_off[j] ||
+          preset->n[M + j] != t_off[j + 1] - t_off[j])
+        return fail_delete(p, ("material " + std::to_string(j) + " differs in size from the "
+                               "saved plan's").c_str());
+    p->preset_tiles = preset->tiles_per_wg;
+    p->preset_order = preset->strided ? kOrderStrided : kOrderContiguous;
+    p->preset_conv = preset->convention;
+  }
   size_t tab_a = 16, bins_a = 0, tab_b = 16, bins_b = 0;
   for (int j = 0; j < M; ++j) {
     tab_a = std::max(tab_a, align16((size_t)(rho_off[j + 1] - rho_off[j] + SS_PAD) * 8));
@@ -1108,20 +1196,24 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
   const int force = (int)option(SS_OPT_PLAN_ALGO);
   for (int j = 0; j < M; ++j) {
     const int n = (int)(rho_off[j + 1] - rho_off[j]);
-    p->tuned[j] = tune_table(model, hr.data() + rho_off[j], n, budget_a, force);
+    p->tuned[j] = preset ? preset_table(model, hr.data() + rho_off[j], n, budget_a,
+                                        preset->algo[j], preset->bits[j])
+                         : tune_table(model, hr.data() + rho_off[j], n, budget_a, force);
     describe(p->tuned[j], rho_off[j], &p->desc[j], &pool);
     if (p->tuned[j].algo == SS_ALGO_EXPHASH)
       bins_a = std::max(bins_a, align16((size_t)(p->tuned[j].nb + 1) * 2));
   }
   for (int j = 0; j < M; ++j) {
     const int n = (int)(t_off[j + 1] - t_off[j]);
-    p->tuned[M + j] = tune_table(model, ht.data() + t_off[j], n, budget_b, force);
+    p->tuned[M + j] = preset ? preset_table(model, ht.data() + t_off[j], n, budget_b,
+                                            preset->algo[M + j], preset->bits[M + j])
+                             : tune_table(model, ht.data() + t_off[j], n, budget_b, force);
     describe(p->tuned[M + j], t_off[j], &p->desc[M + j], &pool);
     if (p->tuned[M + j].algo == SS_ALGO_EXPHASH)
       bins_b = std::max(bins_b, align16((size_t)(p->tuned[M + j].nb + 1) * 2));
   }
-  if (learned_mode() != kLearnedNone && p->mode != kPairInterp) {
-    if ((rc = apply_learned(p, rho_tables, t_tables, hr, ht, learned_mode())) != SS_OK)
+  if ((preset || learned_mode() != kLearnedNone) && p->mode != kPairInterp) {
+    if ((rc = apply_learned(p, rho_tables, t_tables, hr, ht, learned_mode(), preset)) != SS_OK)
       return fail_delete(p, nullptr, rc);
     bins_a = bins_b = 0;
     for (int j = 0; j < M; ++j) {
@@ -1232,6 +1324,125 @@ int ss_pair_search(ss_plan* p, const double* rho, const double* temp, int32_t* o
       return rc;
   }
   return run_plan(p, rho, out_rho, temp, out_t);
+}
+
+// Saved plans: a text file of the plan's choices, "ss_plan 1" then
+//   mode M descriptors T materials M tiles K strided 0|1 convention 0|1
+//   table t n N algo A bits S          (one line per descriptor)
+//   weights t w0 ... w1152             (one line per learned table)
+//   end
+// Parameters are printed with 9 significant digits, which read back into
+// the same FP32 values.
+int ss_plan_save(const ss_plan* p, const char* path) {
+  clear_error();
+  if (!p || !path) return fail(SS_ERR_INVALID_ARG, "null argument");
+  if (p->mode == kPairInterp)
+    return fail(SS_ERR_UNSUPPORTED, "interpolation plans are not saved (no learned tables)");
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  std::fprintf(f, "ss_plan 1\nmode %d descriptors %d materials %d tiles %d strided %d convention %d\n",
+               p->mode, p->T, p->M, p->tiles_per_wg, p->strided ? 1 : 0, p->convention ? 1 : 0);
+  for (int t = 0; t < p->T; ++t)
+    std::fprintf(f, "table %d n %d algo %d bits %d\n", t, p->desc[t].n, p->tuned[t].algo,
+                 p->tuned[t].algo == SS_ALGO_EXPHASH ? p->tuned[t].bits : -1);
+  for (int t = 0; t < p->T; ++t) {
+    if (p->weights[t].empty()) continue;
+    std::fprintf(f, "weights %d", t);
+    for (float w : p->weights[t]) std::fprintf(f, " %.9g", (double)w);
+    std::fprintf(f, "\n");
+  }
+  std::fprintf(f, "end\n");
+  return std::fclose(f) == 0 ? SS_OK : fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
+}
+
+}  // extern "C"
+
+namespace ss {
+namespace {
+
+int read_preset(const char* path, PlanPreset* pr) {
+  if (!path) return fail(SS_ERR_INVALID_ARG, "path is null");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  std::string text;
+  char buf[1 << 16];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  std::istringstream in(text);
+  const std::string bad = std::string("malformed saved plan ") + path;
+  auto expect = [&](const char* word) {
+    std::string w;
+    return (in >> w) && w == word;
+  };
+  int version = 0;
+  if (!expect("ss_plan") || !(in >> version) || version != 1) return fail(SS_ERR_INVALID_ARG, bad);
+  if (!expect("mode") || !(in >> pr->mode) || !expect("descriptors") || !(in >> pr->descriptors) ||
+      !expect("materials") || !(in >> pr->materials) || !expect("tiles") ||
+      !(in >> pr->tiles_per_wg) || !expect("strided") || !(in >> pr->strided) ||
+      !expect("convention") || !(in >> pr->convention))
+    return fail(SS_ERR_INVALID_ARG, bad);
+  if (pr->mode < kBatched || pr->mode > kPairSplit || pr->descriptors < 1 ||
+      pr->descriptors > (2 << 20) || pr->tiles_per_wg < 1 || pr->tiles_per_wg > 4096)
+    return fail(SS_ERR_INVALID_ARG, bad);
+  const int T = pr->descriptors;
+  pr->n.assign(T, -1);
+  pr->algo.assign(T, 0);
+  pr->bits.assign(T, -1);
+  pr->weights.assign(T, {});
+  for (int t = 0; t < T; ++t) {
+    int idx = -1;
+    if (!expect("table") || !(in >> idx) || idx != t || !expect("n") || !(in >> pr->n[t]) ||
+        !expect("algo") || !(in >> pr->algo[t]) || !expect("bits") || !(in >> pr->bits[t]))
+      return fail(SS_ERR_INVALID_ARG, bad);
+  }
+  std::string w;
+  while (in >> w && w == "weights") {
+    int t = -1;
+    if (!(in >> t) || t < 0 || t >= T || !pr->weights[t].empty())
+      return fail(SS_ERR_INVALID_ARG, bad);
+    pr->weights[t].resize(SS_MLP_PARAMS);
+    for (int i = 0; i < SS_MLP_PARAMS; ++i) {
+      std::string v;
+      if (!(in >> v)) return fail(SS_ERR_INVALID_ARG, bad);
+      char* end = nullptr;
+      pr->weights[t][i] = std::strtof(v.c_str(), &end);
+      if (end == v.c_str() || *end) return fail(SS_ERR_INVALID_ARG, bad);
+    }
+  }
+  if (w != "end") return fail(SS_ERR_INVALID_ARG, bad);
+  return SS_OK;
+}
+
+}  // namespace
+}  // namespace ss
+
+extern "C" {
+
+int ss_multi_plan_load(const char* path, const double* tables, const int64_t* table_off,
+                       int32_t T, const int64_t* query_off, ss_plan** out) {
+  clear_error();
+  if (!out) return fail(SS_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  PlanPreset pr;
+  const int rc = read_preset(path, &pr);
+  if (rc != SS_OK) return rc;
+  return create_batched(tables, table_off, T, query_off, nullptr, out, &pr);
+}
+
+int ss_pair_plan_load(const char* path, const double* rho_tables, const int64_t* rho_off,
+                      const double* t_tables, const int64_t* t_off, int32_t M,
+                      const int64_t* pair_off, ss_plan** out) {
+  clear_error();
+  if (!out) return fail(SS_ERR_INVALID_ARG, "out is null");
+  *out = nullptr;
+  PlanPreset pr;
+  const int rc = read_preset(path, &pr);
+  if (rc != SS_OK) return rc;
+  if (pr.mode != kPairSplit && pr.mode != kPairJoint)
+    return fail(SS_ERR_INVALID_ARG, "the saved plan is not a paired plan");
+  return create_paired(rho_tables, rho_off, t_tables, t_off, M, pair_off, pr.mode, nullptr, out,
+                       &pr);
 }
 
 int ss_plan_destroy(ss_plan* p) {

@@ -197,3 +197,22 @@ def test_learned_accessors_reject_null_handles(L):
     assert L.ss_multi_plan_create_learned(P(0x10000), off, 1, qoff, P(0), ctypes.byref(out)) == -1
     assert b"models" in L.ss_last_error()
     assert out.value is None
+
+
+def test_saved_plan_files_are_checked(L, tmp_path):
+    """Malformed or missing plan files are refused before any device work."""
+    P = ctypes.c_void_p
+    h = ctypes.c_void_p()
+    off = (ctypes.c_int64 * 3)(0, 5, 9)
+    for text in ("", "ss_plan 2\n", "ss_plan 1\nmode 0 descriptors 2 materials 0 tiles 4 "
+                 "strided 1 convention 0\ntable 0 n 5 algo 1 bits -1\nend\n",
+                 "ss_plan 1\nmode 0 descriptors 1 materials 0 tiles 4 strided 1 convention 0\n"
+                 "table 0 n 5 algo 5 bits -1\nweights 0 1 2 3\nend\n"):
+        path = tmp_path / "bad.plan"
+        path.write_text(text)
+        rc = L.ss_multi_plan_load(str(path).encode(), P(0x10000), off, 2, off, ctypes.byref(h))
+        assert rc == -1 and b"malformed" in L.ss_last_error(), text
+    rc = L.ss_multi_plan_load(str(tmp_path / "missing.plan").encode(), P(0x10000), off, 2, off,
+                              ctypes.byref(h))
+    assert rc == -1 and b"cannot open" in L.ss_last_error()
+    assert L.ss_plan_save(None, b"x") == -1
