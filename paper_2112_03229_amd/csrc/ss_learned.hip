@@ -299,7 +299,8 @@ __device__ __forceinline__ double inside(double lo, double hi) {
 //      switching points, then the segment's right breakpoint), and per
 //      piece the active layer-2 units at a point inside it, giving
 //      slope = sum w3_k P_sk and intercept = b3 + sum w3_k Q_sk;
-//   5. the cell table: G (a power of two >= 2 nb, at most kIMaxCells)
+//   5. the cell table: G (a power of two >= 2 nb, at most kIMaxCells,
+//      the smallest that gives the shortest scan)
 //      equal cells over the boundaries' range less its outermost few, each
 //      boundary's cell from the FP32 expression the search uses, the prefix
 //      counts by gap filling, and K, the fullest cell (no table if
@@ -435,26 +436,32 @@ __device__ void compile_model(const float* __restrict__ P, float* __restrict__ i
     int bestK = kIMaxBounds + 1, bestG = 0;
     float bz0 = 0.0f, bcinv = 0.0f;
     if (nb > 0) {
-      int G = 2;
-      while (G < 2 * nb && G < kIMaxCells) G <<= 1;
+      int G0 = 2;
+      while (G0 < 2 * nb && G0 < kIMaxCells) G0 <<= 1;
       const int smax = min(kCellScan, (nb - 1) / 2);
-      for (int t = 0; t <= smax; ++t) {
-        const float lo = bnd[t], span = bnd[nb - 1 - t] - lo;
-        if (!(lo > -inff) || !(span > 0.0f && span < inff)) continue;
-        const float cinv = (float)G / span;
-        int K = 0, run = 0, prev = -1;
-        for (int k = 0; k < nb; ++k) {
-          const int c = cell_of(bnd[k], lo, cinv, G);
-          run = c == prev ? run + 1 : 1;
-          prev = c;
-          K = max(K, run);
+      // finer tables shorten the scan (one LDS step per boundary of the
+      // fullest cell) at 2 bytes per cell: the smallest K wins, then the
+      // fewest cells
+      for (int G = G0; G <= kIMaxCells; G <<= 1) {
+        for (int t = 0; t <= smax; ++t) {
+          const float lo = bnd[t], span = bnd[nb - 1 - t] - lo;
+          if (!(lo > -inff) || !(span > 0.0f && span < inff)) continue;
+          const float cinv = (float)G / span;
+          int K = 0, run = 0, prev = -1;
+          for (int k = 0; k < nb; ++k) {
+            const int c = cell_of(bnd[k], lo, cinv, G);
+            run = c == prev ? run + 1 : 1;
+            prev = c;
+            K = max(K, run);
+          }
+          if (K < bestK) {
+            bestK = K;
+            bestG = G;
+            bz0 = lo;
+            bcinv = cinv;
+          }
         }
-        if (K < bestK) {
-          bestK = K;
-          bestG = G;
-          bz0 = lo;
-          bcinv = cinv;
-        }
+        if (bestK <= 1) break;
       }
     }
     const bool use = bestG > 0 && bestK <= kCellScan;
