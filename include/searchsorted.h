@@ -129,8 +129,10 @@ typedef enum {
                                     afterwards: the workgroup ranges are
                                     dealt to the 8 XCDs round robin in
                                     chunks of C consecutive ranges.  0
-                                    (default): C = 8; 1: dispatch order
-                                    (C = 1); 2..2^24: C = the value (a C of
+                                    (default): C = 1 (dispatch order) when
+                                    the plan's segments average under 64
+                                    tiles of 4096 targets, else C = 8; 1:
+                                    dispatch order; 2..2^24: C = the value (a C of
                                     at least a 1/8 of the ranges gives each
                                     XCD one contiguous part) */
     SS_OPT_PAIR_JOINT = 12,      /* paired plans built afterwards: 0

@@ -17,6 +17,8 @@ struct LearnedSlot {
   int which;        // 0: first tables array, 1: second (paired plans)
   float u0, inv;    // model input normalisation (computed on the device)
   int E;            // error bound (measured on the device)
+  int head[4];      // its compiled image's header: boundary slots, pieces,
+                    // cells, fullest cell (copied by the bound kernel)
   int pad_;
 };
 

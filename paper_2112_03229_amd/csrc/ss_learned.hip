@@ -603,7 +603,10 @@ __global__ __launch_bounds__(256) void bound_many_kernel(const double* tables_a,
   for (int o = 32; o > 0; o >>= 1) local = max(local, __shfl_xor(local, o));
   if ((threadIdx.x & 63) == 0) atomicMax(&worst, local);
   __syncthreads();
-  if (threadIdx.x == 0) slots[blockIdx.x].E = worst + 1;
+  if (threadIdx.x == 0) {
+    slots[blockIdx.x].E = worst + 1;
+    for (int k = 0; k < 4; ++k) slots[blockIdx.x].head[k] = __float_as_int(model[k]);
+  }
 }
 
 // ---------------------------------------------------------------------------

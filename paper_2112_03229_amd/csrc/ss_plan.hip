@@ -476,12 +476,18 @@ constexpr int kPlanQ = 8;
 constexpr int kPairQ = 4;
 constexpr int kDefaultPlanLearnedSteps = 500;
 constexpr int kXcds = 8;                  // accelerator complex dies of an MI355X
-// Default workgroup ranges per XCD turn.  Measured on MI355X, chunks of 1 /
-// 8 / 64 / one contiguous part per XCD: 512-table batch 5.97 / 6.03 / 5.90 /
-// 5.89 TB/s; 4096-material paired workload 5.71 / 5.70 / 5.66 / 5.47.  A
-// contiguous part per XCD gives the dies unequal work (the paired plan's
-// density segments, with the larger tables, come first).
+// Workgroup ranges per XCD turn for plans with long segments.  Measured on
+// MI355X (strided tile order, 5 tiles per workgroup, mean of three runs):
+// the 512-table batch (segments of ~350 tiles) 1.468 ms in dispatch order
+// against 1.447 ms in chunks of 8; the 4096-material paired workload
+// (segments of ~60 tiles) 3.984 against 4.003 ms.  Plans whose segments
+// average under 64 tiles therefore keep dispatch order.  Earlier, with
+// contiguous tile ranges: chunks of 1 / 8 / 64 / one contiguous part per
+// XCD gave 5.97 / 6.03 / 5.90 / 5.89 TB/s on the batch; a contiguous part
+// per XCD gives the dies unequal work (the paired plan's density segments,
+// with the larger tables, come first).
 constexpr int kXcdChunk = 8;
+constexpr int kShortSegmentTiles = 64;  // in tiles of 4096 targets
 // LDS a plan's workgroup may use (tables + bin tables): three 512-thread
 // workgroups per CU fit in 160 KB.
 constexpr size_t kPlanLdsBudget = 48 * 1024;
@@ -627,17 +633,19 @@ int apply_learned(ss_plan* p, const double* tables_a, const double* tables_b,
   int rc = learned_train_slots(tables_a, tables_b, slots, p->d_pool, steps, 0.01f, 1,
                                preset ? given.data() : nullptr, &trained);
   if (rc != SS_OK) return rc;
-  // every image's (boundaries, pieces, cells, fullest cell) header: LDS is
-  // reserved for the largest kept image
-  std::vector<int> head(4 * slots.size());
-  SS_TRY_HIP(hipMemcpy2D(head.data(), 4 * sizeof(int), p->d_pool, kImageBytes, 4 * sizeof(int),
-                         slots.size(), hipMemcpyDeviceToHost));
+  // every image's (boundaries, pieces, cells, fullest cell) header, as the
+  // bound kernel staged it: LDS is reserved for the largest kept image
   p->image_bytes = 0;
   int kept = 0;
   for (size_t i = 0; i < slots.size(); ++i) {
-    const int* hd = head.data() + 4 * i;
+    const int* hd = slots[i].head;
     if (!image_header_valid(hd))
-      return fail(SS_ERR_UNSUPPORTED, "compiled model " + std::to_string(i) + " is malformed");
+      return fail(SS_ERR_UNSUPPORTED,
+                  "compiled model " + std::to_string(i) + " (table " +
+                      std::to_string(slot_desc[i]) + ", n " + std::to_string(slots[i].n) +
+                      ") is malformed: boundary slots " + std::to_string(hd[0]) + ", pieces " +
+                      std::to_string(hd[1]) + ", cells " + std::to_string(hd[2]) +
+                      ", fullest cell " + std::to_string(hd[3]));
     const int t = slot_desc[i];
     int lookup = 2 + hd[3];  // cell read, scan of the fullest cell, piece read
     if (hd[2] == 0) {        // no cell table: bisection over the boundary slots
@@ -873,14 +881,17 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   }
   const int64_t num_wg = (int64_t)wg_start.size();
   const int64_t xcd = option(SS_OPT_PLAN_XCD);
-  const int groups = xcd == 1 ? 1 : kXcds;
+  const int64_t tile_scale = std::max<int64_t>(1, 4096 / per_tile);
+  const bool short_segments =
+      p->total_tiles / std::max(S, 1) / tile_scale < kShortSegmentTiles;
+  const int64_t chunk = xcd >= 2 ? xcd : (xcd == 1 || short_segments) ? 1 : kXcdChunk;
+  const int groups = chunk == 1 ? 1 : kXcds;
   const int64_t grid = (num_wg + groups - 1) / groups * groups;
   if (grid > INT32_MAX) return fail(SS_ERR_INVALID_ARG, "too many tiles for one launch");
   p->grid = (int)grid;
   p->num_wg = (int)num_wg;
   p->xcd_groups = groups;
-  p->xcd_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(xcd >= 2 ? xcd : kXcdChunk,
-                                                            grid / groups));
+  p->xcd_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, grid / groups));
   SS_TRY_HIP(hipMalloc(&p->d_tile_off, sizeof(int64_t) * (S + 1)));
   SS_TRY_HIP(hipMalloc(&p->d_query_off, sizeof(int64_t) * (S + 1)));
   SS_TRY_HIP(hipMalloc(&p->d_wg_start, sizeof(WgStart) * p->num_wg));

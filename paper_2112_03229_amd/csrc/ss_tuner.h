@@ -12,19 +12,20 @@ namespace ss {
 // time is max(memory, compute): memory = 12 bytes / stream bandwidth,
 // compute from the per-kernel terms below.
 struct TunerModel {
-  double stream_gbs = 6200.0;        // sustained bytes/ns of a 12 B/query stream
-  double hash_base_ns = 0.6e-3;      // exponent hash: key, bin read, select
-  double hash_per_k_ns = 0.15e-3;    // per entry of the fixed in-bin scan
-  double bin_base_ns = 0.5e-3;       // bisection: final compare and select
-  double bin_per_step_ns = 0.10e-3;  // per bisection step
-  double learned_base_ns = 1.6e-3;   // learned index: input, prediction and
+  // Defaults: the values calibrate() measures on an MI355X (rounded).
+  double stream_gbs = 6600.0;        // sustained bytes/ns of a 12 B/query stream
+  double hash_base_ns = 3.3e-3;      // exponent hash: key, bin read, select
+  double hash_per_k_ns = 0.4e-3;     // per entry of the fixed in-bin scan
+  double bin_base_ns = 0.0;          // bisection: final compare and select
+  double bin_per_step_ns = 1.05e-3;  // per bisection step
+  double learned_base_ns = 0.0;      // learned index: input, prediction and
                                      // the window's verification
-  double learned_per_step_ns = 0.10e-3;  // per LDS step of its model lookup and
+  double learned_per_step_ns = 1.05e-3;  // per LDS step of its model lookup and
                                          // window bisection
   double bins_per_entry = 4.0;       // most exponent-hash bins per table entry
                                      // (each workgroup copies its bins)
-  double tiles_short = 6;            // target tiles (of 4096) per plan workgroup
-  double tiles_long = 4;             // for segments averaging under / over 64 tiles
+  double tiles_short = 5;            // target tiles (of 4096) per plan workgroup
+  double tiles_long = 5;             // for segments averaging under / over 64 tiles
   int calibrated = 0;                // 1 once measured on this device
 };
 

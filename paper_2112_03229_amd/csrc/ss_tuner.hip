@@ -10,10 +10,12 @@
 // fewer bins (less LDS to stage).  The model's coefficients are measured by
 // ss_tuner_calibrate on the current device: a long HBM stream for the
 // bandwidth, then bisection over tables of 64..4096 entries and the
-// exponent hash at several K on cache-resident targets, fitted by least
-// squares, and a learned index's fixed cost.  The model is cached as JSON
+// exponent hash at several K and the learned index, each timed in plans
+// (the only place the tuner decides) on cache-resident targets, fitted by
+// least squares.  The model is cached as JSON
 // with the device architecture and the HIP runtime version it was measured
 // with; a cache from another architecture or runtime is refused.
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -201,8 +203,12 @@ void env_init() {
 
 }  // namespace
 
+// Set while calibrate() runs: the plans it times read the model directly
+// (a calibration started by the first use must not wait on that first use).
+thread_local bool t_calibrating = false;
+
 TunerModel tuner_model() {
-  std::call_once(g_env_once, env_init);
+  if (!t_calibrating) std::call_once(g_env_once, env_init);
   return model_copy();
 }
 
@@ -276,19 +282,17 @@ int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int
                                int segments, int64_t per_tile) {
   // Every workgroup stages its table before searching, so the targets per
   // workgroup trade staging stalls against load balance.  Measured on MI355X
-  // (steady clocks, tiles aligned to absolute positions, two tiles
-  // prefetched, workgroup ranges cut at segment boundaries and dealt to the
-  // XCDs in chunks of 8), with tiles of 4096 targets: 512 tables with ~350
-  // tiles each: 3 tiles per workgroup 5.92 TB/s, 4: 6.03; 8192 density and
-  // temperature segments with ~60 tiles each: 6: 5.70, 8: 5.63.  Short
-  // segments (under 64 such tiles on average) take 6, long ones 4.  Smaller
-  // tiles (the joint and interpolation forms' 2048 targets) take
-  // proportionally more, the same targets per workgroup.  Scaling held when
-  // measured with 512-target tiles (an earlier learned-plan launch shape):
-  // the 512-table batch with every table learned ran at 88.8 / 97.9 /
-  // 104.3 / 107.1 / 108.0 Gq/s with 4 / 8 / 16 / 32 / 64 tiles of 512.
-  // Those sweeps set the model's defaults (tiles_short, tiles_long).  The
-  // count is then reduced while it leaves fewer than ~6 waves of workgroups.
+  // (steady clocks, tiles of 4096 targets aligned to absolute positions, two
+  // tiles prefetched, a workgroup inside one segment, strided tile order,
+  // mean of three runs): the 512-table batch (~350 tiles per table, chunks
+  // of 8 ranges per XCD) 1.458 / 1.447 / 1.466 ms with 4 / 5 / 6 tiles per
+  // workgroup; the 4096-material paired workload (8192 segments of ~60
+  // tiles, dispatch order) 4.004 / 3.984 / 4.016 ms.  Those sweeps set the
+  // model's defaults (tiles_short and tiles_long, for segments averaging
+  // under and over 64 tiles; both 5 now).  Smaller tiles (the joint and
+  // interpolation forms' 2048 targets) take proportionally more, the same
+  // targets per workgroup.  The count is then reduced while it leaves fewer
+  // than ~6 waves of workgroups.
   const int64_t scale = std::max<int64_t>(1, 4096 / std::max<int64_t>(per_tile, 1));
   const int64_t avg = total_tiles / std::max(segments, 1) / scale;
   int64_t k = (int64_t)std::lround(avg < 64 ? model.tiles_short : model.tiles_long) * scale;
@@ -366,6 +370,89 @@ void fit_line(const std::vector<double>& x, const std::vector<double>& y, double
 namespace ss {
 namespace {
 
+// One plan timing of the calibration: `copies` copies of a host table
+// searched over `per` targets each (the same device targets for every
+// copy), with every table forced to `algo` (or, with learned = 1, given a
+// model).  Reports ns per query, the plan's longest bin and, for learned
+// tables, the modelled cost the plan reports for the first table.
+struct PlanTiming {
+  double ns = 0;
+  int max_k = 0;
+  double learned_ns = -1;
+};
+
+int time_plan(const std::vector<double>& h, int copies, int64_t per, const double* x,
+              int32_t* out, int algo, int learned, PlanTiming* res) {
+  hipStream_t st = current_stream();
+  const int n = (int)h.size();
+  DevBuf tb, xb;
+  SS_TRY_HIP(hipMalloc(&tb.p, sizeof(double) * n * copies));
+  for (int c = 0; c < copies; ++c)
+    SS_TRY_HIP(hipMemcpyAsync(static_cast<double*>(tb.p) + (int64_t)c * n, h.data(), 8 * n,
+                              hipMemcpyHostToDevice, st));
+  std::vector<int64_t> toff(copies + 1), qoff(copies + 1);
+  for (int c = 0; c <= copies; ++c) {
+    toff[c] = (int64_t)c * n;
+    qoff[c] = (int64_t)c * per;
+  }
+  int64_t old_algo = 0, old_learned = 0;
+  (void)ss_get_option(SS_OPT_PLAN_ALGO, &old_algo);
+  (void)ss_get_option(SS_OPT_PLAN_LEARNED, &old_learned);
+  (void)ss_set_option(SS_OPT_PLAN_ALGO, algo);
+  (void)ss_set_option(SS_OPT_PLAN_LEARNED, learned);
+  ss_plan* plan = nullptr;
+  int rc = ss_multi_plan_create(static_cast<double*>(tb.p), toff.data(), copies, qoff.data(),
+                                &plan);
+  (void)ss_set_option(SS_OPT_PLAN_ALGO, old_algo);
+  (void)ss_set_option(SS_OPT_PLAN_LEARNED, old_learned);
+  if (rc != SS_OK) return rc;
+  int64_t summary[8] = {0};
+  std::vector<double> costs(2 * copies, -1.0);
+  rc = ss_plan_info(plan, SS_PLAN_SUMMARY, summary, 8);
+  if (rc == SS_OK) rc = ss_plan_info(plan, SS_PLAN_COSTS, costs.data(), 2 * copies);
+  // the targets: per of the cache-resident calibration targets, repeated
+  if (rc == SS_OK) {
+    hipError_t e = hipMalloc(&xb.p, sizeof(double) * per * copies);
+    for (int c = 0; c < copies && e == hipSuccess; ++c)
+      e = hipMemcpyAsync(static_cast<double*>(xb.p) + (int64_t)c * per, x, 8 * per,
+                         hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) rc = hip_fail(e, "calibration targets");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (rc == SS_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = fail(SS_ERR_HIP, "hipEventCreate");
+  const double* xd = static_cast<const double*>(xb.p);
+  // warm-up: 10 ms of this plan (plan creation left the device idle)
+  const auto w0 = std::chrono::steady_clock::now();
+  while (rc == SS_OK && std::chrono::steady_clock::now() - w0 < std::chrono::milliseconds(10)) {
+    for (int r = 0; r < 8 && rc == SS_OK; ++r) rc = ss_multi_search(plan, xd, out);
+    if (rc == SS_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(SS_ERR_HIP, "warm-up");
+  }
+  // the fastest of three rounds of 10 launches: short launches, so a
+  // round that meets other work on the device is discarded
+  double best_ms = -1;
+  for (int round = 0; round < 3 && rc == SS_OK; ++round) {
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 10 && rc == SS_OK; ++r) rc = ss_multi_search(plan, xd, out);
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (best_ms < 0 || ms < best_ms) best_ms = ms;
+  }
+  if (rc == SS_OK) {
+    res->ns = best_ms * 1e6 / 10 / ((double)per * copies);
+    res->max_k = (int)summary[6];
+    res->learned_ns = costs[1];
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  const std::string why = rc != SS_OK ? ss_last_error() : "";
+  (void)ss_plan_destroy(plan);  // clears the error state
+  return rc != SS_OK ? fail(rc, "calibration plan: " + why) : SS_OK;
+}
+
 // Runs the calibration microbenchmarks and installs the measured model.
 int calibrate() {
   DeviceInfo di;
@@ -373,7 +460,6 @@ int calibrate() {
   if (rc != SS_OK) return rc;
   hipStream_t st = current_stream();
   const int64_t big = (int64_t)1 << 27;    // 1 GiB of targets: HBM stream
-  const int64_t small = (int64_t)1 << 21;  // 16 MiB: stays in the last-level cache
   DevBuf xb, ob, tb;
   SS_TRY_HIP(hipMalloc(&xb.p, big * 8));
   SS_TRY_HIP(hipMalloc(&ob.p, big * 4));
@@ -393,67 +479,70 @@ int calibrate() {
   };
 
   TunerModel m = model_copy();
-  // 1. streaming bandwidth: a one-entry table makes the search trivial
+  // 1. streaming bandwidth: a one-entry table makes the search trivial.
+  // Clocks ramp up under load, so 60 ms of this stream come first and every
+  // timing below runs at steady clocks.
   double ns = 0;
   if ((rc = put_table(1)) != SS_OK) return rc;
+  const auto w0 = std::chrono::steady_clock::now();
+  while (std::chrono::steady_clock::now() - w0 < std::chrono::milliseconds(60)) {
+    for (int r = 0; r < 8 && rc == SS_OK; ++r)
+      rc = launch_single(tab, 1, x, big, out, SS_ALGO_BINARY, -1);
+    if (rc != SS_OK) return rc;
+    SS_TRY_HIP(hipStreamSynchronize(st));
+  }
   if ((rc = time_search(tab, 1, x, big, out, SS_ALGO_BINARY, -1, 3, &ns)) != SS_OK) return rc;
   m.stream_gbs = 12.0 / ns;
-  // 2. bisection on cache-resident targets
+  // The remaining terms decide plans, so they are measured with the plan
+  // kernel: 64 copies of one synthetic table, 64 Ki cache-resident targets
+  // each (32 MiB in all), every table forced to one kernel.
+  t_calibrating = true;
+  struct Guard {
+    ~Guard() { t_calibrating = false; }
+  } guard;
+  const int copies = 64;
+  const int64_t per = 1 << 16;
+  // 2. bisection over tables of 64..4096 entries
   std::vector<double> sx, sy;
   for (int n : {64, 256, 1024, 4096}) {
-    if ((rc = put_table(n)) != SS_OK) return rc;
-    if ((rc = time_search(tab, n, x, small, out, SS_ALGO_BINARY, -1, 10, &ns)) != SS_OK) return rc;
+    std::vector<double> h(n);
+    for (int i = 0; i < n; ++i) h[i] = std::exp2(32.0 * (i + 0.5) / n);
+    PlanTiming pt;
+    if ((rc = time_plan(h, copies, per, x, out, SS_ALGO_BINARY, 0, &pt)) != SS_OK) return rc;
     sx.push_back(bisect_steps(n));
-    sy.push_back(ns);
+    sy.push_back(pt.ns);
   }
   fit_line(sx, sy, &m.bin_base_ns, &m.bin_per_step_ns);
-  // 3. exponent hash at several longest-bin lengths (32 entries per binade)
+  // 3. exponent hash: 1024 entries in groups of k equal values, so that the
+  // longest bin is k at the bits the hash picks
   std::vector<double> kx, ky;
-  if ((rc = put_table(1024)) != SS_OK) return rc;
-  std::vector<double> h(1024);
-  for (int i = 0; i < 1024; ++i) h[i] = std::exp2(32.0 * (i + 0.5) / 1024);
-  for (int s : {2, 3, 4, 5, 6}) {
-    const int K = host_longest_bin(h.data(), 1024, s);
-    if (K > SS_SCAN_MAX) continue;
-    if ((rc = time_search(tab, 1024, x, small, out, SS_ALGO_EXPHASH, s, 10, &ns)) != SS_OK) return rc;
-    kx.push_back(K);
-    ky.push_back(ns);
+  for (int k : {1, 2, 4, 8}) {
+    std::vector<double> h(1024);
+    const int groups = 1024 / k;
+    for (int i = 0; i < 1024; ++i) h[i] = std::exp2(32.0 * (i / k + 0.5) / groups);
+    PlanTiming pt;
+    if ((rc = time_plan(h, copies, per, x, out, SS_ALGO_EXPHASH, 0, &pt)) != SS_OK) return rc;
+    if (pt.max_k < 1 || pt.max_k > SS_SCAN_MAX) continue;
+    kx.push_back(pt.max_k);
+    ky.push_back(pt.ns);
   }
   if (kx.size() >= 2) fit_line(kx, ky, &m.hash_base_ns, &m.hash_per_k_ns);
-  // 4. learned index: a model trained on the same 1024-entry table, searched
-  // on the cache-resident targets; its fixed cost is what remains after
-  // its lookup and window steps at the bisection's per-step cost
+  // 4. learned index: every copy given a model (trained at plan creation);
+  // its steps are LDS steps priced like the bisection's, the rest is its
+  // fixed cost.  The plan reports each table's modelled cost under the
+  // model in force, from which its step count is recovered.
   {
-    ss_mlp_opts o{300, 0.01f, 1};
-    ss_learned* lh = nullptr;
-    if ((rc = ss_learned_build(tab, 1024, &o, &lh)) != SS_OK) return rc;
-    double info[10];
-    rc = ss_learned_info(lh, info, 10);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (rc == SS_OK && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
-      rc = ss_learned_search(lh, x, small, out);  // warm-up
-      if (rc == SS_OK) (void)hipEventRecord(e0, st);
-      for (int r = 0; r < 10 && rc == SS_OK; ++r) rc = ss_learned_search(lh, x, small, out);
-      if (rc == SS_OK) {
-        (void)hipEventRecord(e1, st);
-        (void)hipEventSynchronize(e1);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ns = (double)ms * 1e6 / 10 / (double)small;
-        const int cells = (int)info[8], scan = (int)info[9], slots = (int)info[7];
-        const int lookup = cells > 0 ? 2 + scan : ceil_log2(slots) + 2;
-        // its steps are LDS steps like the bisection's: same per-step cost
-        m.learned_per_step_ns = m.bin_per_step_ns;
-        m.learned_base_ns = std::max(
-            0.0, ns - m.learned_per_step_ns * (learned_window_steps((int)info[0]) + lookup));
-      }
-    } else if (rc == SS_OK) {
-      rc = fail(SS_ERR_HIP, "hipEventCreate");
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    (void)ss_learned_destroy(lh);
-    if (rc != SS_OK) return rc;
+    std::vector<double> h(1024);
+    for (int i = 0; i < 1024; ++i) h[i] = std::exp2(32.0 * (i + 0.5) / 1024);
+    PlanTiming pt;
+    if ((rc = time_plan(h, copies, per, x, out, SS_ALGO_AUTO, 1, &pt)) != SS_OK) return rc;
+    const TunerModel cur = model_copy();
+    const double steps = cur.learned_per_step_ns > 0
+                             ? (pt.learned_ns - cur.learned_base_ns) / cur.learned_per_step_ns
+                             : 0.0;
+    m.learned_per_step_ns = m.bin_per_step_ns;
+    if (pt.learned_ns > 0 && steps > 0)
+      m.learned_base_ns = std::max(0.0, pt.ns - m.learned_per_step_ns * steps);
   }
   m.calibrated = 1;
   std::lock_guard<std::mutex> lk(g_tuner_mu);
