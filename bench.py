@@ -258,7 +258,8 @@ def plan_counts(binding, info) -> dict:
     algos = info["algos"]
     return {"learned_tables": int((algos == binding.ALGO_LEARNED).sum()),
             "exphash_tables": int((algos == binding.ALGO_EXPHASH).sum()),
-            "bisection_tables": int((algos == binding.ALGO_BINARY).sum())}
+            "bisection_tables": int((algos == binding.ALGO_BINARY).sum()),
+            "ballot_tables": int((algos == binding.ALGO_BALLOT).sum())}
 
 
 def with_options(binding, opts: dict, make):
@@ -566,6 +567,29 @@ def measure_batched(torch, binding, inputs, dev) -> dict:
         for t in range(batch.num_tables):
             binding.search_sorted_batch(tabs[t], x[qo[t]:qo[t + 1]], out[qo[t]:qo[t + 1]])
     res["per_table_launches"] = roof(m, time_call(torch, per_table, reps=2))
+    # the same tables with targets that arrive sorted (a smooth walk per
+    # table): the sampled plan measures each table's wave brackets on them
+    # and weighs the ballot scan
+    inputs.batched_smooth_targets(batch, out=host.numpy())
+    x.copy_(host)
+    smooth = {}
+    for name, mk, opts in (
+            ("tuned", make, {}),
+            ("sampled", lambda: binding.MultiPlan(d_tab, batch.table_off, batch.query_off,
+                                                  sample=x), {}),
+            ("ballot_forced", make, {binding.OPT_PLAN_ALGO: binding.ALGO_BALLOT})):
+        t0 = time.perf_counter()
+        plan = with_options(binding, opts, mk)
+        build_s = time.perf_counter() - t0
+        ms = time_call(torch, lambda: plan.search(x, out))
+        row = {**roof(m, ms), **plan_counts(binding, plan.info()), "build_s": round(build_s, 2)}
+        if name == "sampled":
+            br = plan.info()["brackets"]
+            row["mean_bracket"] = round(float(br[br >= 0].mean()), 2)
+        plan.close()
+        smooth[name] = row
+    res["smooth_targets"] = {"workload": "the same 512 tables; each table's targets one smooth "
+                                         "increasing walk over its range", **smooth}
     del x, out, host
     return res
 

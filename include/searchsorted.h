@@ -156,10 +156,10 @@ typedef enum {
                                     bisection; SS_ALGO_EXPHASH = the
                                     exponent hash at the tuner's best bin
                                     bits wherever it applies (bisection
-                                    elsewhere).  Learned models follow
+                                    elsewhere); SS_ALGO_BALLOT = the ballot
+                                    scan.  Learned models follow
                                     SS_OPT_PLAN_LEARNED unless this is
-                                    SS_ALGO_BINARY or SS_ALGO_EXPHASH, which
-                                    imply none */
+                                    not SS_ALGO_AUTO, which implies none */
     SS_OPT_PLAN_ORDER = 15       /* tile order of plans built afterwards:
                                     each segment's tiles go to workgroups of
                                     at most k tiles; 1 = contiguous ranges
@@ -306,6 +306,27 @@ SS_API int ss_multi_plan_create_learned(const double *tables, const int64_t *tab
                                         int32_t T, const int64_t *query_off,
                                         ss_learned *const *models, ss_plan **out);
 
+/* As ss_multi_plan_create, with sample targets that show how the searches'
+ * targets are distributed (paper Sec. 5.2: the best method depends on the
+ * data).  sample: device float64 [query_off[T]], laid out as the targets of
+ * ss_multi_search (the first batch to be searched, say); it is read during
+ * creation only.  For each table the plan measures, over 32 wave-sized
+ * groups of sample targets spread over its tiles (the targets one wave of
+ * the search kernel takes together), the mean number of table entries
+ * between the group's smallest and largest target, and the autotuner adds
+ * the ballot scan (SS_ALGO_BALLOT: a linear scan of that bracket, Sec. 2.1)
+ * as a candidate at its modelled cost for that bracket, against the
+ * bisection (tables the exponent hash does not take: negative entries, too
+ * many bins); the hash is kept where it applies.  Close targets (sorted or
+ * slowly varying streams) give narrow brackets; i.i.d. targets give
+ * brackets near the table's size, where it is never chosen.  Later
+ * searches may pass any targets: results are exact whatever the choice,
+ * but a ballot table searched with spread-out targets is slow.
+ * SS_PLAN_BRACKETS reports the measured brackets.  SYNCHRONOUS. */
+SS_API int ss_multi_plan_create_sampled(const double *tables, const int64_t *table_off,
+                                        int32_t T, const int64_t *query_off,
+                                        const double *sample, ss_plan **out);
+
 /* out_idx[k] = idx_t(targets[k]) for every k in [query_off[t], query_off[t+1]),
  * where idx_t is the operation defined at the top of this header applied to
  * table t.  targets: device float64 [query_off[T]]; out_idx: device int32,
@@ -364,6 +385,15 @@ SS_API int ss_pair_plan_create(const double *rho_tables, const int64_t *rho_off,
 SS_API int ss_pair_search(ss_plan *plan, const double *rho, const double *temp,
                           int32_t *out_rho, int32_t *out_t);
 
+/* As ss_pair_plan_create, with sample pairs (device float64 [pair_off[M]]
+ * each, laid out as the rho and temp arrays of ss_pair_search) from which
+ * the autotuner measures every density and temperature table's ballot
+ * bracket, as in ss_multi_plan_create_sampled.  SYNCHRONOUS. */
+SS_API int ss_pair_plan_create_sampled(const double *rho_tables, const int64_t *rho_off,
+                                       const double *t_tables, const int64_t *t_off, int32_t M,
+                                       const int64_t *pair_off, const double *sample_rho,
+                                       const double *sample_temp, ss_plan **out);
+
 /* Interpolation after the paired search (the step EOSPAC takes after it,
  * Sec. 1): material j also has a value grid F_j over its two axes, stored
  * row-major over (density, temperature) -- F_j[a][b] at
@@ -419,7 +449,7 @@ SS_API int ss_pair_plan_load(const char *path, const double *rho_tables, const i
 SS_API int ss_plan_fallbacks(ss_plan *plan, int64_t *count);
 
 /* What the autotuner chose, for inspection (host output):
- *   SS_PLAN_ALGOS  : int32 per table (ss_algo: binary, exphash or
+ *   SS_PLAN_ALGOS  : int32 per table (ss_algo: binary, exphash, ballot or
  *                    learned); paired plans list the density tables, then
  *                    the temperature tables
  *   SS_PLAN_BITS   : int32 per table (bin bits s, -1 for bisection)
@@ -431,12 +461,16 @@ SS_API int ss_plan_fallbacks(ss_plan *plan, int64_t *count);
  *                    the table's trained learned model (-1 if none was
  *                    trained); in tuner mode a trained table is learned
  *                    exactly when the second is the smaller
+ *   SS_PLAN_BRACKETS: 1 double per table: the mean ballot bracket measured
+ *                    on the sample targets of a sampled plan (-1: not
+ *                    sampled, or no targets)
  * `cap` is the number of elements `out` can hold. */
 typedef enum {
     SS_PLAN_ALGOS = 1,
     SS_PLAN_BITS = 2,
     SS_PLAN_SUMMARY = 3,
-    SS_PLAN_COSTS = 4
+    SS_PLAN_COSTS = 4,
+    SS_PLAN_BRACKETS = 5
 } ss_plan_query;
 SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
 
@@ -566,6 +600,10 @@ SS_API int ss_learned_destroy(ss_learned *h);
  *   learned index  learned_base + learned_per_step * (lookup + window(E)),
  *                  lookup = the model's piece lookup in LDS steps, window(E)
  *                  = floor(log2(2E + 1)) + 3 (bisection and its two checks)
+ *   ballot scan    ballot_base + ballot_per_entry * (B + ceil((n + 1) / 64)),
+ *                  B = the mean bracket measured on sample targets (sampled
+ *                  plans only, against the bisection; otherwise the target
+ *                  order is unknown and it is not a candidate)
  * In tuner mode a table is trained only when the learned cost at the best
  * possible bound (E = 1) undercuts its best plain kernel; after training the
  * measured E and lookup decide.  The model starts from built-in coefficients;
@@ -588,7 +626,8 @@ SS_API int ss_tuner_calibrate(void);
  * index fixed ns, calibrated flag, most bins per table entry}; with count >=
  * 10 also {tiles per workgroup for segments averaging under 64 tiles of 4096
  * targets, for longer segments}; with count >= 11 also {learned index ns per
- * LDS step}.  ss_tuner_set replaces the model with 8, 10 or 11 such values
+ * LDS step}; with count >= 13 also {ballot scan fixed ns, ballot scan ns per
+ * entry}.  ss_tuner_set replaces the model with 8, 10, 11 or 13 such values
  * (all finite and non-negative; bandwidth and bins per entry positive; tiles
  * in 1..4096). */
 SS_API int ss_tuner_get(double *coeffs, int count);

@@ -81,6 +81,8 @@ def _register_extra(L) -> None:
     sigs = {
         "ss_multi_plan_create": [P, P, I32, P, ctypes.POINTER(P)],
         "ss_multi_plan_create_learned": [P, P, I32, P, P, ctypes.POINTER(P)],
+        "ss_multi_plan_create_sampled": [P, P, I32, P, P, ctypes.POINTER(P)],
+        "ss_pair_plan_create_sampled": [P, P, P, P, I32, P, P, P, ctypes.POINTER(P)],
         "ss_multi_search": [P, P, P],
         "ss_plan_destroy": [P],
         "ss_plan_info": [P, I, P, I64],
@@ -231,7 +233,7 @@ def loghash_bins(table: torch.Tensor, nb: int):
 # plans: many tables (batched) and paired lookups
 # ---------------------------------------------------------------------------
 
-PLAN_ALGOS, PLAN_BITS, PLAN_SUMMARY, PLAN_COSTS = 1, 2, 3, 4
+PLAN_ALGOS, PLAN_BITS, PLAN_SUMMARY, PLAN_COSTS, PLAN_BRACKETS = 1, 2, 3, 4, 5
 SUMMARY_KEYS = ("tables", "tiles", "tiles_per_wg", "grid", "block", "lds_bytes",
                 "max_bin", "graph_uses")
 
@@ -288,16 +290,22 @@ class _Plan:
         out["bits"] = bits
         out["plain_ns"] = costs[0::2].copy()
         out["learned_ns"] = costs[1::2].copy()
+        brackets = np.zeros(T, dtype=np.float64)
+        check(lib().ss_plan_info(self._handle, PLAN_BRACKETS, _off_ptr(brackets), T))
+        out["brackets"] = brackets
         return out
 
 
 class MultiPlan(_Plan):
     """Many tables searched in one launch (see ss_multi_plan_create).  With
     models (a list of T LearnedIndex or None), each given model searches its
-    table (ss_multi_plan_create_learned); the plan copies the models."""
+    table (ss_multi_plan_create_learned); the plan copies the models.  With
+    sample (device float64 targets in the search layout) the tuner measures
+    the targets' spread per table and may choose the ballot scan
+    (ss_multi_plan_create_sampled)."""
 
     def __init__(self, tables: torch.Tensor, table_off, query_off, models=None,
-                 saved: str | None = None):
+                 saved: str | None = None, sample: torch.Tensor | None = None):
         _need(tables, torch.float64, "tables")
         self._toff = _host_offsets(table_off, "table_off")
         self._qoff = _host_offsets(query_off, "query_off")
@@ -312,6 +320,15 @@ class MultiPlan(_Plan):
             check(lib().ss_multi_plan_load(os.fsencode(saved), _ptr(tables), _off_ptr(self._toff),
                                            self.num_descriptors, _off_ptr(self._qoff),
                                            ctypes.byref(h)))
+        elif sample is not None:
+            if models is not None:
+                raise ValueError("sample and models cannot be combined")
+            _need(sample, torch.float64, "sample")
+            if sample.numel() != self.num_queries:
+                raise ValueError(f"expected {self.num_queries} sample targets")
+            check(lib().ss_multi_plan_create_sampled(_ptr(tables), _off_ptr(self._toff),
+                                                     self.num_descriptors, _off_ptr(self._qoff),
+                                                     _ptr(sample), ctypes.byref(h)))
         elif models is None:
             check(lib().ss_multi_plan_create(_ptr(tables), _off_ptr(self._toff),
                                              self.num_descriptors, _off_ptr(self._qoff),
@@ -364,10 +381,11 @@ def multi_search_noalloc(tables: torch.Tensor, table_off: torch.Tensor, query_of
 
 
 class PairPlan(_Plan):
-    """Paired density/temperature lookups per material (ss_pair_plan_create)."""
+    """Paired density/temperature lookups per material (ss_pair_plan_create;
+    with sample=(rho, temp), ss_pair_plan_create_sampled)."""
 
     def __init__(self, rho_tables: torch.Tensor, rho_off, t_tables: torch.Tensor, t_off,
-                 pair_off, saved: str | None = None):
+                 pair_off, saved: str | None = None, sample=None):
         _need(rho_tables, torch.float64, "rho_tables")
         _need(t_tables, torch.float64, "t_tables")
         self._roff = _host_offsets(rho_off, "rho_off")
@@ -387,6 +405,16 @@ class PairPlan(_Plan):
                                           _off_ptr(self._roff), _ptr(t_tables),
                                           _off_ptr(self._toff), M, _off_ptr(self._poff),
                                           ctypes.byref(h)))
+        elif sample is not None:
+            s_rho, s_t = sample
+            _need(s_rho, torch.float64, "sample rho")
+            _need(s_t, torch.float64, "sample temp")
+            if s_rho.numel() != self.num_queries or s_t.numel() != self.num_queries:
+                raise ValueError(f"expected {self.num_queries} sample pairs")
+            check(lib().ss_pair_plan_create_sampled(_ptr(rho_tables), _off_ptr(self._roff),
+                                                    _ptr(t_tables), _off_ptr(self._toff), M,
+                                                    _off_ptr(self._poff), _ptr(s_rho), _ptr(s_t),
+                                                    ctypes.byref(h)))
         else:
             check(lib().ss_pair_plan_create(_ptr(rho_tables), _off_ptr(self._roff),
                                             _ptr(t_tables), _off_ptr(self._toff), M,
@@ -418,7 +446,7 @@ class PairPlan(_Plan):
 
 TUNER_KEYS = ("stream_gbs", "hash_base_ns", "hash_per_k_ns", "bin_base_ns", "bin_per_step_ns",
               "learned_base_ns", "calibrated", "bins_per_entry", "tiles_short", "tiles_long",
-              "learned_per_step_ns")
+              "learned_per_step_ns", "ballot_base_ns", "ballot_per_entry_ns")
 
 
 class InterpPlan(PairPlan):

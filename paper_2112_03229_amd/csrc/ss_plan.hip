@@ -39,7 +39,7 @@ struct TableDesc {
   int64_t bins_off;  // first entry in the bin pool (exponent hash), else 0
   int64_t p_off;     // first float of its compiled model in the image pool (learned), else 0
   int n;
-  int algo;          // SS_ALGO_BINARY, SS_ALGO_EXPHASH or SS_ALGO_LEARNED
+  int algo;          // SS_ALGO_BINARY, SS_ALGO_EXPHASH, SS_ALGO_BALLOT or SS_ALGO_LEARNED
   int shift, kmin, kmaxc, nb, K;
   int E;             // learned: error bound
   float u0, inv;     // learned: input normalisation
@@ -110,9 +110,10 @@ struct MultiArgs {
 struct Staged {
   HashParams hp;   // exponent hash (hp.ok) ...
   int learned;     // ... or learned model (its image staged in LDS) ...
-  int n;           // ... or bisection
+  int n;           // ... or bisection ...
   int E;
   float u0, inv;
+  int ballot;      // ... or the ballot scan
 };
 
 // Copies one table (+inf padded) and, for the exponent hash, its bin table
@@ -125,7 +126,7 @@ __device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* _
                                              uint16_t* C, float* model) {
   stage_table(sa, tables + d.tab_off, d.n);
   Staged st{{0, d.shift, d.kmin, d.kmaxc, d.nb, d.K}, d.algo == SS_ALGO_LEARNED, d.n, d.E,
-            d.u0, d.inv};
+            d.u0, d.inv, d.algo == SS_ALGO_BALLOT};
   if (d.algo == SS_ALGO_LEARNED) stage_image(model, params + d.p_off);
   if (d.algo == SS_ALGO_EXPHASH) {
     st.hp.ok = 1;
@@ -152,6 +153,7 @@ __device__ __forceinline__ void search_staged(const Staged& st, const double* sa
     }
   }
   if (st.hp.ok) search_exphash<Q>(sa, C, st.n, st.hp, x, r);
+  else if (st.ballot) search_ballot<Q>(sa, st.n, x, r);  // every lane of the wave takes it
   else search_binary<Q>(sa, st.n, x, r);
 }
 
@@ -406,6 +408,77 @@ __global__ __launch_bounds__(256) void plan_bins_kernel(const double* __restrict
   if (threadIdx.x == 0) k_out[t] = hp.K;
 }
 
+// One table's searches as a sample for the ballot scan's cost: the table
+// (device), its target array and the targets [q0, q1) searched in it.
+struct BracketJob {
+  const double* tab;
+  const double* x;
+  int64_t q0, q1;
+  int n;
+  int pad_;
+};
+
+// The ballot scan's work per wave on sample targets: for each job (one
+// workgroup), `samples` wave footprints spread evenly over its tiles.  The
+// footprint of wave slot w of tile b is what one wave of the plan kernel
+// searches together: targets b * per_tile + w * 64 + lane + j * nt, j < Q,
+// inside [q0, q1).  Its bracket is #{a < max} - #{a < min} over those
+// targets (NaN ignored), the entries each lane then scans.  Writes the mean
+// bracket per job, -1 for a job without targets.
+__global__ __launch_bounds__(256) void plan_bracket_kernel(const BracketJob* jobs, int nt, int Q,
+                                                           int64_t per_tile, int samples,
+                                                           double* mean_out) {
+  __shared__ double sum;
+  __shared__ int count;
+  const BracketJob jb = jobs[blockIdx.x];
+  if (threadIdx.x == 0) {
+    sum = 0;
+    count = 0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  const int slots = max(nt / 64, 1);
+  if (jb.q1 > jb.q0) {
+    const int64_t b0 = jb.q0 / per_tile, b1 = (jb.q1 - 1) / per_tile;
+    const int64_t tiles = b1 - b0 + 1;
+    for (int f = wave; f < samples; f += waves) {
+      const int64_t b = b0 + (int64_t)f * tiles / samples;
+      const int64_t base = b * per_tile + (int64_t)(f % slots) * 64 + lane;
+      double lo = __builtin_nan(""), hi = __builtin_nan("");
+      for (int j = 0; j < Q; ++j) {
+        const int64_t k = base + (int64_t)j * nt;
+        if (k >= jb.q0 && k < jb.q1) {
+          const double v = jb.x[k];
+          lo = fmin(lo, v);
+          hi = fmax(hi, v);
+        }
+      }
+      const double wmin = wave_min(lo), wmax = wave_max(hi);
+      if (lane == 0 && wmin == wmin) {  // some target of the footprint is a number
+        int c[2];
+        const double v[2] = {wmin, wmax};
+        for (int e = 0; e < 2; ++e) {  // #{a < v} by bisection over the table
+          int first = 0, len = jb.n;
+          while (len > 0) {
+            const int half = len >> 1;
+            if (jb.tab[first + half] < v[e]) {
+              first += half + 1;
+              len -= half + 1;
+            } else {
+              len = half;
+            }
+          }
+          c[e] = first;
+        }
+        atomicAdd(&sum, (double)(c[1] - c[0]));
+        atomicAdd(&count, 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) mean_out[blockIdx.x] = count > 0 ? sum / count : -1.0;
+}
+
 }  // namespace ss
 
 // ---------------------------------------------------------------------------
@@ -442,6 +515,8 @@ struct ss_plan {
   int tiles_per_wg = 0;
   bool strided = false;
   std::vector<std::vector<float>> weights;  // per descriptor: a learned table's parameters
+  std::vector<double> brackets;             // per descriptor: mean ballot bracket on the
+                                            // sample targets (-1: not sampled)
   int preset_tiles = 0;                     // from a saved plan: tiles per workgroup,
   int preset_order = -1;                    // tile order (SS_OPT_PLAN_ORDER value) and
   int preset_conv = -1;                     // convention, else -1 / 0 (options decide)
@@ -548,6 +623,74 @@ struct PlanPreset {
   std::vector<std::vector<float>> weights;
 };
 
+// Block size and targets per lane of a plan of this form.
+int plan_block() {
+  return option(SS_OPT_BLOCK_SIZE) > 0 ? (int)option(SS_OPT_BLOCK_SIZE) : kPlanBlock;
+}
+int plan_q(int mode) { return mode == kPairJoint || mode == kPairInterp ? kPairQ : kPlanQ; }
+
+// Wave footprints sampled per table for the ballot scan's bracket.
+constexpr int kBracketSamples = 32;
+
+// Mean ballot bracket of every job on its sample targets, with the tile
+// shape of a plan of this form (-1 for a job without targets).
+// SYNCHRONOUS on the current stream.
+int sample_brackets(const std::vector<BracketJob>& jobs, int mode, std::vector<double>* mean) {
+  mean->assign(jobs.size(), -1.0);
+  if (jobs.empty()) return SS_OK;
+  hipStream_t st = current_stream();
+  void* dj = nullptr;
+  void* dm = nullptr;
+  hipError_t e = hipMalloc(&dj, sizeof(BracketJob) * jobs.size());
+  if (e == hipSuccess) e = hipMalloc(&dm, sizeof(double) * jobs.size());
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dj, jobs.data(), sizeof(BracketJob) * jobs.size(), hipMemcpyHostToDevice,
+                       st);
+  if (e == hipSuccess) {
+    const int nt = plan_block(), Q = plan_q(mode);
+    hipLaunchKernelGGL(plan_bracket_kernel, dim3((unsigned)jobs.size()), dim3(256), 0, st,
+                       static_cast<const BracketJob*>(dj), nt, Q, (int64_t)nt * Q,
+                       kBracketSamples, static_cast<double*>(dm));
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(mean->data(), dm, sizeof(double) * jobs.size(), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (dj) (void)hipFree(dj);
+  if (dm) (void)hipFree(dm);
+  return e == hipSuccess ? SS_OK : hip_fail(e, "ballot bracket sampling");
+}
+
+// Turns a tuned choice into the ballot scan, at its modelled cost for the
+// sampled bracket (unknown, -1: a full scan of the table).
+void make_ballot(const TunerModel& model, double bracket, TunedTable* t) {
+  t->algo = SS_ALGO_BALLOT;
+  t->bits = -1;
+  t->kmin = t->kmaxc = t->nb = t->K = 0;
+  t->est_ns = ballot_cost_ns(model, bracket >= 0 ? bracket : (double)t->n, t->n);
+}
+
+// The per-table choice with sampled targets: SS_OPT_PLAN_ALGO forcing the
+// ballot scan takes it everywhere; the tuner weighs it against the
+// bisection only, where its modelled cost for the sampled bracket is lower.
+// Against the exponent hash it never won in a plan: measured on MI355X with
+// 256 tables of 16 / 48 / 128 / 400 entries and 2.8e6 sorted targets each
+// (brackets of 0.02 to 0.5 entries), the hash took 1.370 / 1.370 / 1.383 /
+// 1.384 ms, the ballot scan 1.419 / 1.421 / 1.413 / 1.389 and the bisection
+// 1.404 / 1.377 / 1.375 / 1.435.  Both searches are far below the memory
+// time there; the ballot scan's two wave-wide reductions per tile add
+// latency that the hash does not have.  With i.i.d. targets the ballot scan
+// took 1.55 / 2.72 / 6.17 / 18.2 ms.
+void consider_ballot(const TunerModel& model, double bracket, int force, TunedTable* t) {
+  if (t->n < 1) return;
+  if (force == SS_ALGO_BALLOT) {
+    make_ballot(model, bracket, t);
+    return;
+  }
+  if (force != SS_ALGO_AUTO || !(bracket >= 0) || t->algo != SS_ALGO_BINARY) return;
+  if (ballot_cost_ns(model, bracket, t->n) < t->est_ns * (1.0 - 1e-9)) make_ballot(model, bracket, t);
+}
+
 // The saved choice for one table, re-derived from the table as it is now:
 // the exponent hash at the saved bits if it still applies within the LDS
 // budget (its bin parameters and longest bin recomputed from the entries),
@@ -556,6 +699,11 @@ struct PlanPreset {
 TunedTable preset_table(const TunerModel& model, const double* a, int n, size_t budget,
                         int algo, int bits) {
   if (algo == SS_ALGO_BINARY) return tune_table(model, a, n, budget, SS_ALGO_BINARY);
+  if (algo == SS_ALGO_BALLOT && n >= 1) {
+    TunedTable t = tune_table(model, a, n, budget, SS_ALGO_BINARY);
+    make_ballot(model, -1.0, &t);
+    return t;
+  }
   if (algo == SS_ALGO_EXPHASH && bits >= 0 && bits <= SS_MAX_BITS && n >= 1 && n <= 65535) {
     TunedTable t = tune_table(model, a, n, budget, SS_ALGO_EXPHASH);
     if (t.algo == SS_ALGO_EXPHASH && t.bits == bits) return t;
@@ -788,10 +936,10 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
     p->max_k = std::max(p->max_k, k[t]);
   }
 
-  p->block = option(SS_OPT_BLOCK_SIZE) > 0 ? (int)option(SS_OPT_BLOCK_SIZE) : kPlanBlock;
+  p->block = plan_block();
   // learned plans take the same targets per lane as plain ones (measured
   // on the batched and split forms: 8 beat 4, 2 and 1)
-  p->q = p->mode == kPairJoint || p->mode == kPairInterp ? kPairQ : kPlanQ;
+  p->q = plan_q(p->mode);
   const int64_t per_tile = (int64_t)p->block * p->q;
   // tiles of every segment, numbered back to back; a segment's positions are
   // taken relative to the start of its own target array
@@ -985,7 +1133,7 @@ extern "C" {
 // learned models, else SS_OPT_PLAN_LEARNED may train them.
 static int create_batched(const double* tables, const int64_t* table_off, int32_t T,
                           const int64_t* query_off, ss_learned* const* models, ss_plan** out,
-                          const PlanPreset* preset = nullptr) {
+                          const PlanPreset* preset = nullptr, const double* sample = nullptr) {
   clear_error();
   if (!out) return fail(SS_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
@@ -997,6 +1145,10 @@ static int create_batched(const double* tables, const int64_t* table_off, int32_
   if ((rc = check_span(tables, total_n, sizeof(double), alignof(double), "tables")) != SS_OK)
     return rc;
   if (total_n > 0 && (rc = check_device_ptr(tables, "tables")) != SS_OK) return rc;
+  if (sample && query_off[T] > 0 &&
+      ((rc = check_span(sample, query_off[T], 8, 8, "sample")) != SS_OK ||
+       (rc = check_device_ptr(sample, "sample")) != SS_OK))
+    return rc;
 
   std::vector<double> host(total_n);
   if (total_n > 0) {
@@ -1031,13 +1183,27 @@ static int create_batched(const double* tables, const int64_t* table_off, int32_
   if (max_tab > kPlanLdsBudget)
     return fail_delete(p, "a table exceeds the 48 KB LDS staging budget (6136 entries)",
                        SS_ERR_UNSUPPORTED);
+  const int force = (int)option(SS_OPT_PLAN_ALGO);
+  p->brackets.assign(T, -1.0);
+  if (sample && !preset) {
+    std::vector<BracketJob> jobs(T);
+    for (int t = 0; t < T; ++t)
+      jobs[t] = {tables + table_off[t], sample, query_off[t], query_off[t + 1],
+                 (int)(table_off[t + 1] - table_off[t]), 0};
+    if ((rc = sample_brackets(jobs, kBatched, &p->brackets)) != SS_OK)
+      return fail_delete(p, nullptr, rc);
+  }
   int64_t pool = 0;
   for (int t = 0; t < T; ++t) {
     const int n = (int)(table_off[t + 1] - table_off[t]);
-    p->tuned[t] = preset ? preset_table(model, host.data() + table_off[t], n,
-                                        kPlanLdsBudget - max_tab, preset->algo[t], preset->bits[t])
-                         : tune_table(model, host.data() + table_off[t], n,
-                                      kPlanLdsBudget - max_tab, (int)option(SS_OPT_PLAN_ALGO));
+    if (preset) {
+      p->tuned[t] = preset_table(model, host.data() + table_off[t], n, kPlanLdsBudget - max_tab,
+                                 preset->algo[t], preset->bits[t]);
+    } else {
+      p->tuned[t] = tune_table(model, host.data() + table_off[t], n, kPlanLdsBudget - max_tab,
+                               force);
+      consider_ballot(model, p->brackets[t], force, &p->tuned[t]);
+    }
     describe(p->tuned[t], table_off[t], &p->desc[t], &pool);
     if (p->tuned[t].algo == SS_ALGO_EXPHASH)
       max_bins = std::max(max_bins, align16((size_t)(p->tuned[t].nb + 1) * 2));
@@ -1063,6 +1229,16 @@ static int create_batched(const double* tables, const int64_t* table_off, int32_
 int ss_multi_plan_create(const double* tables, const int64_t* table_off, int32_t T,
                          const int64_t* query_off, ss_plan** out) {
   return create_batched(tables, table_off, T, query_off, nullptr, out);
+}
+
+int ss_multi_plan_create_sampled(const double* tables, const int64_t* table_off, int32_t T,
+                                 const int64_t* query_off, const double* sample,
+                                 ss_plan** out) {
+  if (!sample) {
+    clear_error();
+    return fail(SS_ERR_INVALID_ARG, "sample is null");
+  }
+  return create_batched(tables, table_off, T, query_off, nullptr, out, nullptr, sample);
 }
 
 int ss_multi_plan_create_learned(const double* tables, const int64_t* table_off, int32_t T,
@@ -1100,7 +1276,8 @@ namespace {
 // values: the interpolation form's value grids, else null).
 int create_paired(const double* rho_tables, const int64_t* rho_off, const double* t_tables,
                   const int64_t* t_off, int32_t M, const int64_t* pair_off, int mode,
-                  const double* values, ss_plan** out, const PlanPreset* preset = nullptr) {
+                  const double* values, ss_plan** out, const PlanPreset* preset = nullptr,
+                  const double* sample_rho = nullptr, const double* sample_t = nullptr) {
   if (!out) return fail(SS_ERR_INVALID_ARG, "out is null");
   *out = nullptr;
   if (M < 1 || M > (1 << 20)) return fail(SS_ERR_INVALID_ARG, "M must be in 1..2^20");
@@ -1113,6 +1290,12 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
   if ((rc = check_span(t_tables, ntt, 8, 8, "t_tables")) != SS_OK) return rc;
   if (nr > 0 && (rc = check_device_ptr(rho_tables, "rho_tables")) != SS_OK) return rc;
   if (ntt > 0 && (rc = check_device_ptr(t_tables, "t_tables")) != SS_OK) return rc;
+  if (sample_rho && pair_off[M] > 0 &&
+      ((rc = check_span(sample_rho, pair_off[M], 8, 8, "sample_rho")) != SS_OK ||
+       (rc = check_span(sample_t, pair_off[M], 8, 8, "sample_temp")) != SS_OK ||
+       (rc = check_device_ptr(sample_rho, "sample_rho")) != SS_OK ||
+       (rc = check_device_ptr(sample_t, "sample_temp")) != SS_OK))
+    return rc;
   std::vector<double> hr(nr), ht(ntt);
   hipStream_t st = current_stream();
   if (nr > 0) SS_TRY_HIP(hipMemcpyAsync(hr.data(), rho_tables, 8 * nr, hipMemcpyDeviceToHost, st));
@@ -1205,20 +1388,41 @@ int create_paired(const double* rho_tables, const int64_t* rho_off, const double
   }
   int64_t pool = 0;
   const int force = (int)option(SS_OPT_PLAN_ALGO);
+  // both axes' searches of material j cover the pairs [pair_off[j], pair_off[j + 1])
+  p->brackets.assign(2 * M, -1.0);
+  if (sample_rho && !preset) {
+    std::vector<BracketJob> jobs(2 * M);
+    for (int j = 0; j < M; ++j) {
+      jobs[j] = {rho_tables + rho_off[j], sample_rho, pair_off[j], pair_off[j + 1],
+                 (int)(rho_off[j + 1] - rho_off[j]), 0};
+      jobs[M + j] = {t_tables + t_off[j], sample_t, pair_off[j], pair_off[j + 1],
+                     (int)(t_off[j + 1] - t_off[j]), 0};
+    }
+    if ((rc = sample_brackets(jobs, mode, &p->brackets)) != SS_OK)
+      return fail_delete(p, nullptr, rc);
+  }
   for (int j = 0; j < M; ++j) {
     const int n = (int)(rho_off[j + 1] - rho_off[j]);
-    p->tuned[j] = preset ? preset_table(model, hr.data() + rho_off[j], n, budget_a,
-                                        preset->algo[j], preset->bits[j])
-                         : tune_table(model, hr.data() + rho_off[j], n, budget_a, force);
+    if (preset) {
+      p->tuned[j] = preset_table(model, hr.data() + rho_off[j], n, budget_a, preset->algo[j],
+                                 preset->bits[j]);
+    } else {
+      p->tuned[j] = tune_table(model, hr.data() + rho_off[j], n, budget_a, force);
+      consider_ballot(model, p->brackets[j], force, &p->tuned[j]);
+    }
     describe(p->tuned[j], rho_off[j], &p->desc[j], &pool);
     if (p->tuned[j].algo == SS_ALGO_EXPHASH)
       bins_a = std::max(bins_a, align16((size_t)(p->tuned[j].nb + 1) * 2));
   }
   for (int j = 0; j < M; ++j) {
     const int n = (int)(t_off[j + 1] - t_off[j]);
-    p->tuned[M + j] = preset ? preset_table(model, ht.data() + t_off[j], n, budget_b,
-                                            preset->algo[M + j], preset->bits[M + j])
-                             : tune_table(model, ht.data() + t_off[j], n, budget_b, force);
+    if (preset) {
+      p->tuned[M + j] = preset_table(model, ht.data() + t_off[j], n, budget_b,
+                                     preset->algo[M + j], preset->bits[M + j]);
+    } else {
+      p->tuned[M + j] = tune_table(model, ht.data() + t_off[j], n, budget_b, force);
+      consider_ballot(model, p->brackets[M + j], force, &p->tuned[M + j]);
+    }
     describe(p->tuned[M + j], t_off[j], &p->desc[M + j], &pool);
     if (p->tuned[M + j].algo == SS_ALGO_EXPHASH)
       bins_b = std::max(bins_b, align16((size_t)(p->tuned[M + j].nb + 1) * 2));
@@ -1268,6 +1472,17 @@ int ss_pair_plan_create(const double* rho_tables, const int64_t* rho_off, const 
   clear_error();
   return create_paired(rho_tables, rho_off, t_tables, t_off, M, pair_off,
                        option(SS_OPT_PAIR_JOINT) ? kPairJoint : kPairSplit, nullptr, out);
+}
+
+int ss_pair_plan_create_sampled(const double* rho_tables, const int64_t* rho_off,
+                                const double* t_tables, const int64_t* t_off, int32_t M,
+                                const int64_t* pair_off, const double* sample_rho,
+                                const double* sample_temp, ss_plan** out) {
+  clear_error();
+  if (!sample_rho || !sample_temp) return fail(SS_ERR_INVALID_ARG, "a sample array is null");
+  return create_paired(rho_tables, rho_off, t_tables, t_off, M, pair_off,
+                       option(SS_OPT_PAIR_JOINT) ? kPairJoint : kPairSplit, nullptr, out,
+                       nullptr, sample_rho, sample_temp);
 }
 
 int ss_interp_plan_create(const double* rho_tables, const int64_t* rho_off,
@@ -1486,6 +1701,12 @@ int ss_plan_info(const ss_plan* p, int what, void* out, int64_t cap) {
       for (int t = 0; t < p->T; ++t)
         o[t] = what == SS_PLAN_ALGOS ? p->tuned[t].algo
                                      : (p->tuned[t].algo == SS_ALGO_EXPHASH ? p->tuned[t].bits : -1);
+      return SS_OK;
+    }
+    case SS_PLAN_BRACKETS: {
+      if (cap < p->T) return fail(SS_ERR_INVALID_ARG, "cap smaller than the table count");
+      double* o = static_cast<double*>(out);
+      for (int t = 0; t < p->T; ++t) o[t] = t < (int)p->brackets.size() ? p->brackets[t] : -1.0;
       return SS_OK;
     }
     case SS_PLAN_COSTS: {

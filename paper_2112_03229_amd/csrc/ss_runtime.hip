@@ -228,9 +228,11 @@ int ss_set_option(int opt, int64_t v) {
       ss::g_convention = v;
       return SS_OK;
     case SS_OPT_PLAN_ALGO:
-      if (v != SS_ALGO_AUTO && v != SS_ALGO_BINARY && v != SS_ALGO_EXPHASH)
+      if (v != SS_ALGO_AUTO && v != SS_ALGO_BINARY && v != SS_ALGO_EXPHASH &&
+          v != SS_ALGO_BALLOT)
         return ss::fail(SS_ERR_INVALID_ARG,
-                        "SS_OPT_PLAN_ALGO: SS_ALGO_AUTO, SS_ALGO_BINARY or SS_ALGO_EXPHASH");
+                        "SS_OPT_PLAN_ALGO: SS_ALGO_AUTO, SS_ALGO_BINARY, SS_ALGO_EXPHASH or "
+                        "SS_ALGO_BALLOT");
       ss::g_plan_algo = v;
       return SS_OK;
     case SS_OPT_PLAN_ORDER:

@@ -26,8 +26,16 @@ struct TunerModel {
                                      // (each workgroup copies its bins)
   double tiles_short = 5;            // target tiles (of 4096) per plan workgroup
   double tiles_long = 5;             // for segments averaging under / over 64 tiles
+  double ballot_base_ns = 2.0e-3;    // ballot scan: wave bracket and select
+  double ballot_per_entry_ns = 0.5e-3;  // per iteration of its bracket scan or
+                                        // of its 64-entry ballot pass
   int calibrated = 0;                // 1 once measured on this device
 };
+
+// Modelled compute cost (ns per query) of the ballot scan on a table of n
+// entries whose waves' targets span `bracket` entries on average (the
+// per-lane scan) after ceil((n + 1) / 64) ballot steps.
+double ballot_cost_ns(const TunerModel& model, double bracket, int n);
 
 // Modelled compute cost (ns per query) of the learned index with error bound
 // E and a model whose piece lookup takes `lookup_steps` LDS steps.
@@ -39,7 +47,7 @@ int learned_window_steps(int E);
 
 struct TunedTable {
   int n = 0;
-  int algo = 1;        // SS_ALGO_BINARY or SS_ALGO_EXPHASH (or SS_ALGO_LEARNED)
+  int algo = 1;        // SS_ALGO_BINARY, SS_ALGO_EXPHASH, SS_ALGO_BALLOT or SS_ALGO_LEARNED
   int bits = -1;       // s for the exponent hash
   int kmin = 0, kmaxc = 0, nb = 0;
   int K = 0;           // longest bin (exact)

@@ -111,11 +111,14 @@ int load_file(const char* path, TunerModel* m, std::string* arch) {
       !parse_key(text, "bins_per_entry", &t.bins_per_entry) ||
       !parse_key(text, "tiles_short", &t.tiles_short) ||
       !parse_key(text, "tiles_long", &t.tiles_long) ||
+      !parse_key(text, "ballot_base_ns", &t.ballot_base_ns) ||
+      !parse_key(text, "ballot_per_entry_ns", &t.ballot_per_entry_ns) ||
       !parse_key(text, "hip_runtime", &runtime) || !parse_key(text, "calibrated", &cal))
     return fail(SS_ERR_INVALID_ARG, std::string("malformed tuner cache ") + path);
   if (!(t.stream_gbs > 0) || !(t.hash_base_ns >= 0) || !(t.bin_per_step_ns >= 0) ||
-      !(t.learned_base_ns >= 0) || !(t.learned_per_step_ns >= 0) || !(t.bins_per_entry > 0) || !(t.tiles_short >= 1) ||
-      !(t.tiles_long >= 1) || t.tiles_short > 4096 || t.tiles_long > 4096)
+      !(t.learned_base_ns >= 0) || !(t.learned_per_step_ns >= 0) || !(t.bins_per_entry > 0) ||
+      !(t.tiles_short >= 1) || !(t.tiles_long >= 1) || t.tiles_short > 4096 ||
+      t.tiles_long > 4096 || !(t.ballot_base_ns >= 0) || !(t.ballot_per_entry_ns >= 0))
     return fail(SS_ERR_INVALID_ARG, std::string("implausible tuner cache ") + path);
   t.calibrated = cal != 0;
   std::string a;
@@ -163,11 +166,13 @@ int save_model(const char* path) {
                "  \"bin_base_ns\": %.17g,\n  \"bin_per_step_ns\": %.17g,\n"
                "  \"learned_base_ns\": %.17g,\n  \"learned_per_step_ns\": %.17g,\n"
                "  \"bins_per_entry\": %.17g,\n"
-               "  \"tiles_short\": %.17g,\n  \"tiles_long\": %.17g,\n  \"calibrated\": %d\n}\n",
+               "  \"tiles_short\": %.17g,\n  \"tiles_long\": %.17g,\n"
+               "  \"ballot_base_ns\": %.17g,\n  \"ballot_per_entry_ns\": %.17g,\n"
+               "  \"calibrated\": %d\n}\n",
                arch.c_str(), runtime_version(), m.stream_gbs, m.hash_base_ns, m.hash_per_k_ns,
                m.bin_base_ns, m.bin_per_step_ns, m.learned_base_ns, m.learned_per_step_ns,
-               m.bins_per_entry,
-               m.tiles_short, m.tiles_long, m.calibrated);
+               m.bins_per_entry, m.tiles_short, m.tiles_long, m.ballot_base_ns,
+               m.ballot_per_entry_ns, m.calibrated);
   const bool ok = std::fclose(f) == 0;
   return ok ? SS_OK : fail(SS_ERR_INVALID_ARG, std::string("cannot write ") + path);
 }
@@ -215,6 +220,11 @@ TunerModel tuner_model() {
 double learned_cost_ns(const TunerModel& model, int E, int lookup_steps) {
   return model.learned_base_ns +
          model.learned_per_step_ns * (learned_window_steps(E) + lookup_steps);
+}
+
+double ballot_cost_ns(const TunerModel& model, double bracket, int n) {
+  return model.ballot_base_ns +
+         model.ballot_per_entry_ns * (std::max(bracket, 0.0) + (double)((n + 64) / 64));
 }
 
 int learned_window_steps(int E) {
@@ -379,10 +389,13 @@ struct PlanTiming {
   double ns = 0;
   int max_k = 0;
   double learned_ns = -1;
+  double bracket = -1;
 };
 
+// sampled: the plan is created with its own targets as the sample, and the
+// first table's measured ballot bracket is reported.
 int time_plan(const std::vector<double>& h, int copies, int64_t per, const double* x,
-              int32_t* out, int algo, int learned, PlanTiming* res) {
+              int32_t* out, int algo, int learned, PlanTiming* res, bool sampled = false) {
   hipStream_t st = current_stream();
   const int n = (int)h.size();
   DevBuf tb, xb;
@@ -390,6 +403,12 @@ int time_plan(const std::vector<double>& h, int copies, int64_t per, const doubl
   for (int c = 0; c < copies; ++c)
     SS_TRY_HIP(hipMemcpyAsync(static_cast<double*>(tb.p) + (int64_t)c * n, h.data(), 8 * n,
                               hipMemcpyHostToDevice, st));
+  // the targets: per of the cache-resident calibration targets, repeated
+  SS_TRY_HIP(hipMalloc(&xb.p, sizeof(double) * per * copies));
+  for (int c = 0; c < copies; ++c)
+    SS_TRY_HIP(hipMemcpyAsync(static_cast<double*>(xb.p) + (int64_t)c * per, x, 8 * per,
+                              hipMemcpyDeviceToDevice, st));
+  const double* xd = static_cast<const double*>(xb.p);
   std::vector<int64_t> toff(copies + 1), qoff(copies + 1);
   for (int c = 0; c <= copies; ++c) {
     toff[c] = (int64_t)c * n;
@@ -401,27 +420,21 @@ int time_plan(const std::vector<double>& h, int copies, int64_t per, const doubl
   (void)ss_set_option(SS_OPT_PLAN_ALGO, algo);
   (void)ss_set_option(SS_OPT_PLAN_LEARNED, learned);
   ss_plan* plan = nullptr;
-  int rc = ss_multi_plan_create(static_cast<double*>(tb.p), toff.data(), copies, qoff.data(),
-                                &plan);
+  int rc = sampled ? ss_multi_plan_create_sampled(static_cast<double*>(tb.p), toff.data(), copies,
+                                                  qoff.data(), xd, &plan)
+                   : ss_multi_plan_create(static_cast<double*>(tb.p), toff.data(), copies,
+                                          qoff.data(), &plan);
   (void)ss_set_option(SS_OPT_PLAN_ALGO, old_algo);
   (void)ss_set_option(SS_OPT_PLAN_LEARNED, old_learned);
   if (rc != SS_OK) return rc;
   int64_t summary[8] = {0};
-  std::vector<double> costs(2 * copies, -1.0);
+  std::vector<double> costs(2 * copies, -1.0), brackets(copies, -1.0);
   rc = ss_plan_info(plan, SS_PLAN_SUMMARY, summary, 8);
   if (rc == SS_OK) rc = ss_plan_info(plan, SS_PLAN_COSTS, costs.data(), 2 * copies);
-  // the targets: per of the cache-resident calibration targets, repeated
-  if (rc == SS_OK) {
-    hipError_t e = hipMalloc(&xb.p, sizeof(double) * per * copies);
-    for (int c = 0; c < copies && e == hipSuccess; ++c)
-      e = hipMemcpyAsync(static_cast<double*>(xb.p) + (int64_t)c * per, x, 8 * per,
-                         hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) rc = hip_fail(e, "calibration targets");
-  }
+  if (rc == SS_OK) rc = ss_plan_info(plan, SS_PLAN_BRACKETS, brackets.data(), copies);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (rc == SS_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = fail(SS_ERR_HIP, "hipEventCreate");
-  const double* xd = static_cast<const double*>(xb.p);
   // warm-up: 10 ms of this plan (plan creation left the device idle)
   const auto w0 = std::chrono::steady_clock::now();
   while (rc == SS_OK && std::chrono::steady_clock::now() - w0 < std::chrono::milliseconds(10)) {
@@ -444,6 +457,7 @@ int time_plan(const std::vector<double>& h, int copies, int64_t per, const doubl
     res->ns = best_ms * 1e6 / 10 / ((double)per * copies);
     res->max_k = (int)summary[6];
     res->learned_ns = costs[1];
+    res->bracket = brackets[0];
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -544,6 +558,29 @@ int calibrate() {
     if (pt.learned_ns > 0 && steps > 0)
       m.learned_base_ns = std::max(0.0, pt.ns - m.learned_per_step_ns * steps);
   }
+  // 5. ballot scan: sorted targets over tables of 64, 256 and 1024 entries
+  // (a wave's targets then span about n / 18 entries), its bracket measured
+  // by the plan on those targets; ballot steps are priced like scan steps
+  {
+    std::vector<double> hs(per);
+    for (int64_t i = 0; i < per; ++i) hs[i] = std::exp2(32.0 * ((double)i + 0.5) / (double)per);
+    DevBuf sx;
+    SS_TRY_HIP(hipMalloc(&sx.p, 8 * per));
+    SS_TRY_HIP(hipMemcpyAsync(sx.p, hs.data(), 8 * per, hipMemcpyHostToDevice, st));
+    std::vector<double> bx, by;
+    for (int n : {64, 256, 1024}) {
+      std::vector<double> h(n);
+      for (int i = 0; i < n; ++i) h[i] = std::exp2(32.0 * (i + 0.5) / n);
+      PlanTiming pt;
+      if ((rc = time_plan(h, copies, per, static_cast<const double*>(sx.p), out, SS_ALGO_BALLOT,
+                          0, &pt, true)) != SS_OK)
+        return rc;
+      if (pt.bracket < 0) continue;
+      bx.push_back(pt.bracket + (double)((n + 64) / 64));
+      by.push_back(pt.ns);
+    }
+    if (bx.size() >= 2) fit_line(bx, by, &m.ballot_base_ns, &m.ballot_per_entry_ns);
+  }
   m.calibrated = 1;
   std::lock_guard<std::mutex> lk(g_tuner_mu);
   g_model = m;
@@ -581,6 +618,10 @@ int ss_tuner_get(double* coeffs, int count) {
     coeffs[9] = m.tiles_long;
   }
   if (count >= 11) coeffs[10] = m.learned_per_step_ns;
+  if (count >= 13) {
+    coeffs[11] = m.ballot_base_ns;
+    coeffs[12] = m.ballot_per_entry_ns;
+  }
   return SS_OK;
 }
 
@@ -597,12 +638,16 @@ int ss_tuner_set(const double* coeffs, int count) {
   m.learned_base_ns = coeffs[5];
   m.calibrated = coeffs[6] != 0;
   m.bins_per_entry = coeffs[7];
-  const int used = count >= 11 ? 11 : count >= 10 ? 10 : 8;
+  const int used = count >= 13 ? 13 : count >= 11 ? 11 : count >= 10 ? 10 : 8;
   if (count >= 10) {
     m.tiles_short = coeffs[8];
     m.tiles_long = coeffs[9];
   }
   if (count >= 11) m.learned_per_step_ns = coeffs[10];
+  if (count >= 13) {
+    m.ballot_base_ns = coeffs[11];
+    m.ballot_per_entry_ns = coeffs[12];
+  }
   for (int i = 0; i < used; ++i)
     if (!(coeffs[i] >= 0) || !std::isfinite(coeffs[i]))
       return fail(SS_ERR_INVALID_ARG, "coefficients must be finite and non-negative");

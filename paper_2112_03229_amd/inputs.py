@@ -238,6 +238,18 @@ def batched_targets(batch: Batch, seed: int = 512, threads: int = 0, out=None,
                                 threads=threads, out=out)
 
 
+def batched_smooth_targets(batch: Batch, seed: int = 513, threads: int = 0, out=None):
+    """Each table's targets as one smooth increasing walk over its range (the
+    single-table "smooth" order, per segment): targets that arrive sorted."""
+    o = _out(batch.num_queries, out)
+    for t in range(batch.num_tables):
+        a, b = int(batch.query_off[t]), int(batch.query_off[t + 1])
+        if b > a:
+            smooth_walk(seed + t, float(batch.lo[t]), float(batch.hi[t]), b - a,
+                        threads=threads, out=o[a:b])
+    return o[:batch.num_queries]
+
+
 def learned_table(seed: int = 2000, n: int = 2000):
     return sorted_log_table(seed, n, 1e-8, 1e6, pin_ends=True)
 

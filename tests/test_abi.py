@@ -55,7 +55,7 @@ def test_version_and_options(L):
     for v in (b.PLAN_LEARNED_ALL, b.PLAN_LEARNED_NONE, b.PLAN_LEARNED_TUNER):
         b.set_option(b.OPT_PLAN_LEARNED, v)
         assert b.get_option(b.OPT_PLAN_LEARNED) == v
-    for v in (b.ALGO_BINARY, b.ALGO_EXPHASH, b.ALGO_AUTO):
+    for v in (b.ALGO_BINARY, b.ALGO_EXPHASH, b.ALGO_BALLOT, b.ALGO_AUTO):
         b.set_option(b.OPT_PLAN_ALGO, v)
         assert b.get_option(b.OPT_PLAN_ALGO) == v
     for v in (1, 2, 0):
@@ -66,7 +66,7 @@ def test_version_and_options(L):
                      (b.OPT_CHECK_POINTERS, 2), (b.OPT_PAIR_JOINT, 2), (b.OPT_CONVENTION, 2),
                      (b.OPT_PLAN_XCD, -1), (b.OPT_PLAN_XCD, (1 << 24) + 1),
                      (b.OPT_PLAN_LEARNED, 3), (b.OPT_PLAN_LEARNED, -1),
-                     (b.OPT_PLAN_ALGO, b.ALGO_LEARNED), (b.OPT_PLAN_ALGO, b.ALGO_BALLOT),
+                     (b.OPT_PLAN_ALGO, b.ALGO_LEARNED), (b.OPT_PLAN_ALGO, b.ALGO_LOGHASH),
                      (b.OPT_PLAN_ALGO, 8), (b.OPT_PLAN_ORDER, 3), (b.OPT_PLAN_ORDER, -1),
                      (999, 0)):
         with pytest.raises(b.SearchSortedError) as e:
@@ -92,6 +92,15 @@ def test_argument_errors_before_device_work(L):
     # m == 0 is a no-op that touches nothing
     assert L.search_sorted_batch(P(0), 0, P(0), 0, P(0)) == 0
     assert L.ss_exphash_bins(fake, 0, 0, fake, 16, None) == -1
+    # sampled plans: a null sample is refused before anything else
+    import numpy as np
+    off = np.array([0, 4], dtype=np.int64)
+    h = P()
+    assert L.ss_multi_plan_create_sampled(fake, off.ctypes.data, 1, off.ctypes.data, None,
+                                          ctypes.byref(h)) == -1
+    assert b"sample" in L.ss_last_error()
+    assert L.ss_pair_plan_create_sampled(fake, off.ctypes.data, fake, off.ctypes.data, 1,
+                                         off.ctypes.data, fake, None, ctypes.byref(h)) == -1
 
 
 def test_host_pointers_are_rejected(L):
