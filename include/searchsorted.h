@@ -169,6 +169,19 @@ typedef enum {
                                     side); 0 (default) = 2 */
 } ss_option;
 
+/* Environment, read once when the library is loaded:
+ *   SS_<NAME>=<value> sets option SS_OPT_<NAME> as ss_set_option would
+ *   (SS_FORCE_ALGO, SS_BUCKET_BITS, SS_PLAN_ALGO, SS_CONVENTION, ... every
+ *   option above); the values are integers, and the two algorithm options
+ *   also take the names auto, binary, ballot, exphash, binary_global,
+ *   learned, loghash and skiplist.  A value the option refuses is reported
+ *   on stderr and ignored.  Calls to ss_set_option override them later.
+ *   SS_LOG=1 writes one line per library decision to stderr, prefixed
+ *   "[ss] ": options taken from the environment, every plan's per-table
+ *   kernel counts, tile shape, grid, LDS and XCD mapping, a sampled plan's
+ *   mean bracket, tuner calibrations and model loads, learned builds.
+ *   SS_TUNER_CACHE: see the autotuner section below. */
+
 /* Human-readable message for the calling thread's most recent error
  * (empty string if none).  The pointer stays valid until the next library
  * call on the same thread. */

@@ -22,6 +22,11 @@ hipStream_t current_stream();
 
 int64_t option(int opt);
 
+// SS_LOG: 1 or more writes one line per library decision to stderr.
+bool log_enabled();
+// printf-style line on stderr, prefixed "[ss] ", when SS_LOG is set.
+void log_line(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
 struct DeviceInfo {
   int device = -1;
   int num_cus = 0;

@@ -937,6 +937,8 @@ int ss_learned_build(const double* table, int64_t n, const ss_mlp_opts* opts, ss
     delete h;
     return rc;
   }
+  log_line("learned model: n %d, %d Adam steps, loss %.3g, error bound E = %d", h->n, o.steps,
+           h->loss, h->E);
   *out = h;
   return SS_OK;
 }

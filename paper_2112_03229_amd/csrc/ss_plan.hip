@@ -1095,6 +1095,30 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
     SS_TRY_HIP(hipGraphAddKernelNode(&p->search_node, p->graph, nullptr, 0, &kp));
   }
   SS_TRY_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  if (log_enabled()) {
+    int count[8] = {0};
+    double br_sum = 0;
+    int br_n = 0;
+    for (int t = 0; t < p->T; ++t) {
+      ++count[std::min(std::max(p->tuned[t].algo, 0), 7)];
+      if (t < (int)p->brackets.size() && p->brackets[t] >= 0) {
+        br_sum += p->brackets[t];
+        ++br_n;
+      }
+    }
+    static const char* kForm[] = {"batched", "paired-joint", "paired-split", "interpolation"};
+    log_line("plan %s: %d tables (exphash %d, bisection %d, ballot %d, learned %d), %lld "
+             "targets, %lld tiles of %d, %d per workgroup %s, grid %d x %d, LDS %zu B, XCD "
+             "chunk %d%s",
+             kForm[p->mode], p->T, count[SS_ALGO_EXPHASH], count[SS_ALGO_BINARY],
+             count[SS_ALGO_BALLOT], count[SS_ALGO_LEARNED], (long long)p->total_queries,
+             (long long)p->total_tiles, p->block * p->q, p->tiles_per_wg,
+             p->strided ? "strided" : "contiguous", p->grid, p->block, p->lds,
+             p->xcd_groups > 1 ? p->xcd_chunk : 1, p->convention ? ", paper convention" : "");
+    if (br_n > 0)
+      log_line("plan sample: mean ballot bracket %.2f entries over %d tables", br_sum / br_n,
+               br_n);
+  }
   return SS_OK;
 }
 

@@ -1,6 +1,11 @@
 // Library runtime: error state, stream selection, options, device queries
 // and argument checks behind the C ABI.
+#include <algorithm>
 #include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -150,6 +155,105 @@ int blocks_per_cu(const void* kernel, int threads, size_t lds) {
   return blocks;
 }
 
+namespace {
+std::atomic<int> g_log{0};
+}  // namespace
+
+bool log_enabled() { return g_log.load(std::memory_order_relaxed) > 0; }
+
+void log_line(const char* fmt, ...) {
+  if (!log_enabled()) return;
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[ss] %s\n", buf);
+}
+
+}  // namespace ss
+
+extern "C" int ss_set_option(int opt, int64_t v);
+
+namespace ss {
+namespace {
+
+// Options from the environment, applied once when the library is loaded:
+// SS_<NAME>=<value> for the option SS_OPT_<NAME>, an integer or (for the
+// two algorithm options) an algorithm name.  Values the option refuses are
+// reported on stderr and ignored.
+struct EnvOption {
+  const char* name;
+  int opt;
+  bool algo;
+};
+constexpr EnvOption kEnvOptions[] = {
+    {"SS_FORCE_ALGO", SS_OPT_FORCE_ALGO, true},
+    {"SS_BUCKET_BITS", SS_OPT_BUCKET_BITS, false},
+    {"SS_BUCKET_CAP", SS_OPT_BUCKET_CAP, false},
+    {"SS_BLOCK_SIZE", SS_OPT_BLOCK_SIZE, false},
+    {"SS_GRID_BLOCKS", SS_OPT_GRID_BLOCKS, false},
+    {"SS_CHECK_POINTERS", SS_OPT_CHECK_POINTERS, false},
+    {"SS_TARGETS_PER_LANE", SS_OPT_TARGETS_PER_LANE, false},
+    {"SS_PLAN_TILES", SS_OPT_PLAN_TILES, false},
+    {"SS_PLAN_LEARNED", SS_OPT_PLAN_LEARNED, false},
+    {"SS_LEARNED_STEPS", SS_OPT_LEARNED_STEPS, false},
+    {"SS_PLAN_XCD", SS_OPT_PLAN_XCD, false},
+    {"SS_PAIR_JOINT", SS_OPT_PAIR_JOINT, false},
+    {"SS_CONVENTION", SS_OPT_CONVENTION, false},
+    {"SS_PLAN_ALGO", SS_OPT_PLAN_ALGO, true},
+    {"SS_PLAN_ORDER", SS_OPT_PLAN_ORDER, false},
+};
+
+constexpr const char* kAlgoNames[] = {"auto",          "binary",  "ballot",  "exphash",
+                                      "binary_global", "learned", "loghash", "skiplist"};
+
+// Parses a whole decimal integer (or, if algo, an algorithm name).
+bool parse_value(const char* text, bool algo, int64_t* v) {
+  if (algo)
+    for (int i = 0; i < (int)(sizeof(kAlgoNames) / sizeof(kAlgoNames[0])); ++i)
+      if (std::strcmp(text, kAlgoNames[i]) == 0) {
+        *v = i;
+        return true;
+      }
+  char* end = nullptr;
+  const long long x = std::strtoll(text, &end, 10);
+  if (end == text || *end) return false;
+  *v = x;
+  return true;
+}
+
+struct EnvInit {
+  EnvInit() {
+    const char* lv = std::getenv("SS_LOG");
+    int64_t level = 0;
+    if (lv && *lv) {
+      if (parse_value(lv, false, &level) && level >= 0)
+        g_log = (int)std::min<int64_t>(level, 9);
+      else
+        std::fprintf(stderr, "[ss] ignoring SS_LOG=%s: expected a non-negative integer\n", lv);
+    }
+    for (const EnvOption& e : kEnvOptions) {
+      const char* text = std::getenv(e.name);
+      if (!text || !*text) continue;
+      int64_t v = 0;
+      if (!parse_value(text, e.algo, &v)) {
+        std::fprintf(stderr, "[ss] ignoring %s=%s: not %s\n", e.name, text,
+                     e.algo ? "an integer or algorithm name" : "an integer");
+        continue;
+      }
+      if (ss_set_option(e.opt, v) != SS_OK) {
+        std::fprintf(stderr, "[ss] ignoring %s=%s: %s\n", e.name, text, t_last_error.c_str());
+        t_last_error.clear();
+        continue;
+      }
+      log_line("option %s = %lld (environment)", e.name, (long long)v);
+    }
+  }
+};
+const EnvInit g_env_init;
+
+}  // namespace
 }  // namespace ss
 
 extern "C" {

@@ -189,6 +189,7 @@ void env_init() {
   TunerModel m;
   std::string arch;
   if (load_file(path, &m, &arch) == SS_OK) {
+    log_line("tuner model loaded from SS_TUNER_CACHE %s (%s)", path, arch.c_str());
     std::lock_guard<std::mutex> lk(g_tuner_mu);
     g_model = m;
     g_model_arch = arch;
@@ -582,6 +583,12 @@ int calibrate() {
     if (bx.size() >= 2) fit_line(bx, by, &m.ballot_base_ns, &m.ballot_per_entry_ns);
   }
   m.calibrated = 1;
+  log_line("tuner calibrated on %s: stream %.0f GB/s; per query (ps): hash %.2f + %.3f K, "
+           "bisection %.2f + %.3f per step, learned %.2f + %.3f per step, ballot %.2f + %.4f "
+           "per entry",
+           di.arch, m.stream_gbs, 1e3 * m.hash_base_ns, 1e3 * m.hash_per_k_ns,
+           1e3 * m.bin_base_ns, 1e3 * m.bin_per_step_ns, 1e3 * m.learned_base_ns,
+           1e3 * m.learned_per_step_ns, 1e3 * m.ballot_base_ns, 1e3 * m.ballot_per_entry_ns);
   std::lock_guard<std::mutex> lk(g_tuner_mu);
   g_model = m;
   g_model_arch = arch_base(di.arch);
@@ -675,6 +682,7 @@ int ss_tuner_load(const char* path) {
   std::string arch;
   int rc = load_file(path, &m, &arch);
   if (rc != SS_OK) return rc;
+  log_line("tuner model loaded from %s (%s)", path, arch.c_str());
   std::lock_guard<std::mutex> lk(g_tuner_mu);
   g_model = m;
   g_model_arch = arch;

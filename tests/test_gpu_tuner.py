@@ -128,3 +128,30 @@ def test_env_cache_calibrates_once(gpu, tmp_path):
     third, err = run_child(path)
     assert "refused" in err and third["stream_gbs"] != 1.5 and third["calibrated"] == 1.0
     assert json.loads(path.read_text())["arch"].startswith("gfx950")
+
+
+LOG_CHILD = r"""
+import sys
+sys.path.insert(0, {repo!r})
+import numpy as np, torch
+from paper_2112_03229_amd import binding
+t = torch.from_numpy(np.geomspace(1e-3, 1e3, 100)).cuda()
+x = torch.from_numpy(np.sort(np.geomspace(2e-3, 5e2, 100000))).cuda()
+plan = binding.MultiPlan(t, np.array([0, 100]), np.array([0, 100000]), sample=x)
+plan.search(x)
+torch.cuda.synchronize()
+"""
+
+
+def test_log_reports_plan_decisions(gpu, tmp_path):
+    env = dict(os.environ, SS_LOG="1", SS_TUNER_CACHE=str(tmp_path / "tuner.json"))
+    say("case SS_LOG=1: plan and tuner decisions on stderr")
+    r = subprocess.run([sys.executable, "-c", LOG_CHILD.format(repo=REPO)], env=env,
+                       capture_output=True, text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("[ss] ")]
+    say("\n".join(lines))
+    assert any(ln.startswith("[ss] tuner calibrated on gfx950") for ln in lines)
+    assert any(ln.startswith("[ss] plan batched: 1 tables") and "100000 targets" in ln
+               for ln in lines)
+    assert any(ln.startswith("[ss] plan sample: mean ballot bracket") for ln in lines)
