@@ -584,6 +584,14 @@ SS_API int ss_learned_fallbacks(ss_learned *h, int64_t *count);
  * every table entry's predicted index lies within E - 1 of its index. */
 SS_API int ss_learned_error_bound(const ss_learned *h, int32_t *E);
 
+/* Replaces the error bound the searches use (0 <= E <= 65535; plans built
+ * afterwards with this handle take it too), to exercise the verification:
+ * a bound below the measured one makes windows miss, and those targets are
+ * answered by the fallback bisection (results stay exact, the fallback
+ * count rises); a larger one widens every window.  ss_learned_error_bound
+ * then reports the value in force, and ss_learned_save writes it. */
+SS_API int ss_learned_set_error_bound(ss_learned *h, int32_t E);
+
 /* Statistics of the most recent ss_learned_search: the targets answered by
  * the fallback (the same count as ss_learned_fallbacks).  SYNCHRONOUS. */
 SS_API int ss_learned_stats(ss_learned *h, int64_t *fallbacks);

@@ -100,6 +100,7 @@ def _register_extra(L) -> None:
         "ss_learned_info": [P, P, I],
         "ss_learned_fallbacks": [P, ctypes.POINTER(I64)],
         "ss_learned_error_bound": [P, ctypes.POINTER(I32)],
+        "ss_learned_set_error_bound": [P, I32],
         "ss_learned_stats": [P, ctypes.POINTER(I64)],
         "ss_learned_predict": [P, P, I64, P],
         "ss_learned_weights": [P, P, I64],
@@ -619,6 +620,10 @@ class LearnedIndex:
         v = ctypes.c_int32()
         check(lib().ss_learned_error_bound(self._handle, ctypes.byref(v)))
         return v.value
+
+    def set_error_bound(self, E: int) -> None:
+        """Replaces the bound the searches use (ss_learned_set_error_bound)."""
+        check(lib().ss_learned_set_error_bound(self._handle, int(E)))
 
     def stats(self) -> int:
         """Fallbacks of the most recent search (ss_learned_stats)."""

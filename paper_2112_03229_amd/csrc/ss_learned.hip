@@ -1129,6 +1129,14 @@ int ss_learned_error_bound(const ss_learned* h, int32_t* E) {
   return SS_OK;
 }
 
+int ss_learned_set_error_bound(ss_learned* h, int32_t E) {
+  clear_error();
+  if (!h) return fail(SS_ERR_INVALID_ARG, "null handle");
+  if (E < 0 || E > 65535) return fail(SS_ERR_INVALID_ARG, "E must be in 0..65535");
+  h->E = E;
+  return SS_OK;
+}
+
 int ss_learned_stats(ss_learned* h, int64_t* fallbacks) {
   return ss_learned_fallbacks(h, fallbacks);
 }

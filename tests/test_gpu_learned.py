@@ -384,3 +384,42 @@ def test_plan_with_attached_models(binding, gpu, oracle_mod, inputs_mod):
     with pytest.raises(binding.SearchSortedError):
         binding.MultiPlan(tt, off, batch.query_off, models=[None, copy, None, None, None, None])
     copy.close()
+
+
+def test_error_bound_forced_below_measured(binding, gpu, oracle_mod, inputs_mod, trained):
+    """E forced to 0 (and to 1): the verification rejects every window that
+    misses, the fallback answers those targets, and every index stays exact;
+    a wide bound verifies every window.  A plan built with a reduced bound
+    counts its fallbacks the same way."""
+    table, t, li = trained
+    E0 = li.error_bound()
+    x = targets_for(inputs_mod, table, 200003, seed=17)
+    want = oracle_mod.search_lt(table, x)
+    xd = torch.from_numpy(x).to(gpu)
+    try:
+        seen = {}
+        for E in (0, 1, E0, 4 * E0 + 100):
+            say(f"case learned E forced to {E} (measured {E0})")
+            li.set_error_bound(E)
+            assert li.error_bound() == E
+            got = li.search(xd).cpu().numpy()
+            assert np.array_equal(got, want), E
+            seen[E] = li.fallbacks()
+        say(f"fallbacks by E: {seen}")
+        # NaN targets fail every window check whatever E (their count is 2
+        # here); every other target verifies once E reaches the measured bound
+        nan = int(np.isnan(x).sum())
+        assert seen[E0] == nan and seen[4 * E0 + 100] == nan
+        assert seen[0] >= seen[1] > seen[E0]
+        # a plan attached while the bound is 0 takes it
+        li.set_error_bound(0)
+        plan = binding.MultiPlan(t, np.array([0, table.size]), np.array([0, x.size]),
+                                 models=[li])
+        assert np.array_equal(plan.search(xd).cpu().numpy(), want)
+        assert plan.fallbacks() > 0
+        plan.close()
+        with pytest.raises(binding.SearchSortedError):
+            li.set_error_bound(-1)
+    finally:
+        li.set_error_bound(E0)
+    assert li.error_bound() == E0
