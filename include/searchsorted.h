@@ -182,6 +182,22 @@ typedef enum {
  *   mean bracket, tuner calibrations and model loads, learned builds.
  *   SS_TUNER_CACHE: see the autotuner section below. */
 
+/* Device bounds checks (the library built with -DSS_DEVICE_CHECKS=1, the
+ * variant in _lib/checked/ that the package loads with SS_LIBRARY pointing
+ * at it; slower, for tests).  Its kernels test every LDS index of the search
+ * routines against the region it reads (the staged table and its +inf
+ * padding, bin tables, model images), every full tile's target range and
+ * every plan workgroup's staged layout and tile; a violation is counted and
+ * the index clamped into its region, so the kernel never reads or writes
+ * outside it.  ss_debug_violations (host out) returns the violations counted
+ * since its last call on the current device and clears them; SYNCHRONOUS.
+ * ss_debug_selftest runs a one-thread kernel that clamps one out-of-range
+ * index (touching nothing outside a one-int buffer): afterwards
+ * ss_debug_violations reports 1.  In the normal build both return
+ * SS_ERR_UNSUPPORTED. */
+SS_API int ss_debug_violations(int64_t *count);
+SS_API int ss_debug_selftest(void);
+
 /* Human-readable message for the calling thread's most recent error
  * (empty string if none).  The pointer stays valid until the next library
  * call on the same thread. */

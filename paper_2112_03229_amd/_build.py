@@ -61,15 +61,16 @@ def hip_flags():
     ]
 
 
-def build_hip(verbose: bool = False, jobs: int = 4) -> str:
-    os.makedirs(LIBDIR, exist_ok=True)
-    objdir = os.path.join(LIBDIR, "obj")
+def build_hip(verbose: bool = False, jobs: int = 4, libdir: str = LIBDIR,
+              extra: tuple = ()) -> str:
+    os.makedirs(libdir, exist_ok=True)
+    objdir = os.path.join(libdir, "obj")
     os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
     objs, procs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *hip_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *hip_flags(), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))
@@ -81,11 +82,21 @@ def build_hip(verbose: bool = False, jobs: int = 4) -> str:
     for p, s in procs:
         if p.wait() != 0:
             raise RuntimeError(f"hipcc failed on {s}")
-    out = os.path.join(LIBDIR, "libsearchsorted.so")
+    out = os.path.join(libdir, "libsearchsorted.so")
     tmp = out + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, out)
     return out
+
+
+# The device-checked variant: every search routine's LDS index and every
+# full tile's target range is tested in the kernels, violations are counted
+# (ss_debug_violations) and clamped instead of faulting.  Slower; for tests.
+CHECKED_LIBDIR = os.path.join(LIBDIR, "checked")
+
+
+def build_checked(verbose: bool = False) -> str:
+    return build_hip(verbose, libdir=CHECKED_LIBDIR, extra=("-DSS_DEVICE_CHECKS=1",))
 
 
 CLANG = "/opt/rocm/llvm/bin/clang"
@@ -136,6 +147,7 @@ def build_sanitized(outdir: str, verbose: bool = False) -> dict:
 def build_all(verbose: bool = False) -> None:
     build_inputs(verbose)
     build_hip(verbose)
+    build_checked(verbose)
 
 
 if __name__ == "__main__":

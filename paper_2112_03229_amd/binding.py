@@ -90,6 +90,8 @@ def _register_extra(L) -> None:
         "ss_pair_plan_create": [P, P, P, P, I32, P, ctypes.POINTER(P)],
         "ss_pair_search": [P, P, P, P, P],
         "ss_tuner_calibrate": [],
+        "ss_debug_violations": [ctypes.POINTER(I64)],
+        "ss_debug_selftest": [],
         "ss_tuner_get": [P, I],
         "ss_tuner_set": [P, I],
         "ss_tuner_save": [ctypes.c_char_p],
@@ -439,6 +441,22 @@ class PairPlan(_Plan):
         check(lib().ss_pair_search(self._handle, _ptr(rho), _ptr(temp), _ptr(out_rho),
                                    _ptr(out_t)))
         return out_rho, out_t
+
+
+def debug_violations() -> int:
+    """Bounds-check violations counted since the last call (device-checked
+    library only; SearchSortedError SS_ERR_UNSUPPORTED otherwise)."""
+    v = ctypes.c_int64()
+    use_current_stream()
+    check(lib().ss_debug_violations(ctypes.byref(v)))
+    return v.value
+
+
+def debug_selftest() -> None:
+    """One deliberately clamped index in a one-thread kernel (device-checked
+    library only): afterwards debug_violations() reports 1."""
+    use_current_stream()
+    check(lib().ss_debug_selftest())
 
 
 # ---------------------------------------------------------------------------

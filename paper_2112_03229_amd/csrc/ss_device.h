@@ -10,11 +10,57 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/searchsorted.h"
+
 #define SS_PAD 8            // +inf sentinels after the staged table
 #define SS_SCAN_MAX SS_PAD  // longest fixed in-bin scan; longer bins bisect
 #define SS_MAX_BITS 20      // bin bits that fit in the high word of a double
 
 namespace ss {
+
+// ---------------------------------------------------------------------------
+// Device bounds checks.  In a checked build (compiled with
+// -DSS_DEVICE_CHECKS=1) SS_IN(i, lo, hi) tests lo <= i < hi for an index
+// about to be used in an access to a region of hi entries; a violation is
+// counted in this module's device counter and i is clamped into the
+// region, so the checked kernels report an indexing mistake instead of
+// reading or writing outside it.  SS_ASSERT(c) counts a violated condition.
+// In normal builds both compile to nothing.  read_violations (host) returns
+// and clears the module's count.
+// ---------------------------------------------------------------------------
+#if SS_DEVICE_CHECKS
+static __device__ unsigned long long g_ss_violations = 0;
+
+__device__ __forceinline__ int checked_index(int i, int lo, int hi) {
+  if (i < lo || i >= hi) {
+    atomicAdd(&g_ss_violations, 1ull);
+    i = i < lo ? lo : hi - 1;
+  }
+  return i;
+}
+#define SS_IN(i, lo, hi) ::ss::checked_index((i), (lo), (hi))
+#define SS_ASSERT(c)                                     \
+  do {                                                   \
+    if (!(c)) atomicAdd(&::ss::g_ss_violations, 1ull);   \
+  } while (0)
+
+static inline int read_violations(unsigned long long* out) {
+  unsigned long long zero = 0;
+  if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_ss_violations), sizeof(*out)) != hipSuccess ||
+      hipMemcpyToSymbol(HIP_SYMBOL(g_ss_violations), &zero, sizeof(zero)) != hipSuccess) {
+    (void)hipGetLastError();
+    return SS_ERR_HIP;
+  }
+  return SS_OK;
+}
+#else
+#define SS_IN(i, lo, hi) (i)
+#define SS_ASSERT(c) ((void)0)
+static inline int read_violations(unsigned long long* out) {
+  *out = 0;
+  return SS_ERR_UNSUPPORTED;  // not a checked build
+}
+#endif
 
 // High 32 bits of the IEEE-754 encoding, as a signed integer: sign bit,
 // 11-bit biased exponent, 20 leading fraction bits.
@@ -100,7 +146,7 @@ __device__ __forceinline__ void build_bins(const double* __restrict__ sa, int n,
     const int kb = clampi(hash_key(sa[i], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
     const int kp =
         i == 0 ? -1 : clampi(hash_key(sa[i - 1], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
-    for (int b = kp + 1; b <= kb; ++b) C[b] = (CT)i;
+    for (int b = kp + 1; b <= kb; ++b) C[SS_IN(b, 0, hp.nb + 1)] = (CT)i;
     int run = 1;
     if (kp == kb) {
       run = 2;
@@ -132,12 +178,13 @@ __device__ __forceinline__ void search_binary(const double* __restrict__ sa, int
   while (len > 1) {
     const int half = len >> 1;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) base[q] = (sa[base[q] + half] < x[q]) ? base[q] + half : base[q];
+    for (int q = 0; q < Q; ++q)
+      base[q] = (sa[SS_IN(base[q] + half, 0, n + SS_PAD)] < x[q]) ? base[q] + half : base[q];
     len -= half;
   }
   // n == 0: sa[0] is the +inf sentinel, so the count is 0.
 #pragma unroll
-  for (int q = 0; q < Q; ++q) r[q] = base[q] + (sa[base[q]] < x[q] ? 1 : 0) - 1;
+  for (int q = 0; q < Q; ++q) r[q] = base[q] + (sa[SS_IN(base[q], 0, n + SS_PAD)] < x[q] ? 1 : 0) - 1;
 }
 
 // Global-memory variant for tables too large to stage (same arithmetic).
@@ -179,7 +226,7 @@ __device__ __forceinline__ void search_exphash(const double* __restrict__ sa,
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     b[q] = clampi(hash_key(x[q], hp.shift), hp.kmin, hp.kmaxc) - hp.kmin;
-    j0[q] = min((int)C[b[q]], n);
+    j0[q] = min((int)C[SS_IN(b[q], 0, hp.nb + 1)], n);
   }
   if (hp.K <= SS_SCAN_MAX) {
     int cnt[Q];
@@ -188,7 +235,7 @@ __device__ __forceinline__ void search_exphash(const double* __restrict__ sa,
 #pragma nounroll
     for (int k = 0; k < hp.K; ++k) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) cnt[q] += (sa[j0[q] + k] < x[q]) ? 1 : 0;
+      for (int q = 0; q < Q; ++q) cnt[q] += (sa[SS_IN(j0[q] + k, 0, n + SS_PAD)] < x[q]) ? 1 : 0;
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) r[q] = (x[q] != x[q]) ? -1 : j0[q] + cnt[q] - 1;
@@ -199,7 +246,7 @@ __device__ __forceinline__ void search_exphash(const double* __restrict__ sa,
     int hi[Q], pos[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      hi[q] = min(max((int)C[b[q] + 1], j0[q]), n);
+      hi[q] = min(max((int)C[SS_IN(b[q] + 1, 0, hp.nb + 1)], j0[q]), n);
       pos[q] = j0[q];
     }
     int step = 1;
@@ -209,7 +256,7 @@ __device__ __forceinline__ void search_exphash(const double* __restrict__ sa,
       for (int q = 0; q < Q; ++q) {
         const int cand = pos[q] + step;
         const int ridx = max(min(cand, hi[q]) - 1, 0);
-        const bool lt = sa[ridx] < x[q];
+        const bool lt = sa[SS_IN(ridx, 0, n + SS_PAD)] < x[q];
         pos[q] = ((cand <= hi[q]) & lt) ? cand : pos[q];
       }
     }
@@ -249,7 +296,7 @@ __device__ __forceinline__ void search_ballot(const double* __restrict__ sa, int
   const double wmax = wave_max(lmax);
   int lo = 0, hi = 0;
   for (int c = 0; c < n; c += 64) {
-    const double e = sa[min(c + lane, n)];  // index n is the +inf sentinel
+    const double e = sa[SS_IN(min(c + lane, n), 0, n + SS_PAD)];  // index n is the +inf sentinel
     lo += __popcll(__ballot(e < wmin));
     hi += __popcll(__ballot(e < wmax));
   }
@@ -259,7 +306,7 @@ __device__ __forceinline__ void search_ballot(const double* __restrict__ sa, int
 #pragma unroll
   for (int q = 0; q < Q; ++q) cnt[q] = 0;
   for (int j = lo; j < hi; ++j) {
-    const double aj = sa[j];
+    const double aj = sa[SS_IN(j, 0, n + SS_PAD)];
 #pragma unroll
     for (int q = 0; q < Q; ++q) cnt[q] += (aj < x[q]) ? 1 : 0;
   }
@@ -305,6 +352,7 @@ __device__ __forceinline__ void convention_out(int n, const double (&x)[Q], int 
 template <int Q>
 __device__ __forceinline__ void load_tile(const double* __restrict__ x, int64_t m, int64_t base,
                                           int nt, bool full, double (&xv)[Q]) {
+  SS_ASSERT(base >= 0 && (!full || base + (int64_t)(Q - 1) * nt < m));
   if (full) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) xv[q] = __builtin_nontemporal_load(x + base + (int64_t)q * nt);
@@ -321,6 +369,7 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ x, int64_t 
 template <int Q>
 __device__ __forceinline__ void store_tile(int32_t* __restrict__ out, int64_t m, int64_t base,
                                            int nt, bool full, const int (&r)[Q]) {
+  SS_ASSERT(base >= 0 && (!full || base + (int64_t)(Q - 1) * nt < m));
   if (full) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) __builtin_nontemporal_store(r[q], out + base + (int64_t)q * nt);

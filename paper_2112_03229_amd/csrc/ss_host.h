@@ -43,6 +43,16 @@ int check_span(const void* p, int64_t count, size_t elem, size_t align, const ch
 int check_device_ptr(const void* p, const char* name);
 bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
 
+// Device bounds-check violations counted by each module's kernels since
+// the last read, then cleared (checked builds; SS_ERR_UNSUPPORTED
+// otherwise).  One per translation unit: each holds its own counter.
+int violations_single(unsigned long long* out);
+int violations_plan(unsigned long long* out);
+int violations_learned(unsigned long long* out);
+int violations_noalloc(unsigned long long* out);
+// Checked builds: one clamped out-of-range index in a one-thread kernel.
+int checks_selftest();
+
 // Workgroups of `kernel` that fit on one CU with `threads` threads and
 // `lds` bytes of dynamic LDS (cached).
 int blocks_per_cu(const void* kernel, int threads, size_t lds);

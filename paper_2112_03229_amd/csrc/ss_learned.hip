@@ -1199,3 +1199,7 @@ int learned_export(const ss_learned* h, LearnedExport* out) {
   return SS_OK;
 }
 }  // namespace ss
+
+namespace ss {
+int violations_learned(unsigned long long* out) { return read_violations(out); }
+}  // namespace ss

@@ -92,7 +92,7 @@ __device__ __forceinline__ void build_log_bins(const double* __restrict__ sa, in
   for (int i = tid; i < n; i += nt) {
     const int kb = log_key(sa[i], p);
     const int kp = i == 0 ? -1 : log_key(sa[i - 1], p);
-    for (int b = kp + 1; b <= kb; ++b) C[b] = (CT)i;
+    for (int b = kp + 1; b <= kb; ++b) C[SS_IN(b, 0, p.nb + 1)] = (CT)i;
   }
   // bins past the last entry's key (the clamp keeps a[n-1] in nb - 1, so
   // only a table whose keys are not ordered leaves any) hold n
@@ -125,7 +125,7 @@ __device__ __forceinline__ void search_loghash(const double* __restrict__ sa,
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     b[q] = log_key(x[q], p);
-    j0[q] = min((int)C[b[q]], n);
+    j0[q] = min((int)C[SS_IN(b[q], 0, p.nb + 1)], n);
   }
   if (p.K <= SS_SCAN_MAX) {
     int cnt[Q];
@@ -133,12 +133,13 @@ __device__ __forceinline__ void search_loghash(const double* __restrict__ sa,
     for (int q = 0; q < Q; ++q) {
       cnt[q] = 0;
       j1[q] = min(j0[q] + p.K, n);  // a[n] is the +inf sentinel
-      ok[q] = (j0[q] == 0 || sa[max(j0[q] - 1, 0)] < x[q]) && x[q] <= sa[j1[q]];
+      ok[q] = (j0[q] == 0 || sa[max(j0[q] - 1, 0)] < x[q]) &&
+              x[q] <= sa[SS_IN(j1[q], 0, n + SS_PAD)];
     }
 #pragma nounroll
     for (int k = 0; k < p.K; ++k) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) cnt[q] += (sa[j0[q] + k] < x[q]) ? 1 : 0;
+      for (int q = 0; q < Q; ++q) cnt[q] += (sa[SS_IN(j0[q] + k, 0, n + SS_PAD)] < x[q]) ? 1 : 0;
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) r[q] = j0[q] + cnt[q] - 1;
@@ -146,7 +147,7 @@ __device__ __forceinline__ void search_loghash(const double* __restrict__ sa,
     int pos[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      j1[q] = min(max((int)C[b[q] + 1], j0[q]), n);
+      j1[q] = min(max((int)C[SS_IN(b[q] + 1, 0, p.nb + 1)], j0[q]), n);
       pos[q] = j0[q];
       ok[q] = (j0[q] == 0 || sa[max(j0[q] - 1, 0)] < x[q]) && x[q] <= sa[j1[q]];
     }
@@ -157,7 +158,7 @@ __device__ __forceinline__ void search_loghash(const double* __restrict__ sa,
       for (int q = 0; q < Q; ++q) {
         const int cand = pos[q] + step;
         const int ridx = max(min(cand, j1[q]) - 1, 0);
-        pos[q] = ((cand <= j1[q]) & (sa[ridx] < x[q])) ? cand : pos[q];
+        pos[q] = ((cand <= j1[q]) & (sa[SS_IN(ridx, 0, n + SS_PAD)] < x[q])) ? cand : pos[q];
       }
     }
 #pragma unroll
@@ -169,10 +170,10 @@ __device__ __forceinline__ void search_loghash(const double* __restrict__ sa,
       int base = 0, len = n;
       while (len > 1) {
         const int half = len >> 1;
-        base = (sa[base + half] < x[q]) ? base + half : base;
+        base = (sa[SS_IN(base + half, 0, n + SS_PAD)] < x[q]) ? base + half : base;
         len -= half;
       }
-      r[q] = base + (sa[base] < x[q] ? 1 : 0) - 1;
+      r[q] = base + (sa[SS_IN(base, 0, n + SS_PAD)] < x[q] ? 1 : 0) - 1;
     }
     if (x[q] != x[q]) r[q] = -1;
   }

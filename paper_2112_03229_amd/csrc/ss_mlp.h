@@ -138,29 +138,30 @@ __device__ __forceinline__ void mlp_eval_q(const float* m, const ImageHead& h,
     int base[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      base[q] = C[cell_of(z[q], h.z0, h.cinv, h.G)];
+      base[q] = C[SS_IN(cell_of(z[q], h.z0, h.cinv, h.G), 0, h.G + 1)];
       i[q] = base[q];
     }
     // base + k < nb + kCellScan <= nbp: reads past the cell's boundaries
     // meet later cells' boundaries (not below z) or the +inf padding
     for (int k = 0; k < h.K; ++k) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) i[q] += (b[base[q] + k] < z[q]) ? 1 : 0;
+      for (int q = 0; q < Q; ++q) i[q] += (b[SS_IN(base[q] + k, 0, h.nbp)] < z[q]) ? 1 : 0;
     }
   } else {
 #pragma unroll
     for (int q = 0; q < Q; ++q) i[q] = 0;
     for (int step = h.nbp >> 1; step >= 1; step >>= 1) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) i[q] = (b[i[q] + step - 1] < z[q]) ? i[q] + step : i[q];
+      for (int q = 0; q < Q; ++q)
+        i[q] = (b[SS_IN(i[q] + step - 1, 0, h.nbp)] < z[q]) ? i[q] + step : i[q];
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q) i[q] += (b[i[q]] < z[q]) ? 1 : 0;
+    for (int q = 0; q < Q; ++q) i[q] += (b[SS_IN(i[q], 0, h.nbp)] < z[q]) ? 1 : 0;
   }
   typedef float f2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const f2 sq = *reinterpret_cast<const f2*>(m + kIHead + h.nbp + 2 * i[q]);
+    const f2 sq = *reinterpret_cast<const f2*>(m + kIHead + h.nbp + 2 * SS_IN(i[q], 0, h.nbp));
     p[q] = fmaf(sq.x, z[q], sq.y);
   }
 }
@@ -200,8 +201,8 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
   for (int q = 0; q < Q; ++q) {
     const int g = predicted_index(p[q], n);
     const int L = max(g - E, -1), R = min(g + E, n - 1);
-    const bool lo_ok = L < 0 || sa[max(L, 0)] < x[q];
-    const bool hi_ok = R >= n - 1 || x[q] <= sa[min(R + 1, n - 1)];
+    const bool lo_ok = L < 0 || sa[SS_IN(max(L, 0), 0, n)] < x[q];
+    const bool hi_ok = R >= n - 1 || x[q] <= sa[SS_IN(min(R + 1, n - 1), 0, n)];
     ok |= (lo_ok && hi_ok) ? 1u << q : 0u;
     fell_back[q] = (lo_ok && hi_ok) ? 0 : 1;
     pos[q] = L + 1;
@@ -225,10 +226,13 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
     for (int q = 0; q < Q; ++q) {
       const int kb = rb[q] + s8;  // a[k], k = pos + s - 1 >= 0
       bool lt;
-      if constexpr (SENTINEL)
+      if constexpr (SENTINEL) {
+        SS_ASSERT(kb >= 0);  // min(kb, n8) reads a[0..n], a[n] the sentinel
         lt = *reinterpret_cast<const double*>(sb + min(kb, n8)) < x[q];
-      else
+      } else {
+        SS_ASSERT(kb >= 0);  // min(kb, n8 - 8) reads a[0..n-1]
         lt = kb < n8 && *reinterpret_cast<const double*>(sb + min(kb, n8 - 8)) < x[q];
+      }
       rb[q] = lt ? kb : rb[q];
     }
   }
@@ -239,10 +243,10 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
       int base = 0, len = n;
       while (len > 1) {
         const int half = len >> 1;
-        base = (sa[base + half] < x[q]) ? base + half : base;
+        base = (sa[SS_IN(base + half, 0, n)] < x[q]) ? base + half : base;
         len -= half;
       }
-      r[q] = base + (sa[base] < x[q] ? 1 : 0) - 1;
+      r[q] = base + (sa[SS_IN(base, 0, n)] < x[q] ? 1 : 0) - 1;
     }
   }
 }

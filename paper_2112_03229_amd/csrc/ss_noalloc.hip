@@ -247,3 +247,7 @@ int ss_multi_search_noalloc(const double* tables, int64_t total_n, const int64_t
 }
 
 }  // extern "C"
+
+namespace ss {
+int violations_noalloc(unsigned long long* out) { return read_violations(out); }
+}  // namespace ss

@@ -319,6 +319,18 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   if constexpr (PAIRED)
     stb = stage_desc(a.desc[a.pair_base + ws.seg], a.tables_b, a.bins, a.params, sb, Cb, Mb);
   if constexpr (INTERP) grid = stage_grid(a, ws.seg, sta.n, stb.n, lds_grid);
+#if SS_DEVICE_CHECKS
+  // the host's LDS layout holds what was staged (learned images are
+  // checked by their lookups)
+  SS_ASSERT((sta.n + SS_PAD) * 8 <= a.lds_bins_a);
+  SS_ASSERT(!sta.hp.ok || a.lds_bins_a + (sta.hp.nb + 1) * 2 <= a.lds_tab_b);
+  if constexpr (PAIRED) {
+    SS_ASSERT(a.lds_tab_b + (stb.n + SS_PAD) * 8 <= a.lds_bins_b);
+    SS_ASSERT(!stb.hp.ok ||
+              a.lds_bins_b + (stb.hp.nb + 1) * 2 <= (INTERP ? a.lds_grid : a.lds_model_a));
+  }
+  if constexpr (INTERP) SS_ASSERT(!grid.l || sta.n * stb.n <= a.grid_cap);
+#endif
   __syncthreads();
   // headers of staged learned models (unused for other tables)
   ImageHead oa{}, ob{};
@@ -336,6 +348,7 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
       if constexpr (PAIRED) load_range<Q>(a.xb, nx2, cb2);
     }
     const bool full = cur.q0 + per_tile == cur.q1;
+    SS_ASSERT(cur.q0 >= q0 && cur.q1 <= q1 && cur.q0 < cur.q1 && cur.q1 - cur.q0 <= per_tile);
     int r[Q], fell[Q];
     search_tile<Q, LEARN, CONV>(sta, sa, Ca, Ma, oa, ca, r, fell);
     if constexpr (!INTERP)
@@ -1761,3 +1774,7 @@ int ss_plan_info(const ss_plan* p, int what, void* out, int64_t cap) {
 }
 
 }  // extern "C"
+
+namespace ss {
+int violations_plan(unsigned long long* out) { return read_violations(out); }
+}  // namespace ss

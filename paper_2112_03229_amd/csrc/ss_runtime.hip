@@ -348,6 +348,27 @@ int ss_set_option(int opt, int64_t v) {
   }
 }
 
+int ss_debug_violations(int64_t* count) {
+  ss::clear_error();
+  if (!count) return ss::fail(SS_ERR_INVALID_ARG, "count is null");
+  *count = 0;
+  int (*readers[])(unsigned long long*) = {ss::violations_single, ss::violations_plan,
+                                           ss::violations_learned, ss::violations_noalloc};
+  for (auto rd : readers) {
+    unsigned long long v = 0;
+    const int rc = rd(&v);
+    if (rc == SS_ERR_UNSUPPORTED) return ss::fail(rc, "not a device-checked build");
+    if (rc != SS_OK) return ss::fail(rc, "reading the bounds-check counters");
+    *count += (int64_t)v;
+  }
+  return SS_OK;
+}
+
+int ss_debug_selftest(void) {
+  ss::clear_error();
+  return ss::checks_selftest();
+}
+
 int ss_get_option(int opt, int64_t* value_out) {
   if (!value_out) return ss::fail(SS_ERR_INVALID_ARG, "value_out is null");
   switch (opt) {

@@ -487,3 +487,33 @@ int ss_loghash_bins(const double* table, int64_t n, int64_t nb, int32_t* counts,
 }
 
 }  // extern "C"
+
+namespace ss {
+#if SS_DEVICE_CHECKS
+namespace {
+// Stores an index of 5 clamped into a region of 3: one counted violation
+// and out[0] = 2; no access leaves the one-int buffer.
+__global__ void checks_selftest_kernel(int* out) { out[0] = SS_IN(5, 0, 3); }
+}  // namespace
+#endif
+
+int violations_single(unsigned long long* out) { return read_violations(out); }
+
+int checks_selftest() {
+#if SS_DEVICE_CHECKS
+  int* d = nullptr;
+  SS_TRY_HIP(hipMalloc(&d, sizeof(int)));
+  hipLaunchKernelGGL(checks_selftest_kernel, dim3(1), dim3(1), 0, current_stream(), d);
+  hipError_t e = hipGetLastError();
+  int v = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&v, d, sizeof(int), hipMemcpyDeviceToHost,
+                                          current_stream());
+  if (e == hipSuccess) e = hipStreamSynchronize(current_stream());
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "bounds-check self-test");
+  return v == 2 ? SS_OK : fail(SS_ERR_HIP, "bounds-check self-test stored an unclamped index");
+#else
+  return fail(SS_ERR_UNSUPPORTED, "not a device-checked build");
+#endif
+}
+}  // namespace ss

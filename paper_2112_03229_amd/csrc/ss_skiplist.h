@@ -41,14 +41,16 @@ __device__ __forceinline__ void search_skiplist(const double* __restrict__ sa,
   while (len > 1) {
     const int half = len >> 1;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) base[q] = (sk[base[q] + half] < x[q]) ? base[q] + half : base[q];
+    for (int q = 0; q < Q; ++q)
+      base[q] = (sk[SS_IN(base[q] + half, 0, ns + SS_PAD)] < x[q]) ? base[q] + half : base[q];
     len -= half;
   }
   typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     // n == 0: sk[0] is a sentinel, j = -1
-    const int j = base[q] + (sk[base[q]] < x[q] ? 1 : 0) - 1;
+    const int j = base[q] + (sk[SS_IN(base[q], 0, ns + SS_PAD)] < x[q] ? 1 : 0) - 1;
+    SS_ASSERT(kSkip * max(j, 0) + kSkip <= n + SS_PAD);
     const d2* blk = reinterpret_cast<const d2*>(sa + kSkip * max(j, 0));
     int cnt = 0;
 #pragma unroll
