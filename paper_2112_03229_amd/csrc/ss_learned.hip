@@ -624,7 +624,17 @@ struct LearnedArgs {
   int E;
   float u0, inv;
   int model_off;  // byte offset of the model's LDS image (after the table; 0 if not staged)
+  int tail;       // +inf entries staged after the table (window_tail(n, E))
 };
+
+// Stages a[-2..n + tail) at sa: -inf, -inf, the table, tail copies of +inf
+// (the window's end checks and steps then need no clamps).
+__device__ __forceinline__ void stage_table_bounded(double* __restrict__ sa,
+                                                    const double* __restrict__ table, int n,
+                                                    int tail) {
+  for (int i = (int)threadIdx.x - 2; i < n + tail; i += blockDim.x)
+    sa[i] = i < 0 ? -__builtin_inf() : i < n ? table[i] : __builtin_inf();
+}
 
 // GLOBAL = 1: the table is too large to stage and is read in place from
 // global memory (L2-resident after the first reads); only the model is
@@ -632,7 +642,8 @@ struct LearnedArgs {
 template <int Q, int CONV, int GLOBAL>
 __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
-  const double* sa = GLOBAL ? a.table : reinterpret_cast<const double*>(lds);
+  // staged: two -inf entries, then the table (16-byte aligned)
+  const double* sa = GLOBAL ? a.table : reinterpret_cast<const double*>(lds + 16);
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
   const int64_t ntiles = (a.m + per_tile - 1) / per_tile;
@@ -640,7 +651,8 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   int64_t t = blockIdx.x;
   double cur[Q];
   if (t < ntiles) load_tile<Q>(a.x, a.m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= a.m, cur);
-  if constexpr (!GLOBAL) stage_table(reinterpret_cast<double*>(lds), a.table, a.n);
+  if constexpr (!GLOBAL)
+    stage_table_bounded(reinterpret_cast<double*>(lds + 16), a.table, a.n, a.tail);
   stage_image(model, a.img);
   __syncthreads();
   const ImageHead hd = image_head(model);
@@ -653,16 +665,23 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
     if constexpr (CONV) {
       double xs[Q];
       convention_in<Q>(cur, xs);
-      search_learned<Q, !GLOBAL>(sa, a.n, model, hd, a.E, a.u0, a.inv, xs, r, fell);
+      search_learned<Q, GLOBAL ? kWinGlobal : kWinBounded>(sa, a.n, model, hd, a.E, a.u0,
+                                                             a.inv, xs, r, fell);
       convention_out<Q>(a.n, cur, r);
     } else {
-      search_learned<Q, !GLOBAL>(sa, a.n, model, hd, a.E, a.u0, a.inv, cur, r, fell);
+      search_learned<Q, GLOBAL ? kWinGlobal : kWinBounded>(sa, a.n, model, hd, a.E, a.u0,
+                                                             a.inv, cur, r, fell);
     }
     const int64_t base = t * per_tile + threadIdx.x;
     const bool full = (t + 1) * per_tile <= a.m;
     // lanes past the end of the ragged last tile searched a stand-in
+    if (full) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) fb += (full || base + (int64_t)q * nt < a.m) ? fell[q] : 0;
+      for (int q = 0; q < Q; ++q) fb += fell[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) fb += base + (int64_t)q * nt < a.m ? fell[q] : 0;
+    }
     store_tile<Q>(a.out, a.m, base, nt, full, r);
     for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
   }
@@ -1054,8 +1073,10 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
     return rc;
   DeviceInfo di;
   if ((rc = device_info(&di)) != SS_OK) return rc;
-  // the table is staged with the model when both fit, else read in place
-  size_t tab = ((size_t)(h->n + SS_PAD) * 8 + 15) / 16 * 16;
+  // the table is staged with the model when both fit (two -inf entries,
+  // the table, window_tail +inf entries), else read in place
+  const int tail = window_tail(h->n, h->E);
+  size_t tab = 16 + ((size_t)(h->n + tail) * 8 + 15) / 16 * 16;
   const bool staged = tab + (size_t)h->image_floats * 4 <= kLearnedStageLimit;
   if (!staged) tab = 0;
   const size_t lds = tab + (size_t)h->image_floats * 4;
@@ -1070,7 +1091,7 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
   int64_t grid = (int64_t)blocks_per_cu(kern, kLearnedBlock, lds) * di.num_cus * 4;
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
   LearnedArgs a{h->table, h->d_image, targets, out_idx, h->d_fallbacks, m, h->n, h->E, h->u0,
-                h->inv, (int)tab};
+                h->inv, (int)tab, tail};
   void* args[] = {&a};
   SS_TRY_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(kLearnedBlock), args, lds, st));
   return SS_OK;

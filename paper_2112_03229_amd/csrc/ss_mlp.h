@@ -180,11 +180,26 @@ __device__ __forceinline__ int predicted_index(float p, int n) {
   return (int)fminf(fmaxf(g, -1.0f), (float)(n - 1));
 }
 
+// How search_learned may read the table sa:
+//   kWinGlobal : in place in global memory, no sentinels: every read is
+//                clamped into [0, n);
+//   kWinPadded : staged in LDS with SS_PAD +inf entries from a[n] on (plans);
+//   kWinBounded: staged with a -inf at a[-1] and at least
+//                window_tail(n, E) +inf entries from a[n] on, so that the
+//                window's end checks and steps need no clamps or branches.
+constexpr int kWinGlobal = 0, kWinPadded = 1, kWinBounded = 2;
+
+// +inf entries a kWinBounded table needs after a[n - 1]: the window steps
+// read at most index max(n - 1 + E, 2E - 1) (from L = max(g - E, -1) at most
+// 2 step - 1 <= 2E further, g <= n - 1).
+__host__ __device__ constexpr int window_tail(int n, int E) {
+  return E + 1 > 2 * E - n + 1 ? (E + 1 > SS_PAD ? E + 1 : SS_PAD)
+                               : (2 * E - n + 1 > SS_PAD ? 2 * E - n + 1 : SS_PAD);
+}
+
 // The verified window search for Q targets per lane.  m is the model's
-// compiled image in LDS, h its header.  sa is the table:
-// staged in LDS with +inf sentinels from a[n] on (SENTINEL), or read in
-// place from global memory (no sentinel; reads stay inside [0, n)).
-template <int Q, bool SENTINEL = true>
+// compiled image in LDS, h its header, sa the table read as MODE says.
+template <int Q, int MODE = kWinPadded>
 __device__ __forceinline__ void search_learned(const double* __restrict__ sa, int n,
                                                const float* m, const ImageHead& h, int E,
                                                float u0, float inv, const double (&x)[Q],
@@ -201,8 +216,14 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
   for (int q = 0; q < Q; ++q) {
     const int g = predicted_index(p[q], n);
     const int L = max(g - E, -1), R = min(g + E, n - 1);
-    const bool lo_ok = L < 0 || sa[SS_IN(max(L, 0), 0, n)] < x[q];
-    const bool hi_ok = R >= n - 1 || x[q] <= sa[SS_IN(min(R + 1, n - 1), 0, n)];
+    bool lo_ok, hi_ok;
+    if constexpr (MODE == kWinBounded) {  // a[-1] = -inf, a[n] = +inf
+      lo_ok = sa[SS_IN(L, -1, n)] < x[q];
+      hi_ok = x[q] <= sa[SS_IN(R + 1, 0, n + 1)];
+    } else {
+      lo_ok = L < 0 || sa[SS_IN(max(L, 0), 0, n)] < x[q];
+      hi_ok = R >= n - 1 || x[q] <= sa[SS_IN(min(R + 1, n - 1), 0, n)];
+    }
     ok |= (lo_ok && hi_ok) ? 1u << q : 0u;
     fell_back[q] = (lo_ok && hi_ok) ? 0 : 1;
     pos[q] = L + 1;
@@ -215,30 +236,53 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
   // 2 step - 1 >= 2E covers the window.  Lanes whose window failed run the
   // same steps harmlessly and are redone below.
   // The steps track r = pos - 1 as a byte offset into the table, which
-  // saves the index arithmetic of each step (the kernel is vector-bound).
+  // saves the index arithmetic of each step (the kernel is vector-bound);
+  // with the bounded table as the entry's 32-bit LDS address itself, one
+  // add per step (the table starts 16 bytes into LDS, so &a[-1] is a
+  // valid address).
   const char* sb = reinterpret_cast<const char*>(sa);
   const int n8 = n * 8;
-  int rb[Q];
+  if constexpr (MODE == kWinBounded) {
+    typedef const char __attribute__((address_space(3))) lds_char;
+    typedef const double __attribute__((address_space(3))) lds_double;
+    lds_char* const lb = (lds_char*)sb;
+    lds_char* pb[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) rb[q] = (pos[q] - 1) * 8;
-  for (int s8 = step * 8; s8 >= 8; s8 >>= 1) {
+    for (int q = 0; q < Q; ++q) pb[q] = lb + (pos[q] - 1) * 8;
+    for (int s8 = step * 8; s8 >= 8; s8 >>= 1) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int kb = rb[q] + s8;  // a[k], k = pos + s - 1 >= 0
-      bool lt;
-      if constexpr (SENTINEL) {
-        SS_ASSERT(kb >= 0);  // min(kb, n8) reads a[0..n], a[n] the sentinel
-        lt = *reinterpret_cast<const double*>(sb + min(kb, n8)) < x[q];
-      } else {
-        SS_ASSERT(kb >= 0);  // min(kb, n8 - 8) reads a[0..n-1]
-        lt = kb < n8 && *reinterpret_cast<const double*>(sb + min(kb, n8 - 8)) < x[q];
+      for (int q = 0; q < Q; ++q) {
+        lds_char* kp = pb[q] + s8;  // &a[k], k = pos + s - 1 >= 0: the +inf tail covers it
+        SS_ASSERT(kp >= lb && kp < lb + 8 * (n + window_tail(n, E)));
+        pb[q] = *(lds_double*)kp < x[q] ? kp : pb[q];
       }
-      rb[q] = lt ? kb : rb[q];
     }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) r[q] = (int)((pb[q] - lb) >> 3);
+  } else {
+    int rb[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) rb[q] = (pos[q] - 1) * 8;
+    for (int s8 = step * 8; s8 >= 8; s8 >>= 1) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int kb = rb[q] + s8;  // a[k], k = pos + s - 1 >= 0
+        bool lt;
+        if constexpr (MODE == kWinPadded) {
+          SS_ASSERT(kb >= 0);  // min(kb, n8) reads a[0..n], a[n] the sentinel
+          lt = *reinterpret_cast<const double*>(sb + min(kb, n8)) < x[q];
+        } else {
+          SS_ASSERT(kb >= 0);  // min(kb, n8 - 8) reads a[0..n-1]
+          lt = kb < n8 && *reinterpret_cast<const double*>(sb + min(kb, n8 - 8)) < x[q];
+        }
+        rb[q] = lt ? kb : rb[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) r[q] = rb[q] >> 3;
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    r[q] = rb[q] >> 3;
     if (!((ok >> q) & 1u)) {  // fallback: bisection over the whole table
       int base = 0, len = n;
       while (len > 1) {
