@@ -85,6 +85,16 @@ __device__ __forceinline__ void stage_table(double* __restrict__ sa,
     sa[i] = i < n ? table[i] : __builtin_inf();
 }
 
+// The bounded form for the learned search's window (see window_tail):
+// a[-2..n + tail) at sa = -inf, -inf, the table, tail copies of +inf.  sa
+// must have 16 bytes of its region before it.
+__device__ __forceinline__ void stage_table_bounded(double* __restrict__ sa,
+                                                    const double* __restrict__ table, int n,
+                                                    int tail) {
+  for (int i = (int)threadIdx.x - 2; i < n + tail; i += blockDim.x)
+    sa[i] = i < 0 ? -__builtin_inf() : i < n ? table[i] : __builtin_inf();
+}
+
 // ---------------------------------------------------------------------------
 // Exponent-hash bins (a2): parameters and the prefix-count table in LDS.
 //   key(v) = hi_word(v) >> (20 - s),  kmin = key(a[0]),  nb = key(a[n-1]) - kmin + 1

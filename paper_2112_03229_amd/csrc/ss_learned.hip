@@ -627,14 +627,6 @@ struct LearnedArgs {
   int tail;       // +inf entries staged after the table (window_tail(n, E))
 };
 
-// Stages a[-2..n + tail) at sa: -inf, -inf, the table, tail copies of +inf
-// (the window's end checks and steps then need no clamps).
-__device__ __forceinline__ void stage_table_bounded(double* __restrict__ sa,
-                                                    const double* __restrict__ table, int n,
-                                                    int tail) {
-  for (int i = (int)threadIdx.x - 2; i < n + tail; i += blockDim.x)
-    sa[i] = i < 0 ? -__builtin_inf() : i < n ? table[i] : __builtin_inf();
-}
 
 // GLOBAL = 1: the table is too large to stage and is read in place from
 // global memory (L2-resident after the first reads); only the model is

@@ -43,6 +43,8 @@ struct TableDesc {
   int shift, kmin, kmaxc, nb, K;
   int E;             // learned: error bound
   float u0, inv;     // learned: input normalisation
+  int tail;          // learned, bounded staging: +inf entries after the table
+  int pad_;
 };
 
 // Everything a workgroup needs to issue its first target loads, in one
@@ -120,11 +122,15 @@ struct Staged {
 // into LDS with 16-byte loads (the pool's bin tables start 16-byte aligned;
 // tables are 8-byte aligned, so they are copied in 8-byte words); for a
 // learned table, its model's LDS image.
+template <bool BOUNDED>
 __device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* __restrict__ tables,
                                              const uint16_t* __restrict__ bins,
                                              const float* __restrict__ params, double* sa,
                                              uint16_t* C, float* model) {
-  stage_table(sa, tables + d.tab_off, d.n);
+  if (BOUNDED && d.algo == SS_ALGO_LEARNED)
+    stage_table_bounded(sa, tables + d.tab_off, d.n, d.tail);
+  else
+    stage_table(sa, tables + d.tab_off, d.n);
   Staged st{{0, d.shift, d.kmin, d.kmaxc, d.nb, d.K}, d.algo == SS_ALGO_LEARNED, d.n, d.E,
             d.u0, d.inv, d.algo == SS_ALGO_BALLOT};
   if (d.algo == SS_ALGO_LEARNED) stage_image(model, params + d.p_off);
@@ -148,7 +154,8 @@ __device__ __forceinline__ void search_staged(const Staged& st, const double* sa
   for (int q = 0; q < Q; ++q) fell[q] = 0;
   if constexpr (LEARN) {
     if (st.learned) {  // uniform across the workgroup
-      search_learned<Q>(sa, st.n, model, hd, st.E, st.u0, st.inv, x, r, fell);
+      search_learned<Q, LEARN == 2 ? kWinBounded : kWinPadded>(sa, st.n, model, hd, st.E, st.u0,
+                                                               st.inv, x, r, fell);
       return;
     }
   }
@@ -253,10 +260,14 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   constexpr bool INTERP = MODE == kPairInterp;
   constexpr bool PAIRED = MODE == kPairJoint || INTERP;
   constexpr bool SPLIT = MODE == kPairSplit;
+  // LEARN = 2: learned tables are staged bounded (a -inf entry before the
+  // table, the +inf tail after it), so every table region starts 16 bytes in
+  constexpr bool BOUNDED = LEARN == 2;
+  constexpr int kLead = BOUNDED ? 16 : 0;
   extern __shared__ __align__(16) unsigned char lds[];
-  double* sa = reinterpret_cast<double*>(lds);
+  double* sa = reinterpret_cast<double*>(lds + kLead);
   uint16_t* Ca = reinterpret_cast<uint16_t*>(lds + a.lds_bins_a);
-  double* sb = reinterpret_cast<double*>(lds + a.lds_tab_b);
+  double* sb = reinterpret_cast<double*>(lds + a.lds_tab_b + kLead);
   uint16_t* Cb = reinterpret_cast<uint16_t*>(lds + a.lds_bins_b);
   float* Ma = reinterpret_cast<float*>(lds + a.lds_model_a);
   float* Mb = reinterpret_cast<float*>(lds + a.lds_model_b);
@@ -315,17 +326,23 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   Staged sta, stb{};
   Grid grid{nullptr, nullptr};
   double* lds_grid = reinterpret_cast<double*>(lds + a.lds_grid);
-  sta = stage_desc(a.desc[ws.seg], part ? a.tables_b : a.tables_a, a.bins, a.params, sa, Ca, Ma);
+  sta = stage_desc<BOUNDED>(a.desc[ws.seg], part ? a.tables_b : a.tables_a, a.bins, a.params, sa,
+                           Ca, Ma);
   if constexpr (PAIRED)
-    stb = stage_desc(a.desc[a.pair_base + ws.seg], a.tables_b, a.bins, a.params, sb, Cb, Mb);
+    stb = stage_desc<BOUNDED>(a.desc[a.pair_base + ws.seg], a.tables_b, a.bins, a.params, sb, Cb,
+                              Mb);
   if constexpr (INTERP) grid = stage_grid(a, ws.seg, sta.n, stb.n, lds_grid);
 #if SS_DEVICE_CHECKS
   // the host's LDS layout holds what was staged (learned images are
   // checked by their lookups)
-  SS_ASSERT((sta.n + SS_PAD) * 8 <= a.lds_bins_a);
+  SS_ASSERT(kLead + (sta.n + (BOUNDED && sta.learned ? a.desc[ws.seg].tail : SS_PAD)) * 8 <=
+            a.lds_bins_a);
   SS_ASSERT(!sta.hp.ok || a.lds_bins_a + (sta.hp.nb + 1) * 2 <= a.lds_tab_b);
   if constexpr (PAIRED) {
-    SS_ASSERT(a.lds_tab_b + (stb.n + SS_PAD) * 8 <= a.lds_bins_b);
+    SS_ASSERT(a.lds_tab_b + kLead +
+                  (stb.n + (BOUNDED && stb.learned ? a.desc[a.pair_base + ws.seg].tail : SS_PAD)) *
+                      8 <=
+              a.lds_bins_b);
     SS_ASSERT(!stb.hp.ok ||
               a.lds_bins_b + (stb.hp.nb + 1) * 2 <= (INTERP ? a.lds_grid : a.lds_model_a));
   }
@@ -535,6 +552,7 @@ struct ss_plan {
   int preset_conv = -1;                     // convention, else -1 / 0 (options decide)
   int num_wg = 0, xcd_groups = 1, xcd_chunk = 1;
   int grid = 0, block = 0, q = 0;
+  int learn = 0;  // plan kernel's learned form: 0 none, 1 clamped window, 2 bounded staging
   size_t lds = 0;
   int max_k = 0;
   ss::MultiArgs args{};
@@ -611,6 +629,8 @@ void describe(const TunedTable& tt, int64_t tab_off, TableDesc* d, int64_t* pool
   d->p_off = 0;
   d->E = 0;
   d->u0 = d->inv = 0.0f;
+  d->tail = 0;
+  d->pad_ = 0;
   if (tt.algo == SS_ALGO_EXPHASH) {
     d->bins_off = *pool_len;
     *pool_len += tt.nb + 1;
@@ -897,19 +917,21 @@ const void* plan_kernel_conv(bool conv) {
               : reinterpret_cast<const void*>(&multi_kernel<MODE, Q, LEARN, 0>);
 }
 
-const void* plan_kernel(int mode, bool learned, bool conv) {
+// learn: 0 no learned tables; 1 learned, clamped window; 2 learned, bounded staging
+template <int MODE, int Q>
+const void* plan_kernel_learn(int learn, bool conv) {
+  return learn == 2   ? plan_kernel_conv<MODE, Q, 2>(conv)
+         : learn == 1 ? plan_kernel_conv<MODE, Q, 1>(conv)
+                      : plan_kernel_conv<MODE, Q, 0>(conv);
+}
+
+const void* plan_kernel(int mode, int learn, bool conv) {
   switch (mode) {
     case kPairInterp:
       return reinterpret_cast<const void*>(&multi_kernel<kPairInterp, kPairQ, 0, 0>);
-    case kPairJoint:
-      return learned ? plan_kernel_conv<kPairJoint, kPairQ, 1>(conv)
-                     : plan_kernel_conv<kPairJoint, kPairQ, 0>(conv);
-    case kPairSplit:
-      return learned ? plan_kernel_conv<kPairSplit, kPlanQ, 1>(conv)
-                     : plan_kernel_conv<kPairSplit, kPlanQ, 0>(conv);
-    default:
-      return learned ? plan_kernel_conv<kBatched, kPlanQ, 1>(conv)
-                     : plan_kernel_conv<kBatched, kPlanQ, 0>(conv);
+    case kPairJoint: return plan_kernel_learn<kPairJoint, kPairQ>(learn, conv);
+    case kPairSplit: return plan_kernel_learn<kPairSplit, kPlanQ>(learn, conv);
+    default: return plan_kernel_learn<kBatched, kPlanQ>(learn, conv);
   }
 }
 
@@ -928,6 +950,31 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
                 size_t lds_tab_a, size_t lds_bins_a, size_t lds_tab_b, size_t lds_bins_b) {
   hipStream_t st = current_stream();
   const int T = p->T;
+  // Learned tables are staged bounded (a -inf entry before, window_tail
+  // +inf entries after) when every region still fits the staging budget
+  // that way; the window's checks and steps then need no clamps.  Every
+  // table region then starts 16 bytes in.  Otherwise the clamped form.
+  p->learn = p->learned_tables > 0 ? 1 : 0;
+  if (p->learned_tables > 0) {
+    const bool two = p->mode == kPairJoint || p->mode == kPairInterp;
+    size_t need_a = 16, need_b = two ? 16 : 0;
+    for (int t = 0; t < T; ++t) {
+      const TableDesc& d = p->desc[t];
+      const int rows = d.n + (d.algo == SS_ALGO_LEARNED ? window_tail(d.n, d.E) : SS_PAD);
+      const size_t need = 16 + align16((size_t)rows * 8);
+      if (two && t >= p->M) need_b = std::max(need_b, need);
+      else need_a = std::max(need_a, need);
+    }
+    if (!two) need_a = std::max(need_a, lds_tab_a);
+    if (need_a + lds_bins_a + need_b + lds_bins_b <= kPlanLdsBudget + 16 * 1024) {
+      p->learn = 2;
+      lds_tab_a = std::max(lds_tab_a, need_a);
+      if (two) lds_tab_b = std::max(lds_tab_b, need_b);
+      for (int t = 0; t < T; ++t)
+        if (p->desc[t].algo == SS_ALGO_LEARNED)
+          p->desc[t].tail = window_tail(p->desc[t].n, p->desc[t].E);
+    }
+  }
   SS_TRY_HIP(hipMalloc(&p->d_desc, sizeof(TableDesc) * T));
   SS_TRY_HIP(hipMalloc(&p->d_bins, sizeof(uint16_t) * std::max<int64_t>(pool_len, 8)));
   SS_TRY_HIP(hipMalloc(&p->d_k, sizeof(int) * T));
@@ -985,7 +1032,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   // interpolation locates cells with the strict index (its own definition)
   p->convention = p->mode != kPairInterp &&
                   (p->preset_conv >= 0 ? p->preset_conv : option(SS_OPT_CONVENTION)) != 0;
-  p->kernel = plan_kernel(p->mode, learned, p->convention);
+  p->kernel = plan_kernel(p->mode, p->learn, p->convention);
   DeviceInfo di;
   int rc = device_info(&di);
   if (rc != SS_OK) return rc;
