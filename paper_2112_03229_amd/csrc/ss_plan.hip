@@ -168,6 +168,21 @@ struct TileRange {
   int64_t q0, q1;
 };
 
+// Adds a tile's learned window misses to the lane's count; lanes past the
+// end of a short tile searched a stand-in and are not counted.  full is
+// uniform, so a whole tile takes the short path.
+template <int Q>
+__device__ __forceinline__ void count_fallbacks(bool full, TileRange cur, int nt,
+                                                const int (&fell)[Q], int& count) {
+  if (full) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) count += fell[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) count += cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1 ? fell[q] : 0;
+  }
+}
+
 template <int Q>
 __device__ __forceinline__ void load_range(const double* __restrict__ x, TileRange r,
                                            double (&v)[Q]) {
@@ -370,11 +385,7 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     search_tile<Q, LEARN, CONV>(sta, sa, Ca, Ma, oa, ca, r, fell);
     if constexpr (!INTERP)
       store_tile<Q>(oa_, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
-    if constexpr (LEARN) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q)
-        fallbacks += (full || cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1) ? fell[q] : 0;
-    }
+    if constexpr (LEARN) count_fallbacks<Q>(full, cur, nt, fell, fallbacks);
     if constexpr (INTERP) {
       int rt[Q];
       search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, ob, cb, rt, fell);
@@ -391,11 +402,7 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     } else if constexpr (PAIRED) {
       search_tile<Q, LEARN, CONV>(stb, sb, Cb, Mb, ob, cb, r, fell);
       store_tile<Q>(a.ob, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
-      if constexpr (LEARN) {
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-          fallbacks += (full || cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1) ? fell[q] : 0;
-      }
+      if constexpr (LEARN) count_fallbacks<Q>(full, cur, nt, fell, fallbacks);
     }
     cur = nx1;
     nx1 = nx2;
