@@ -85,13 +85,14 @@ __device__ __forceinline__ void stage_table(double* __restrict__ sa,
     sa[i] = i < n ? table[i] : __builtin_inf();
 }
 
-// The bounded form for the learned search's window (see window_tail):
-// a[-2..n + tail) at sa = -inf, -inf, the table, tail copies of +inf.  sa
-// must have 16 bytes of its region before it.
+// The bounded form for the learned search's window (see window_front and
+// window_tail): a[-front..n + tail) at sa = front copies of -inf, the
+// table, tail copies of +inf.  sa must have front entries of its region
+// before it.
 __device__ __forceinline__ void stage_table_bounded(double* __restrict__ sa,
                                                     const double* __restrict__ table, int n,
-                                                    int tail) {
-  for (int i = (int)threadIdx.x - 2; i < n + tail; i += blockDim.x)
+                                                    int front, int tail) {
+  for (int i = (int)threadIdx.x - front; i < n + tail; i += blockDim.x)
     sa[i] = i < 0 ? -__builtin_inf() : i < n ? table[i] : __builtin_inf();
 }
 

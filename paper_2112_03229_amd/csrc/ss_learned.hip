@@ -624,7 +624,8 @@ struct LearnedArgs {
   int E;
   float u0, inv;
   int model_off;  // byte offset of the model's LDS image (after the table; 0 if not staged)
-  int tail;       // +inf entries staged after the table (window_tail(n, E))
+  int lead;       // byte offset of a[0] in LDS (window_lead(E); staged only)
+  int tail;       // +inf entries staged after the table (window_tail(E))
 };
 
 
@@ -634,8 +635,8 @@ struct LearnedArgs {
 template <int Q, int CONV, int GLOBAL>
 __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
-  // staged: two -inf entries, then the table (16-byte aligned)
-  const double* sa = GLOBAL ? a.table : reinterpret_cast<const double*>(lds + 16);
+  // staged: the -inf front, then the table (16-byte aligned)
+  const double* sa = GLOBAL ? a.table : reinterpret_cast<const double*>(lds + a.lead);
   const int nt = blockDim.x;
   const int64_t per_tile = (int64_t)nt * Q;
   const int64_t ntiles = (a.m + per_tile - 1) / per_tile;
@@ -644,16 +645,18 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
   double cur[Q];
   if (t < ntiles) load_tile<Q>(a.x, a.m, t * per_tile + threadIdx.x, nt, (t + 1) * per_tile <= a.m, cur);
   if constexpr (!GLOBAL)
-    stage_table_bounded(reinterpret_cast<double*>(lds + 16), a.table, a.n, a.tail);
+    stage_table_bounded(reinterpret_cast<double*>(lds + a.lead), a.table, a.n,
+                        window_front(a.E), a.tail);
   stage_image(model, a.img);
   __syncthreads();
   const ImageHead hd = image_head(model);
-  int fb = 0;
+  uint64_t fb = 0;  // the wave's fallbacks (uniform: counted from ballots)
   for (; t < ntiles; t += gridDim.x) {
     const int64_t tn = t + gridDim.x;
     double nxt[Q];
     if (tn < ntiles) load_tile<Q>(a.x, a.m, tn * per_tile + threadIdx.x, nt, (tn + 1) * per_tile <= a.m, nxt);
-    int r[Q], fell[Q];
+    int r[Q];
+    uint64_t fell[Q];
     if constexpr (CONV) {
       double xs[Q];
       convention_in<Q>(cur, xs);
@@ -669,18 +672,17 @@ __global__ __launch_bounds__(256) void learned_kernel(LearnedArgs a) {
     // lanes past the end of the ragged last tile searched a stand-in
     if (full) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) fb += fell[q];
+      for (int q = 0; q < Q; ++q) fb += __builtin_popcountll(fell[q]);
     } else {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) fb += base + (int64_t)q * nt < a.m ? fell[q] : 0;
+      for (int q = 0; q < Q; ++q)
+        fb += __builtin_popcountll(fell[q] & __builtin_amdgcn_ballot_w64(base + (int64_t)q * nt < a.m));
     }
     store_tile<Q>(a.out, a.m, base, nt, full, r);
     for (int q = 0; q < Q; ++q) cur[q] = nxt[q];
   }
   // one atomic per wavefront
-  unsigned long long w = (unsigned long long)fb;
-  for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
-  if ((threadIdx.x & 63) == 0 && w) atomicAdd(a.fallbacks, w);
+  if ((threadIdx.x & 63) == 0 && fb) atomicAdd(a.fallbacks, (unsigned long long)fb);
 }
 
 __global__ void clear_counter_kernel(unsigned long long* c) { *c = 0ull; }
@@ -1065,10 +1067,10 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
     return rc;
   DeviceInfo di;
   if ((rc = device_info(&di)) != SS_OK) return rc;
-  // the table is staged with the model when both fit (two -inf entries,
-  // the table, window_tail +inf entries), else read in place
-  const int tail = window_tail(h->n, h->E);
-  size_t tab = 16 + ((size_t)(h->n + tail) * 8 + 15) / 16 * 16;
+  // the table is staged with the model when both fit (window_front -inf
+  // entries, the table, window_tail +inf entries), else read in place
+  const int tail = window_tail(h->E), lead = window_lead(h->E);
+  size_t tab = (size_t)lead + ((size_t)(h->n + tail) * 8 + 15) / 16 * 16;
   const bool staged = tab + (size_t)h->image_floats * 4 <= kLearnedStageLimit;
   if (!staged) tab = 0;
   const size_t lds = tab + (size_t)h->image_floats * 4;
@@ -1083,7 +1085,7 @@ int ss_learned_search(ss_learned* h, const double* targets, int64_t m, int32_t* 
   int64_t grid = (int64_t)blocks_per_cu(kern, kLearnedBlock, lds) * di.num_cus * 4;
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, ntiles));
   LearnedArgs a{h->table, h->d_image, targets, out_idx, h->d_fallbacks, m, h->n, h->E, h->u0,
-                h->inv, (int)tab, tail};
+                h->inv, (int)tab, lead, tail};
   void* args[] = {&a};
   SS_TRY_HIP(hipLaunchKernel(kern, dim3((unsigned)grid), dim3(kLearnedBlock), args, lds, st));
   return SS_OK;

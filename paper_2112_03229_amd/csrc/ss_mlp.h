@@ -184,50 +184,38 @@ __device__ __forceinline__ int predicted_index(float p, int n) {
 //   kWinGlobal : in place in global memory, no sentinels: every read is
 //                clamped into [0, n);
 //   kWinPadded : staged in LDS with SS_PAD +inf entries from a[n] on (plans);
-//   kWinBounded: staged with a -inf at a[-1] and at least
-//                window_tail(n, E) +inf entries from a[n] on, so that the
+//   kWinBounded: staged with window_front(E) -inf entries before a[0] and
+//                window_tail(E) +inf entries from a[n] on, so that the
 //                window's end checks and steps need no clamps or branches.
 constexpr int kWinGlobal = 0, kWinPadded = 1, kWinBounded = 2;
 
-// +inf entries a kWinBounded table needs after a[n - 1]: the window steps
-// read at most index max(n - 1 + E, 2E - 1) (from L = max(g - E, -1) at most
-// 2 step - 1 <= 2E further, g <= n - 1).
-__host__ __device__ constexpr int window_tail(int n, int E) {
-  return E + 1 > 2 * E - n + 1 ? (E + 1 > SS_PAD ? E + 1 : SS_PAD)
-                               : (2 * E - n + 1 > SS_PAD ? 2 * E - n + 1 : SS_PAD);
-}
+// A kWinBounded window [g - E, g + E] for a predicted g in [-1, n - 1] is
+// read without clamping: its lower check reads a[g - E] >= a[-E - 1], its
+// upper check a[g + E + 1] <= a[n + E].  The steps read from a[g - E] at
+// most one step ahead of an entry below the target (or of a[g - E]): step
+// s <= 2E + 1 at first, s <= E after that, and every entry below a
+// non-NaN target lies at or before a[n - 1], so no step reads past a[n + E].
+__host__ __device__ constexpr int window_front(int E) { return E + 1; }
+__host__ __device__ constexpr int window_tail(int E) { return E + 1 > SS_PAD ? E + 1 : SS_PAD; }
+// Bytes before a[0] of a bounded region: the front, rounded up to 16.
+__host__ __device__ constexpr int window_lead(int E) { return (window_front(E) * 8 + 15) / 16 * 16; }
 
 // The verified window search for Q targets per lane.  m is the model's
 // compiled image in LDS, h its header, sa the table read as MODE says.
+// fell[q] is the wave's mask of lanes whose target q took the fallback;
+// called by every lane of the wave.
 template <int Q, int MODE = kWinPadded>
 __device__ __forceinline__ void search_learned(const double* __restrict__ sa, int n,
                                                const float* m, const ImageHead& h, int E,
                                                float u0, float inv, const double (&x)[Q],
-                                               int (&r)[Q], int (&fell_back)[Q]) {
+                                               int (&r)[Q], uint64_t (&fell)[Q]) {
   float z[Q], p[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) z[q] = model_input(x[q], u0, inv);
   mlp_eval_q<Q>(m, h, z, p);
   int step = 1;
   while (step * 2 <= 2 * E + 1) step *= 2;  // >= half the window length
-  int pos[Q];
   unsigned ok = 0;  // bit q: target q's window was verified
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int g = predicted_index(p[q], n);
-    const int L = max(g - E, -1), R = min(g + E, n - 1);
-    bool lo_ok, hi_ok;
-    if constexpr (MODE == kWinBounded) {  // a[-1] = -inf, a[n] = +inf
-      lo_ok = sa[SS_IN(L, -1, n)] < x[q];
-      hi_ok = x[q] <= sa[SS_IN(R + 1, 0, n + 1)];
-    } else {
-      lo_ok = L < 0 || sa[SS_IN(max(L, 0), 0, n)] < x[q];
-      hi_ok = R >= n - 1 || x[q] <= sa[SS_IN(min(R + 1, n - 1), 0, n)];
-    }
-    ok |= (lo_ok && hi_ok) ? 1u << q : 0u;
-    fell_back[q] = (lo_ok && hi_ok) ? 0 : 1;
-    pos[q] = L + 1;
-  }
   // Window search, all Q together.  If the window is verified, pos = #{a <
   // x} lies in [L+1, R+1]: every entry up to a[L] is below x and every
   // entry from a[R+1] on is not, so the steps need no upper bound (a read
@@ -238,31 +226,49 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
   // The steps track r = pos - 1 as a byte offset into the table, which
   // saves the index arithmetic of each step (the kernel is vector-bound);
   // with the bounded table as the entry's 32-bit LDS address itself, one
-  // add per step (the table starts 16 bytes into LDS, so &a[-1] is a
-  // valid address).
+  // add per step.
   const char* sb = reinterpret_cast<const char*>(sa);
-  const int n8 = n * 8;
   if constexpr (MODE == kWinBounded) {
     typedef const char __attribute__((address_space(3))) lds_char;
     typedef const double __attribute__((address_space(3))) lds_double;
     lds_char* const lb = (lds_char*)sb;
+    lds_char* const lw = lb - 8 * E;  // &a[g - E] for g = 0
+    const int span = 8 * (2 * E + 1);  // from a[L] to a[R + 1]
     lds_char* pb[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) pb[q] = lb + (pos[q] - 1) * 8;
+    for (int q = 0; q < Q; ++q) {
+      pb[q] = lw + 8 * predicted_index(p[q], n);  // &a[L], L = g - E >= -E - 1
+      SS_ASSERT(pb[q] >= lb - 8 * window_front(E) && pb[q] + span < lb + 8 * (n + window_tail(E)));
+      const bool lo_ok = *(lds_double*)pb[q] < x[q];
+      const bool hi_ok = x[q] <= *(lds_double*)(pb[q] + span);
+      ok |= (lo_ok && hi_ok) ? 1u << q : 0u;
+      fell[q] = __builtin_amdgcn_ballot_w64(!(lo_ok && hi_ok));
+    }
     for (int s8 = step * 8; s8 >= 8; s8 >>= 1) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        lds_char* kp = pb[q] + s8;  // &a[k], k = pos + s - 1 >= 0: the +inf tail covers it
-        SS_ASSERT(kp >= lb && kp < lb + 8 * (n + window_tail(n, E)));
+        lds_char* kp = pb[q] + s8;  // &a[k]: inside the staged front and tail
+        SS_ASSERT(kp >= lb - 8 * window_front(E) && kp < lb + 8 * (n + window_tail(E)));
         pb[q] = *(lds_double*)kp < x[q] ? kp : pb[q];
       }
     }
+    // a verified window ends on the last entry below x: a[-1] (-inf) at the
+    // lowest
 #pragma unroll
-    for (int q = 0; q < Q; ++q) r[q] = (int)((pb[q] - lb) >> 3);
+    for (int q = 0; q < Q; ++q) r[q] = (int)(pb[q] - lb) >> 3;
   } else {
     int rb[Q];
+    const int n8 = n * 8;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) rb[q] = (pos[q] - 1) * 8;
+    for (int q = 0; q < Q; ++q) {
+      const int g = predicted_index(p[q], n);
+      const int L = max(g - E, -1), R = min(g + E, n - 1);
+      const bool lo_ok = L < 0 || sa[SS_IN(max(L, 0), 0, n)] < x[q];
+      const bool hi_ok = R >= n - 1 || x[q] <= sa[SS_IN(min(R + 1, n - 1), 0, n)];
+      ok |= (lo_ok && hi_ok) ? 1u << q : 0u;
+      fell[q] = __builtin_amdgcn_ballot_w64(!(lo_ok && hi_ok));
+      rb[q] = L * 8;  // (pos - 1) * 8, pos = L + 1
+    }
     for (int s8 = step * 8; s8 >= 8; s8 >>= 1) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {

@@ -97,6 +97,7 @@ struct MultiArgs {
                              // are xb[query_off[s] - split ...])
   int lds_bins_a, lds_tab_b, lds_bins_b;  // byte offsets in LDS
   int lds_model_a, lds_model_b;           // learned models' LDS images
+  int lead;          // bounded learned staging: bytes of every table region before a[0]
   // kPairInterp: value grids (material j's grid at value_off[j], row-major
   // over (density, temperature)), the interpolated output and whether the
   // index outputs oa / ob are written
@@ -128,7 +129,7 @@ __device__ __forceinline__ Staged stage_desc(const TableDesc& d, const double* _
                                              const float* __restrict__ params, double* sa,
                                              uint16_t* C, float* model) {
   if (BOUNDED && d.algo == SS_ALGO_LEARNED)
-    stage_table_bounded(sa, tables + d.tab_off, d.n, d.tail);
+    stage_table_bounded(sa, tables + d.tab_off, d.n, window_front(d.E), d.tail);
   else
     stage_table(sa, tables + d.tab_off, d.n);
   Staged st{{0, d.shift, d.kmin, d.kmaxc, d.nb, d.K}, d.algo == SS_ALGO_LEARNED, d.n, d.E,
@@ -149,7 +150,7 @@ template <int Q, int LEARN>
 __device__ __forceinline__ void search_staged(const Staged& st, const double* sa,
                                               const uint16_t* C, const float* model,
                                               const ImageHead& hd, const double (&x)[Q],
-                                              int (&r)[Q], int (&fell)[Q]) {
+                                              int (&r)[Q], uint64_t (&fell)[Q]) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) fell[q] = 0;
   if constexpr (LEARN) {
@@ -168,18 +169,20 @@ struct TileRange {
   int64_t q0, q1;
 };
 
-// Adds a tile's learned window misses to the lane's count; lanes past the
-// end of a short tile searched a stand-in and are not counted.  full is
-// uniform, so a whole tile takes the short path.
+// Adds a tile's learned window misses (the wave's masks) to the wave's
+// count; lanes past the end of a short tile searched a stand-in and are not
+// counted.  full is uniform, so a whole tile takes the short path.
 template <int Q>
 __device__ __forceinline__ void count_fallbacks(bool full, TileRange cur, int nt,
-                                                const int (&fell)[Q], int& count) {
+                                                const uint64_t (&fell)[Q], uint64_t& count) {
   if (full) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) count += fell[q];
+    for (int q = 0; q < Q; ++q) count += __builtin_popcountll(fell[q]);
   } else {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) count += cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1 ? fell[q] : 0;
+    for (int q = 0; q < Q; ++q)
+      count += __builtin_popcountll(
+          fell[q] & __builtin_amdgcn_ballot_w64(cur.q0 + threadIdx.x + (int64_t)q * nt < cur.q1));
   }
 }
 
@@ -210,7 +213,7 @@ __device__ __forceinline__ void store_tile_f64(double* __restrict__ out, int64_t
 template <int Q, int LEARN, int CONV>
 __device__ __forceinline__ void search_tile(const Staged& st, const double* sa, const uint16_t* C,
                                             const float* model, const ImageHead& hd,
-                                            const double (&x)[Q], int (&r)[Q], int (&fell)[Q]) {
+                                            const double (&x)[Q], int (&r)[Q], uint64_t (&fell)[Q]) {
   if constexpr (CONV) {
     double xs[Q];
     convention_in<Q>(x, xs);
@@ -275,14 +278,15 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
   constexpr bool INTERP = MODE == kPairInterp;
   constexpr bool PAIRED = MODE == kPairJoint || INTERP;
   constexpr bool SPLIT = MODE == kPairSplit;
-  // LEARN = 2: learned tables are staged bounded (a -inf entry before the
-  // table, the +inf tail after it), so every table region starts 16 bytes in
+  // LEARN = 2: learned tables are staged bounded (the -inf front before the
+  // table, the +inf tail after it), so every table region starts a.lead
+  // bytes in
   constexpr bool BOUNDED = LEARN == 2;
-  constexpr int kLead = BOUNDED ? 16 : 0;
+  const int lead = BOUNDED ? a.lead : 0;
   extern __shared__ __align__(16) unsigned char lds[];
-  double* sa = reinterpret_cast<double*>(lds + kLead);
+  double* sa = reinterpret_cast<double*>(lds + lead);
   uint16_t* Ca = reinterpret_cast<uint16_t*>(lds + a.lds_bins_a);
-  double* sb = reinterpret_cast<double*>(lds + a.lds_tab_b + kLead);
+  double* sb = reinterpret_cast<double*>(lds + a.lds_tab_b + lead);
   uint16_t* Cb = reinterpret_cast<uint16_t*>(lds + a.lds_bins_b);
   float* Ma = reinterpret_cast<float*>(lds + a.lds_model_a);
   float* Mb = reinterpret_cast<float*>(lds + a.lds_model_b);
@@ -350,14 +354,16 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
 #if SS_DEVICE_CHECKS
   // the host's LDS layout holds what was staged (learned images are
   // checked by their lookups)
-  SS_ASSERT(kLead + (sta.n + (BOUNDED && sta.learned ? a.desc[ws.seg].tail : SS_PAD)) * 8 <=
+  SS_ASSERT(lead + (sta.n + (BOUNDED && sta.learned ? a.desc[ws.seg].tail : SS_PAD)) * 8 <=
             a.lds_bins_a);
+  SS_ASSERT(!(BOUNDED && sta.learned) || window_front(sta.E) * 8 <= lead);
   SS_ASSERT(!sta.hp.ok || a.lds_bins_a + (sta.hp.nb + 1) * 2 <= a.lds_tab_b);
   if constexpr (PAIRED) {
-    SS_ASSERT(a.lds_tab_b + kLead +
+    SS_ASSERT(a.lds_tab_b + lead +
                   (stb.n + (BOUNDED && stb.learned ? a.desc[a.pair_base + ws.seg].tail : SS_PAD)) *
                       8 <=
               a.lds_bins_b);
+    SS_ASSERT(!(BOUNDED && stb.learned) || window_front(stb.E) * 8 <= lead);
     SS_ASSERT(!stb.hp.ok ||
               a.lds_bins_b + (stb.hp.nb + 1) * 2 <= (INTERP ? a.lds_grid : a.lds_model_a));
   }
@@ -370,7 +376,7 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     oa = image_head(Ma);
     if constexpr (PAIRED) ob = image_head(Mb);
   }
-  int fallbacks = 0;
+  uint64_t fallbacks = 0;  // the wave's learned window misses (uniform)
   for (int k = 0; k < count; ++k) {
     double ca2[Q], cb2[Q];
     TileRange nx2{0, 0};
@@ -381,7 +387,8 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     }
     const bool full = cur.q0 + per_tile == cur.q1;
     SS_ASSERT(cur.q0 >= q0 && cur.q1 <= q1 && cur.q0 < cur.q1 && cur.q1 - cur.q0 <= per_tile);
-    int r[Q], fell[Q];
+    int r[Q];
+    uint64_t fell[Q];
     search_tile<Q, LEARN, CONV>(sta, sa, Ca, Ma, oa, ca, r, fell);
     if constexpr (!INTERP)
       store_tile<Q>(oa_, cur.q1, cur.q0 + threadIdx.x, nt, full, r);
@@ -417,9 +424,7 @@ __global__ __launch_bounds__(1024) void multi_kernel(MultiArgs a) {
     }
   }
   if constexpr (LEARN) {
-    unsigned long long w = (unsigned long long)fallbacks;
-    for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
-    if ((threadIdx.x & 63) == 0 && w) atomicAdd(a.fallbacks, w);
+    if ((threadIdx.x & 63) == 0 && fallbacks) atomicAdd(a.fallbacks, (unsigned long long)fallbacks);
   }
 }
 
@@ -560,6 +565,7 @@ struct ss_plan {
   int num_wg = 0, xcd_groups = 1, xcd_chunk = 1;
   int grid = 0, block = 0, q = 0;
   int learn = 0;  // plan kernel's learned form: 0 none, 1 clamped window, 2 bounded staging
+  int lead = 0;   // learn = 2: bytes of every table region before a[0]
   size_t lds = 0;
   int max_k = 0;
   ss::MultiArgs args{};
@@ -957,29 +963,36 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
                 size_t lds_tab_a, size_t lds_bins_a, size_t lds_tab_b, size_t lds_bins_b) {
   hipStream_t st = current_stream();
   const int T = p->T;
-  // Learned tables are staged bounded (a -inf entry before, window_tail
-  // +inf entries after) when every region still fits the staging budget
-  // that way; the window's checks and steps then need no clamps.  Every
-  // table region then starts 16 bytes in.  Otherwise the clamped form.
+  // Learned tables are staged bounded (window_front -inf entries before,
+  // window_tail +inf entries after) when every region still fits the
+  // staging budget that way; the window's checks and steps then need no
+  // clamps.  Every table region then starts `lead` bytes in, the largest
+  // front of the plan's learned tables.  Otherwise the clamped form.
   p->learn = p->learned_tables > 0 ? 1 : 0;
+  p->lead = 0;
   if (p->learned_tables > 0) {
     const bool two = p->mode == kPairJoint || p->mode == kPairInterp;
-    size_t need_a = 16, need_b = two ? 16 : 0;
+    size_t lead = 16;
+    for (int t = 0; t < T; ++t)
+      if (p->desc[t].algo == SS_ALGO_LEARNED)
+        lead = std::max(lead, (size_t)window_lead(p->desc[t].E));
+    size_t need_a = lead, need_b = two ? lead : 0;
     for (int t = 0; t < T; ++t) {
       const TableDesc& d = p->desc[t];
-      const int rows = d.n + (d.algo == SS_ALGO_LEARNED ? window_tail(d.n, d.E) : SS_PAD);
-      const size_t need = 16 + align16((size_t)rows * 8);
+      const int rows = d.n + (d.algo == SS_ALGO_LEARNED ? window_tail(d.E) : SS_PAD);
+      const size_t need = lead + align16((size_t)rows * 8);
       if (two && t >= p->M) need_b = std::max(need_b, need);
       else need_a = std::max(need_a, need);
     }
     if (!two) need_a = std::max(need_a, lds_tab_a);
     if (need_a + lds_bins_a + need_b + lds_bins_b <= kPlanLdsBudget + 16 * 1024) {
       p->learn = 2;
+      p->lead = (int)lead;
       lds_tab_a = std::max(lds_tab_a, need_a);
       if (two) lds_tab_b = std::max(lds_tab_b, need_b);
       for (int t = 0; t < T; ++t)
         if (p->desc[t].algo == SS_ALGO_LEARNED)
-          p->desc[t].tail = window_tail(p->desc[t].n, p->desc[t].E);
+          p->desc[t].tail = window_tail(p->desc[t].E);
     }
   }
   SS_TRY_HIP(hipMalloc(&p->d_desc, sizeof(TableDesc) * T));
@@ -1140,6 +1153,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   a.lds_bins_b = (int)(lds_tab_a + lds_bins_a + lds_tab_b);
   a.lds_model_a = model_a;
   a.lds_model_b = model_b;
+  a.lead = p->lead;
 
   // the graph holds the one search launch (preceded, with learned tables, by
   // a one-thread node clearing the fallback counter); pointers are updated
