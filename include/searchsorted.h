@@ -535,6 +535,10 @@ SS_API int ss_plan_info(const ss_plan *plan, int what, void *out, int64_t cap);
  * [L, R] = [g - E, g + E] clamped to [-1, n-1] is accepted if
  * (L == -1 or a[L] < x) and (R == n-1 or x <= a[R+1]); the index is then
  * found by bisection inside it, otherwise by bisection over the whole table.
+ * A table staged in LDS with -inf entries before a[0] and +inf entries after
+ * a[n-1] takes the window unclamped and widened at the top to
+ * [g - E, g - E + 2s - 1], s the largest power of two <= 2E + 1 (the
+ * bisection's 2s positions), with the same acceptance test.
  * E = 1 + the largest |g(x) - idx(x)| over the entries, their upward
  * neighbours and the log-midpoints between entries, measured on the device
  * with the search's own prediction code.

@@ -143,9 +143,17 @@ __device__ __forceinline__ void mlp_eval_q(const float* m, const ImageHead& h,
     }
     // base + k < nb + kCellScan <= nbp: reads past the cell's boundaries
     // meet later cells' boundaries (not below z) or the +inf padding
-    for (int k = 0; k < h.K; ++k) {
+    if (h.K <= 2) {  // uniform: both boundaries from one two-word read
 #pragma unroll
-      for (int q = 0; q < Q; ++q) i[q] += (b[SS_IN(base[q] + k, 0, h.nbp)] < z[q]) ? 1 : 0;
+      for (int q = 0; q < Q; ++q) {
+        const int k = SS_IN(base[q], 0, h.nbp - 1);
+        i[q] += (b[k] < z[q] ? 1 : 0) + (b[k + 1] < z[q] ? 1 : 0);
+      }
+    } else {
+      for (int k = 0; k < h.K; ++k) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) i[q] += (b[SS_IN(base[q] + k, 0, h.nbp)] < z[q]) ? 1 : 0;
+      }
     }
   } else {
 #pragma unroll
@@ -189,14 +197,26 @@ __device__ __forceinline__ int predicted_index(float p, int n) {
 //                window's end checks and steps need no clamps or branches.
 constexpr int kWinGlobal = 0, kWinPadded = 1, kWinBounded = 2;
 
-// A kWinBounded window [g - E, g + E] for a predicted g in [-1, n - 1] is
-// read without clamping: its lower check reads a[g - E] >= a[-E - 1], its
-// upper check a[g + E + 1] <= a[n + E].  The steps read from a[g - E] at
-// most one step ahead of an entry below the target (or of a[g - E]): step
-// s <= 2E + 1 at first, s <= E after that, and every entry below a
-// non-NaN target lies at or before a[n - 1], so no step reads past a[n + E].
+// The window bisection's first step for a bound E: the largest power of
+// two <= 2E + 1, so that its 2 step positions cover the 2E + 1 of [g - E,
+// g + E].
+__host__ __device__ constexpr int window_step(int E) {
+  int s = 1;
+  while (s * 2 <= 2 * E + 1) s *= 2;
+  return s;
+}
+
+// A kWinBounded window is [L, L + 2 step - 1], L = g - E for a predicted g
+// in [-1, n - 1], read without clamping: its lower check reads a[L] >=
+// a[-E - 1], its upper check a[L + 2 step] <= a[n - 1 - E + 2 step].  The
+// steps read from a[L] at most one step ahead of an entry below the target
+// (or of a[L]): step s <= 2E + 1 at first, s <= E after that, and every
+// entry below a non-NaN target lies at or before a[n - 1], so no step
+// reads past a[n - 1 + 2 step - E] either.
 __host__ __device__ constexpr int window_front(int E) { return E + 1; }
-__host__ __device__ constexpr int window_tail(int E) { return E + 1 > SS_PAD ? E + 1 : SS_PAD; }
+__host__ __device__ constexpr int window_tail(int E) {
+  return 2 * window_step(E) - E > SS_PAD ? 2 * window_step(E) - E : SS_PAD;
+}
 // Bytes before a[0] of a bounded region: the front, rounded up to 16.
 __host__ __device__ constexpr int window_lead(int E) { return (window_front(E) * 8 + 15) / 16 * 16; }
 
@@ -213,16 +233,16 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
 #pragma unroll
   for (int q = 0; q < Q; ++q) z[q] = model_input(x[q], u0, inv);
   mlp_eval_q<Q>(m, h, z, p);
-  int step = 1;
-  while (step * 2 <= 2 * E + 1) step *= 2;  // >= half the window length
+  const int step = window_step(E);  // >= half the window length
   unsigned ok = 0;  // bit q: target q's window was verified
   // Window search, all Q together.  If the window is verified, pos = #{a <
   // x} lies in [L+1, R+1]: every entry up to a[L] is below x and every
   // entry from a[R+1] on is not, so the steps need no upper bound (a read
   // at or past R+1 never advances pos; a read past the table counts as
   // +inf: the sentinel a[n], or an explicit test without one).
-  // 2 step - 1 >= 2E covers the window.  Lanes whose window failed run the
-  // same steps harmlessly and are redone below.
+  // 2 step - 1 >= R - L covers the window (R = g + E, or L + 2 step - 1 for
+  // a bounded table).  Lanes whose window failed run the same steps
+  // harmlessly and are redone below.
   // The steps track r = pos - 1 as a byte offset into the table, which
   // saves the index arithmetic of each step (the kernel is vector-bound);
   // with the bounded table as the entry's 32-bit LDS address itself, one
@@ -233,7 +253,7 @@ __device__ __forceinline__ void search_learned(const double* __restrict__ sa, in
     typedef const double __attribute__((address_space(3))) lds_double;
     lds_char* const lb = (lds_char*)sb;
     lds_char* const lw = lb - 8 * E;  // &a[g - E] for g = 0
-    const int span = 8 * (2 * E + 1);  // from a[L] to a[R + 1]
+    const int span = 16 * step;  // from a[L] to a[R + 1], R + 1 = L + 2 step
     lds_char* pb[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
