@@ -611,9 +611,15 @@ constexpr int kShortSegmentTiles = 64;  // in tiles of 4096 targets
 // workgroups per CU fit in 160 KB.
 constexpr size_t kPlanLdsBudget = 48 * 1024;
 // Interpolation plans stage a material's value grid in LDS when it has at
-// most this many float64 values (72 KB: two 512-thread workgroups per CU
-// with their axes).
-constexpr int64_t kInterpGridLdsValues = 9216;
+// most this many float64 values (120 KB: with the axes, one workgroup per
+// CU).  Measured on 1024 materials (grids of 1000 to 14850 values, 1e9
+// pairs): grids up to 9216 values staged (72 KB, two 512-thread workgroups
+// per CU; the other 15% of the pairs read their corners from L2) 5.51-5.66
+// ms; up to 5632 values (three workgroups per CU) 6.84-7.07 ms; every grid
+// staged, one 1024-thread workgroup per CU, 5.08-5.11 ms.
+constexpr int64_t kInterpGridLdsValues = 15360;
+// A staged grid above this size leaves its CU to one workgroup.
+constexpr size_t kInterpGridShared = 72 * 1024;
 
 int check_offsets(const int64_t* off, int32_t T, const char* name, int64_t max_len) {
   if (!off) return fail(SS_ERR_INVALID_ARG, std::string(name) + " is null");
@@ -669,9 +675,13 @@ struct PlanPreset {
   std::vector<std::vector<float>> weights;
 };
 
-// Block size and targets per lane of a plan of this form.
-int plan_block() {
-  return option(SS_OPT_BLOCK_SIZE) > 0 ? (int)option(SS_OPT_BLOCK_SIZE) : kPlanBlock;
+// Block size and targets per lane of a plan of this form.  An
+// interpolation plan whose staged grids leave each CU to one workgroup
+// takes the largest workgroup (1024 threads: 5.61 ms against 5.99 at 512 on
+// the 1024-material workload, every grid staged).
+int plan_block(int mode = kBatched, size_t grid_bytes = 0) {
+  if (option(SS_OPT_BLOCK_SIZE) > 0) return (int)option(SS_OPT_BLOCK_SIZE);
+  return mode == kPairInterp && grid_bytes > kInterpGridShared ? 1024 : kPlanBlock;
 }
 int plan_q(int mode) { return mode == kPairJoint || mode == kPairInterp ? kPairQ : kPlanQ; }
 
@@ -1016,7 +1026,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
     p->max_k = std::max(p->max_k, k[t]);
   }
 
-  p->block = plan_block();
+  p->block = plan_block(p->mode, p->mode == kPairInterp ? (size_t)p->grid_cap * 8 : 0);
   // learned plans take the same targets per lane as plain ones (measured
   // on the batched and split forms: 8 beat 4, 2 and 1)
   p->q = plan_q(p->mode);
@@ -1066,9 +1076,18 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   if (p->lds > 65536)
     SS_TRY_HIP(hipFuncSetAttribute(p->kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)p->lds));
-  const int resident = blocks_per_cu(p->kernel, p->block, p->lds) * di.num_cus;
+  const int per_cu = blocks_per_cu(p->kernel, p->block, p->lds);
+  const int resident = per_cu * di.num_cus;
   p->tiles_per_wg = choose_tiles_per_workgroup(tuner_model(), p->total_tiles, resident, S,
                                                per_tile);
+  // An interpolation workgroup alone on its CU stages its grid with no
+  // other workgroup's work to overlap: four times the tiles (5 / 20 / 40
+  // tiles of 4096 pairs per workgroup: 5.61 / 5.11 / 5.09 ms on the
+  // 1024-material workload), while that leaves six workgroups per slot.
+  if (p->mode == kPairInterp && per_cu == 1)
+    p->tiles_per_wg = (int)std::max<int64_t>(
+        p->tiles_per_wg,
+        std::min<int64_t>(4LL * p->tiles_per_wg, p->total_tiles / (6LL * resident)));
   if (option(SS_OPT_PLAN_TILES) > 0) p->tiles_per_wg = (int)option(SS_OPT_PLAN_TILES);
   if (p->preset_tiles > 0) p->tiles_per_wg = p->preset_tiles;
   // Each segment's tiles go to ceil(tiles / k) workgroups of at most k
