@@ -593,6 +593,17 @@ namespace {
 constexpr int kPlanBlock = 512;
 constexpr int kPlanQ = 8;
 constexpr int kPairQ = 4;
+// Batched and split plans whose learned tables carry at least this share of
+// the targets take 4 targets per lane (the learned search at 8 holds 121
+// VGPRs, 4 waves per SIMD; at 4, 65 and 7).  Measured: every table learned,
+// the 512-table batch 374-376 Gq/s at 8 against 423-425 at 4, the paired
+// workload 353 against 404-405; one learned table among 512 (the others
+// exponent hash), 506 at 8 against 493 at 4.  The per-target costs those
+// imply break even at a learned share of about 15%.
+constexpr double kLearnedQ4Share = 0.15;
+// Set by the tuner's calibration: learned plans take kPlanQ whatever their
+// share (the cost a learned table has in a plan of few of them).
+thread_local bool t_learned_q_fixed = false;
 constexpr int kDefaultPlanLearnedSteps = 500;
 constexpr int kXcds = 8;                  // accelerator complex dies of an MI355X
 // Workgroup ranges per XCD turn for plans with long segments.  Measured on
@@ -683,7 +694,10 @@ int plan_block(int mode = kBatched, size_t grid_bytes = 0) {
   if (option(SS_OPT_BLOCK_SIZE) > 0) return (int)option(SS_OPT_BLOCK_SIZE);
   return mode == kPairInterp && grid_bytes > kInterpGridShared ? 1024 : kPlanBlock;
 }
-int plan_q(int mode) { return mode == kPairJoint || mode == kPairInterp ? kPairQ : kPlanQ; }
+int plan_q(int mode, double learned_share = 0.0) {
+  if (mode == kPairJoint || mode == kPairInterp) return kPairQ;
+  return learned_share >= kLearnedQ4Share ? kPairQ : kPlanQ;
+}
 
 // Wave footprints sampled per table for the ballot scan's bracket.
 constexpr int kBracketSamples = 32;
@@ -948,13 +962,23 @@ const void* plan_kernel_learn(int learn, bool conv) {
                       : plan_kernel_conv<MODE, Q, 0>(conv);
 }
 
-const void* plan_kernel(int mode, int learn, bool conv) {
+// Batched and split plans: kPlanQ targets per lane, or kPairQ for plans of
+// mostly learned targets (which always have learned tables).
+template <int MODE>
+const void* plan_kernel_q(int q, int learn, bool conv) {
+  if (q == kPairQ && learn > 0)
+    return learn == 2 ? plan_kernel_conv<MODE, kPairQ, 2>(conv)
+                      : plan_kernel_conv<MODE, kPairQ, 1>(conv);
+  return plan_kernel_learn<MODE, kPlanQ>(learn, conv);
+}
+
+const void* plan_kernel(int mode, int q, int learn, bool conv) {
   switch (mode) {
     case kPairInterp:
       return reinterpret_cast<const void*>(&multi_kernel<kPairInterp, kPairQ, 0, 0>);
     case kPairJoint: return plan_kernel_learn<kPairJoint, kPairQ>(learn, conv);
-    case kPairSplit: return plan_kernel_learn<kPairSplit, kPlanQ>(learn, conv);
-    default: return plan_kernel_learn<kBatched, kPlanQ>(learn, conv);
+    case kPairSplit: return plan_kernel_q<kPairSplit>(q, learn, conv);
+    default: return plan_kernel_q<kBatched>(q, learn, conv);
   }
 }
 
@@ -1027,9 +1051,18 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   }
 
   p->block = plan_block(p->mode, p->mode == kPairInterp ? (size_t)p->grid_cap * 8 : 0);
-  // learned plans take the same targets per lane as plain ones (measured
-  // on the batched and split forms: 8 beat 4, 2 and 1)
-  p->q = plan_q(p->mode);
+  // targets per lane: the form's, or fewer for a plan of mostly learned
+  // targets (segment s searches descriptor s in the batched and split forms)
+  double learned_share = 0.0;
+  if (p->learned_tables > 0 && !t_learned_q_fixed &&
+      (p->mode == kBatched || p->mode == kPairSplit)) {
+    int64_t lq = 0;
+    for (int s = 0; s < p->S; ++s)
+      if (p->desc[s].algo == SS_ALGO_LEARNED) lq += p->query_off[s + 1] - p->query_off[s];
+    const int64_t all = p->query_off[p->S] - p->query_off[0];
+    learned_share = all > 0 ? (double)lq / (double)all : 0.0;
+  }
+  p->q = plan_q(p->mode, learned_share);
   const int64_t per_tile = (int64_t)p->block * p->q;
   // tiles of every segment, numbered back to back; a segment's positions are
   // taken relative to the start of its own target array
@@ -1062,7 +1095,7 @@ int finish_plan(ss_plan* p, const double* tables_a, const double* tables_b, int6
   // interpolation locates cells with the strict index (its own definition)
   p->convention = p->mode != kPairInterp &&
                   (p->preset_conv >= 0 ? p->preset_conv : option(SS_OPT_CONVENTION)) != 0;
-  p->kernel = plan_kernel(p->mode, p->learn, p->convention);
+  p->kernel = plan_kernel(p->mode, p->q, p->learn, p->convention);
   DeviceInfo di;
   int rc = device_info(&di);
   if (rc != SS_OK) return rc;
@@ -1864,4 +1897,5 @@ int ss_plan_info(const ss_plan* p, int what, void* out, int64_t cap) {
 
 namespace ss {
 int violations_plan(unsigned long long* out) { return read_violations(out); }
+void plan_learned_q_fixed(bool fixed) { t_learned_q_fixed = fixed; }
 }  // namespace ss

@@ -72,6 +72,11 @@ TunedTable tune_table(const TunerModel& model, const double* a, int n, size_t bi
 int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int resident,
                                int segments, int64_t per_tile);
 
+// While set (on this thread), plans with learned tables keep the plain
+// targets per lane whatever their learned share: the calibration prices a
+// learned table as it runs in a plan of few of them (ss_plan.hip).
+void plan_learned_q_fixed(bool fixed);
+
 // Longest run of equal exponent-hash keys (the largest bin) at bits s.
 int host_longest_bin(const double* a, int n, int s);
 

@@ -420,11 +420,15 @@ int time_plan(const std::vector<double>& h, int copies, int64_t per, const doubl
   (void)ss_get_option(SS_OPT_PLAN_LEARNED, &old_learned);
   (void)ss_set_option(SS_OPT_PLAN_ALGO, algo);
   (void)ss_set_option(SS_OPT_PLAN_LEARNED, learned);
+  // a learned table is priced as it runs among plain tables (a plan of
+  // mostly learned targets runs faster than that)
+  plan_learned_q_fixed(true);
   ss_plan* plan = nullptr;
   int rc = sampled ? ss_multi_plan_create_sampled(static_cast<double*>(tb.p), toff.data(), copies,
                                                   qoff.data(), xd, &plan)
                    : ss_multi_plan_create(static_cast<double*>(tb.p), toff.data(), copies,
                                           qoff.data(), &plan);
+  plan_learned_q_fixed(false);
   (void)ss_set_option(SS_OPT_PLAN_ALGO, old_algo);
   (void)ss_set_option(SS_OPT_PLAN_LEARNED, old_learned);
   if (rc != SS_OK) return rc;

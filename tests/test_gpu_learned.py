@@ -353,6 +353,43 @@ def test_save_and_load(binding, gpu, oracle_mod, inputs_mod, trained, tmp_path):
         binding.LearnedIndex.load(t, str(bad))
 
 
+def plan_tiles(query_off, per_tile):
+    """Tiles of a batched plan: each segment's aligned blocks of per_tile."""
+    q0, q1 = np.asarray(query_off[:-1]), np.asarray(query_off[1:])
+    return int(np.where(q1 > q0, (q1 - 1) // per_tile - q0 // per_tile + 1, 0).sum())
+
+
+def test_plan_targets_per_lane_follow_learned_share(binding, gpu, oracle_mod, inputs_mod):
+    """A batched plan whose learned tables carry at least 15% of the targets
+    searches 4 targets per lane (tiles of 2048 targets at 512 threads), one
+    with fewer learned targets keeps 8 (tiles of 4096), like a plain plan;
+    the indices are exact either way."""
+    batch = inputs_mod.batched_layout(seed=37, num_tables=6, query_scale=0.1)
+    tt = torch.from_numpy(batch.tables).to(gpu)
+    off, qoff = batch.table_off, np.asarray(batch.query_off)
+    x = np.empty(batch.num_queries)
+    inputs_mod.batched_targets(batch, out=x)
+    want = oracle_mod.search_lt_segments(batch.tables, off, x, qoff)
+    xd = torch.from_numpy(x).to(gpu)
+    counts = np.diff(qoff)
+    small = int(np.argmin(counts))
+    assert counts[small] / counts.sum() < 0.15 and plan_tiles(qoff, 2048) > plan_tiles(qoff, 4096)
+    for learned in ([small], list(range(6))):
+        share = counts[learned].sum() / counts.sum()
+        say(f"case learned tables {learned} share {share:.3f}")
+        models = [None] * 6
+        for t in learned:
+            models[t] = binding.LearnedIndex(tt[off[t]:off[t + 1]], steps=300, seed=t)
+        plan = binding.MultiPlan(tt, off, qoff, models=models)
+        for m in models:
+            if m is not None:
+                m.close()
+        q = 4 if share >= 0.15 else 8
+        assert plan.info()["tiles"] == plan_tiles(qoff, 512 * q)
+        assert np.array_equal(plan.search(xd).cpu().numpy(), want)
+        plan.close()
+
+
 def test_plan_with_attached_models(binding, gpu, oracle_mod, inputs_mod):
     """Learned handles built on tables of a batch are attached to a batched
     plan (ss_multi_plan_create_learned): those tables are searched through
