@@ -359,8 +359,8 @@ def paired_headline(torch, binding, inputs, dev, args) -> tuple:
     searches = 2 * m
     value = searches * args.steps / wall / 1e9
     achieved = searches * BYTES_PER_QUERY / (avg_launch_ms * 1e-3) / 1e9
-    learned = counts["learned_tables"] > 0
-    kernel = f"ss::multi_kernel<2, 8, {int(learned)}, 0> (split paired plan)"
+    kernel = (f"ss::multi_kernel<2, {info['targets_per_lane']}, {info['learned_form']}, 0> "
+              "(split paired plan)")
     result = {
         "metric": METRIC,
         "value": round(value, 3),

@@ -484,7 +484,10 @@ SS_API int ss_plan_fallbacks(ss_plan *plan, int64_t *count);
  *   SS_PLAN_BITS   : int32 per table (bin bits s, -1 for bisection)
  *   SS_PLAN_SUMMARY: 8 int64 {tables, tiles, tiles per workgroup, grid,
  *                    block, lds_bytes, longest bin (9 = 9 or more),
- *                    graph launches so far}
+ *                    graph launches so far}; with cap >= 10 also the
+ *                    targets per lane and the learned form of the search
+ *                    kernel (0: no learned table, 1: clamped windows,
+ *                    2: bounded staging)
  *   SS_PLAN_COSTS  : 2 doubles per table (cap >= 2 T): the autotuner's
  *                    modelled ns per query of its best plain kernel, and of
  *                    the table's trained learned model (-1 if none was

@@ -238,7 +238,7 @@ def loghash_bins(table: torch.Tensor, nb: int):
 
 PLAN_ALGOS, PLAN_BITS, PLAN_SUMMARY, PLAN_COSTS, PLAN_BRACKETS = 1, 2, 3, 4, 5
 SUMMARY_KEYS = ("tables", "tiles", "tiles_per_wg", "grid", "block", "lds_bytes",
-                "max_bin", "graph_uses")
+                "max_bin", "graph_uses", "targets_per_lane", "learned_form")
 
 
 def _host_offsets(off, name):
@@ -282,10 +282,10 @@ class _Plan:
         T = self.num_descriptors
         algos = np.zeros(T, dtype=np.int32)
         bits = np.zeros(T, dtype=np.int32)
-        summ = np.zeros(8, dtype=np.int64)
+        summ = np.zeros(len(SUMMARY_KEYS), dtype=np.int64)
         check(lib().ss_plan_info(self._handle, PLAN_ALGOS, _off_ptr(algos), T))
         check(lib().ss_plan_info(self._handle, PLAN_BITS, _off_ptr(bits), T))
-        check(lib().ss_plan_info(self._handle, PLAN_SUMMARY, _off_ptr(summ), 8))
+        check(lib().ss_plan_info(self._handle, PLAN_SUMMARY, _off_ptr(summ), summ.size))
         costs = np.zeros(2 * T, dtype=np.float64)
         check(lib().ss_plan_info(self._handle, PLAN_COSTS, _off_ptr(costs), 2 * T))
         out = dict(zip(SUMMARY_KEYS, (int(v) for v in summ)))

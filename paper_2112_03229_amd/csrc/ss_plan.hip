@@ -1886,6 +1886,10 @@ int ss_plan_info(const ss_plan* p, int what, void* out, int64_t cap) {
       o[5] = (int64_t)p->lds;
       o[6] = p->max_k;
       o[7] = p->graph_uses;
+      if (cap >= 10) {
+        o[8] = p->q;
+        o[9] = p->learn;
+      }
       return SS_OK;
     }
     default:

@@ -374,6 +374,11 @@ def test_plan_targets_per_lane_follow_learned_share(binding, gpu, oracle_mod, in
     counts = np.diff(qoff)
     small = int(np.argmin(counts))
     assert counts[small] / counts.sum() < 0.15 and plan_tiles(qoff, 2048) > plan_tiles(qoff, 4096)
+    plain = binding.MultiPlan(tt, off, qoff)
+    info = plain.info()
+    assert info["targets_per_lane"] == 8 and info["learned_form"] == 0
+    assert info["tiles"] == plan_tiles(qoff, 4096)
+    plain.close()
     for learned in ([small], list(range(6))):
         share = counts[learned].sum() / counts.sum()
         say(f"case learned tables {learned} share {share:.3f}")
@@ -385,7 +390,9 @@ def test_plan_targets_per_lane_follow_learned_share(binding, gpu, oracle_mod, in
             if m is not None:
                 m.close()
         q = 4 if share >= 0.15 else 8
-        assert plan.info()["tiles"] == plan_tiles(qoff, 512 * q)
+        info = plan.info()
+        assert info["targets_per_lane"] == q and info["learned_form"] in (1, 2)
+        assert info["tiles"] == plan_tiles(qoff, 512 * q)
         assert np.array_equal(plan.search(xd).cpu().numpy(), want)
         plan.close()
 
