@@ -51,24 +51,54 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Sources each profiled kernel is compiled from: a counter record in
-# profiles/traffic.json is used only while these files are unchanged.
+# Sources each profiled kernel and its launch are built from: a counter
+# record in profiles/traffic.json is used only while their code is
+# unchanged.  Comments and blank space do not count (the digest is taken
+# over the text with comments removed and space collapsed), so a record
+# survives edits of wording but not of code.
 KERNEL_SOURCES = {
-    "single": ("csrc/ss_single.hip", "csrc/ss_device.h", "csrc/ss_host.h"),
+    "single": ("csrc/ss_single.hip", "csrc/ss_device.h", "csrc/ss_host.h", "csrc/ss_loghash.h",
+               "csrc/ss_skiplist.h", "../include/searchsorted.h"),
     "plan": ("csrc/ss_plan.hip", "csrc/ss_device.h", "csrc/ss_host.h", "csrc/ss_mlp.h",
-             "csrc/ss_learned.h", "csrc/ss_tuner.h"),
+             "csrc/ss_learned.h", "csrc/ss_tuner.h", "csrc/ss_tuner.hip",
+             "../include/searchsorted.h"),
     "learned": ("csrc/ss_learned.hip", "csrc/ss_device.h", "csrc/ss_host.h", "csrc/ss_mlp.h",
-                "csrc/ss_learned.h"),
+                "csrc/ss_learned.h", "../include/searchsorted.h"),
 }
+
+
+def _code_only(text: str) -> str:
+    """C/C++ source without comments, runs of white space collapsed (string
+    and character literals kept as they are)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == "/" and text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif c == "/" and text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
 
 
 def kernel_source_digest(group: str) -> str:
     h = hashlib.sha256()
     pkg = os.path.join(HERE, "paper_2112_03229_amd")
     for name in KERNEL_SOURCES[group]:
-        with open(os.path.join(pkg, name), "rb") as f:
+        with open(os.path.normpath(os.path.join(pkg, name)), encoding="utf-8") as f:
             h.update(name.encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
