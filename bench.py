@@ -805,7 +805,10 @@ def measure_interp(torch, binding, inputs, dev) -> dict:
                              "achieved_gbs": round(gbs_i, 1),
                              "frac": round(gbs_i / HBM_PEAK_GBS, 4)},
             "value_grid_mb": round(it.values.nbytes / 1e6, 1),
-            "tiles_per_wg": info["tiles_per_wg"], "lds_bytes": info["lds_bytes"]}
+            "tiles_per_wg": info["tiles_per_wg"], "lds_bytes": info["lds_bytes"],
+            "block": info["block"],
+            "traffic": measured_traffic("multi_kernel<interp>|interp-1024"),
+            "traffic_with_indices": measured_traffic("multi_kernel<interp-indices>|interp-1024")}
 
 
 def measure_learned(torch, binding, inputs, dev) -> dict:
