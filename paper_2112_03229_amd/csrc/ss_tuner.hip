@@ -300,10 +300,10 @@ int choose_tiles_per_workgroup(const TunerModel& model, int64_t total_tiles, int
   // workgroup; the 4096-material paired workload (8192 segments of ~60
   // tiles, dispatch order) 4.004 / 3.984 / 4.016 ms.  Those sweeps set the
   // model's defaults (tiles_short and tiles_long, for segments averaging
-  // under and over 64 tiles; both 5 now).  Smaller tiles (the joint and
-  // interpolation forms' 2048 targets) take proportionally more, the same
-  // targets per workgroup.  The count is then reduced while it leaves fewer
-  // than ~6 waves of workgroups.
+  // under and over 64 tiles; both 5 now).  Smaller tiles (the 2048 targets
+  // of the joint form and of plans of mostly learned targets) take
+  // proportionally more, the same targets per workgroup.  The count is then
+  // reduced while it leaves fewer than ~6 waves of workgroups.
   const int64_t scale = std::max<int64_t>(1, 4096 / std::max<int64_t>(per_tile, 1));
   const int64_t avg = total_tiles / std::max(segments, 1) / scale;
   int64_t k = (int64_t)std::lround(avg < 64 ? model.tiles_short : model.tiles_long) * scale;
