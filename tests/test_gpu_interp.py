@@ -71,6 +71,38 @@ def test_interp_matches_oracle(binding, gpu, oracle_mod, inputs_mod):
     assert np.array_equal(f2, f, equal_nan=True)
 
 
+@pytest.mark.parametrize("axes,block", [(((20, 60), (10, 40)), 512),
+                                        (((100, 250), (60, 120)), 1024)])
+def test_interp_grid_staging_forms(binding, gpu, oracle_mod, inputs_mod, axes, block):
+    """Small grids (all under 72 KB: two 512-thread workgroups per CU) and
+    large ones (up to 30000 values: those over 15360 are read from L2, the
+    rest staged by one 1024-thread workgroup per CU) in one plan each,
+    against the oracle, with the index outputs."""
+    n_rho, n_t = axes
+    it = inputs_mod.interp_layout(seed=7, materials=32, total_pairs=10**6 + 3, n_rho=n_rho,
+                                  n_t=n_t)
+    p = it.pairs
+    sizes = np.diff(it.value_off)
+    if block == 1024:
+        assert sizes.max() > 15360 and np.any((sizes > 9216) & (sizes <= 15360))
+    else:
+        assert sizes.max() <= 9216
+    rho, temp = inputs_mod.paired_targets(p, seed=7)
+    say(f"case interp staging block={block} largest grid {sizes.max()}")
+    plan = make_plan(binding, gpu, it)
+    assert plan.info()["block"] == block
+    o_r = torch.empty(p.num_pairs, dtype=torch.int32, device=gpu)
+    o_t = torch.empty_like(o_r)
+    f = plan.interpolate(torch.from_numpy(rho).to(gpu), torch.from_numpy(temp).to(gpu),
+                         out_rho=o_r, out_t=o_t).cpu().numpy()
+    check(oracle_mod, it, rho, temp, f)
+    assert np.array_equal(o_r.cpu().numpy(), oracle_mod.search_lt_segments(
+        p.rho.tables, p.rho.table_off, rho, p.rho.query_off))
+    assert np.array_equal(o_t.cpu().numpy(), oracle_mod.search_lt_segments(
+        p.temp.tables, p.temp.table_off, temp, p.temp.query_off))
+    plan.close()
+
+
 def test_grid_nodes_are_exact(binding, gpu, inputs_mod):
     it = inputs_mod.interp_layout(seed=6, materials=8, total_pairs=8)
     p = it.pairs
