@@ -760,6 +760,31 @@ def measure_paper_shape(torch, binding, inputs, dev) -> dict:
                 call(k % PAPER_BUFFERS)
         res[algo] = roof(PAPER_M, time_call(torch, g.replay, reps=5) / 64)
         del g
+    # the automatic choice's calls as SMALL_STREAMS independent chains (chain
+    # c takes calls k = c mod SMALL_STREAMS, whose buffers no other chain
+    # writes), so that the device may overlap them
+    g = torch.cuda.CUDAGraph()
+    chains = [torch.cuda.Stream() for _ in range(SMALL_STREAMS)]
+    with torch.cuda.graph(g, capture_error_mode="relaxed"):
+        main = torch.cuda.current_stream()
+        for c, s in enumerate(chains):
+            s.wait_stream(main)
+            with torch.cuda.stream(s):
+                for k in range(c, 64, SMALL_STREAMS):
+                    binding.search_sorted_batch(t, x[k % PAPER_BUFFERS], out[k % PAPER_BUFFERS])
+        for s in chains:
+            main.wait_stream(s)
+    ref = torch.empty_like(out)
+    for b in range(PAPER_BUFFERS):
+        binding.search_sorted_batch(t, x[b], ref[b])
+    out.fill_(-7)
+    g.replay()
+    torch.cuda.synchronize()
+    res["auto_independent_chains"] = {**roof(PAPER_M, time_call(torch, g.replay, reps=5) / 64),
+                                      "chains": SMALL_STREAMS,
+                                      "matches_eager": bool(torch.equal(out, ref))}
+    del ref
+    del g
     del x, out
     return res
 
