@@ -115,8 +115,11 @@ for joint in (0, 1):
         same(o_t.cpu().numpy(), wt, "paired T")
         plan.close()
 
-# interpolation (staged grids and grids read from global memory)
-it = inputs.interp_layout(seed=73, materials=24, total_pairs=300007)
+# interpolation (staged grids and grids read from global memory: axes up
+# to 250 x 120 points, grids over the 15360 values staged)
+it = inputs.interp_layout(seed=73, materials=24, total_pairs=300007, n_rho=(100, 250),
+                          n_t=(60, 120))
+assert np.diff(it.value_off).max() > 15360 and np.diff(it.value_off).min() <= 15360
 ip = it.pairs
 ir, itp = inputs.paired_targets(ip, seed=73)
 say("case interpolation")
