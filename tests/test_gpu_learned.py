@@ -397,6 +397,48 @@ def test_plan_targets_per_lane_follow_learned_share(binding, gpu, oracle_mod, in
         plan.close()
 
 
+def test_learned_plan_ragged_segments(binding, gpu, oracle_mod, inputs_mod):
+    """Every table learned, so 4 targets per lane (tiles of 2048), with
+    segments of 0, 1, 7, 2047, 2049 and 4097 targets starting at unaligned
+    positions: the short first and last tiles of each segment, the empty
+    one and the single-target one are exact, in both conventions."""
+    counts = [1, 7, 0, 2047, 2049, 4097]
+    batch = inputs_mod.batched_layout(seed=41, num_tables=6, query_scale=1e-3)
+    tt = torch.from_numpy(batch.tables).to(gpu)
+    off = batch.table_off
+    qoff = np.zeros(7, dtype=np.int64)
+    qoff[1:] = np.cumsum(counts)
+    x = np.empty(int(qoff[-1]))
+    for j in range(6):
+        tab = batch.tables[off[j]:off[j + 1]]
+        if counts[j]:
+            x[qoff[j]:qoff[j + 1]] = inputs_mod.table_targets(tab, counts[j], seed=j)
+    x[3] = np.nan
+    xd = torch.from_numpy(x).to(gpu)
+    models = [binding.LearnedIndex(tt[off[j]:off[j + 1]], steps=200, seed=j) for j in range(6)]
+    try:
+        for conv in (0, 1):
+            binding.set_option(binding.OPT_CONVENTION, conv)
+            say(f"case ragged learned plan convention={conv}")
+            plan = binding.MultiPlan(tt, off, qoff, models=models)
+            info = plan.info()
+            assert info["targets_per_lane"] == 4 and info["learned_form"] in (1, 2)
+            if conv:
+                want = np.empty(x.size, dtype=np.int32)
+                for j in range(6):
+                    if counts[j]:
+                        want[qoff[j]:qoff[j + 1]] = oracle_mod.search_le_clamped(
+                            batch.tables[off[j]:off[j + 1]], x[qoff[j]:qoff[j + 1]])
+            else:
+                want = oracle_mod.search_lt_segments(batch.tables, off, x, qoff)
+            assert np.array_equal(plan.search(xd).cpu().numpy(), want)
+            plan.close()
+    finally:
+        binding.set_option(binding.OPT_CONVENTION, 0)
+        for m in models:
+            m.close()
+
+
 def test_plan_with_attached_models(binding, gpu, oracle_mod, inputs_mod):
     """Learned handles built on tables of a batch are attached to a batched
     plan (ss_multi_plan_create_learned): those tables are searched through
